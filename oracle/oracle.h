@@ -1,0 +1,60 @@
+/*
+ * FP64 CPU oracle of the gliding-assay micro-step.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * this library.  It shares no source with the HIP path: its own trig tables, its own
+ * loops, its own sums.  Every array is a host, C-contiguous double array:
+ *   psi [nx][ny][nth], M [nx][ny][nth][ns], m0/m1 [nx][ny][nth],
+ *   u [2][nx][ny], gradu [4][nx][ny] = (dux/dx, dux/dy, duy/dx, duy/dy),
+ *   stress [3][nx][ny] = (xx, xy, yy), mom [7][nx][ny] = (c, nx, ny, Dxx, Dxy, Dyy, B).
+ *
+ * Model: Cook & Shinar, Sec. 2 (Eqs. (1)-(6) of the model-summary table) and Alg. 2.
+ */
+#ifndef MMK_ORACLE_H
+#define MMK_ORACLE_H
+
+typedef struct {
+    int nx, ny, nth, ns;
+    double lx, ly, L;
+    double k_on, k_off, v0;
+    double F, sigma_f;
+    int limiter;              /* 0: superbee MUSCL, 1: first-order upwind (sigma = 0) */
+} oracle_params;
+
+/* superbee slope of the two one-sided differences a (left) and b (right) */
+double oracle_superbee(double a, double b);
+
+/* right-hand side of the motor walk + attach/detach equation on one column of ns cells */
+void oracle_motor_rhs(const oracle_params *p, const double *z, double *R);
+
+/* one explicit-midpoint step of one column: Mout = M + dt R(M + dt/2 R(M)) */
+void oracle_column_step(const oracle_params *p, double dt, const double *M, double *Mout);
+
+/* zeroth and first arclength moments of one column */
+void oracle_column_moments(const oracle_params *p, const double *M, double *m0, double *m1);
+
+/* all columns: Mout, m0, m1 (m1 may be NULL) */
+void oracle_motor_step(const oracle_params *p, double dt, const double *M, double *Mout,
+                       double *m0, double *m1);
+
+/* conservative donor-cell update of psi with velocities built from m0, u, gradu */
+void oracle_psi_step(const oracle_params *p, double dt, const double *psi, const double *m0,
+                     const double *u, const double *gradu, double *psi_out);
+
+/* theta-moments and extra stress of (psi, m0, m1) */
+void oracle_moments(const oracle_params *p, const double *psi, const double *m0,
+                    const double *m1, double *stress, double *mom);
+
+/* compensated FP64 totals: mass = sum psi dx dy dth, sum_sigma[c] = sum sigma_c dx dy */
+void oracle_global_sums(const oracle_params *p, const double *psi, const double *stress,
+                        double *mass, double *sum_sigma);
+
+/* nsteps micro-steps with one fluid field; psi and M are updated in place.
+ * m0/m1 receive the moments of the final M (either may be NULL). */
+void oracle_run(const oracle_params *p, double dt, int nsteps, double *psi, double *M,
+                const double *u, const double *gradu, double *m0, double *m1);
+
+int oracle_max_threads(void);
+void oracle_set_threads(int n);
+
+#endif

@@ -1,0 +1,169 @@
+"""ctypes front end of the C oracle (liboracle.so).  TEST INFRASTRUCTURE ONLY.
+
+`OracleA` mirrors the call sequence of the HIP library (set_state, set_fluid, step(K, dt),
+get_*) on host numpy float64 arrays so that the tests can drive both the same way.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+TWO_PI = 2.0 * np.pi
+
+
+class _Params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nth", C.c_int), ("ns", C.c_int),
+                ("lx", C.c_double), ("ly", C.c_double), ("L", C.c_double),
+                ("k_on", C.c_double), ("k_off", C.c_double), ("v0", C.c_double),
+                ("F", C.c_double), ("sigma_f", C.c_double), ("limiter", C.c_int)]
+
+
+_lib = None
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build
+            build.build()
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER(_Params)
+        L.oracle_superbee.argtypes = [C.c_double, C.c_double]
+        L.oracle_superbee.restype = C.c_double
+        L.oracle_motor_rhs.argtypes = [P, _dp, _dp]
+        L.oracle_column_step.argtypes = [P, C.c_double, _dp, _dp]
+        L.oracle_column_moments.argtypes = [P, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_motor_step.argtypes = [P, C.c_double, _dp, _dp, C.c_void_p, C.c_void_p]
+        L.oracle_psi_step.argtypes = [P, C.c_double, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_moments.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_global_sums.argtypes = [P, _dp, _dp, C.POINTER(C.c_double), _dp]
+        L.oracle_run.argtypes = [P, C.c_double, C.c_int, _dp, _dp, _dp, _dp, C.c_void_p, C.c_void_p]
+        L.oracle_max_threads.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def cparams(p) -> _Params:
+    """Accepts any object with the ModelParams attribute names."""
+    return _Params(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, p.k_on, p.k_off, p.v0,
+                   p.F, p.sigma_f, int(getattr(p, "limiter", 0)))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def superbee(a, b):
+    return lib().oracle_superbee(float(a), float(b))
+
+
+def motor_rhs(p, z):
+    z = _f64(z)
+    R = np.empty_like(z)
+    lib().oracle_motor_rhs(C.byref(cparams(p)), z, R)
+    return R
+
+
+def column_step(p, dt, M):
+    M = _f64(M)
+    out = np.empty_like(M)
+    lib().oracle_column_step(C.byref(cparams(p)), float(dt), M, out)
+    return out
+
+
+def column_moments(p, M):
+    a, b = C.c_double(), C.c_double()
+    lib().oracle_column_moments(C.byref(cparams(p)), _f64(M), C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def motor_step(p, dt, M):
+    M = _f64(M)
+    out = np.empty_like(M)
+    m0 = np.empty(M.shape[:-1])
+    m1 = np.empty(M.shape[:-1])
+    lib().oracle_motor_step(C.byref(cparams(p)), float(dt), M, out, _ptr(m0), _ptr(m1))
+    return out, m0, m1
+
+
+def psi_step(p, dt, psi, m0, u, gradu):
+    psi = _f64(psi)
+    out = np.empty_like(psi)
+    lib().oracle_psi_step(C.byref(cparams(p)), float(dt), psi, _f64(m0), _f64(u), _f64(gradu), out)
+    return out
+
+
+def moments(p, psi, m0, m1):
+    stress = np.empty((3, p.nx, p.ny))
+    mom = np.empty((7, p.nx, p.ny))
+    lib().oracle_moments(C.byref(cparams(p)), _f64(psi), _f64(m0), _f64(m1), stress, mom)
+    return stress, mom
+
+
+def global_sums(p, psi, stress):
+    mass = C.c_double()
+    ss = np.empty(3)
+    lib().oracle_global_sums(C.byref(cparams(p)), _f64(psi), _f64(stress), C.byref(mass), ss)
+    return mass.value, ss
+
+
+def max_threads():
+    return lib().oracle_max_threads()
+
+
+def set_threads(n):
+    lib().oracle_set_threads(int(n))
+
+
+class OracleA:
+    """Host-side stepper with the same call order as the HIP library's context."""
+
+    def __init__(self, p):
+        self.p = p
+        self.psi = None
+        self.M = None
+        self.u = None
+        self.gradu = None
+        self.m0 = None
+        self.m1 = None
+
+    def set_params(self, k_on, k_off, v0):
+        self.p.k_on, self.p.k_off, self.p.v0 = float(k_on), float(k_off), float(v0)
+
+    def set_state(self, psi, M=None):
+        p = self.p
+        self.psi = _f64(psi).copy()
+        self.M = (np.zeros((p.nx, p.ny, p.ntheta, p.ns)) if M is None else _f64(M).copy())
+        self.m0 = self.m1 = None
+
+    def set_fluid(self, u, gradu):
+        self.u, self.gradu = _f64(u).copy(), _f64(gradu).copy()
+
+    def step(self, K, dt):
+        p = self.p
+        m0 = np.empty(self.psi.shape)
+        m1 = np.empty(self.psi.shape)
+        lib().oracle_run(C.byref(cparams(p)), float(dt), int(K), self.psi, self.M, self.u,
+                         self.gradu, _ptr(m0), _ptr(m1))
+        self.m0, self.m1 = m0, m1
+
+    def get_state(self):
+        return self.psi.copy(), self.M.copy()
+
+    def get_stress_moments(self):
+        return moments(self.p, self.psi, self.m0, self.m1)
+
+    def get_sums(self):
+        stress, _ = self.get_stress_moments()
+        return global_sums(self.p, self.psi, stress)
