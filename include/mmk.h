@@ -1,0 +1,138 @@
+/*
+ * mmk - micro-step library for the microscale kinetic theory of a gliding motility assay
+ * (S. Cook and T. Shinar, "Enabling Simulation of High-Dimensional Micro-Macro Biophysical
+ * Models through Hybrid CPU and Multi-GPU Parallelism").  MI355X (gfx950), HIP.
+ *
+ * One micro-step, at every configuration point (x, y, th) of a periodic nx x ny box with
+ * ntheta orientations and ns arclength cells per filament:
+ *   1. bound-motor density M(s) walks towards the plus end at speed v0, attaches at k_on and
+ *      detaches at k_off M (Sec. 2, Eq. (4)), superbee-limited flux (Sec. 2), two-stage
+ *      midpoint Runge-Kutta (Sec. 3.1, Alg. 2);
+ *   2. s-moments m0 = sum M ds and m1 = sum (s - L/2) M ds (Eq. (5) reduced to one filament);
+ *   3. conservative donor-cell update of the filament density Psi(x, y, th) with velocity
+ *      u - F m0 p and rotation rate p_perp . grad(u) . p (Sec. 2, Eqs. (1)-(3));
+ *   4. on the last micro-step of a call: theta-moments of Psi and the extra stress
+ *      sigma = sigma_f (D - c I / 2) + F sum Psi m1 p p dth (extra-stress step of Alg. 1).
+ *
+ * Conventions for every function below:
+ *  - Arrays are DEVICE pointers on the context's device, C-contiguous, in the context's
+ *    precision (double for MMK_FP64, float for MMK_FP32), with layouts
+ *      psi [nx][ny][ntheta], M [nx][ny][ntheta][ns] (s fastest),
+ *      u [2][nx][ny] = (u_x, u_y), gradu [4][nx][ny] = (dux/dx, dux/dy, duy/dx, duy/dy),
+ *      sigma [3][nx][ny] = (xx, xy, yy), moments [7][nx][ny] = (c, n_x, n_y, Dxx, Dxy, Dyy, B),
+ *      m0 / m1 [nx][ny][ntheta].
+ *    Host arguments are marked "host".
+ *  - The caller owns every buffer it passes, including the workspace.  The library never
+ *    allocates device memory; it only reads and writes inside the workspace and the
+ *    arguments during calls.  Input pointers are not retained after a call returns.
+ *  - All device work is ordered on the HIP stream given to mmk_create.  Functions return
+ *    once the work is enqueued, except those marked "synchronizes".
+ *  - Every function returns an mmk_status and never aborts; mmk_last_error() gives the text.
+ *    A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef MMK_H
+#define MMK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mmk_ctx mmk_ctx;
+
+typedef enum {
+    MMK_OK = 0,
+    MMK_ERR_ARG = -1,          /* bad sizes, null pointers, non-finite or <= 0 dt, ... */
+    MMK_ERR_NOMEM = -2,        /* workspace smaller than mmk_workspace_bytes() */
+    MMK_ERR_HIP = -3,          /* a HIP runtime call failed (message says which) */
+    MMK_ERR_STATE = -4,        /* call order: step before set_state/set_fluid, ... */
+    MMK_ERR_UNSUPPORTED = -5   /* sizes the kernels are not built for */
+} mmk_status;
+
+typedef enum { MMK_FP64 = 0, MMK_FP32 = 1 } mmk_precision;
+typedef enum { MMK_SUPERBEE = 0, MMK_UPWIND1 = 1 } mmk_limiter;
+
+typedef struct {
+    int32_t nx, ny;        /* periodic grid, >= 1 each */
+    int32_t ntheta;        /* orientations th_k = 2 pi k / ntheta, 1 .. 4096 */
+    int32_t ns;            /* arclength cells s_l = (l + 1/2) L / ns, 1 .. 512 */
+    double lx, ly;         /* box size (> 0) */
+    double L;              /* filament length (> 0) */
+    double k_on, k_off;    /* attachment rate (free pool taken as 1) and detachment rate */
+    double v0;             /* motor walking speed along +s, >= 0 */
+    double F;              /* motor force coefficient: gliding speed F m0 along -p */
+    double sigma_f;        /* filament extra-stress coefficient */
+    int32_t precision;     /* mmk_precision: storage AND arithmetic of every field */
+    int32_t limiter;       /* mmk_limiter; MMK_UPWIND1 sets the superbee slope to 0 */
+} mmk_params;
+
+/* Bytes of device workspace a context needs.  ckpt_every > 0 reserves the adjoint tape:
+ * checkpoints of (Psi, M) every ckpt_every steps for up to max_tape_steps taped steps, a
+ * ckpt_every-step recompute buffer, adjoint fields and one fluid slot per taped step.
+ * ckpt_every = 0 (max_tape_steps ignored) gives the forward-only size.  Returns 0 on
+ * invalid params. */
+size_t mmk_workspace_bytes(const mmk_params *p, int32_t ckpt_every, int32_t max_tape_steps);
+
+/* Creates a context on the current HIP device.  workspace: device pointer, 256-byte
+ * aligned, ws_bytes >= mmk_workspace_bytes(p, ckpt_every, max_tape_steps).  hip_stream:
+ * a hipStream_t (NULL = the null stream).  *out receives the context (host memory owned by
+ * the library, freed by mmk_destroy).  Fills the trig tables in the workspace (async). */
+mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, void *hip_stream,
+                      int32_t ckpt_every, int32_t max_tape_steps, mmk_ctx **out);
+mmk_status mmk_destroy(mmk_ctx *ctx);
+
+/* Replaces k_on, k_off, v0 (host values) for the following steps. */
+mmk_status mmk_set_params(mmk_ctx *ctx, double k_on, double k_off, double v0);
+
+/* Copies the state in: psi [nx][ny][ntheta]; M [nx][ny][ntheta][ns], or NULL for M = 0. */
+mmk_status mmk_set_state(mmk_ctx *ctx, const void *psi, const void *M);
+
+/* Copies the fluid velocity u [2][nx][ny] and its gradient gradu [4][nx][ny] in; they act
+ * on every following micro-step until replaced (the macro exchange). */
+mmk_status mmk_set_fluid(mmk_ctx *ctx, const void *u, const void *gradu);
+
+/* Runs K >= 0 micro-steps of size dt (finite, > 0), motors first then Psi driven by the new
+ * m0.  The last step also computes stress, moments and the FP64 global sums.  No host sync. */
+mmk_status mmk_step(mmk_ctx *ctx, int32_t K, double dt);
+
+/* Copies the current state out (either pointer may be NULL). */
+mmk_status mmk_get_state(mmk_ctx *ctx, void *psi, void *M);
+/* Stress / moments of the state after the last mmk_step with K > 0. */
+mmk_status mmk_get_stress(mmk_ctx *ctx, void *sigma);
+mmk_status mmk_get_moments(mmk_ctx *ctx, void *moments);
+/* s-moments of the current M: m0 always, m1 as of the last step that produced outputs. */
+mmk_status mmk_get_motor_moments(mmk_ctx *ctx, void *m0, void *m1);
+/* host outputs, synchronizes: mass = sum Psi dx dy dth and sum_sigma[c] = sum sigma_c dx dy,
+ * both accumulated in FP64 in a fixed order (bitwise reproducible). */
+mmk_status mmk_get_sums(mmk_ctx *ctx, double *mass, double sum_sigma[3]);
+
+/* Adjoint tape.  mmk_tape_begin records the current state as checkpoint 0 and the current
+ * fluid; later set_fluid/step calls are recorded (at most max_tape_steps steps).
+ * mmk_tape_backward (synchronizes) returns the gradient of
+ *     L = <g_sigma, sigma(T)> + <g_moments, moments(T)>
+ * (either cotangent may be NULL = 0) with respect to the taped initial Psi (g_psi0, device,
+ * [nx][ny][ntheta]) and to k_on, k_off, v0 (g_params, host double[3]).  dt is held fixed.
+ * It recomputes each checkpoint segment forward, then runs the hand-written reverse
+ * kernels.  The forward state is left as it was.  mmk_tape_end drops the tape. */
+mmk_status mmk_tape_begin(mmk_ctx *ctx, int32_t ckpt_every);
+mmk_status mmk_tape_backward(mmk_ctx *ctx, const void *g_sigma, const void *g_moments,
+                             void *g_psi0, double g_params[3]);
+mmk_status mmk_tape_end(mmk_ctx *ctx);
+
+/* Kernel timing: with enable != 0 every launch is bracketed by HIP events on the context's
+ * stream.  mmk_profile_read (synchronizes) sums the elapsed times of kernel `kernel_id`
+ * (0 motor step, 1 psi step, 2 global sums, 3 reverse psi step, 4 reverse motor step)
+ * since profiling was enabled; up to 65536 launches per id are timed. */
+mmk_status mmk_profile(mmk_ctx *ctx, int32_t enable);
+mmk_status mmk_profile_read(mmk_ctx *ctx, int32_t kernel_id, double *total_ms, int64_t *launches);
+
+/* Message of the last failure on ctx; with ctx == NULL, of the last failed mmk_create or
+ * mmk_workspace_bytes on this thread. */
+const char *mmk_last_error(const mmk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,127 @@
+// Device helpers for gfx950 (CDNA4, wave64): DPP lane moves inside 16-lane rows and
+// error-free transformations for compensated sums.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace mmk {
+
+// DPP control codes (GFX9 encoding).
+enum : int {
+    DPP_QUAD_XOR1 = 0xB1,        // quad_perm [1,0,3,2]
+    DPP_QUAD_XOR2 = 0x4E,        // quad_perm [2,3,0,1]
+    DPP_ROW_SHL1 = 0x101,        // lane i <- lane i+1 within the 16-lane row
+    DPP_ROW_SHR1 = 0x111,        // lane i <- lane i-1 within the 16-lane row
+    DPP_ROW_MIRROR = 0x140,      // lane i <- lane 15-i
+    DPP_ROW_HALF_MIRROR = 0x141  // lane i <- lane 7-i within each half row
+};
+
+// v from the lane selected by CTRL; lanes whose source is outside the row keep `old`.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v, float old) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, old), __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v, double old) {
+    const uint64_t vb = __builtin_bit_cast(uint64_t, v), ob = __builtin_bit_cast(uint64_t, old);
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)ob, (int)(uint32_t)vb, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(ob >> 32), (int)(uint32_t)(vb >> 32),
+                                               CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Lane moves inside groups of G consecutive lanes (G in 1, 2, 4, 8, 16; groups never straddle
+// a DPP row).  from_prev: value of lane g-1 of the group, `edge` on lane 0.  from_next: value
+// of lane g+1, `edge` on lane G-1.
+template <int G, typename T>
+__device__ __forceinline__ T from_prev(T v, T edge, int g) {
+    if constexpr (G == 1) {
+        return edge;
+    } else {
+        T r = dpp<DPP_ROW_SHR1>(v, edge);
+        if constexpr (G < 16) r = (g == 0) ? edge : r;
+        return r;
+    }
+}
+template <int G, typename T>
+__device__ __forceinline__ T from_next(T v, T edge, int g) {
+    if constexpr (G == 1) {
+        return edge;
+    } else {
+        T r = dpp<DPP_ROW_SHL1>(v, edge);
+        if constexpr (G < 16) r = (g == G - 1) ? edge : r;
+        return r;
+    }
+}
+
+// Sum over the G lanes of a group (butterfly); every lane of the group gets the total.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+    if constexpr (G >= 2) v += dpp<DPP_QUAD_XOR1>(v, v);
+    if constexpr (G >= 4) v += dpp<DPP_QUAD_XOR2>(v, v);
+    if constexpr (G >= 8) v += dpp<DPP_ROW_HALF_MIRROR>(v, v);
+    if constexpr (G >= 16) v += dpp<DPP_ROW_MIRROR>(v, v);
+    return v;
+}
+
+// Knuth's TwoSum: s + e == a + b exactly (round-to-nearest, no contraction).
+#pragma clang fp contract(off)
+template <typename T>
+__device__ __forceinline__ void two_sum(T a, T b, T &s, T &e) {
+    s = a + b;
+    T bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Compensated running sum: hi + lo carries the value; adding x keeps the rounding error.
+template <typename T>
+struct CSum {
+    T hi, lo;
+    __device__ __forceinline__ CSum() : hi(0), lo(0) {}
+    __device__ __forceinline__ void add(T x) {
+        T s, e;
+        two_sum(hi, x, s, e);
+        hi = s;
+        lo += e;
+    }
+    __device__ __forceinline__ T value() const { return hi + lo; }
+};
+
+// Kahan's running sum (4 operations per term).
+template <typename T>
+struct KahanT {
+    T sum = 0, comp = 0;
+    __device__ __forceinline__ void add(T x) {
+        const T y = x - comp;
+        const T t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+    }
+};
+using Kahan = KahanT<float>;
+
+// Compensated butterfly over the G lanes of a group, starting from a Kahan pair
+// (value = s - e).  Every lane of the group gets the total.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum_comp(T s, T kahan_comp) {
+    T e = -kahan_comp;
+    auto level = [&](auto tag) {
+        constexpr int CTRL = decltype(tag)::value;
+        T s2 = dpp<CTRL>(s, s), e2 = dpp<CTRL>(e, e);
+        T t, err;
+        two_sum(s, s2, t, err);
+        s = t;
+        e = e + e2 + err;
+    };
+    if constexpr (G >= 2) level(std::integral_constant<int, DPP_QUAD_XOR1>{});
+    if constexpr (G >= 4) level(std::integral_constant<int, DPP_QUAD_XOR2>{});
+    if constexpr (G >= 8) level(std::integral_constant<int, DPP_ROW_HALF_MIRROR>{});
+    if constexpr (G >= 16) level(std::integral_constant<int, DPP_ROW_MIRROR>{});
+    return s + e;
+}
+#pragma clang fp contract(on)
+
+}  // namespace mmk

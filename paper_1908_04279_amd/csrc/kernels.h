@@ -1,0 +1,60 @@
+// Internal launch interface between the C-ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mmk {
+
+// Constants of the motor column step, already in the field precision.
+template <typename T>
+struct MotorConst {
+    T k_on, k_off, v0;
+    T nv_ds;       // -v0 / ds
+    T dt, half_dt; // step and midpoint stage
+    T ds, ds2;     // m0 = ds * sum M,  m1 = ds^2 * sum (l + 1/2 - ns/2) M
+};
+
+// Forward motor step over `ncol` independent columns of `ns` cells.
+//   M_out = M + dt R(M + dt/2 R(M));  m0 = sum M_out ds;  m1 (if non-null) likewise.
+template <typename T>
+hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
+                             int limiter, const MotorConst<T> &c, hipStream_t s);
+
+// Geometry and constants of the filament-density step.
+template <typename T>
+struct PsiConst {
+    int nx, ny, nth;
+    T dt, inv_dx, inv_dy, inv_dth, F, sigma_f, dth;
+};
+
+// Precomputed angle tables: [9][nth] = cos th_k, sin th_k, cos th_{k+1/2}, sin th_{k+1/2},
+// cos(2 th_k)/2, sin(2 th_k)/2, cos^2, cos sin, sin^2.
+enum { TAB_C = 0, TAB_S, TAB_CH, TAB_SH, TAB_H1, TAB_H2, TAB_CC, TAB_CS, TAB_SS, TAB_N };
+
+struct PsiLaunch {
+    int ti, tj;          // tile of pencils per block
+    int tiles_i, tiles_j;
+    int blocks;          // grid size (XCD-banded, >= tiles)
+    int group;           // lanes per pencil group (16, 32 or 64)
+    size_t lds_bytes;
+};
+PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem);
+
+// Donor-cell update psi_out = psi_in - dt div(flux).  If `stress` is non-null, also writes
+// stress[3][nx][ny], mom[7][nx][ny] of (psi_out, m0, m1) and per-block FP64 partials
+// partials[blocks][4] = (sum psi_out, sum sxx, sum sxy, sum syy).
+template <typename T>
+hipError_t launch_psi_step(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u,
+                           const T *G, const T *tab, T *stress, T *mom, double *partials,
+                           const PsiConst<T> &c, const PsiLaunch &pl, hipStream_t s);
+
+// Fixed-order compensated FP64 sum of partials[n][4] -> out[4] * scale[4].
+hipError_t launch_reduce_partials(const double *partials, int n, double *out, double s0,
+                                  double s1, hipStream_t s);
+
+// out[i] = 0, i < n (typed fill so graph capture never records a memset node)
+template <typename T>
+hipError_t launch_zero(T *out, int64_t n, hipStream_t s);
+
+}  // namespace mmk

@@ -1,0 +1,525 @@
+// C-ABI of the micro-step library: argument checks, workspace layout, launch sequencing.
+// Every step of the method runs in the HIP kernels of motor.hip, psi.hip and adjoint.hip;
+// this file only validates, carves the caller's workspace and enqueues work on the stream.
+#include "../../include/mmk.h"
+#include "kernels.h"
+#include "tape.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace mmk;
+
+namespace {
+
+thread_local std::string g_create_error;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr int kMaxTheta = 512;
+constexpr int kMaxS = 512;
+constexpr int kProfIds = 5;
+constexpr int kProfMax = 65536;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t M[2], psi[2], m0, m1, u, G, stress, mom, tab, partials, sums;
+    TapeLayout tape;
+    size_t total;
+    int psi_blocks;
+};
+
+int64_t n_psi(const mmk_params &p) { return (int64_t)p.nx * p.ny * p.ntheta; }
+int64_t n_m(const mmk_params &p) { return n_psi(p) * p.ns; }
+size_t esize(const mmk_params &p) { return p.precision == MMK_FP32 ? 4 : 8; }
+
+// Returns an error message, or empty when the parameters are usable.
+std::string check_params(const mmk_params *p) {
+    if (!p) return "params is NULL";
+    if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
+    if (p->ntheta < 1) return "ntheta must be >= 1";
+    if (p->ns < 1) return "ns must be >= 1";
+    if (p->precision != MMK_FP32 && p->precision != MMK_FP64) return "precision must be MMK_FP64 or MMK_FP32";
+    if (p->limiter != MMK_SUPERBEE && p->limiter != MMK_UPWIND1) return "limiter must be MMK_SUPERBEE or MMK_UPWIND1";
+    const double vals[] = {p->lx, p->ly, p->L, p->k_on, p->k_off, p->v0, p->F, p->sigma_f};
+    for (double v : vals)
+        if (!std::isfinite(v)) return "non-finite model parameter";
+    if (p->lx <= 0 || p->ly <= 0 || p->L <= 0) return "lx, ly and L must be > 0";
+    if (p->v0 < 0) return "v0 must be >= 0 (motors walk towards s = L)";
+    if ((int64_t)p->nx * p->ny > ((int64_t)1 << 31)) return "nx * ny too large";
+    return "";
+}
+
+std::string check_supported(const mmk_params *p) {
+    if (p->ntheta > kMaxTheta) return "ntheta > 512 is not supported by the psi kernel";
+    if (p->ns > kMaxS) return "ns > 512 is not supported by the motor kernel";
+    if (plan_psi(p->nx, p->ny, p->ntheta, esize(*p)).lds_bytes > 64 * 1024)
+        return "ntheta too large for the psi kernel's LDS tile at this precision";
+    return "";
+}
+
+Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
+    Layout L{};
+    const size_t e = esize(p);
+    const size_t nm = (size_t)n_m(p), np = (size_t)n_psi(p), nxy = (size_t)p.nx * p.ny;
+    const PsiLaunch pl = plan_psi(p.nx, p.ny, p.ntheta, e);
+    L.psi_blocks = pl.blocks;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.M[0] = take(nm * e);
+    L.M[1] = take(nm * e);
+    L.psi[0] = take(np * e);
+    L.psi[1] = take(np * e);
+    L.m0 = take(np * e);
+    L.m1 = take(np * e);
+    L.u = take(2 * nxy * e);
+    L.G = take(4 * nxy * e);
+    L.stress = take(3 * nxy * e);
+    L.mom = take(7 * nxy * e);
+    L.tab = take(TAB_N * (size_t)p.ntheta * e);
+    L.partials = take((size_t)pl.blocks * 4 * sizeof(double));
+    L.sums = take(4 * sizeof(double));
+    off = tape_layout(&L.tape, off, nm, np, nxy, e, ckpt_every, max_tape_steps);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct mmk_ctx {
+    mmk_params p{};
+    size_t esz = 8;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char *ws = nullptr;
+    Layout L{};
+    PsiLaunch pl{};
+    int cur = 0;  // index of the current M / psi buffers
+    bool have_state = false, have_fluid = false, have_out = false;
+    std::string err;
+    bool prof = false;
+    std::vector<hipEvent_t> ev[kProfIds];  // start/stop pairs
+    int nev[kProfIds] = {0, 0, 0, 0, 0};
+    TapeState tape;
+    std::vector<double> host_tab64;  // host copies of the angle tables (outlive the async copy)
+    std::vector<float> host_tab32;
+
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    void *vat(size_t off) const { return ws + off; }
+};
+
+static mmk_status fail(mmk_ctx *c, mmk_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_create_error = buf;
+    return st;
+}
+
+static mmk_status hipfail(mmk_ctx *c, hipError_t e, const char *what) {
+    return fail(c, MMK_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call, what)                       \
+    do {                                              \
+        hipError_t _e = (call);                       \
+        if (_e != hipSuccess) return hipfail(ctx, _e, what); \
+    } while (0)
+
+// ---- profiling: event pairs around launches ---------------------------------------------
+static hipError_t prof_begin(mmk_ctx *c, int id, int *slot) {
+    *slot = -1;
+    if (!c->prof || c->nev[id] >= kProfMax) return hipSuccess;
+    int i = c->nev[id];
+    while ((int)c->ev[id].size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        c->ev[id].push_back(e);
+    }
+    *slot = i;
+    return hipEventRecord(c->ev[id][2 * i], c->stream);
+}
+static hipError_t prof_end(mmk_ctx *c, int id, int slot) {
+    if (slot < 0) return hipSuccess;
+    c->nev[id] = slot + 1;
+    return hipEventRecord(c->ev[id][2 * slot + 1], c->stream);
+}
+
+// ---- typed step ---------------------------------------------------------------------------
+template <typename T>
+static MotorConst<T> motor_const(const mmk_params &p, double dt) {
+    const double ds = p.L / p.ns;
+    MotorConst<T> c;
+    c.k_on = (T)p.k_on;
+    c.k_off = (T)p.k_off;
+    c.v0 = (T)p.v0;
+    c.nv_ds = (T)(-p.v0 / ds);
+    c.dt = (T)dt;
+    c.half_dt = (T)(0.5 * dt);
+    c.ds = (T)ds;
+    c.ds2 = (T)(ds * ds);
+    return c;
+}
+
+template <typename T>
+static PsiConst<T> psi_const(const mmk_params &p, double dt) {
+    PsiConst<T> c;
+    c.nx = p.nx;
+    c.ny = p.ny;
+    c.nth = p.ntheta;
+    c.dt = (T)dt;
+    c.inv_dx = (T)(p.nx / p.lx);
+    c.inv_dy = (T)(p.ny / p.ly);
+    c.inv_dth = (T)(p.ntheta / kTwoPi);
+    c.F = (T)p.F;
+    c.sigma_f = (T)p.sigma_f;
+    c.dth = (T)(kTwoPi / p.ntheta);
+    return c;
+}
+
+// One micro-step from (M_in, psi_in) to (M_out, psi_out).  With out = true also the
+// stress, moments and the block partials of the global sums.
+template <typename T>
+static mmk_status micro_step(mmk_ctx *c, const T *M_in, T *M_out, const T *psi_in, T *psi_out, T *m0,
+                             const T *u, const T *G, double dt, bool out) {
+    const mmk_params &p = c->p;
+    const MotorConst<T> mc = motor_const<T>(p, dt);
+    T *m1 = out ? c->at<T>(c->L.m1) : nullptr;
+    int slot;
+    HIPCHK(c, prof_begin(c, 0, &slot), "hipEventRecord");
+    HIPCHK(c, launch_motor_step<T>(M_in, M_out, m0, m1, n_psi(p), p.ns, p.limiter, mc, c->stream),
+           "motor step launch");
+    HIPCHK(c, prof_end(c, 0, slot), "hipEventRecord");
+    const PsiConst<T> pc = psi_const<T>(p, dt);
+    HIPCHK(c, prof_begin(c, 1, &slot), "hipEventRecord");
+    HIPCHK(c, launch_psi_step<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab),
+                                 out ? c->at<T>(c->L.stress) : nullptr, out ? c->at<T>(c->L.mom) : nullptr,
+                                 out ? c->at<double>(c->L.partials) : nullptr, pc, c->pl, c->stream),
+           "psi step launch");
+    HIPCHK(c, prof_end(c, 1, slot), "hipEventRecord");
+    return MMK_OK;
+}
+
+template <typename T>
+static mmk_status global_sums(mmk_ctx *c) {
+    const mmk_params &p = c->p;
+    const double dx = p.lx / p.nx, dy = p.ly / p.ny, dth = kTwoPi / p.ntheta;
+    int slot;
+    HIPCHK(c, prof_begin(c, 2, &slot), "hipEventRecord");
+    HIPCHK(c, launch_reduce_partials(c->at<double>(c->L.partials), c->pl.blocks, c->at<double>(c->L.sums),
+                                     dx * dy * dth, dx * dy, c->stream),
+           "global sums launch");
+    HIPCHK(c, prof_end(c, 2, slot), "hipEventRecord");
+    return MMK_OK;
+}
+
+template <typename T>
+static mmk_status run_steps(mmk_ctx *c, int K, double dt) {
+    for (int n = 0; n < K; ++n) {
+        const bool last = (n == K - 1);
+        const int a = c->cur, b = 1 - c->cur;
+        mmk_status st = tape_before_step(c, &c->tape, dt);
+        if (st != MMK_OK) return st;
+        st = micro_step<T>(c, c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), c->at<T>(c->L.psi[a]),
+                           c->at<T>(c->L.psi[b]), c->at<T>(c->L.m0), c->at<T>(c->L.u), c->at<T>(c->L.G), dt,
+                           last);
+        if (st != MMK_OK) return st;
+        c->cur = b;
+        st = tape_after_step(c, &c->tape);
+        if (st != MMK_OK) return st;
+    }
+    if (K > 0) {
+        c->have_out = true;
+        return global_sums<T>(c);
+    }
+    return MMK_OK;
+}
+
+// ---- internal accessors used by the tape ---------------------------------------------------
+namespace mmk {
+const mmk_params &ctx_params(const mmk_ctx *c) { return c->p; }
+hipStream_t ctx_stream(const mmk_ctx *c) { return c->stream; }
+char *ctx_ws(const mmk_ctx *c) { return c->ws; }
+size_t ctx_esz(const mmk_ctx *c) { return c->esz; }
+const TapeLayout &ctx_tape_layout(const mmk_ctx *c) { return c->L.tape; }
+void *ctx_cur_M(const mmk_ctx *c) { return c->ws + c->L.M[c->cur]; }
+void *ctx_cur_psi(const mmk_ctx *c) { return c->ws + c->L.psi[c->cur]; }
+void *ctx_fluid_u(const mmk_ctx *c) { return c->ws + c->L.u; }
+void *ctx_fluid_G(const mmk_ctx *c) { return c->ws + c->L.G; }
+void *ctx_m0(const mmk_ctx *c) { return c->ws + c->L.m0; }
+void *ctx_m1(const mmk_ctx *c) { return c->ws + c->L.m1; }
+void *ctx_tab(const mmk_ctx *c) { return c->ws + c->L.tab; }
+const PsiLaunch &ctx_psi_launch(const mmk_ctx *c) { return c->pl; }
+mmk_status ctx_fail(mmk_ctx *c, mmk_status st, const char *msg) { return fail(c, st, "%s", msg); }
+mmk_status ctx_hipfail(mmk_ctx *c, hipError_t e, const char *what) { return hipfail(c, e, what); }
+hipError_t ctx_prof_begin(mmk_ctx *c, int id, int *slot) { return prof_begin(c, id, slot); }
+hipError_t ctx_prof_end(mmk_ctx *c, int id, int slot) { return prof_end(c, id, slot); }
+template <typename T>
+mmk_status ctx_forward_step(mmk_ctx *c, const T *M_in, T *M_out, const T *psi_in, T *psi_out, T *m0,
+                            const T *u, const T *G, double dt) {
+    return micro_step<T>(c, M_in, M_out, psi_in, psi_out, m0, u, G, dt, false);
+}
+template mmk_status ctx_forward_step<float>(mmk_ctx *, const float *, float *, const float *, float *, float *,
+                                            const float *, const float *, double);
+template mmk_status ctx_forward_step<double>(mmk_ctx *, const double *, double *, const double *, double *,
+                                             double *, const double *, const double *, double);
+}  // namespace mmk
+
+// ---- C-ABI ----------------------------------------------------------------------------------
+extern "C" {
+
+size_t mmk_workspace_bytes(const mmk_params *p, int32_t ckpt_every, int32_t max_tape_steps) {
+    std::string m = check_params(p);
+    if (m.empty()) m = check_supported(p);
+    if (m.empty() && ckpt_every < 0) m = "ckpt_every must be >= 0";
+    if (m.empty() && ckpt_every > 0 && max_tape_steps < 0) m = "max_tape_steps must be >= 0";
+    if (!m.empty()) {
+        g_create_error = m;
+        return 0;
+    }
+    return make_layout(*p, ckpt_every, ckpt_every > 0 ? max_tape_steps : 0).total;
+}
+
+mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, void *hip_stream,
+                      int32_t ckpt_every, int32_t max_tape_steps, mmk_ctx **out) {
+    if (!out) return fail(nullptr, MMK_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    std::string m = check_params(p);
+    if (!m.empty()) return fail(nullptr, MMK_ERR_ARG, "%s", m.c_str());
+    m = check_supported(p);
+    if (!m.empty()) return fail(nullptr, MMK_ERR_UNSUPPORTED, "%s", m.c_str());
+    if (ckpt_every < 0 || (ckpt_every > 0 && max_tape_steps < 0))
+        return fail(nullptr, MMK_ERR_ARG, "ckpt_every and max_tape_steps must be >= 0");
+    if (!workspace) return fail(nullptr, MMK_ERR_ARG, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, MMK_ERR_ARG, "workspace must be 256-byte aligned");
+    const Layout L = make_layout(*p, ckpt_every, ckpt_every > 0 ? max_tape_steps : 0);
+    if (ws_bytes < L.total)
+        return fail(nullptr, MMK_ERR_NOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+
+    mmk_ctx *c = new mmk_ctx();
+    c->p = *p;
+    c->esz = esize(*p);
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char *)workspace;
+    c->L = L;
+    c->pl = plan_psi(p->nx, p->ny, p->ntheta, c->esz);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return hipfail(nullptr, e, "hipGetDevice");
+    }
+    // angle tables, computed on the host in FP64 and rounded to the field precision
+    const int nth = p->ntheta;
+    const double dth = kTwoPi / nth;
+    std::vector<double> t((size_t)TAB_N * nth);
+    for (int k = 0; k < nth; ++k) {
+        const double th = k * dth, tf = (k + 0.5) * dth;
+        const double co = std::cos(th), si = std::sin(th);
+        t[TAB_C * nth + k] = co;
+        t[TAB_S * nth + k] = si;
+        t[TAB_CH * nth + k] = std::cos(tf);
+        t[TAB_SH * nth + k] = std::sin(tf);
+        t[TAB_H1 * nth + k] = 0.5 * std::cos(2.0 * th);
+        t[TAB_H2 * nth + k] = 0.5 * std::sin(2.0 * th);
+        t[TAB_CC * nth + k] = co * co;
+        t[TAB_CS * nth + k] = co * si;
+        t[TAB_SS * nth + k] = si * si;
+    }
+    c->host_tab64 = t;
+    if (c->esz == 4) {
+        c->host_tab32.assign(t.begin(), t.end());
+        e = hipMemcpyAsync(c->ws + L.tab, c->host_tab32.data(), t.size() * 4, hipMemcpyHostToDevice, c->stream);
+    } else {
+        e = hipMemcpyAsync(c->ws + L.tab, c->host_tab64.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return hipfail(nullptr, e, "copy of angle tables");
+    }
+    tape_init(&c->tape, ckpt_every, ckpt_every > 0 ? max_tape_steps : 0);
+    *out = c;
+    return MMK_OK;
+}
+
+mmk_status mmk_destroy(mmk_ctx *c) {
+    if (!c) return MMK_ERR_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < kProfIds; ++i)
+        for (hipEvent_t e : c->ev[i]) (void)hipEventDestroy(e);
+    delete c;
+    return MMK_OK;
+}
+
+mmk_status mmk_set_params(mmk_ctx *c, double k_on, double k_off, double v0) {
+    if (!c) return MMK_ERR_ARG;
+    if (!std::isfinite(k_on) || !std::isfinite(k_off) || !std::isfinite(v0))
+        return fail(c, MMK_ERR_ARG, "non-finite rate");
+    if (v0 < 0) return fail(c, MMK_ERR_ARG, "v0 must be >= 0");
+    if (c->tape.active && c->tape.steps > 0)
+        return fail(c, MMK_ERR_STATE, "parameters cannot change inside a taped run");
+    c->p.k_on = k_on;
+    c->p.k_off = k_off;
+    c->p.v0 = v0;
+    return MMK_OK;
+}
+
+mmk_status mmk_set_state(mmk_ctx *c, const void *psi, const void *M) {
+    if (!c) return MMK_ERR_ARG;
+    if (!psi) return fail(c, MMK_ERR_ARG, "psi is NULL");
+    if (c->tape.active) return fail(c, MMK_ERR_STATE, "set_state during a taped run");
+    const size_t np = (size_t)n_psi(c->p) * c->esz, nm = (size_t)n_m(c->p) * c->esz;
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.psi[c->cur], psi, np, hipMemcpyDeviceToDevice, c->stream),
+           "copy of psi");
+    if (M) {
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.M[c->cur], M, nm, hipMemcpyDeviceToDevice, c->stream), "copy of M");
+    } else if (c->esz == 4) {
+        HIPCHK(c, launch_zero<float>(c->at<float>(c->L.M[c->cur]), n_m(c->p), c->stream), "zero M");
+    } else {
+        HIPCHK(c, launch_zero<double>(c->at<double>(c->L.M[c->cur]), n_m(c->p), c->stream), "zero M");
+    }
+    c->have_state = true;
+    c->have_out = false;
+    return MMK_OK;
+}
+
+mmk_status mmk_set_fluid(mmk_ctx *c, const void *u, const void *gradu) {
+    if (!c) return MMK_ERR_ARG;
+    if (!u || !gradu) return fail(c, MMK_ERR_ARG, "u or gradu is NULL");
+    const size_t nxy = (size_t)c->p.nx * c->p.ny * c->esz;
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.u, u, 2 * nxy, hipMemcpyDeviceToDevice, c->stream), "copy of u");
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.G, gradu, 4 * nxy, hipMemcpyDeviceToDevice, c->stream), "copy of gradu");
+    c->have_fluid = true;
+    return tape_on_fluid(c, &c->tape);
+}
+
+mmk_status mmk_step(mmk_ctx *c, int32_t K, double dt) {
+    if (!c) return MMK_ERR_ARG;
+    if (K < 0) return fail(c, MMK_ERR_ARG, "K must be >= 0");
+    if (!std::isfinite(dt) || dt <= 0) return fail(c, MMK_ERR_ARG, "dt must be finite and > 0");
+    if (!c->have_state) return fail(c, MMK_ERR_STATE, "mmk_step before mmk_set_state");
+    if (!c->have_fluid) return fail(c, MMK_ERR_STATE, "mmk_step before mmk_set_fluid");
+    if (K == 0) return MMK_OK;
+    if (c->tape.active && c->tape.steps + K > c->tape.max_steps)
+        return fail(c, MMK_ERR_ARG, "taped run would exceed max_tape_steps (%d)", c->tape.max_steps);
+    return c->esz == 4 ? run_steps<float>(c, K, dt) : run_steps<double>(c, K, dt);
+}
+
+mmk_status mmk_get_state(mmk_ctx *c, void *psi, void *M) {
+    if (!c) return MMK_ERR_ARG;
+    if (!c->have_state) return fail(c, MMK_ERR_STATE, "no state set");
+    if (psi)
+        HIPCHK(c, hipMemcpyAsync(psi, c->ws + c->L.psi[c->cur], (size_t)n_psi(c->p) * c->esz,
+                                 hipMemcpyDeviceToDevice, c->stream), "copy of psi");
+    if (M)
+        HIPCHK(c, hipMemcpyAsync(M, c->ws + c->L.M[c->cur], (size_t)n_m(c->p) * c->esz, hipMemcpyDeviceToDevice,
+                                 c->stream), "copy of M");
+    return MMK_OK;
+}
+
+mmk_status mmk_get_stress(mmk_ctx *c, void *sigma) {
+    if (!c) return MMK_ERR_ARG;
+    if (!sigma) return fail(c, MMK_ERR_ARG, "sigma is NULL");
+    if (!c->have_out) return fail(c, MMK_ERR_STATE, "no outputs: run mmk_step with K > 0 first");
+    HIPCHK(c, hipMemcpyAsync(sigma, c->ws + c->L.stress, 3 * (size_t)c->p.nx * c->p.ny * c->esz,
+                             hipMemcpyDeviceToDevice, c->stream), "copy of stress");
+    return MMK_OK;
+}
+
+mmk_status mmk_get_moments(mmk_ctx *c, void *mom) {
+    if (!c) return MMK_ERR_ARG;
+    if (!mom) return fail(c, MMK_ERR_ARG, "moments is NULL");
+    if (!c->have_out) return fail(c, MMK_ERR_STATE, "no outputs: run mmk_step with K > 0 first");
+    HIPCHK(c, hipMemcpyAsync(mom, c->ws + c->L.mom, 7 * (size_t)c->p.nx * c->p.ny * c->esz,
+                             hipMemcpyDeviceToDevice, c->stream), "copy of moments");
+    return MMK_OK;
+}
+
+mmk_status mmk_get_motor_moments(mmk_ctx *c, void *m0, void *m1) {
+    if (!c) return MMK_ERR_ARG;
+    if (!c->have_out) return fail(c, MMK_ERR_STATE, "no outputs: run mmk_step with K > 0 first");
+    const size_t np = (size_t)n_psi(c->p) * c->esz;
+    if (m0) HIPCHK(c, hipMemcpyAsync(m0, c->ws + c->L.m0, np, hipMemcpyDeviceToDevice, c->stream), "copy of m0");
+    if (m1) HIPCHK(c, hipMemcpyAsync(m1, c->ws + c->L.m1, np, hipMemcpyDeviceToDevice, c->stream), "copy of m1");
+    return MMK_OK;
+}
+
+mmk_status mmk_get_sums(mmk_ctx *c, double *mass, double sum_sigma[3]) {
+    if (!c) return MMK_ERR_ARG;
+    if (!c->have_out) return fail(c, MMK_ERR_STATE, "no outputs: run mmk_step with K > 0 first");
+    double h[4];
+    HIPCHK(c, hipMemcpyAsync(h, c->ws + c->L.sums, sizeof h, hipMemcpyDeviceToHost, c->stream), "copy of sums");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (mass) *mass = h[0];
+    if (sum_sigma) {
+        sum_sigma[0] = h[1];
+        sum_sigma[1] = h[2];
+        sum_sigma[2] = h[3];
+    }
+    return MMK_OK;
+}
+
+mmk_status mmk_tape_begin(mmk_ctx *c, int32_t ckpt_every) {
+    if (!c) return MMK_ERR_ARG;
+    return tape_begin(c, &c->tape, ckpt_every, c->have_state, c->have_fluid, c->cur);
+}
+
+mmk_status mmk_tape_backward(mmk_ctx *c, const void *g_sigma, const void *g_moments, void *g_psi0,
+                             double g_params[3]) {
+    if (!c) return MMK_ERR_ARG;
+    return c->esz == 4 ? tape_backward<float>(c, &c->tape, g_sigma, g_moments, g_psi0, g_params)
+                       : tape_backward<double>(c, &c->tape, g_sigma, g_moments, g_psi0, g_params);
+}
+
+mmk_status mmk_tape_end(mmk_ctx *c) {
+    if (!c) return MMK_ERR_ARG;
+    c->tape.active = false;
+    c->tape.steps = 0;
+    return MMK_OK;
+}
+
+mmk_status mmk_profile(mmk_ctx *c, int32_t enable) {
+    if (!c) return MMK_ERR_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    c->prof = enable != 0;
+    for (int i = 0; i < kProfIds; ++i) c->nev[i] = 0;
+    return MMK_OK;
+}
+
+mmk_status mmk_profile_read(mmk_ctx *c, int32_t id, double *total_ms, int64_t *launches) {
+    if (!c) return MMK_ERR_ARG;
+    if (id < 0 || id >= kProfIds) return fail(c, MMK_ERR_ARG, "kernel id out of range");
+    if (!total_ms || !launches) return fail(c, MMK_ERR_ARG, "NULL output");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    double tot = 0;
+    for (int i = 0; i < c->nev[id]; ++i) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[id][2 * i], c->ev[id][2 * i + 1]), "hipEventElapsedTime");
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = c->nev[id];
+    return MMK_OK;
+}
+
+const char *mmk_last_error(const mmk_ctx *c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

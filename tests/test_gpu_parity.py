@@ -1,0 +1,158 @@
+"""FP64 HIP path against the FP64 oracle, element by element, through the C-ABI.
+
+Tolerance: 1e-12 norm-wise relative error (max |gpu - oracle| / max |oracle|) per field.
+"""
+import numpy as np
+import pytest
+
+from paper_1908_04279_amd import inputs as gen
+from paper_1908_04279_amd.inputs import ModelParams
+from tests.conftest import rel_err
+from tests.runners import run_gpu, run_oracle, run_oracle_uniform_columns, seeded_case
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+FIELDS = ["psi", "M", "m0", "m1", "stress", "mom"]
+
+
+def compare(g, o, fields=FIELDS, tol=TOL):
+    errs = {f: rel_err(g[f], o[f]) for f in fields}
+    errs["mass"] = abs(g["mass"] - o["mass"]) / abs(o["mass"])
+    errs["sum_sigma"] = rel_err(g["sum_sigma"], o["sum_sigma"])
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+
+
+def test_c1_all_fields():
+    p = gen.params_for("c1_fp64_16x16x16x16")
+    psi0, M0, fl, dt = seeded_case(p)
+    g = run_gpu(p, psi0, M0, fl, 100, 100, dt)
+    o = run_oracle(p, psi0, np.zeros((16, 16, 16, 16)), fl, 100, 100, dt)
+    compare(g, o)
+
+
+@pytest.mark.parametrize("ns", [8, 16, 32, 64, 128, 256, 1, 2, 3, 5, 20, 33, 100, 300])
+def test_random_M0_every_column_length(ns):
+    """Exact tilings (8 .. 256) and the masked generic kernel (any other length), with
+    columns that differ, an odd grid and three fluid exchanges."""
+    p = ModelParams(nx=5, ny=7, ntheta=12, ns=ns, k_on=0.9, k_off=0.6, v0=1.2, F=0.8)
+    psi0, M0, fl, dt = seeded_case(p, n_exchanges=3, M0_kind="random")
+    g = run_gpu(p, psi0, M0, fl, 4, 12, dt)
+    o = run_oracle(p, psi0, M0, fl, 4, 12, dt)
+    compare(g, o)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 3, 2), (2, 1, 5), (3, 3, 64), (9, 17, 33), (1, 1, 128)])
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_degenerate_and_ragged_grids(shape, limiter):
+    nx, ny, nt = shape
+    p = ModelParams(nx=nx, ny=ny, ntheta=nt, ns=16, limiter=limiter, lx=3.0, ly=5.0)
+    psi0, M0, fl, dt = seeded_case(p, n_exchanges=2, M0_kind="random")
+    g = run_gpu(p, psi0, M0, fl, 5, 9, dt)
+    o = run_oracle(p, psi0, M0, fl, 5, 9, dt)
+    compare(g, o)
+
+
+def test_tile_tails_span_several_tiles():
+    """Grid bigger than one psi tile in both directions with ragged tails, ns = 64."""
+    p = ModelParams(nx=21, ny=19, ntheta=64, ns=64)
+    psi0, M0, fl, dt = seeded_case(p, n_exchanges=2, M0_kind="random")
+    g = run_gpu(p, psi0, M0, fl, 10, 20, dt)
+    o = run_oracle(p, psi0, M0, fl, 10, 20, dt)
+    compare(g, o)
+
+
+def test_c2_full_size_against_column_decomposition():
+    """128^2 x 64 x 32, 1000 steps, a new fluid field every 10 steps, M0 = 0.  Every GPU
+    column is checked against the oracle column; psi, stress and moments in full."""
+    p = gen.params_for("c2_fp64_128x128x64x32")
+    psi0, _, fl, dt = seeded_case(p, n_exchanges=100)
+    print("gpu run", flush=True)
+    g = run_gpu(p, psi0, None, fl, 10, 1000, dt)
+    print("oracle run", flush=True)
+    o = run_oracle_uniform_columns(p, psi0, fl, 10, 1000, dt)
+    o["M"] = np.broadcast_to(o["col"], g["M"].shape)
+    compare(g, o)
+
+
+def test_k_zero_is_a_no_op_and_state_round_trips():
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=4, ny=3, ntheta=8, ns=16)
+    psi0, M0, fl, dt = seeded_case(p, M0_kind="random")
+    ctx = mmk.Context(p)
+    ctx.set_state(torch.as_tensor(psi0), torch.as_tensor(M0))
+    ctx.set_fluid(*map(torch.as_tensor, fl[0]))
+    ctx.step(0, dt)
+    psi, M = ctx.get_state()
+    assert np.array_equal(psi.cpu().numpy(), psi0) and np.array_equal(M.cpu().numpy(), M0)
+    with pytest.raises(mmk.MMKError) as ei:
+        ctx.get_stress()
+    assert ei.value.status == mmk.MMK_ERR_STATE
+
+
+def test_repeat_runs_are_bitwise_identical_and_resume_matches():
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=24, ny=20, ntheta=32, ns=32)
+    psi0, M0, fl, dt = seeded_case(p, M0_kind="random")
+    a = run_gpu(p, psi0, M0, fl, 30, 30, dt)
+    b = run_gpu(p, psi0, M0, fl, 30, 30, dt)
+    for f in FIELDS:
+        assert np.array_equal(a[f], b[f]), f
+    assert a["mass"] == b["mass"] and a["sum_sigma"] == b["sum_sigma"]
+    # 15 steps, copy out, new context, 15 more steps == 30 steps
+    c1 = run_gpu(p, psi0, M0, fl, 15, 15, dt, keep_ctx=True)
+    psi, M = c1["ctx"].get_state()
+    c1["ctx"].close()
+    c2 = run_gpu(p, psi.cpu().numpy(), M.cpu().numpy(), fl, 15, 15, dt)
+    for f in FIELDS:
+        assert np.array_equal(c2[f], a[f]), f
+
+
+def test_gpu_invariants():
+    import torch
+    from paper_1908_04279_amd import mmk
+    # mass conservation and positivity over 200 steps of the C1 workload with random M0
+    p = gen.params_for("c1_fp64_16x16x16x16")
+    psi0, M0, fl, dt = seeded_case(p, n_exchanges=4, M0_kind="random")
+    g = run_gpu(p, psi0, M0, fl, 50, 200, dt)
+    assert abs(g["mass"] - 1.0) <= 1e-13
+    assert g["psi"].min() >= 0.0
+    # uniform isotropic state with zero flow is bitwise steady
+    q = ModelParams(nx=6, ny=5, ntheta=8, ns=16)
+    psi = np.full((6, 5, 8), 0.37)
+    M = np.full((6, 5, 8, 16), 0.81)
+    zero = (np.zeros((2, 6, 5)), np.zeros((4, 6, 5)))
+    h = run_gpu(q, psi, M, [zero], 40, 40, 0.01)
+    assert np.array_equal(h["psi"], psi)
+    assert np.allclose(h["mom"][3], 0.5 * h["mom"][0], rtol=1e-15, atol=0)
+
+
+def test_error_codes():
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=4, ny=4, ntheta=8, ns=16)
+    ctx = mmk.Context(p)
+    with pytest.raises(mmk.MMKError) as ei:
+        ctx.step(1, 0.01)
+    assert ei.value.status == mmk.MMK_ERR_STATE
+    psi0, M0, fl, dt = seeded_case(p)
+    ctx.set_state(torch.as_tensor(psi0))
+    with pytest.raises(mmk.MMKError) as ei:
+        ctx.step(1, 0.01)
+    assert ei.value.status == mmk.MMK_ERR_STATE and "set_fluid" in str(ei.value)
+    ctx.set_fluid(*map(torch.as_tensor, fl[0]))
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(mmk.MMKError) as ei:
+            ctx.step(1, bad)
+        assert ei.value.status == mmk.MMK_ERR_ARG
+    with pytest.raises(mmk.MMKError) as ei:
+        ctx.step(-1, dt)
+    assert ei.value.status == mmk.MMK_ERR_ARG
+    with pytest.raises(mmk.MMKError) as ei:
+        ctx.tape_begin(5)
+    assert ei.value.status == mmk.MMK_ERR_STATE
+    ctx.step(3, dt)
+    assert np.isfinite(ctx.get_stress().cpu().numpy()).all()
