@@ -39,7 +39,8 @@ struct PsiLaunch {
     int group;           // lanes per pencil group (16, 32 or 64)
     size_t lds_bytes;
 };
-PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem);
+// nfields: staged fields per halo pencil (2 forward: psi, m0; 3 reverse: lam, psi, m0)
+PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem, int nfields);
 
 // Donor-cell update psi_out = psi_in - dt div(flux).  If `stress` is non-null, also writes
 // stress[3][nx][ny], mom[7][nx][ny] of (psi_out, m0, m1) and per-block FP64 partials

@@ -2,6 +2,7 @@
 // Every step of the method runs in the HIP kernels of motor.hip, psi.hip and adjoint.hip;
 // this file only validates, carves the caller's workspace and enqueues work on the stream.
 #include "../../include/mmk.h"
+#include "consts.h"
 #include "kernels.h"
 #include "tape.h"
 
@@ -19,7 +20,6 @@ using namespace mmk;
 namespace {
 
 thread_local std::string g_create_error;
-constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr int kMaxTheta = 512;
 constexpr int kMaxS = 512;
 constexpr int kProfIds = 5;
@@ -58,7 +58,7 @@ std::string check_params(const mmk_params *p) {
 std::string check_supported(const mmk_params *p) {
     if (p->ntheta > kMaxTheta) return "ntheta > 512 is not supported by the psi kernel";
     if (p->ns > kMaxS) return "ns > 512 is not supported by the motor kernel";
-    if (plan_psi(p->nx, p->ny, p->ntheta, esize(*p)).lds_bytes > 64 * 1024)
+    if (plan_psi(p->nx, p->ny, p->ntheta, esize(*p), 2).lds_bytes > 64 * 1024)
         return "ntheta too large for the psi kernel's LDS tile at this precision";
     return "";
 }
@@ -67,7 +67,7 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     Layout L{};
     const size_t e = esize(p);
     const size_t nm = (size_t)n_m(p), np = (size_t)n_psi(p), nxy = (size_t)p.nx * p.ny;
-    const PsiLaunch pl = plan_psi(p.nx, p.ny, p.ntheta, e);
+    const PsiLaunch pl = plan_psi(p.nx, p.ny, p.ntheta, e, 2);
     L.psi_blocks = pl.blocks;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -102,7 +102,7 @@ struct mmk_ctx {
     int device = 0;
     char *ws = nullptr;
     Layout L{};
-    PsiLaunch pl{};
+    PsiLaunch pl{}, pl_rev{};
     int cur = 0;  // index of the current M / psi buffers
     bool have_state = false, have_fluid = false, have_out = false;
     std::string err;
@@ -162,37 +162,6 @@ static hipError_t prof_end(mmk_ctx *c, int id, int slot) {
 }
 
 // ---- typed step ---------------------------------------------------------------------------
-template <typename T>
-static MotorConst<T> motor_const(const mmk_params &p, double dt) {
-    const double ds = p.L / p.ns;
-    MotorConst<T> c;
-    c.k_on = (T)p.k_on;
-    c.k_off = (T)p.k_off;
-    c.v0 = (T)p.v0;
-    c.nv_ds = (T)(-p.v0 / ds);
-    c.dt = (T)dt;
-    c.half_dt = (T)(0.5 * dt);
-    c.ds = (T)ds;
-    c.ds2 = (T)(ds * ds);
-    return c;
-}
-
-template <typename T>
-static PsiConst<T> psi_const(const mmk_params &p, double dt) {
-    PsiConst<T> c;
-    c.nx = p.nx;
-    c.ny = p.ny;
-    c.nth = p.ntheta;
-    c.dt = (T)dt;
-    c.inv_dx = (T)(p.nx / p.lx);
-    c.inv_dy = (T)(p.ny / p.ly);
-    c.inv_dth = (T)(p.ntheta / kTwoPi);
-    c.F = (T)p.F;
-    c.sigma_f = (T)p.sigma_f;
-    c.dth = (T)(kTwoPi / p.ntheta);
-    return c;
-}
-
 // One micro-step from (M_in, psi_in) to (M_out, psi_out).  With out = true also the
 // stress, moments and the block partials of the global sums.
 template <typename T>
@@ -266,6 +235,8 @@ void *ctx_m0(const mmk_ctx *c) { return c->ws + c->L.m0; }
 void *ctx_m1(const mmk_ctx *c) { return c->ws + c->L.m1; }
 void *ctx_tab(const mmk_ctx *c) { return c->ws + c->L.tab; }
 const PsiLaunch &ctx_psi_launch(const mmk_ctx *c) { return c->pl; }
+const PsiLaunch &ctx_psi_launch_rev(const mmk_ctx *c) { return c->pl_rev; }
+bool ctx_have_out(const mmk_ctx *c) { return c->have_out; }
 mmk_status ctx_fail(mmk_ctx *c, mmk_status st, const char *msg) { return fail(c, st, "%s", msg); }
 mmk_status ctx_hipfail(mmk_ctx *c, hipError_t e, const char *what) { return hipfail(c, e, what); }
 hipError_t ctx_prof_begin(mmk_ctx *c, int id, int *slot) { return prof_begin(c, id, slot); }
@@ -306,6 +277,8 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     if (!m.empty()) return fail(nullptr, MMK_ERR_UNSUPPORTED, "%s", m.c_str());
     if (ckpt_every < 0 || (ckpt_every > 0 && max_tape_steps < 0))
         return fail(nullptr, MMK_ERR_ARG, "ckpt_every and max_tape_steps must be >= 0");
+    if (ckpt_every > 0 && plan_psi(p->nx, p->ny, p->ntheta, esize(*p), 3).lds_bytes > 64 * 1024)
+        return fail(nullptr, MMK_ERR_UNSUPPORTED, "ntheta too large for the reverse psi kernel at this precision");
     if (!workspace) return fail(nullptr, MMK_ERR_ARG, "workspace is NULL");
     if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, MMK_ERR_ARG, "workspace must be 256-byte aligned");
     const Layout L = make_layout(*p, ckpt_every, ckpt_every > 0 ? max_tape_steps : 0);
@@ -318,7 +291,8 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     c->stream = (hipStream_t)hip_stream;
     c->ws = (char *)workspace;
     c->L = L;
-    c->pl = plan_psi(p->nx, p->ny, p->ntheta, c->esz);
+    c->pl = plan_psi(p->nx, p->ny, p->ntheta, c->esz, 2);
+    c->pl_rev = plan_psi(p->nx, p->ny, p->ntheta, c->esz, 3);
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) {
         delete c;

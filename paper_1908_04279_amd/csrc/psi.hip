@@ -15,24 +15,48 @@
 #include "device_util.h"
 #include "kernels.h"
 
+#include <cstdio>
+#include <cstdlib>
 #include <type_traits>
 
 namespace mmk {
 
-PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem) {
+static size_t psi_lds(int ti, int tj, int nth, size_t elem, int nf) {
+    const size_t halo = (size_t)(ti + 2) * (tj + 2);
+    return elem * (nf * halo * nth + 2 * halo + 4 * (size_t)ti * tj + TAB_N * (size_t)nth) + 16 + 4 * 4 * sizeof(double);
+}
+
+// Tile choice: the largest of the candidate tiles whose LDS footprint stays <= 40 KB (so
+// several blocks share a CU), else <= 64 KB.  MMK_PSI_TILE=TIxTJ overrides (measurements).
+PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem, int nf) {
     static const int cand[][2] = {{8, 8}, {4, 8}, {4, 4}, {2, 4}, {2, 2}, {1, 2}, {1, 1}};
     PsiLaunch pl{};
     pl.group = nth <= 16 ? 16 : (nth <= 32 ? 32 : 64);
-    for (auto &c : cand) {
-        const int ti = c[0], tj = c[1];
-        const size_t halo = (size_t)(ti + 2) * (tj + 2);
-        const size_t lds = elem * (2 * halo * nth + 2 * halo + 4 * (size_t)ti * tj + TAB_N * (size_t)nth)
-                           + 16 + 4 * 4 * sizeof(double);
-        pl.ti = ti;
-        pl.tj = tj;
-        pl.lds_bytes = lds;
-        if (lds <= 64 * 1024) break;
+    bool chosen = false;
+    if (const char *e = nf == 2 ? getenv("MMK_PSI_TILE") : nullptr) {
+        int a = 0, b = 0;
+        if (sscanf(e, "%dx%d", &a, &b) == 2 && a > 0 && b > 0 && a <= 16 && b <= 16 &&
+            psi_lds(a, b, nth, elem, nf) <= 64 * 1024) {
+            pl.ti = a;
+            pl.tj = b;
+            chosen = true;
+        }
     }
+    for (size_t limit : {(size_t)40 * 1024, (size_t)64 * 1024}) {
+        if (chosen) break;
+        for (auto &c : cand)
+            if (psi_lds(c[0], c[1], nth, elem, nf) <= limit) {
+                pl.ti = c[0];
+                pl.tj = c[1];
+                chosen = true;
+                break;
+            }
+    }
+    if (!chosen) {
+        pl.ti = 1;
+        pl.tj = 1;
+    }
+    pl.lds_bytes = psi_lds(pl.ti, pl.tj, nth, elem, nf);
     pl.tiles_i = (nx + pl.ti - 1) / pl.ti;
     pl.tiles_j = (ny + pl.tj - 1) / pl.tj;
     const int tiles = pl.tiles_i * pl.tiles_j;
@@ -87,22 +111,64 @@ struct Acc<float> {
     __device__ float total(int G) const { return group_total_comp(c, G); }
 };
 
+// Per-lane constants of one orientation k: p, the two theta faces and the moment weights.
 template <typename T>
+struct AngleK {
+    T co, si, chp, shp, chm, shm, h1, h2, cc, cs, ss;
+    int k, kp, km;
+};
+
+template <typename T>
+__device__ __forceinline__ AngleK<T> angle_k(const T *s_tab, int nth, int k) {
+    AngleK<T> a;
+    a.k = k;
+    a.kp = (k + 1 == nth) ? 0 : k + 1;
+    a.km = (k == 0) ? nth - 1 : k - 1;
+    a.co = s_tab[TAB_C * nth + k];
+    a.si = s_tab[TAB_S * nth + k];
+    a.chp = s_tab[TAB_CH * nth + k];
+    a.shp = s_tab[TAB_SH * nth + k];
+    a.chm = s_tab[TAB_CH * nth + a.km];
+    a.shm = s_tab[TAB_SH * nth + a.km];
+    a.h1 = s_tab[TAB_H1 * nth + k];
+    a.h2 = s_tab[TAB_H2 * nth + k];
+    a.cc = s_tab[TAB_CC * nth + k];
+    a.cs = s_tab[TAB_CS * nth + k];
+    a.ss = s_tab[TAB_SS * nth + k];
+    return a;
+}
+
+// periodic index for i in [-1, n + 16): a halo index is off by at most one tile
+__device__ __forceinline__ int wrap(int i, int n) {
+    if (i < 0) i += n;
+    while (i >= n) i -= n;
+    return i;
+}
+
+// NTH_C, TI_C, TJ_C > 0 fix ntheta and the tile at compile time (index arithmetic folds,
+// halo loads are batched so many are in flight); 0 takes them from the launch arguments.
+template <typename T, int NTH_C, int TI_C, int TJ_C>
 __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, T *__restrict__ psi_out,
                                                   const T *__restrict__ m0, const T *__restrict__ m1,
                                                   const T *__restrict__ u, const T *__restrict__ Gr,
                                                   const T *__restrict__ tab, T *__restrict__ stress,
                                                   T *__restrict__ mom, double *__restrict__ partials,
                                                   PsiConst<T> c, PsiLaunch pl) {
+    constexpr bool FIXED = NTH_C > 0 && TI_C > 0 && TJ_C > 0;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int nx = c.nx, ny = c.ny, nth = c.nth;
-    const int TI = pl.ti, TJ = pl.tj, HI = TI + 2, HJ = TJ + 2, NH = HI * HJ;
+    const int nx = c.nx, ny = c.ny;
+    const int nth = NTH_C ? NTH_C : c.nth;
+    const int TI = TI_C ? TI_C : pl.ti, TJ = TJ_C ? TJ_C : pl.tj;
+    const int HI = TI + 2, HJ = TJ + 2, NH = HI * HJ;
+    const int G = NTH_C ? (NTH_C <= 16 ? 16 : (NTH_C <= 32 ? 32 : 64)) : pl.group;
+    const int NG = 256 / G;
     T *s_psi = reinterpret_cast<T *>(smem);          // [NH][nth]
     T *s_m0 = s_psi + (size_t)NH * nth;               // [NH][nth]
     T *s_u = s_m0 + (size_t)NH * nth;                 // [2][NH]
     T *s_G = s_u + 2 * NH;                            // [4][TI*TJ]
     T *s_tab = s_G + 4 * TI * TJ;                     // [TAB_N][nth]
-    const size_t red_off = ((reinterpret_cast<uintptr_t>(s_tab + TAB_N * nth) - reinterpret_cast<uintptr_t>(smem)) + 15) & ~(size_t)15;
+    const size_t red_off =
+        ((reinterpret_cast<uintptr_t>(s_tab + TAB_N * nth) - reinterpret_cast<uintptr_t>(smem)) + 15) & ~(size_t)15;
     double *s_red = reinterpret_cast<double *>(smem + red_off);  // [4 waves][4]
     const bool out = (stress != nullptr);
     const int tid = threadIdx.x;
@@ -117,37 +183,111 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
     }
     const int i0 = (tile / pl.tiles_j) * TI, j0 = (tile % pl.tiles_j) * TJ;
     const int64_t nxy = (int64_t)nx * ny;
+    // With G = 64 a pencil group is exactly one wave: its pencil index is wave-uniform, so it
+    // goes to a scalar register and the per-pencil address arithmetic runs on the SALU.
+    const int grp = (G == 64) ? __builtin_amdgcn_readfirstlane(tid / 64) : tid / G;
+    const int kk = tid % G;
 
-    const int G = pl.group, NG = 256 / G;
-    const int grp = tid / G, kk = tid % G;
-
-    for (int q = grp; q < NH; q += NG) {
-        const int qi = q / HJ, qj = q - qi * HJ;
-        if ((qi == 0 || qi == HI - 1) && (qj == 0 || qj == HJ - 1)) continue;  // corners unused
-        const int gi = (i0 + qi - 1 + nx) % nx, gj = (j0 + qj - 1 + ny) % ny;
-        const int64_t pen = (int64_t)gi * ny + gj;
-        const T *sp = psi_in + pen * nth;
-        const T *sm = m0 + pen * nth;
-        for (int k = kk; k < nth; k += G) {
-            s_psi[q * nth + k] = sp[k];
-            s_m0[q * nth + k] = sm[k];
-        }
-        if (kk == 0) {
-            s_u[q] = u[pen];
-            s_u[NH + q] = u[nxy + pen];
-        }
-    }
-    for (int p = tid; p < TI * TJ; p += 256) {
-        const int gi = (i0 + p / TJ) % nx, gj = (j0 + p % TJ) % ny;
-        const int64_t pen = (int64_t)gi * ny + gj;
+    // ---- stage psi and m0 of the tile and its one-pencil halo (corners skipped) ----
+    if constexpr (FIXED) {
+        // Every global load of the staging phase is issued before the first LDS write, so the
+        // in-order vmcnt waits never serialise them.
+        constexpr int G_ = NTH_C <= 16 ? 16 : (NTH_C <= 32 ? 32 : 64);
+        constexpr int NG_ = 256 / G_, KPL = (NTH_C + G_ - 1) / G_;
+        constexpr int HJ_ = TJ_C + 2, NH_ = (TI_C + 2) * HJ_, NP_ = TI_C * TJ_C;
+        constexpr int NQ = (NH_ + NG_ - 1) / NG_;
+        constexpr int NT = (TAB_N * NTH_C + 255) / 256;
+        static_assert(NH_ <= 256 && NP_ <= 256, "tile too large for one pass");
+        T rp[NQ][KPL], rm[NQ][KPL];
+        int dst[NQ];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) s_G[a * TI * TJ + p] = Gr[a * nxy + pen];
+        for (int v = 0; v < NQ; ++v) {
+            const int q = grp + v * NG_;
+            const int qi = q / HJ_, qj = q - qi * HJ_;
+            const bool ok = q < NH_ && !((qi == 0 || qi == TI_C + 1) && (qj == 0 || qj == TJ_C + 1));
+            dst[v] = ok ? q : -1;
+            const int64_t pen = (int64_t)wrap(i0 + qi - 1, nx) * ny + wrap(j0 + qj - 1, ny);
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                const int k = kk + j * G_;
+                if (ok && k < NTH_C) {
+                    rp[v][j] = psi_in[pen * NTH_C + k];
+                    rm[v][j] = m0[pen * NTH_C + k];
+                }
+            }
+        }
+        // fluid velocity of halo pencil tid, gradient of tile pencil tid, angle tables
+        T ru0 = 0, ru1 = 0, rg[4] = {0, 0, 0, 0}, rt[NT];
+        if (tid < NH_) {
+            const int qi = tid / HJ_, qj = tid - qi * HJ_;
+            const int64_t pen = (int64_t)wrap(i0 + qi - 1, nx) * ny + wrap(j0 + qj - 1, ny);
+            ru0 = u[pen];
+            ru1 = u[nxy + pen];
+        }
+        if (tid < NP_) {
+            const int64_t pen = (int64_t)wrap(i0 + tid / TJ_C, nx) * ny + wrap(j0 + tid % TJ_C, ny);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) rg[a] = Gr[a * nxy + pen];
+        }
+#pragma unroll
+        for (int v = 0; v < NT; ++v)
+            if (tid + 256 * v < TAB_N * NTH_C) rt[v] = tab[tid + 256 * v];
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) {
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                const int k = kk + j * G_;
+                if (dst[v] >= 0 && k < NTH_C) {
+                    s_psi[dst[v] * NTH_C + k] = rp[v][j];
+                    s_m0[dst[v] * NTH_C + k] = rm[v][j];
+                }
+            }
+        }
+        if (tid < NH_) {
+            s_u[tid] = ru0;
+            s_u[NH_ + tid] = ru1;
+        }
+        if (tid < NP_)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) s_G[a * NP_ + tid] = rg[a];
+#pragma unroll
+        for (int v = 0; v < NT; ++v)
+            if (tid + 256 * v < TAB_N * NTH_C) s_tab[tid + 256 * v] = rt[v];
+    } else {
+        for (int q = grp; q < NH; q += NG) {
+            const int qi = q / HJ, qj = q - qi * HJ;
+            if ((qi == 0 || qi == HI - 1) && (qj == 0 || qj == HJ - 1)) continue;
+            const int64_t pen = (int64_t)wrap(i0 + qi - 1, nx) * ny + wrap(j0 + qj - 1, ny);
+            const T *sp = psi_in + pen * nth;
+            const T *sm = m0 + pen * nth;
+            for (int k = kk; k < nth; k += G) {
+                s_psi[q * nth + k] = sp[k];
+                s_m0[q * nth + k] = sm[k];
+            }
+            if (kk == 0) {
+                s_u[q] = u[pen];
+                s_u[NH + q] = u[nxy + pen];
+            }
+        }
+        for (int p = tid; p < TI * TJ; p += 256) {
+            const int64_t pen = (int64_t)wrap(i0 + p / TJ, nx) * ny + wrap(j0 + p % TJ, ny);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) s_G[a * TI * TJ + p] = Gr[a * nxy + pen];
+        }
+        for (int k = tid; k < TAB_N * nth; k += 256) s_tab[k] = tab[k];
     }
-    for (int k = tid; k < TAB_N * nth; k += 256) s_tab[k] = tab[k];
     __syncthreads();
 
-    const T *t_c = s_tab + TAB_C * nth, *t_s = s_tab + TAB_S * nth;
-    const T *t_ch = s_tab + TAB_CH * nth, *t_sh = s_tab + TAB_SH * nth;
+    // ---- donor-cell update, one pencil per lane group, th over the group's lanes ----
+    constexpr int KMAX = NTH_C ? (NTH_C + 63) / 64 : 0;  // k slots per lane when fixed
+    AngleK<T> ak[KMAX > 0 ? KMAX : 1];
+    if constexpr (FIXED) {
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+            const int k = kk + j * G;
+            if (k < nth) ak[j] = angle_k(s_tab, nth, k);
+        }
+    }
     double acc_mass = 0, acc_s0 = 0, acc_s1 = 0, acc_s2 = 0;
 
     for (int p = grp; p < TI * TJ; p += NG) {
@@ -162,52 +302,53 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
         const int64_t pen = (int64_t)gi * ny + gj;
         Acc<T> a_c, a_nx, a_ny, a_dxx, a_dxy, a_dyy, a_b, a_sxx, a_sxy, a_syy;
 
-        for (int k = kk; k < nth; k += G) {
-            const int kp = (k + 1 == nth) ? 0 : k + 1;
-            const int km = (k == 0) ? nth - 1 : k - 1;
+        auto cell = [&](const AngleK<T> &a) {
+            const int k = a.k;
             const T ps = s_psi[q * nth + k];
-            const T co = t_c[k], si = t_s[k];
             const T mc = s_m0[q * nth + k];
-            // x faces
-            const T ax_c = ux_c - c.F * mc * co;
-            const T ax_m = ux_m - c.F * s_m0[qxm * nth + k] * co;
-            const T ax_p = ux_p - c.F * s_m0[qxp * nth + k] * co;
+            // x faces: cell velocity u_x - F m0 cos th, face value the mean of the two cells
+            const T ax_c = ux_c - c.F * mc * a.co;
+            const T ax_m = ux_m - c.F * s_m0[qxm * nth + k] * a.co;
+            const T ax_p = ux_p - c.F * s_m0[qxp * nth + k] * a.co;
             const T Axp = T(0.5) * (ax_c + ax_p), Axm = T(0.5) * (ax_m + ax_c);
             const T fxp = donor(Axp, ps, s_psi[qxp * nth + k]);
             const T fxm = donor(Axm, s_psi[qxm * nth + k], ps);
             // y faces
-            const T ay_c = uy_c - c.F * mc * si;
-            const T ay_m = uy_m - c.F * s_m0[qym * nth + k] * si;
-            const T ay_p = uy_p - c.F * s_m0[qyp * nth + k] * si;
+            const T ay_c = uy_c - c.F * mc * a.si;
+            const T ay_m = uy_m - c.F * s_m0[qym * nth + k] * a.si;
+            const T ay_p = uy_p - c.F * s_m0[qyp * nth + k] * a.si;
             const T Ayp = T(0.5) * (ay_c + ay_p), Aym = T(0.5) * (ay_m + ay_c);
             const T fyp = donor(Ayp, ps, s_psi[qyp * nth + k]);
             const T fym = donor(Aym, s_psi[qym * nth + k], ps);
-            // theta faces k+1/2 and k-1/2 (= (k-1)+1/2)
-            const T chp = t_ch[k], shp = t_sh[k], chm = t_ch[km], shm = t_sh[km];
-            const T wp = -shp * (Gxx * chp + Gxy * shp) + chp * (Gyx * chp + Gyy * shp);
-            const T wm = -shm * (Gxx * chm + Gxy * shm) + chm * (Gyx * chm + Gyy * shm);
-            const T ftp = donor(wp, ps, s_psi[q * nth + kp]);
-            const T ftm = donor(wm, s_psi[q * nth + km], ps);
+            // theta faces k+1/2 and k-1/2: rotation rate p_perp . gradu . p
+            const T wp = -a.shp * (Gxx * a.chp + Gxy * a.shp) + a.chp * (Gyx * a.chp + Gyy * a.shp);
+            const T wm = -a.shm * (Gxx * a.chm + Gxy * a.shm) + a.chm * (Gyx * a.chm + Gyy * a.shm);
+            const T ftp = donor(wp, ps, s_psi[q * nth + a.kp]);
+            const T ftm = donor(wm, s_psi[q * nth + a.km], ps);
             const T div = (fxp - fxm) * c.inv_dx + (fyp - fym) * c.inv_dy + (ftp - ftm) * c.inv_dth;
             const T pn = ps - c.dt * div;
             psi_out[pen * nth + k] = pn;
             if (out) {
-                const T mm1 = m1[pen * nth + k];
-                const T cc = s_tab[TAB_CC * nth + k], cs = s_tab[TAB_CS * nth + k], ss = s_tab[TAB_SS * nth + k];
-                const T h1 = s_tab[TAB_H1 * nth + k], h2 = s_tab[TAB_H2 * nth + k];
+                const T fm = c.F * m1[pen * nth + k];
                 a_c.add(pn);
-                a_nx.add(pn * co);
-                a_ny.add(pn * si);
-                a_dxx.add(pn * cc);
-                a_dxy.add(pn * cs);
-                a_dyy.add(pn * ss);
+                a_nx.add(pn * a.co);
+                a_ny.add(pn * a.si);
+                a_dxx.add(pn * a.cc);
+                a_dxy.add(pn * a.cs);
+                a_dyy.add(pn * a.ss);
                 a_b.add(pn * mc);
-                const T fm = c.F * mm1;
-                a_sxx.add(pn * (c.sigma_f * h1 + fm * cc));
-                a_sxy.add(pn * (c.sigma_f * h2 + fm * cs));
-                a_syy.add(pn * (-c.sigma_f * h1 + fm * ss));
+                a_sxx.add(pn * (c.sigma_f * a.h1 + fm * a.cc));
+                a_sxy.add(pn * (c.sigma_f * a.h2 + fm * a.cs));
+                a_syy.add(pn * (-c.sigma_f * a.h1 + fm * a.ss));
                 acc_mass += (double)pn;
             }
+        };
+        if constexpr (FIXED) {
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (kk + j * G < nth) cell(ak[j]);
+        } else {
+            for (int k = kk; k < nth; k += G) cell(angle_k(s_tab, nth, k));
         }
         if (out) {
             const T dth = c.dth;
@@ -234,7 +375,7 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
     }
 
     if (out) {
-        // fixed-order block reduction of the FP64 partials: wave butterfly, then wave 0..3
+        // fixed-order block reduction of the FP64 partials: wave butterfly, then waves 0..3
         double v[4] = {acc_mass, acc_s0, acc_s1, acc_s2};
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -244,19 +385,39 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
             for (int a = 0; a < 4; ++a) s_red[wave * 4 + a] = v[a];
         __syncthreads();
         if (tid < 4) {
-            double s = 0;
-            for (int w = 0; w < 4; ++w) s += s_red[w * 4 + tid];
-            partials[(size_t)blockIdx.x * 4 + tid] = s;
+            double sum = 0;
+            for (int w = 0; w < 4; ++w) sum += s_red[w * 4 + tid];
+            partials[(size_t)blockIdx.x * 4 + tid] = sum;
         }
     }
+}
+
+template <typename T, int NTH, int TI, int TJ>
+static void launch_fixed(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u, const T *G,
+                         const T *tab, T *stress, T *mom, double *partials, const PsiConst<T> &c,
+                         const PsiLaunch &pl, hipStream_t s) {
+    hipLaunchKernelGGL((k_psi_step<T, NTH, TI, TJ>), dim3(pl.blocks), dim3(256), pl.lds_bytes, s, psi_in,
+                       psi_out, m0, m1, u, G, tab, stress, mom, partials, c, pl);
 }
 
 template <typename T>
 hipError_t launch_psi_step(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u,
                            const T *G, const T *tab, T *stress, T *mom, double *partials,
                            const PsiConst<T> &c, const PsiLaunch &pl, hipStream_t s) {
-    hipLaunchKernelGGL(k_psi_step<T>, dim3(pl.blocks), dim3(256), pl.lds_bytes, s, psi_in, psi_out, m0, m1,
-                       u, G, tab, stress, mom, partials, c, pl);
+#define MMK_PSI_CASE(N, A, B)                                                                        \
+    if (c.nth == N && pl.ti == A && pl.tj == B) {                                                    \
+        launch_fixed<T, N, A, B>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, c, pl, s); \
+        return hipGetLastError();                                                                    \
+    }
+#define MMK_PSI_TILES(N) MMK_PSI_CASE(N, 8, 8) MMK_PSI_CASE(N, 4, 8) MMK_PSI_CASE(N, 4, 4) MMK_PSI_CASE(N, 2, 4)
+    MMK_PSI_TILES(16)
+    MMK_PSI_TILES(32)
+    MMK_PSI_TILES(64)
+    MMK_PSI_TILES(128)
+#undef MMK_PSI_TILES
+#undef MMK_PSI_CASE
+    hipLaunchKernelGGL((k_psi_step<T, 0, 0, 0>), dim3(pl.blocks), dim3(256), pl.lds_bytes, s, psi_in, psi_out,
+                       m0, m1, u, G, tab, stress, mom, partials, c, pl);
     return hipGetLastError();
 }
 

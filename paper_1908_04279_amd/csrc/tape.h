@@ -50,6 +50,8 @@ void *ctx_m0(const mmk_ctx *c);
 void *ctx_m1(const mmk_ctx *c);
 void *ctx_tab(const mmk_ctx *c);
 const PsiLaunch &ctx_psi_launch(const mmk_ctx *c);
+const PsiLaunch &ctx_psi_launch_rev(const mmk_ctx *c);
+bool ctx_have_out(const mmk_ctx *c);
 mmk_status ctx_fail(mmk_ctx *c, mmk_status st, const char *msg);
 mmk_status ctx_hipfail(mmk_ctx *c, hipError_t e, const char *what);
 hipError_t ctx_prof_begin(mmk_ctx *c, int id, int *slot);

@@ -1,0 +1,62 @@
+"""FP32 storage-and-arithmetic path against the FP64 oracle.
+
+Bar: norm-wise relative error <= 1e-5 on stress and moments (the FP32 target); the errors
+of psi, M, m0 and the mass drift are printed alongside."""
+import numpy as np
+import pytest
+
+from paper_1908_04279_amd import inputs as gen
+from paper_1908_04279_amd.inputs import ModelParams
+from tests.conftest import rel_err
+from tests.runners import run_gpu, run_oracle, run_oracle_uniform_columns, seeded_case
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def report(g, o, fields):
+    errs = {f: rel_err(g[f], o[f]) for f in fields}
+    errs["mass"] = abs(g["mass"] - o["mass"]) / abs(o["mass"])
+    errs["sum_sigma"] = rel_err(g["sum_sigma"], o["sum_sigma"])
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    return errs
+
+
+@pytest.mark.parametrize("ns", [16, 32, 64, 128, 20])
+def test_random_M0_small_grids(ns):
+    p = ModelParams(nx=9, ny=7, ntheta=16, ns=ns)
+    psi0, M0, fl, dt = seeded_case(p, n_exchanges=3, M0_kind="random")
+    g = run_gpu(p, psi0, M0, fl, 10, 30, dt, precision=1)
+    o = run_oracle(p, psi0, M0, fl, 10, 30, dt)
+    e = report(g, o, ["psi", "M", "m0", "m1", "stress", "mom"])
+    assert e["stress"] <= TOL and e["mom"] <= TOL
+    assert e["psi"] <= TOL and e["M"] <= TOL
+
+
+def test_c1_fp32():
+    p = gen.params_for("c1_fp64_16x16x16x16")
+    psi0, M0, fl, dt = seeded_case(p)
+    g = run_gpu(p, psi0, None, fl, 100, 100, dt, precision=1)
+    o = run_oracle(p, psi0, np.zeros((16, 16, 16, 16)), fl, 100, 100, dt)
+    e = report(g, o, ["psi", "M", "m0", "m1", "stress", "mom"])
+    assert e["stress"] <= TOL and e["mom"] <= TOL
+
+
+def test_c3_fp32_full_size():
+    """256^2 x 64 x 64 FP32, 500 steps, a new fluid field every 10 steps, against the FP64
+    oracle (column decomposition: M0 = 0 gives identical columns)."""
+    p = gen.params_for("c3_fp32_256x256x64x64")
+    psi0, _, fl, dt = seeded_case(p, n_exchanges=50)
+    print("gpu", flush=True)
+    g = run_gpu(p, psi0, None, fl, 10, 500, dt, precision=1, want_M=False, keep_ctx=True)
+    import torch
+    _, M = g["ctx"].get_state()
+    print("oracle", flush=True)
+    o = run_oracle_uniform_columns(p, psi0, fl, 10, 500, dt)
+    col = torch.as_tensor(o["col"], dtype=torch.float64, device=M.device)
+    m_err = float((M.double() - col).abs().max() / col.abs().max())
+    g["ctx"].close()
+    e = report(g, o, ["psi", "m0", "m1", "stress", "mom"])
+    print(f"M (all columns vs the oracle column): {m_err:.2e}; mass drift {abs(g['mass'] - 1.0):.2e}", flush=True)
+    assert e["stress"] <= TOL and e["mom"] <= TOL
+    assert m_err <= TOL and e["psi"] <= TOL
