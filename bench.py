@@ -98,6 +98,83 @@ def run_forward(p, precision, steps, warmup, K, profile=True):
     return dict(elapsed=elapsed, steps=steps, dt=dt, prof=prof, mass=mass)
 
 
+def run_adjoint(name, precision):
+    """Forward with tape (checkpoints every C steps, fluid exchange every K) and the
+    reverse pass (recompute + reverse kernels), timed separately."""
+    import torch
+    from paper_1908_04279_amd import inputs as gen
+    from paper_1908_04279_amd import mmk
+    c = gen.CONFIGS[name]
+    p = gen.params_for(name)
+    n, K, C = c["steps"], c["K"], c["ckpt"]
+    fl_np = gen.fluid_schedule(p.nx, p.ny, -(-n // K), new_each=c["new_fluid_each_exchange"])
+    dt = gen.cfl_dt(p, fl_np)
+    torch.cuda.reset_peak_memory_stats()
+    ctx = mmk.Context(p, precision=precision, ckpt_every=C, max_tape_steps=n)
+    fl = [(torch.as_tensor(u).to(ctx.device, ctx.dtype), torch.as_tensor(g).to(ctx.device, ctx.dtype))
+          for u, g in fl_np]
+    psi0 = torch.as_tensor(gen.make_psi0(p.nx, p.ny, p.ntheta, seed=0)).to(ctx.device, ctx.dtype)
+    target = torch.as_tensor(gen.make_target_stress(p.nx, p.ny)).to(ctx.device, ctx.dtype)
+
+    def forward():
+        ctx.set_state(psi0)
+        ctx.set_fluid(*fl[0])
+        ctx.tape_begin(C)
+        done, e = 0, 0
+        while done < n:
+            if e > 0:
+                ctx.set_fluid(*fl[e])
+            k = min(K, n - done)
+            ctx.step(k, dt)
+            done += k
+            e += 1
+        return ctx.get_stress()
+
+    out = {}
+    for rep in range(2):       # the first pair is a warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sigma = forward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        d = sigma - target
+        g_sigma = torch.stack([d[0], 2 * d[1], d[2]]) / torch.sqrt((d[0] ** 2 + 2 * d[1] ** 2 + d[2] ** 2).sum())
+        if rep == 1:
+            ctx.profile(True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g_psi0, g_par = ctx.tape_backward(g_sigma.contiguous(), None)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        ctx.tape_end()
+        out = dict(forward_s=t1 - t0, backward_s=t3 - t2, g_params=g_par)
+    ms_r, n_r = ctx.profile_read("motor_step_reverse")
+    ms_p, n_p = ctx.profile_read("psi_step_reverse")
+    b = 4 if precision == mmk.FP32 else 8
+    n_m = p.nx * p.ny * p.ntheta * p.ns
+    rev_bytes = b * (3 * n_m + p.nx * p.ny * p.ntheta)
+    out.update(ratio=out["backward_s"] / out["forward_s"], steps=n, ckpt_every=C,
+               workspace_gb=ctx.ws_bytes / 1e9,
+               peak_device_gb=torch.cuda.max_memory_allocated() / 1e9,
+               motor_reverse_avg_us=ms_r / n_r * 1e3,
+               motor_reverse_gbs=rev_bytes / (ms_r / n_r / 1e3) / 1e9,
+               psi_reverse_avg_us=ms_p / n_p * 1e3)
+    ctx.profile(False)
+    ctx.close()
+    return out
+
+
+def copy_calibration(nbytes, reps):
+    """A plain device copy of known size (for scaling the HBM byte counters)."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": nbytes, "reps": reps}), flush=True)
+
+
 def counters_traffic(bytes_per_launch):
     """HBM bytes per motor-step launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on a different motor kernel source."""
@@ -144,8 +221,11 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fp32", "fp64"], default="all",
+    ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint"], default="all",
                     help="restrict to one leg (used for profiler runs)")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this micro-step path runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -156,6 +236,12 @@ def main():
     from paper_1908_04279_amd import mmk
     mmk.lib()   # fail loudly if the HIP library is missing
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        copy_calibration(args.copy_calib, 10)
+        return
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint_fp32": run_adjoint("c5_adjoint_fp32_256x256x64x32", mmk.FP32)}), flush=True)
+        return
 
     p = gen.params_for("c3_fp32_256x256x64x64")
     K = 10
@@ -204,6 +290,12 @@ def main():
                        "steps": res["fp64"]["steps"]}
         out["fp32_over_fp64"] = s["steps_per_s"] / s64["steps_per_s"]
     out["adjoint_over_forward"] = None
+    if args.only == "all" and not args.no_adjoint:
+        log("[bench] adjoint legs")
+        adj32 = run_adjoint("c5_adjoint_fp32_256x256x64x32", mmk.FP32)
+        adj64 = run_adjoint("c4_adjoint_fp64_64x64x32x32", mmk.FP64)
+        out["adjoint_over_forward"] = adj32["ratio"]
+        out["adjoint"] = {"fp32_256x256x64x32_C25": adj32, "fp64_64x64x32x32_C20": adj64}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -15,7 +15,9 @@ enum : int {
     DPP_ROW_SHL1 = 0x101,        // lane i <- lane i+1 within the 16-lane row
     DPP_ROW_SHR1 = 0x111,        // lane i <- lane i-1 within the 16-lane row
     DPP_ROW_MIRROR = 0x140,      // lane i <- lane 15-i
-    DPP_ROW_HALF_MIRROR = 0x141  // lane i <- lane 7-i within each half row
+    DPP_ROW_HALF_MIRROR = 0x141, // lane i <- lane 7-i within each half row
+    DPP_WAVE_SHL1 = 0x130,       // lane i <- lane i+1 across the whole wave
+    DPP_WAVE_SHR1 = 0x138        // lane i <- lane i-1 across the whole wave
 };
 
 // v from the lane selected by CTRL; lanes whose source is outside the row keep `old`.
@@ -33,16 +35,16 @@ __device__ __forceinline__ double dpp(double v, double old) {
     return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Lane moves inside groups of G consecutive lanes (G in 1, 2, 4, 8, 16; groups never straddle
-// a DPP row).  from_prev: value of lane g-1 of the group, `edge` on lane 0.  from_next: value
-// of lane g+1, `edge` on lane G-1.
+// Lane moves inside groups of G consecutive lanes (G a power of two, 1 .. 64; a group of up to
+// 16 lanes sits inside one DPP row, larger groups use the wave-wide shifts).  from_prev: value
+// of lane g-1 of the group, `edge` on lane 0.  from_next: value of lane g+1, `edge` on lane G-1.
 template <int G, typename T>
 __device__ __forceinline__ T from_prev(T v, T edge, int g) {
     if constexpr (G == 1) {
         return edge;
     } else {
-        T r = dpp<DPP_ROW_SHR1>(v, edge);
-        if constexpr (G < 16) r = (g == 0) ? edge : r;
+        T r = dpp<(G <= 16 ? DPP_ROW_SHR1 : DPP_WAVE_SHR1)>(v, edge);
+        if constexpr (G != 16 && G != 64) r = (g == 0) ? edge : r;
         return r;
     }
 }
@@ -51,8 +53,8 @@ __device__ __forceinline__ T from_next(T v, T edge, int g) {
     if constexpr (G == 1) {
         return edge;
     } else {
-        T r = dpp<DPP_ROW_SHL1>(v, edge);
-        if constexpr (G < 16) r = (g == G - 1) ? edge : r;
+        T r = dpp<(G <= 16 ? DPP_ROW_SHL1 : DPP_WAVE_SHL1)>(v, edge);
+        if constexpr (G != 16 && G != 64) r = (g == G - 1) ? edge : r;
         return r;
     }
 }
@@ -64,6 +66,8 @@ __device__ __forceinline__ T group_sum(T v) {
     if constexpr (G >= 4) v += dpp<DPP_QUAD_XOR2>(v, v);
     if constexpr (G >= 8) v += dpp<DPP_ROW_HALF_MIRROR>(v, v);
     if constexpr (G >= 16) v += dpp<DPP_ROW_MIRROR>(v, v);
+    if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
     return v;
 }
 
@@ -120,8 +124,68 @@ __device__ __forceinline__ T group_sum_comp(T s, T kahan_comp) {
     if constexpr (G >= 4) level(std::integral_constant<int, DPP_QUAD_XOR2>{});
     if constexpr (G >= 8) level(std::integral_constant<int, DPP_ROW_HALF_MIRROR>{});
     if constexpr (G >= 16) level(std::integral_constant<int, DPP_ROW_MIRROR>{});
+    auto cross = [&](int m) {
+        const T s2 = __shfl_xor(s, m, 64), e2 = __shfl_xor(e, m, 64);
+        T t, err;
+        two_sum(s, s2, t, err);
+        s = t;
+        e = e + e2 + err;
+    };
+    if constexpr (G >= 32) cross(16);
+    if constexpr (G >= 64) cross(32);
     return s + e;
 }
 #pragma clang fp contract(on)
+
+// 16-byte vector loads/stores of CPL consecutive cells (NT: nontemporal, streamed past the
+// caches); other sizes fall back to 8-byte or scalar accesses.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int CPL, bool NT>
+__device__ __forceinline__ void load_cells(const T *p, T (&x)[CPL]) {
+    constexpr int B = CPL * (int)sizeof(T);
+    if constexpr (B % 16 == 0) {
+        const u32x4 *q = reinterpret_cast<const u32x4 *>(p);
+#pragma unroll
+        for (int i = 0; i < B / 16; ++i) {
+            u32x4 w;
+            if constexpr (NT)
+                w = __builtin_nontemporal_load(q + i);
+            else
+                w = q[i];
+            __builtin_memcpy(&x[i * (16 / sizeof(T))], &w, 16);
+        }
+    } else if constexpr (B == 8) {
+        const uint2 w = *reinterpret_cast<const uint2 *>(p);
+        __builtin_memcpy(&x[0], &w, 8);
+    } else {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) x[j] = p[j];
+    }
+}
+
+template <typename T, int CPL, bool NT>
+__device__ __forceinline__ void store_cells(T *p, const T (&x)[CPL]) {
+    constexpr int B = CPL * (int)sizeof(T);
+    if constexpr (B % 16 == 0) {
+        u32x4 *q = reinterpret_cast<u32x4 *>(p);
+#pragma unroll
+        for (int i = 0; i < B / 16; ++i) {
+            u32x4 w;
+            __builtin_memcpy(&w, &x[i * (16 / sizeof(T))], 16);
+            if constexpr (NT)
+                __builtin_nontemporal_store(w, q + i);
+            else
+                q[i] = w;
+        }
+    } else if constexpr (B == 8) {
+        uint2 w;
+        __builtin_memcpy(&w, &x[0], 8);
+        *reinterpret_cast<uint2 *>(p) = w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) p[j] = x[j];
+    }
+}
 
 }  // namespace mmk

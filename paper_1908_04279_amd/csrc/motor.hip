@@ -19,8 +19,6 @@
 
 namespace mmk {
 
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
 // Superbee slope of the one-sided differences a (left) and b (right): zero unless a and b
 // have the same strict sign, else sgn(b) max(min(2|a|,|b|), min(|a|,2|b|)).
 template <typename T>
@@ -70,53 +68,6 @@ __device__ __forceinline__ void motor_rhs(const T (&z)[CPL], T (&R)[CPL], const 
     for (int j = 0; j < CPL; ++j) {
         const T left = (j == 0) ? hl : h[j - 1];
         R[j] = c.nv_ds * (h[j] - left) + (c.k_on - c.k_off * z[j]);
-    }
-}
-
-template <typename T, int CPL, bool NT>
-__device__ __forceinline__ void load_cells(const T *p, T (&x)[CPL]) {
-    constexpr int B = CPL * (int)sizeof(T);
-    if constexpr (B % 16 == 0) {
-        const u32x4 *q = reinterpret_cast<const u32x4 *>(p);
-#pragma unroll
-        for (int i = 0; i < B / 16; ++i) {
-            u32x4 w;
-            if constexpr (NT)
-                w = __builtin_nontemporal_load(q + i);
-            else
-                w = q[i];
-            __builtin_memcpy(&x[i * (16 / sizeof(T))], &w, 16);
-        }
-    } else if constexpr (B == 8) {
-        const uint2 w = *reinterpret_cast<const uint2 *>(p);
-        __builtin_memcpy(&x[0], &w, 8);
-    } else {
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) x[j] = p[j];
-    }
-}
-
-template <typename T, int CPL, bool NT>
-__device__ __forceinline__ void store_cells(T *p, const T (&x)[CPL]) {
-    constexpr int B = CPL * (int)sizeof(T);
-    if constexpr (B % 16 == 0) {
-        u32x4 *q = reinterpret_cast<u32x4 *>(p);
-#pragma unroll
-        for (int i = 0; i < B / 16; ++i) {
-            u32x4 w;
-            __builtin_memcpy(&w, &x[i * (16 / sizeof(T))], 16);
-            if constexpr (NT)
-                __builtin_nontemporal_store(w, q + i);
-            else
-                q[i] = w;
-        }
-    } else if constexpr (B == 8) {
-        uint2 w;
-        __builtin_memcpy(&w, &x[0], 8);
-        *reinterpret_cast<uint2 *>(p) = w;
-    } else {
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) p[j] = x[j];
     }
 }
 
@@ -236,22 +187,20 @@ static hipError_t launch_cfg(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
     return launch_lim<T, CPL, LPC, RAGGED, 1>(M_in, M_out, m0, m1, ncol, ns, c, s, (unsigned)blocks);
 }
 
-// Lanes per column for the exact tilings (0: use the masked generic kernel).
+// Lanes per column for the exact tilings (0: use the masked generic kernel).  Default: 16
+// bytes of the column per lane (4 FP32 or 2 FP64 cells), so every vector load and store of a
+// wave covers one contiguous span.  MMK_MOTOR_LPC overrides (measurements).
 static int lanes_per_column(int ns, int elem) {
-    int lpc = 0;
-    switch (ns) {
-        case 8: lpc = 2; break;
-        case 16: lpc = 4; break;
-        case 32: lpc = 8; break;
-        case 64: lpc = elem == 4 ? 8 : 16; break;
-        case 128: lpc = 16; break;
-        case 256: lpc = 16; break;
-        default: return 0;
-    }
+    const int cpl = 16 / elem;
+    if (ns < 2 * cpl || ns % cpl != 0) return 0;
+    int lpc = ns / cpl;
+    if (lpc > 64 || (lpc & (lpc - 1)) != 0) return 0;
     if (const char *e = getenv("MMK_MOTOR_LPC")) {
         const int want = atoi(e);
-        const int cpl = want > 0 ? ns / want : 0;
-        if (want > 0 && ns % want == 0 && want <= 16 && (cpl == 4 || cpl == 8 || cpl == 16)) lpc = want;
+        if (want >= 2 && want <= 64 && (want & (want - 1)) == 0 && ns % want == 0) {
+            const int c = ns / want;
+            if (c * elem >= 16 && c <= 16) lpc = want;
+        }
     }
     return lpc;
 }
@@ -259,23 +208,20 @@ static int lanes_per_column(int ns, int elem) {
 template <typename T>
 hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                              int limiter, const MotorConst<T> &c, hipStream_t s) {
-    // exact tilings: ns = CPL * LPC, 16- or 32-byte lane vectors.  lanes_per_column() picks
-    // the split (tunable through MMK_MOTOR_LPC for measurements).
     const int lpc = lanes_per_column(ns, (int)sizeof(T));
-    switch (ns * 1000 + lpc) {
-        case 8002: return launch_cfg<T, 4, 2, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        case 16004: return launch_cfg<T, 4, 4, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        case 16002: return launch_cfg<T, 8, 2, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        case 32008: return launch_cfg<T, 4, 8, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        case 32004: return launch_cfg<T, 8, 4, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        case 64016: return launch_cfg<T, 4, 16, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        case 64008: return launch_cfg<T, 8, 8, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        case 64004: return launch_cfg<T, 16, 4, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        case 128016: return launch_cfg<T, 8, 16, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        case 128008: return launch_cfg<T, 16, 8, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        case 256016: return launch_cfg<T, 16, 16, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-        default: break;
+#define MMK_MOTOR_CASE(NS, LPC)                                                                   \
+    if (ns == NS && lpc == LPC)                                                                   \
+        return launch_cfg<T, NS / LPC, LPC, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
+    if constexpr (sizeof(T) == 4) {
+        MMK_MOTOR_CASE(8, 2) MMK_MOTOR_CASE(16, 4) MMK_MOTOR_CASE(32, 8) MMK_MOTOR_CASE(64, 16)
+        MMK_MOTOR_CASE(64, 8) MMK_MOTOR_CASE(128, 32) MMK_MOTOR_CASE(128, 16) MMK_MOTOR_CASE(256, 64)
+        MMK_MOTOR_CASE(256, 32)
+    } else {
+        MMK_MOTOR_CASE(4, 2) MMK_MOTOR_CASE(8, 4) MMK_MOTOR_CASE(16, 8) MMK_MOTOR_CASE(32, 16)
+        MMK_MOTOR_CASE(64, 32) MMK_MOTOR_CASE(64, 16) MMK_MOTOR_CASE(128, 64) MMK_MOTOR_CASE(128, 32)
+        MMK_MOTOR_CASE(256, 64)
     }
+#undef MMK_MOTOR_CASE
     // any other length: 16 lanes per column, masked tail cells, scalar loads
     if (ns <= 16) return launch_cfg<T, 1, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
     if (ns <= 32) return launch_cfg<T, 2, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);

@@ -12,6 +12,7 @@
 // group of G lanes (16, 32 or 64) walks one pencil over th; the theta-reductions of the
 // output step are shuffles inside that group.  Tiles are banded per XCD so the halo
 // re-reads of neighbouring tiles hit the same L2.
+#include "adjoint.h"
 #include "device_util.h"
 #include "kernels.h"
 
@@ -145,8 +146,99 @@ __device__ __forceinline__ int wrap(int i, int n) {
     return i;
 }
 
-// NTH_C, TI_C, TJ_C > 0 fix ntheta and the tile at compile time (index arithmetic folds,
-// halo loads are batched so many are in flight); 0 takes them from the launch arguments.
+// Stages NF fields of a TI x TJ tile plus its one-pencil halo (cross stencil: corner pencils
+// skipped) into LDS (field f at s_f + f * NH * nth), with u of the halo, gradu of the tile and
+// the angle tables.  NTH_C, TI_C, TJ_C > 0 fix ntheta and the tile at compile time: then every
+// global load of the phase is issued before the first LDS write, so the in-order vmcnt waits
+// never serialise them; 0 takes them from the launch arguments (any ntheta).
+template <typename T, int NTH_C, int TI_C, int TJ_C, int NF>
+__device__ __forceinline__ void stage_tile(const T *const (&src)[NF], T *s_f, T *s_u, T *s_G, T *s_tab,
+                                           const T *__restrict__ u, const T *__restrict__ Gr,
+                                           const T *__restrict__ tab, int i0, int j0, int nx, int ny, int nth,
+                                           int TI, int TJ, int G, int grp, int kk, int tid) {
+    constexpr bool FIXED = NTH_C > 0 && TI_C > 0 && TJ_C > 0;
+    const int HI = TI + 2, HJ = TJ + 2, NH = HI * HJ, NG = 256 / G;
+    const int64_t nxy = (int64_t)nx * ny;
+    if constexpr (FIXED) {
+        constexpr int G_ = NTH_C <= 16 ? 16 : (NTH_C <= 32 ? 32 : 64);
+        constexpr int NG_ = 256 / G_, KPL = (NTH_C + G_ - 1) / G_;
+        constexpr int HJ_ = TJ_C + 2, NH_ = (TI_C + 2) * HJ_, NP_ = TI_C * TJ_C;
+        constexpr int NQ = (NH_ + NG_ - 1) / NG_;
+        constexpr int NT = (TAB_N * NTH_C + 255) / 256;
+        static_assert(NH_ <= 256 && NP_ <= 256, "tile too large for one pass");
+        T r[NF][NQ][KPL];
+        int dst[NQ];
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) {
+            const int q = grp + v * NG_;
+            const int qi = q / HJ_, qj = q - qi * HJ_;
+            const bool ok = q < NH_ && !((qi == 0 || qi == TI_C + 1) && (qj == 0 || qj == TJ_C + 1));
+            dst[v] = ok ? q : -1;
+            const int64_t pen = (int64_t)wrap(i0 + qi - 1, nx) * ny + wrap(j0 + qj - 1, ny);
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                const int k = kk + j * G_;
+                if (ok && k < NTH_C)
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) r[f][v][j] = src[f][pen * NTH_C + k];
+            }
+        }
+        T ru0 = 0, ru1 = 0, rg[4] = {0, 0, 0, 0}, rt[NT];
+        if (tid < NH_) {
+            const int qi = tid / HJ_, qj = tid - qi * HJ_;
+            const int64_t pen = (int64_t)wrap(i0 + qi - 1, nx) * ny + wrap(j0 + qj - 1, ny);
+            ru0 = u[pen];
+            ru1 = u[nxy + pen];
+        }
+        if (tid < NP_) {
+            const int64_t pen = (int64_t)wrap(i0 + tid / TJ_C, nx) * ny + wrap(j0 + tid % TJ_C, ny);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) rg[a] = Gr[a * nxy + pen];
+        }
+#pragma unroll
+        for (int v = 0; v < NT; ++v)
+            if (tid + 256 * v < TAB_N * NTH_C) rt[v] = tab[tid + 256 * v];
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) {
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                const int k = kk + j * G_;
+                if (dst[v] >= 0 && k < NTH_C)
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) s_f[(size_t)f * NH_ * NTH_C + dst[v] * NTH_C + k] = r[f][v][j];
+            }
+        }
+        if (tid < NH_) {
+            s_u[tid] = ru0;
+            s_u[NH_ + tid] = ru1;
+        }
+        if (tid < NP_)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) s_G[a * NP_ + tid] = rg[a];
+#pragma unroll
+        for (int v = 0; v < NT; ++v)
+            if (tid + 256 * v < TAB_N * NTH_C) s_tab[tid + 256 * v] = rt[v];
+    } else {
+        for (int q = grp; q < NH; q += NG) {
+            const int qi = q / HJ, qj = q - qi * HJ;
+            if ((qi == 0 || qi == HI - 1) && (qj == 0 || qj == HJ - 1)) continue;
+            const int64_t pen = (int64_t)wrap(i0 + qi - 1, nx) * ny + wrap(j0 + qj - 1, ny);
+            for (int k = kk; k < nth; k += G)
+                for (int f = 0; f < NF; ++f) s_f[(size_t)f * NH * nth + q * nth + k] = src[f][pen * nth + k];
+            if (kk == 0) {
+                s_u[q] = u[pen];
+                s_u[NH + q] = u[nxy + pen];
+            }
+        }
+        for (int p = tid; p < TI * TJ; p += 256) {
+            const int64_t pen = (int64_t)wrap(i0 + p / TJ, nx) * ny + wrap(j0 + p % TJ, ny);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) s_G[a * TI * TJ + p] = Gr[a * nxy + pen];
+        }
+        for (int k = tid; k < TAB_N * nth; k += 256) s_tab[k] = tab[k];
+    }
+}
+
 template <typename T, int NTH_C, int TI_C, int TJ_C>
 __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, T *__restrict__ psi_out,
                                                   const T *__restrict__ m0, const T *__restrict__ m1,
@@ -159,7 +251,7 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
     const int nx = c.nx, ny = c.ny;
     const int nth = NTH_C ? NTH_C : c.nth;
     const int TI = TI_C ? TI_C : pl.ti, TJ = TJ_C ? TJ_C : pl.tj;
-    const int HI = TI + 2, HJ = TJ + 2, NH = HI * HJ;
+    const int HJ = TJ + 2, NH = (TI + 2) * HJ;
     const int G = NTH_C ? (NTH_C <= 16 ? 16 : (NTH_C <= 32 ? 32 : 64)) : pl.group;
     const int NG = 256 / G;
     T *s_psi = reinterpret_cast<T *>(smem);          // [NH][nth]
@@ -188,94 +280,9 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
     const int grp = (G == 64) ? __builtin_amdgcn_readfirstlane(tid / 64) : tid / G;
     const int kk = tid % G;
 
-    // ---- stage psi and m0 of the tile and its one-pencil halo (corners skipped) ----
-    if constexpr (FIXED) {
-        // Every global load of the staging phase is issued before the first LDS write, so the
-        // in-order vmcnt waits never serialise them.
-        constexpr int G_ = NTH_C <= 16 ? 16 : (NTH_C <= 32 ? 32 : 64);
-        constexpr int NG_ = 256 / G_, KPL = (NTH_C + G_ - 1) / G_;
-        constexpr int HJ_ = TJ_C + 2, NH_ = (TI_C + 2) * HJ_, NP_ = TI_C * TJ_C;
-        constexpr int NQ = (NH_ + NG_ - 1) / NG_;
-        constexpr int NT = (TAB_N * NTH_C + 255) / 256;
-        static_assert(NH_ <= 256 && NP_ <= 256, "tile too large for one pass");
-        T rp[NQ][KPL], rm[NQ][KPL];
-        int dst[NQ];
-#pragma unroll
-        for (int v = 0; v < NQ; ++v) {
-            const int q = grp + v * NG_;
-            const int qi = q / HJ_, qj = q - qi * HJ_;
-            const bool ok = q < NH_ && !((qi == 0 || qi == TI_C + 1) && (qj == 0 || qj == TJ_C + 1));
-            dst[v] = ok ? q : -1;
-            const int64_t pen = (int64_t)wrap(i0 + qi - 1, nx) * ny + wrap(j0 + qj - 1, ny);
-#pragma unroll
-            for (int j = 0; j < KPL; ++j) {
-                const int k = kk + j * G_;
-                if (ok && k < NTH_C) {
-                    rp[v][j] = psi_in[pen * NTH_C + k];
-                    rm[v][j] = m0[pen * NTH_C + k];
-                }
-            }
-        }
-        // fluid velocity of halo pencil tid, gradient of tile pencil tid, angle tables
-        T ru0 = 0, ru1 = 0, rg[4] = {0, 0, 0, 0}, rt[NT];
-        if (tid < NH_) {
-            const int qi = tid / HJ_, qj = tid - qi * HJ_;
-            const int64_t pen = (int64_t)wrap(i0 + qi - 1, nx) * ny + wrap(j0 + qj - 1, ny);
-            ru0 = u[pen];
-            ru1 = u[nxy + pen];
-        }
-        if (tid < NP_) {
-            const int64_t pen = (int64_t)wrap(i0 + tid / TJ_C, nx) * ny + wrap(j0 + tid % TJ_C, ny);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) rg[a] = Gr[a * nxy + pen];
-        }
-#pragma unroll
-        for (int v = 0; v < NT; ++v)
-            if (tid + 256 * v < TAB_N * NTH_C) rt[v] = tab[tid + 256 * v];
-#pragma unroll
-        for (int v = 0; v < NQ; ++v) {
-#pragma unroll
-            for (int j = 0; j < KPL; ++j) {
-                const int k = kk + j * G_;
-                if (dst[v] >= 0 && k < NTH_C) {
-                    s_psi[dst[v] * NTH_C + k] = rp[v][j];
-                    s_m0[dst[v] * NTH_C + k] = rm[v][j];
-                }
-            }
-        }
-        if (tid < NH_) {
-            s_u[tid] = ru0;
-            s_u[NH_ + tid] = ru1;
-        }
-        if (tid < NP_)
-#pragma unroll
-            for (int a = 0; a < 4; ++a) s_G[a * NP_ + tid] = rg[a];
-#pragma unroll
-        for (int v = 0; v < NT; ++v)
-            if (tid + 256 * v < TAB_N * NTH_C) s_tab[tid + 256 * v] = rt[v];
-    } else {
-        for (int q = grp; q < NH; q += NG) {
-            const int qi = q / HJ, qj = q - qi * HJ;
-            if ((qi == 0 || qi == HI - 1) && (qj == 0 || qj == HJ - 1)) continue;
-            const int64_t pen = (int64_t)wrap(i0 + qi - 1, nx) * ny + wrap(j0 + qj - 1, ny);
-            const T *sp = psi_in + pen * nth;
-            const T *sm = m0 + pen * nth;
-            for (int k = kk; k < nth; k += G) {
-                s_psi[q * nth + k] = sp[k];
-                s_m0[q * nth + k] = sm[k];
-            }
-            if (kk == 0) {
-                s_u[q] = u[pen];
-                s_u[NH + q] = u[nxy + pen];
-            }
-        }
-        for (int p = tid; p < TI * TJ; p += 256) {
-            const int64_t pen = (int64_t)wrap(i0 + p / TJ, nx) * ny + wrap(j0 + p % TJ, ny);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) s_G[a * TI * TJ + p] = Gr[a * nxy + pen];
-        }
-        for (int k = tid; k < TAB_N * nth; k += 256) s_tab[k] = tab[k];
-    }
+    const T *const srcs[2] = {psi_in, m0};
+    stage_tile<T, NTH_C, TI_C, TJ_C, 2>(srcs, s_psi, s_u, s_G, s_tab, u, Gr, tab, i0, j0, nx, ny, nth, TI, TJ, G,
+                                        grp, kk, tid);
     __syncthreads();
 
     // ---- donor-cell update, one pencil per lane group, th over the group's lanes ----
@@ -427,6 +434,137 @@ template hipError_t launch_psi_step<float>(const float *, float *, const float *
 template hipError_t launch_psi_step<double>(const double *, double *, const double *, const double *,
                                             const double *, const double *, const double *, double *, double *,
                                             double *, const PsiConst<double> &, const PsiLaunch &, hipStream_t);
+
+// ---------------------------------------------------------------------------------------
+// Reverse of the donor-cell step.  LDS tile of lam', psi and m0 with the same halo.
+//   mu_face = dt/h (lam'_right - lam'_left)
+//   lam_psi_c = lam'_c + sum over c's faces of mu * (upwind weight of psi_c)
+//   dL/dA = mu * (A >= 0 ? psi_left : psi_right);  A_{i+1/2} = (a_i + a_{i+1}) / 2,
+//   a = u - F m0 p  =>  lam_m0_c = -(F/2) [cos th (gAx+ + gAx-) + sin th (gAy+ + gAy-)].
+template <typename T, int NTH_C, int TI_C, int TJ_C>
+__global__ __launch_bounds__(256) void k_psi_reverse(const T *__restrict__ lam_in, const T *__restrict__ psi,
+                                                     const T *__restrict__ m0, const T *__restrict__ u,
+                                                     const T *__restrict__ Gr, const T *__restrict__ tab,
+                                                     T *__restrict__ lam_out, T *__restrict__ lam_m0,
+                                                     int accumulate_m0, PsiConst<T> c, PsiLaunch pl) {
+    constexpr bool FIXED = NTH_C > 0 && TI_C > 0 && TJ_C > 0;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nx = c.nx, ny = c.ny;
+    const int nth = NTH_C ? NTH_C : c.nth;
+    const int TI = TI_C ? TI_C : pl.ti, TJ = TJ_C ? TJ_C : pl.tj;
+    const int HJ = TJ + 2, NH = (TI + 2) * HJ;
+    const int G = NTH_C ? (NTH_C <= 16 ? 16 : (NTH_C <= 32 ? 32 : 64)) : pl.group;
+    const int NG = 256 / G;
+    T *s_lam = reinterpret_cast<T *>(smem);       // [NH][nth]
+    T *s_psi = s_lam + (size_t)NH * nth;           // [NH][nth]
+    T *s_m0 = s_psi + (size_t)NH * nth;            // [NH][nth]
+    T *s_u = s_m0 + (size_t)NH * nth;              // [2][NH]
+    T *s_G = s_u + 2 * NH;                         // [4][TI*TJ]
+    T *s_tab = s_G + 4 * TI * TJ;                  // [TAB_N][nth]
+    const int tid = threadIdx.x;
+    const int per = gridDim.x / 8;
+    const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= pl.tiles_i * pl.tiles_j) return;
+    const int i0 = (tile / pl.tiles_j) * TI, j0 = (tile % pl.tiles_j) * TJ;
+    const int grp = (G == 64) ? __builtin_amdgcn_readfirstlane(tid / 64) : tid / G;
+    const int kk = tid % G;
+    const T *const srcs[3] = {lam_in, psi, m0};
+    stage_tile<T, NTH_C, TI_C, TJ_C, 3>(srcs, s_lam, s_u, s_G, s_tab, u, Gr, tab, i0, j0, nx, ny, nth, TI, TJ, G,
+                                        grp, kk, tid);
+    __syncthreads();
+
+    constexpr int KMAX = NTH_C ? (NTH_C + 63) / 64 : 0;
+    AngleK<T> ak[KMAX > 0 ? KMAX : 1];
+    if constexpr (FIXED) {
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+            const int k = kk + j * G;
+            if (k < nth) ak[j] = angle_k(s_tab, nth, k);
+        }
+    }
+    const T hx = c.dt * c.inv_dx, hy = c.dt * c.inv_dy, ht = c.dt * c.inv_dth;
+    for (int p = grp; p < TI * TJ; p += NG) {
+        const int pi = p / TJ, pj = p - pi * TJ;
+        const int gi = i0 + pi, gj = j0 + pj;
+        if (gi >= nx || gj >= ny) continue;
+        const int q = (pi + 1) * HJ + (pj + 1);
+        const int qxm = q - HJ, qxp = q + HJ, qym = q - 1, qyp = q + 1;
+        const T ux_c = s_u[q], ux_m = s_u[qxm], ux_p = s_u[qxp];
+        const T uy_c = s_u[NH + q], uy_m = s_u[NH + qym], uy_p = s_u[NH + qyp];
+        const T Gxx = s_G[p], Gxy = s_G[TI * TJ + p], Gyx = s_G[2 * TI * TJ + p], Gyy = s_G[3 * TI * TJ + p];
+        const int64_t pen = (int64_t)gi * ny + gj;
+        auto cell = [&](const AngleK<T> &a) {
+            const int k = a.k;
+            const T ps = s_psi[q * nth + k], lc = s_lam[q * nth + k], mc = s_m0[q * nth + k];
+            // face velocities, as in the forward step
+            const T ax_c = ux_c - c.F * mc * a.co;
+            const T ax_m = ux_m - c.F * s_m0[qxm * nth + k] * a.co;
+            const T ax_p = ux_p - c.F * s_m0[qxp * nth + k] * a.co;
+            const T Axp = T(0.5) * (ax_c + ax_p), Axm = T(0.5) * (ax_m + ax_c);
+            const T ay_c = uy_c - c.F * mc * a.si;
+            const T ay_m = uy_m - c.F * s_m0[qym * nth + k] * a.si;
+            const T ay_p = uy_p - c.F * s_m0[qyp * nth + k] * a.si;
+            const T Ayp = T(0.5) * (ay_c + ay_p), Aym = T(0.5) * (ay_m + ay_c);
+            const T wp = -a.shp * (Gxx * a.chp + Gxy * a.shp) + a.chp * (Gyx * a.chp + Gyy * a.shp);
+            const T wm = -a.shm * (Gxx * a.chm + Gxy * a.shm) + a.chm * (Gyx * a.chm + Gyy * a.shm);
+            // face cotangents
+            const T mxp = hx * (s_lam[qxp * nth + k] - lc), mxm = hx * (lc - s_lam[qxm * nth + k]);
+            const T myp = hy * (s_lam[qyp * nth + k] - lc), mym = hy * (lc - s_lam[qym * nth + k]);
+            const T mtp = ht * (s_lam[q * nth + a.kp] - lc), mtm = ht * (lc - s_lam[q * nth + a.km]);
+            T l = lc;
+            l += (Axp >= T(0) ? Axp : T(0)) * mxp;
+            l += (Axm >= T(0) ? T(0) : Axm) * mxm;
+            l += (Ayp >= T(0) ? Ayp : T(0)) * myp;
+            l += (Aym >= T(0) ? T(0) : Aym) * mym;
+            l += (wp >= T(0) ? wp : T(0)) * mtp;
+            l += (wm >= T(0) ? T(0) : wm) * mtm;
+            lam_out[pen * nth + k] = l;
+            const T gAxp = mxp * (Axp >= T(0) ? ps : s_psi[qxp * nth + k]);
+            const T gAxm = mxm * (Axm >= T(0) ? s_psi[qxm * nth + k] : ps);
+            const T gAyp = myp * (Ayp >= T(0) ? ps : s_psi[qyp * nth + k]);
+            const T gAym = mym * (Aym >= T(0) ? s_psi[qym * nth + k] : ps);
+            T lm = -T(0.5) * c.F * (a.co * (gAxp + gAxm) + a.si * (gAyp + gAym));
+            if (accumulate_m0) lm += lam_m0[pen * nth + k];
+            lam_m0[pen * nth + k] = lm;
+        };
+        if constexpr (FIXED) {
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (kk + j * G < nth) cell(ak[j]);
+        } else {
+            for (int k = kk; k < nth; k += G) cell(angle_k(s_tab, nth, k));
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_psi_reverse(const T *lam_in, const T *psi, const T *m0, const T *u, const T *G, const T *tab,
+                              T *lam_out, T *lam_m0, bool accumulate_m0, const PsiConst<T> &c, const PsiLaunch &pl,
+                              hipStream_t s) {
+    const int acc = accumulate_m0 ? 1 : 0;
+#define MMK_REVPSI_CASE(N, A, B)                                                                           \
+    if (c.nth == N && pl.ti == A && pl.tj == B) {                                                          \
+        hipLaunchKernelGGL((k_psi_reverse<T, N, A, B>), dim3(pl.blocks), dim3(256), pl.lds_bytes, s, lam_in, \
+                           psi, m0, u, G, tab, lam_out, lam_m0, acc, c, pl);                               \
+        return hipGetLastError();                                                                          \
+    }
+#define MMK_REVPSI_TILES(N) MMK_REVPSI_CASE(N, 8, 8) MMK_REVPSI_CASE(N, 4, 8) MMK_REVPSI_CASE(N, 4, 4) MMK_REVPSI_CASE(N, 2, 4)
+    MMK_REVPSI_TILES(16)
+    MMK_REVPSI_TILES(32)
+    MMK_REVPSI_TILES(64)
+    MMK_REVPSI_TILES(128)
+#undef MMK_REVPSI_TILES
+#undef MMK_REVPSI_CASE
+    hipLaunchKernelGGL((k_psi_reverse<T, 0, 0, 0>), dim3(pl.blocks), dim3(256), pl.lds_bytes, s, lam_in, psi, m0, u,
+                       G, tab, lam_out, lam_m0, acc, c, pl);
+    return hipGetLastError();
+}
+template hipError_t launch_psi_reverse<float>(const float *, const float *, const float *, const float *,
+                                              const float *, const float *, float *, float *, bool,
+                                              const PsiConst<float> &, const PsiLaunch &, hipStream_t);
+template hipError_t launch_psi_reverse<double>(const double *, const double *, const double *, const double *,
+                                               const double *, const double *, double *, double *, bool,
+                                               const PsiConst<double> &, const PsiLaunch &, hipStream_t);
 
 // ---------------------------------------------------------------------------------------
 // Deterministic FP64 totals of per-block partials: each thread runs a Neumaier sum over a
