@@ -175,9 +175,10 @@ def copy_calibration(nbytes, reps):
     print(json.dumps({"copy_calibration_bytes_each_way": nbytes, "reps": reps}), flush=True)
 
 
-def counters_traffic(bytes_per_launch):
-    """HBM bytes per motor-step launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on a different motor kernel source."""
+def counters_traffic(n_plain, n_out):
+    """HBM bytes per motor-step launch (weighted like `achieved`: n_plain launches without and
+    n_out with the m1 output) from the committed rocprofv3 counter summary, or None when it is
+    missing or was taken on a different motor kernel source."""
     if not os.path.exists(COUNTERS):
         return None
     kv = {}
@@ -189,9 +190,11 @@ def counters_traffic(bytes_per_launch):
     if kv.get("motor_hip_sha256_16") != src_sha:
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        t0 = float(kv["hbm_bytes_per_launch"])
+        t1 = float(kv["hbm_bytes_per_output_launch"])
     except (KeyError, ValueError):
         return None
+    return (n_plain * t0 + n_out * t1) / max(n_plain + n_out, 1)
 
 
 def cpu_baseline(p, sample_steps):
@@ -257,6 +260,7 @@ def main():
         total = (r["steps"] - n_out) * step_bytes(p, b, False) + n_out * step_bytes(p, b, True)
         ms, n = r["prof"]["motor_step"]
         mb = ((n - n_out) * motor_bytes(p, b, False) + n_out * motor_bytes(p, b, True)) / max(n, 1)
+        r["n_motor"], r["n_out"] = n, n_out
         motor_gbs = mb / (ms / n / 1e3) / 1e9
         return dict(steps_per_s=sps, step_gbs=total / r["elapsed"] / 1e9,
                     motor_avg_us=ms / n * 1e3, motor_gbs=motor_gbs, motor_bytes_per_launch=mb,
@@ -274,7 +278,8 @@ def main():
                                    f"{'FP32' if main_leg == 'fp32' else 'FP64'}, fluid exchange every 10 steps",
                        "nx": p.nx, "ny": p.ny, "ntheta": p.ntheta, "ns": p.ns,
                        "motor_cells": p.nx * p.ny * p.ntheta * p.ns, "K": K})
-    traffic = counters_traffic(s["motor_bytes_per_launch"]) if main_leg == "fp32" else None
+    r0 = res[main_leg]
+    traffic = counters_traffic(r0["n_motor"] - r0["n_out"], r0["n_out"]) if main_leg == "fp32" else None
     out["roofline"] = {"bound": "hbm", "achieved": s["motor_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": s["motor_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                        "kernel": "motor column step", "avg_launch_us": s["motor_avg_us"],

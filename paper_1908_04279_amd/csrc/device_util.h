@@ -35,6 +35,20 @@ __device__ __forceinline__ double dpp(double v, double old) {
     return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// v from the lane selected by CTRL where the caller ignores lanes whose source is outside the
+// row (no tied old value, so no extra register copy); those lanes read 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_any(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_any(double v) {
+    const uint64_t vb = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)vb, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(vb >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // Lane moves inside groups of G consecutive lanes (G a power of two, 1 .. 64; a group of up to
 // 16 lanes sits inside one DPP row, larger groups use the wave-wide shifts).  from_prev: value
 // of lane g-1 of the group, `edge` on lane 0.  from_next: value of lane g+1, `edge` on lane G-1.

@@ -146,6 +146,149 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Chunked tiling: lane g of a group of LPC lanes (2 .. 16, inside one DPP row) holds NCH
+// chunks of W = 16 / sizeof(T) consecutive cells, chunk c covering cells [(c LPC + g) W, +W).
+// Every wave instruction then loads or stores whole 16-byte spans of one chunk row, the column
+// spans fewer lanes, and the s-reduction butterfly is shorter.  Cell order is chunk-major, so
+// the neighbour of a chunk's first (last) cell is in lane g-1 (g+1) of the same chunk, or at
+// the group edge in lane LPC-1 of the previous chunk (lane 0 of the next chunk).
+template <int LPC, typename T>
+__device__ __forceinline__ T chunk_left(const T &same_src, const T &wrap_src, bool has_wrap, T edge, int g) {
+    const T s = dpp_any<DPP_ROW_SHR1>(same_src);                      // lane g-1
+    T w = edge;
+    if (has_wrap) w = dpp_any<0x100 + (LPC - 1)>(wrap_src);           // lane g+LPC-1
+    return (g == 0) ? w : s;
+}
+template <int LPC, typename T>
+__device__ __forceinline__ T chunk_right(const T &same_src, const T &wrap_src, bool has_wrap, T edge, int g) {
+    const T s = dpp_any<DPP_ROW_SHL1>(same_src);                      // lane g+1
+    T w = edge;
+    if (has_wrap) w = dpp_any<0x110 + (LPC - 1)>(wrap_src);           // lane g-LPC+1
+    return (g == LPC - 1) ? w : s;
+}
+
+template <typename T, int NCH, int LPC, int LIM>
+__device__ __forceinline__ void motor_rhs_chunked(const T (&z)[NCH][16 / sizeof(T)], T (&R)[NCH][16 / sizeof(T)],
+                                                  const MotorConst<T> &c, int g) {
+    constexpr int W = 16 / sizeof(T);
+    T h[NCH][W];
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+        const T zl = chunk_left<LPC>(z[q][W - 1], z[q > 0 ? q - 1 : 0][W - 1], q > 0, T(0), g);
+        const T zr = chunk_right<LPC>(z[q][0], z[q + 1 < NCH ? q + 1 : q][0], q + 1 < NCH, z[q][W - 1], g);
+        T d[W + 1];
+        d[0] = z[q][0] - zl;
+#pragma unroll
+        for (int j = 1; j < W; ++j) d[j] = z[q][j] - z[q][j - 1];
+        d[W] = zr - z[q][W - 1];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const T sig = (LIM == 0) ? superbee(d[j], d[j + 1]) : T(0);
+            h[q][j] = z[q][j] + T(0.5) * sig;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+        const T hl = chunk_left<LPC>(h[q][W - 1], h[q > 0 ? q - 1 : 0][W - 1], q > 0, T(0), g);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const T left = (j == 0) ? hl : h[q][j - 1];
+            R[q][j] = c.nv_ds * (h[q][j] - left) + (c.k_on - c.k_off * z[q][j]);
+        }
+    }
+}
+
+template <typename T, int NCH, int LPC, int LIM, bool WANT_M1, bool NT>
+__global__ __launch_bounds__(256) void k_motor_step_chunked(const T *__restrict__ M_in, T *__restrict__ M_out,
+                                                            T *__restrict__ m0, T *__restrict__ m1, int64_t ncol,
+                                                            int ns, MotorConst<T> c) {
+    constexpr int W = 16 / sizeof(T);
+    constexpr int COLS = 256 / LPC;
+    const int g = threadIdx.x % LPC;
+    const int64_t col = (int64_t)blockIdx.x * COLS + threadIdx.x / LPC;
+    const bool active = col < ncol;
+    const int64_t cbase = col * (int64_t)ns;
+    T x[NCH][W], R[NCH][W], y[NCH][W];
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+        if (active) {
+            load_cells<T, W, NT>(M_in + cbase + (q * LPC + g) * W, x[q]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < W; ++j) x[q][j] = T(0);
+        }
+    }
+    motor_rhs_chunked<T, NCH, LPC, LIM>(x, R, c, g);
+#pragma unroll
+    for (int q = 0; q < NCH; ++q)
+#pragma unroll
+        for (int j = 0; j < W; ++j) y[q][j] = x[q][j] + c.half_dt * R[q][j];
+    motor_rhs_chunked<T, NCH, LPC, LIM>(y, R, c, g);
+#pragma unroll
+    for (int q = 0; q < NCH; ++q)
+#pragma unroll
+        for (int j = 0; j < W; ++j) y[q][j] = x[q][j] + c.dt * R[q][j];
+    if (active)
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) store_cells<T, W, NT>(M_out + cbase + (q * LPC + g) * W, y[q]);
+
+    // s-moments; cell index l = (q LPC + g) W + j, m1 weight (l + 1/2 - ns/2) exact
+    if constexpr (std::is_same<T, float>::value) {
+        Kahan a0, a1;
+#pragma unroll
+        for (int q = 0; q < NCH; ++q)
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                a0.add(y[q][j]);
+                if constexpr (WANT_M1) a1.add(y[q][j] * (0.5f * (float)(2 * ((q * LPC + g) * W + j) + 1 - ns)));
+            }
+        const float s0 = group_sum_comp<LPC>(a0.sum, a0.comp);
+        if (active && g == 0) m0[col] = s0 * c.ds;
+        if constexpr (WANT_M1) {
+            const float s1 = group_sum_comp<LPC>(a1.sum, a1.comp);
+            if (active && g == 0) m1[col] = s1 * c.ds2;
+        }
+    } else {
+        T a0 = 0, a1 = 0;
+#pragma unroll
+        for (int q = 0; q < NCH; ++q)
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                a0 += y[q][j];
+                if constexpr (WANT_M1) a1 += y[q][j] * (T(0.5) * (T)(2 * ((q * LPC + g) * W + j) + 1 - ns));
+            }
+        const T s0 = group_sum<LPC>(a0);
+        if (active && g == 0) m0[col] = s0 * c.ds;
+        if constexpr (WANT_M1) {
+            const T s1 = group_sum<LPC>(a1);
+            if (active && g == 0) m1[col] = s1 * c.ds2;
+        }
+    }
+}
+
+template <typename T, int NCH, int LPC>
+static hipError_t launch_chunked(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns, int limiter,
+                                 const MotorConst<T> &c, hipStream_t s, bool nt) {
+    constexpr int COLS = 256 / LPC;
+    const int64_t blocks = (ncol + COLS - 1) / COLS;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)blocks);
+#define MMK_CH(LIM, M1, NTV)                                                                                   \
+    hipLaunchKernelGGL((k_motor_step_chunked<T, NCH, LPC, LIM, M1, NTV>), grid, dim3(256), 0, s, M_in, M_out, m0, \
+                       m1, ncol, ns, c)
+    if (limiter == 0) {
+        if (m1) { if (nt) MMK_CH(0, true, true); else MMK_CH(0, true, false); }
+        else { if (nt) MMK_CH(0, false, true); else MMK_CH(0, false, false); }
+    } else {
+        if (m1) { if (nt) MMK_CH(1, true, true); else MMK_CH(1, true, false); }
+        else { if (nt) MMK_CH(1, false, true); else MMK_CH(1, false, false); }
+    }
+#undef MMK_CH
+    return hipGetLastError();
+}
+
 template <typename T, int CPL, int LPC, bool RAGGED, int LIM, bool NT>
 static hipError_t launch_nt(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                             const MotorConst<T> &c, hipStream_t s, unsigned blocks) {
@@ -205,9 +348,31 @@ static int lanes_per_column(int ns, int elem) {
     return lpc;
 }
 
+// Chunks of 16 bytes per lane for the chunked tiling (1: plain tiling).  MMK_MOTOR_NCH
+// overrides the default (measurements).
+static int chunks_per_lane(int ns, int elem) {
+    int nch = 1;
+    if (const char *e = getenv("MMK_MOTOR_NCH")) nch = atoi(e);
+    const int w = 16 / elem;
+    if (nch < 2 || ns % (nch * w) != 0) return 1;
+    const int lpc = ns / (nch * w);
+    if (lpc < 2 || lpc > 16 || (lpc & (lpc - 1)) != 0) return 1;
+    return nch;
+}
+
 template <typename T>
 hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                              int limiter, const MotorConst<T> &c, hipStream_t s) {
+    const int nch = chunks_per_lane(ns, (int)sizeof(T));
+    if (nch > 1) {
+        const bool nt = motor_nontemporal((int)sizeof(T));
+        const int lpc = ns / (nch * (16 / (int)sizeof(T)));
+#define MMK_CHUNK_CASE(NCH, LPC)                                                              \
+        if (nch == NCH && lpc == LPC) return launch_chunked<T, NCH, LPC>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s, nt);
+        MMK_CHUNK_CASE(2, 8) MMK_CHUNK_CASE(4, 4) MMK_CHUNK_CASE(2, 16) MMK_CHUNK_CASE(4, 8) MMK_CHUNK_CASE(2, 4)
+        MMK_CHUNK_CASE(4, 2) MMK_CHUNK_CASE(2, 2)
+#undef MMK_CHUNK_CASE
+    }
     const int lpc = lanes_per_column(ns, (int)sizeof(T));
 #define MMK_MOTOR_CASE(NS, LPC)                                                                   \
     if (ns == NS && lpc == LPC)                                                                   \
