@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -28,7 +29,7 @@ constexpr int kProfMax = 65536;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t M[2], psi[2], m0, m1, u, G, stress, mom, tab, partials, sums;
+    size_t M[2], psi[2], m0[2], m1, u, G, stress, mom, tab, partials, sums;
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -79,7 +80,8 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.M[1] = take(nm * e);
     L.psi[0] = take(np * e);
     L.psi[1] = take(np * e);
-    L.m0 = take(np * e);
+    L.m0[0] = take(np * e);
+    L.m0[1] = take(np * e);
     L.m1 = take(np * e);
     L.u = take(2 * nxy * e);
     L.G = take(4 * nxy * e);
@@ -103,7 +105,14 @@ struct mmk_ctx {
     char *ws = nullptr;
     Layout L{};
     PsiLaunch pl{}, pl_rev{};
-    int cur = 0;  // index of the current M / psi buffers
+    int cur = 0;    // index of the current M / psi buffers
+    int m0cur = 0;  // index of the m0 buffer that belongs to the current M
+    // overlap of the psi step of micro-step n with the motor step of n+1 (side stream, same
+    // default priority as every stream here).  Off by default: on MI355X the motor step alone
+    // saturates HBM and the overlapped order measured slower; MMK_OVERLAP=1 turns it on.
+    bool overlap = false;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_motor = nullptr, ev_psi[2] = {nullptr, nullptr};
     bool have_state = false, have_fluid = false, have_out = false;
     std::string err;
     bool prof = false;
@@ -142,7 +151,7 @@ static mmk_status hipfail(mmk_ctx *c, hipError_t e, const char *what) {
     } while (0)
 
 // ---- profiling: event pairs around launches ---------------------------------------------
-static hipError_t prof_begin(mmk_ctx *c, int id, int *slot) {
+static hipError_t prof_begin_on(mmk_ctx *c, int id, int *slot, hipStream_t s) {
     *slot = -1;
     if (!c->prof || c->nev[id] >= kProfMax) return hipSuccess;
     int i = c->nev[id];
@@ -153,36 +162,50 @@ static hipError_t prof_begin(mmk_ctx *c, int id, int *slot) {
         c->ev[id].push_back(e);
     }
     *slot = i;
-    return hipEventRecord(c->ev[id][2 * i], c->stream);
+    return hipEventRecord(c->ev[id][2 * i], s);
 }
-static hipError_t prof_end(mmk_ctx *c, int id, int slot) {
+static hipError_t prof_end_on(mmk_ctx *c, int id, int slot, hipStream_t s) {
     if (slot < 0) return hipSuccess;
     c->nev[id] = slot + 1;
-    return hipEventRecord(c->ev[id][2 * slot + 1], c->stream);
+    return hipEventRecord(c->ev[id][2 * slot + 1], s);
 }
+static hipError_t prof_begin(mmk_ctx *c, int id, int *slot) { return prof_begin_on(c, id, slot, c->stream); }
+static hipError_t prof_end(mmk_ctx *c, int id, int slot) { return prof_end_on(c, id, slot, c->stream); }
 
 // ---- typed step ---------------------------------------------------------------------------
-// One micro-step from (M_in, psi_in) to (M_out, psi_out).  With out = true also the
-// stress, moments and the block partials of the global sums.
+template <typename T>
+static mmk_status motor_half(mmk_ctx *c, const T *M_in, T *M_out, T *m0, T *m1, double dt, hipStream_t s) {
+    const mmk_params &p = c->p;
+    int slot;
+    HIPCHK(c, prof_begin_on(c, 0, &slot, s), "hipEventRecord");
+    HIPCHK(c, launch_motor_step<T>(M_in, M_out, m0, m1, n_psi(p), p.ns, p.limiter, motor_const<T>(p, dt), s),
+           "motor step launch");
+    HIPCHK(c, prof_end_on(c, 0, slot, s), "hipEventRecord");
+    return MMK_OK;
+}
+
+template <typename T>
+static mmk_status psi_half(mmk_ctx *c, const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u,
+                           const T *G, double dt, bool out, hipStream_t s) {
+    int slot;
+    HIPCHK(c, prof_begin_on(c, 1, &slot, s), "hipEventRecord");
+    HIPCHK(c, launch_psi_step<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab),
+                                 out ? c->at<T>(c->L.stress) : nullptr, out ? c->at<T>(c->L.mom) : nullptr,
+                                 out ? c->at<double>(c->L.partials) : nullptr, psi_const<T>(c->p, dt), c->pl, s),
+           "psi step launch");
+    HIPCHK(c, prof_end_on(c, 1, slot, s), "hipEventRecord");
+    return MMK_OK;
+}
+
+// One micro-step from (M_in, psi_in) to (M_out, psi_out) on the context's stream.  With
+// out = true also the stress, moments and the block partials of the global sums.
 template <typename T>
 static mmk_status micro_step(mmk_ctx *c, const T *M_in, T *M_out, const T *psi_in, T *psi_out, T *m0,
                              const T *u, const T *G, double dt, bool out) {
-    const mmk_params &p = c->p;
-    const MotorConst<T> mc = motor_const<T>(p, dt);
     T *m1 = out ? c->at<T>(c->L.m1) : nullptr;
-    int slot;
-    HIPCHK(c, prof_begin(c, 0, &slot), "hipEventRecord");
-    HIPCHK(c, launch_motor_step<T>(M_in, M_out, m0, m1, n_psi(p), p.ns, p.limiter, mc, c->stream),
-           "motor step launch");
-    HIPCHK(c, prof_end(c, 0, slot), "hipEventRecord");
-    const PsiConst<T> pc = psi_const<T>(p, dt);
-    HIPCHK(c, prof_begin(c, 1, &slot), "hipEventRecord");
-    HIPCHK(c, launch_psi_step<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab),
-                                 out ? c->at<T>(c->L.stress) : nullptr, out ? c->at<T>(c->L.mom) : nullptr,
-                                 out ? c->at<double>(c->L.partials) : nullptr, pc, c->pl, c->stream),
-           "psi step launch");
-    HIPCHK(c, prof_end(c, 1, slot), "hipEventRecord");
-    return MMK_OK;
+    mmk_status st = motor_half<T>(c, M_in, M_out, m0, m1, dt, c->stream);
+    if (st != MMK_OK) return st;
+    return psi_half<T>(c, psi_in, psi_out, m0, m1, u, G, dt, out, c->stream);
 }
 
 template <typename T>
@@ -198,21 +221,58 @@ static mmk_status global_sums(mmk_ctx *c) {
     return MMK_OK;
 }
 
+// Sequential order: motor step then psi step, both on the context's stream (taped runs).
 template <typename T>
-static mmk_status run_steps(mmk_ctx *c, int K, double dt) {
+static mmk_status run_steps_serial(mmk_ctx *c, int K, double dt) {
     for (int n = 0; n < K; ++n) {
         const bool last = (n == K - 1);
         const int a = c->cur, b = 1 - c->cur;
         mmk_status st = tape_before_step(c, &c->tape, dt);
         if (st != MMK_OK) return st;
         st = micro_step<T>(c, c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), c->at<T>(c->L.psi[a]),
-                           c->at<T>(c->L.psi[b]), c->at<T>(c->L.m0), c->at<T>(c->L.u), c->at<T>(c->L.G), dt,
-                           last);
+                           c->at<T>(c->L.psi[b]), c->at<T>(c->L.m0[c->m0cur]), c->at<T>(c->L.u), c->at<T>(c->L.G),
+                           dt, last);
         if (st != MMK_OK) return st;
         c->cur = b;
         st = tape_after_step(c, &c->tape);
         if (st != MMK_OK) return st;
     }
+    return MMK_OK;
+}
+
+// Overlapped order: the psi step of micro-step n (side stream) runs beside the motor step of
+// n+1 (context stream); they touch different fields.  m0 is double-buffered: the motor step
+// n writes the buffer the psi step n-2 read, so it waits for that psi step only.  The
+// context stream waits for the last psi step before returning, so every later call sees
+// the finished state.
+template <typename T>
+static mmk_status run_steps_overlap(mmk_ctx *c, int K, double dt) {
+    for (int n = 0; n < K; ++n) {
+        const bool last = (n == K - 1);
+        const int a = c->cur, b = 1 - c->cur;
+        const int mb = c->m0cur ^ 1;
+        if (n >= 2) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_psi[n & 1], 0), "hipStreamWaitEvent");
+        T *m0 = c->at<T>(c->L.m0[mb]);
+        T *m1 = last ? c->at<T>(c->L.m1) : nullptr;
+        mmk_status st = motor_half<T>(c, c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), m0, m1, dt, c->stream);
+        if (st != MMK_OK) return st;
+        HIPCHK(c, hipEventRecord(c->ev_motor, c->stream), "hipEventRecord");
+        HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_motor, 0), "hipStreamWaitEvent");
+        st = psi_half<T>(c, c->at<T>(c->L.psi[a]), c->at<T>(c->L.psi[b]), m0, m1, c->at<T>(c->L.u),
+                         c->at<T>(c->L.G), dt, last, c->side);
+        if (st != MMK_OK) return st;
+        HIPCHK(c, hipEventRecord(c->ev_psi[n & 1], c->side), "hipEventRecord");
+        c->cur = b;
+        c->m0cur = mb;
+    }
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_psi[(K - 1) & 1], 0), "hipStreamWaitEvent");
+    return MMK_OK;
+}
+
+template <typename T>
+static mmk_status run_steps(mmk_ctx *c, int K, double dt) {
+    mmk_status st = (c->overlap && !c->tape.active) ? run_steps_overlap<T>(c, K, dt) : run_steps_serial<T>(c, K, dt);
+    if (st != MMK_OK) return st;
     if (K > 0) {
         c->have_out = true;
         return global_sums<T>(c);
@@ -231,7 +291,7 @@ void *ctx_cur_M(const mmk_ctx *c) { return c->ws + c->L.M[c->cur]; }
 void *ctx_cur_psi(const mmk_ctx *c) { return c->ws + c->L.psi[c->cur]; }
 void *ctx_fluid_u(const mmk_ctx *c) { return c->ws + c->L.u; }
 void *ctx_fluid_G(const mmk_ctx *c) { return c->ws + c->L.G; }
-void *ctx_m0(const mmk_ctx *c) { return c->ws + c->L.m0; }
+void *ctx_m0(const mmk_ctx *c) { return c->ws + c->L.m0[c->m0cur]; }
 void *ctx_m1(const mmk_ctx *c) { return c->ws + c->L.m1; }
 void *ctx_tab(const mmk_ctx *c) { return c->ws + c->L.tab; }
 const PsiLaunch &ctx_psi_launch(const mmk_ctx *c) { return c->pl; }
@@ -328,6 +388,17 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
         return hipfail(nullptr, e, "copy of angle tables");
     }
     tape_init(&c->tape, ckpt_every, ckpt_every > 0 ? max_tape_steps : 0);
+    if (const char *ov = getenv("MMK_OVERLAP")) c->overlap = atoi(ov) != 0;
+    if (c->overlap) {
+        e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_motor, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_psi[0], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_psi[1], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            mmk_destroy(c);
+            return hipfail(nullptr, e, "side stream / events");
+        }
+    }
     *out = c;
     return MMK_OK;
 }
@@ -335,8 +406,13 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
 mmk_status mmk_destroy(mmk_ctx *c) {
     if (!c) return MMK_ERR_ARG;
     (void)hipStreamSynchronize(c->stream);
+    if (c->side) (void)hipStreamSynchronize(c->side);
     for (int i = 0; i < kProfIds; ++i)
         for (hipEvent_t e : c->ev[i]) (void)hipEventDestroy(e);
+    if (c->ev_motor) (void)hipEventDestroy(c->ev_motor);
+    for (hipEvent_t e : c->ev_psi)
+        if (e) (void)hipEventDestroy(e);
+    if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
     return MMK_OK;
 }
@@ -429,7 +505,8 @@ mmk_status mmk_get_motor_moments(mmk_ctx *c, void *m0, void *m1) {
     if (!c) return MMK_ERR_ARG;
     if (!c->have_out) return fail(c, MMK_ERR_STATE, "no outputs: run mmk_step with K > 0 first");
     const size_t np = (size_t)n_psi(c->p) * c->esz;
-    if (m0) HIPCHK(c, hipMemcpyAsync(m0, c->ws + c->L.m0, np, hipMemcpyDeviceToDevice, c->stream), "copy of m0");
+    if (m0)
+        HIPCHK(c, hipMemcpyAsync(m0, c->ws + c->L.m0[c->m0cur], np, hipMemcpyDeviceToDevice, c->stream), "copy of m0");
     if (m1) HIPCHK(c, hipMemcpyAsync(m1, c->ws + c->L.m1, np, hipMemcpyDeviceToDevice, c->stream), "copy of m1");
     return MMK_OK;
 }

@@ -166,6 +166,74 @@ __device__ __forceinline__ void stage_tile(const T *const (&src)[NF], T *s_f, T 
         constexpr int NQ = (NH_ + NG_ - 1) / NG_;
         constexpr int NT = (TAB_N * NTH_C + 255) / 256;
         static_assert(NH_ <= 256 && NP_ <= 256, "tile too large for one pass");
+        if constexpr (G_ == 64) {
+            // one wave per pencil: wave grp takes halo rows grp, grp+4, ...; the wrapped column
+            // index of each pencil of a row is computed once per wave (uniform, scalar)
+            constexpr int HI_ = TI_C + 2, NR = (HI_ + 3) / 4;
+            int gj[HJ_];
+#pragma unroll
+            for (int qj = 0; qj < HJ_; ++qj) gj[qj] = wrap(j0 + qj - 1, ny);
+            T r[NF][NR][HJ_][KPL];
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) {
+                const int qi = grp + 4 * rr;
+                const int64_t row = (int64_t)wrap(i0 + qi - 1, nx) * ny;
+#pragma unroll
+                for (int qj = 0; qj < HJ_; ++qj) {
+                    const bool ok = qi < HI_ && !((qi == 0 || qi == HI_ - 1) && (qj == 0 || qj == HJ_ - 1));
+                    const int64_t pen = row + gj[qj];
+#pragma unroll
+                    for (int j = 0; j < KPL; ++j) {
+                        const int k = kk + j * 64;
+                        if (ok && k < NTH_C)
+#pragma unroll
+                            for (int f = 0; f < NF; ++f) r[f][rr][qj][j] = src[f][pen * NTH_C + k];
+                    }
+                }
+            }
+            T ru0 = 0, ru1 = 0, rg[4] = {0, 0, 0, 0}, rt[NT];
+            if (tid < NH_) {
+                const int qi = tid / HJ_, qj = tid - qi * HJ_;
+                const int64_t pen = (int64_t)wrap(i0 + qi - 1, nx) * ny + wrap(j0 + qj - 1, ny);
+                ru0 = u[pen];
+                ru1 = u[nxy + pen];
+            }
+            if (tid < NP_) {
+                const int64_t pen = (int64_t)wrap(i0 + tid / TJ_C, nx) * ny + wrap(j0 + tid % TJ_C, ny);
+#pragma unroll
+                for (int a = 0; a < 4; ++a) rg[a] = Gr[a * nxy + pen];
+            }
+#pragma unroll
+            for (int v = 0; v < NT; ++v)
+                if (tid + 256 * v < TAB_N * NTH_C) rt[v] = tab[tid + 256 * v];
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) {
+                const int qi = grp + 4 * rr;
+#pragma unroll
+                for (int qj = 0; qj < HJ_; ++qj) {
+                    const bool ok = qi < HI_ && !((qi == 0 || qi == HI_ - 1) && (qj == 0 || qj == HJ_ - 1));
+                    const int q = qi * HJ_ + qj;
+#pragma unroll
+                    for (int j = 0; j < KPL; ++j) {
+                        const int k = kk + j * 64;
+                        if (ok && k < NTH_C)
+#pragma unroll
+                            for (int f = 0; f < NF; ++f) s_f[(size_t)f * NH_ * NTH_C + q * NTH_C + k] = r[f][rr][qj][j];
+                    }
+                }
+            }
+            if (tid < NH_) {
+                s_u[tid] = ru0;
+                s_u[NH_ + tid] = ru1;
+            }
+            if (tid < NP_)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) s_G[a * NP_ + tid] = rg[a];
+#pragma unroll
+            for (int v = 0; v < NT; ++v)
+                if (tid + 256 * v < TAB_N * NTH_C) s_tab[tid + 256 * v] = rt[v];
+            return;
+        }
         T r[NF][NQ][KPL];
         int dst[NQ];
 #pragma unroll
@@ -297,10 +365,30 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
     }
     double acc_mass = 0, acc_s0 = 0, acc_s1 = 0, acc_s2 = 0;
 
-    for (int p = grp; p < TI * TJ; p += NG) {
-        const int pi = p / TJ, pj = p - pi * TJ;
+    // WALK (one wave per pencil): wave grp takes TJ/4 tile columns and walks each along x, so
+    // the flux through a pencil's upper x-face is carried into the next pencil as its lower
+    // x-face flux (the same value the next pencil would compute: the face velocity is the
+    // symmetric mean of the two cells).  With 64 orientations the lower theta-face flux of
+    // lane k is lane k-1's upper one, taken with a wave rotate.
+    constexpr bool WALK = FIXED && NTH_C >= 64 && (TJ_C % 4 == 0);
+    constexpr bool THROT = WALK && NTH_C == 64;
+    T fx_carry[KMAX > 0 ? KMAX : 1];
+    const int n_iter = WALK ? (TI * TJ) / 4 : (TI * TJ + NG - 1) / NG;
+    for (int it = 0; it < n_iter; ++it) {
+        int pi, pj;
+        if constexpr (WALK) {
+            pi = it % TI_C;
+            pj = grp * (TJ_C / 4) + it / TI_C;
+        } else {
+            const int p = grp + it * NG;
+            if (p >= TI * TJ) break;
+            pi = p / TJ;
+            pj = p - pi * TJ;
+        }
+        const int p = pi * TJ + pj;
         const int gi = i0 + pi, gj = j0 + pj;
         if (gi >= nx || gj >= ny) continue;  // partial tile (uniform across the group)
+        const bool carried = WALK && pi > 0;
         const int q = (pi + 1) * HJ + (pj + 1);
         const int qxm = q - HJ, qxp = q + HJ, qym = q - 1, qyp = q + 1;
         const T ux_c = s_u[q], ux_m = s_u[qxm], ux_p = s_u[qxp];
@@ -309,17 +397,24 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
         const int64_t pen = (int64_t)gi * ny + gj;
         Acc<T> a_c, a_nx, a_ny, a_dxx, a_dxy, a_dyy, a_b, a_sxx, a_sxy, a_syy;
 
-        auto cell = [&](const AngleK<T> &a) {
+        auto cell = [&](const AngleK<T> &a, int slot) {
             const int k = a.k;
             const T ps = s_psi[q * nth + k];
             const T mc = s_m0[q * nth + k];
             // x faces: cell velocity u_x - F m0 cos th, face value the mean of the two cells
             const T ax_c = ux_c - c.F * mc * a.co;
-            const T ax_m = ux_m - c.F * s_m0[qxm * nth + k] * a.co;
             const T ax_p = ux_p - c.F * s_m0[qxp * nth + k] * a.co;
-            const T Axp = T(0.5) * (ax_c + ax_p), Axm = T(0.5) * (ax_m + ax_c);
+            const T Axp = T(0.5) * (ax_c + ax_p);
             const T fxp = donor(Axp, ps, s_psi[qxp * nth + k]);
-            const T fxm = donor(Axm, s_psi[qxm * nth + k], ps);
+            T fxm;
+            if (carried) {
+                fxm = fx_carry[slot];
+            } else {
+                const T ax_m = ux_m - c.F * s_m0[qxm * nth + k] * a.co;
+                const T Axm = T(0.5) * (ax_m + ax_c);
+                fxm = donor(Axm, s_psi[qxm * nth + k], ps);
+            }
+            if constexpr (WALK) fx_carry[slot] = fxp;
             // y faces
             const T ay_c = uy_c - c.F * mc * a.si;
             const T ay_m = uy_m - c.F * s_m0[qym * nth + k] * a.si;
@@ -329,9 +424,14 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
             const T fym = donor(Aym, s_psi[qym * nth + k], ps);
             // theta faces k+1/2 and k-1/2: rotation rate p_perp . gradu . p
             const T wp = -a.shp * (Gxx * a.chp + Gxy * a.shp) + a.chp * (Gyx * a.chp + Gyy * a.shp);
-            const T wm = -a.shm * (Gxx * a.chm + Gxy * a.shm) + a.chm * (Gyx * a.chm + Gyy * a.shm);
             const T ftp = donor(wp, ps, s_psi[q * nth + a.kp]);
-            const T ftm = donor(wm, s_psi[q * nth + a.km], ps);
+            T ftm;
+            if constexpr (THROT) {
+                ftm = dpp_any<DPP_WAVE_ROR1>(ftp);  // lane k-1 (lane 63 for k = 0)
+            } else {
+                const T wm = -a.shm * (Gxx * a.chm + Gxy * a.shm) + a.chm * (Gyx * a.chm + Gyy * a.shm);
+                ftm = donor(wm, s_psi[q * nth + a.km], ps);
+            }
             const T div = (fxp - fxm) * c.inv_dx + (fyp - fym) * c.inv_dy + (ftp - ftm) * c.inv_dth;
             const T pn = ps - c.dt * div;
             psi_out[pen * nth + k] = pn;
@@ -353,9 +453,9 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
         if constexpr (FIXED) {
 #pragma unroll
             for (int j = 0; j < KMAX; ++j)
-                if (kk + j * G < nth) cell(ak[j]);
+                if (kk + j * G < nth) cell(ak[j], j);
         } else {
-            for (int k = kk; k < nth; k += G) cell(angle_k(s_tab, nth, k));
+            for (int k = kk; k < nth; k += G) cell(angle_k(s_tab, nth, k), 0);
         }
         if (out) {
             const T dth = c.dth;
