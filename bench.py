@@ -27,8 +27,15 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "micro-steps/s + HBM GB/s (% peak), FP32 vs FP64 at 256²×64×64; adjoint/fwd ratio"
-COUNTERS = os.path.join(ROOT, "profiles", "motor_step_f32_256x256x64x64_counters.txt")
-MOTOR_SRC = os.path.join(ROOT, "paper_1908_04279_amd", "csrc", "motor.hip")
+CSRC = os.path.join(ROOT, "paper_1908_04279_amd", "csrc")
+# rocprofv3 HBM byte counters of the dominant kernel, and the sources that kernel is built from
+# (the counters count only while those sources are unchanged)
+COUNTERS = {
+    "fused": (os.path.join(ROOT, "profiles", "fused_step_f32_256x256x64x64_counters.txt"),
+              ["fused.hip", "motor_dev.h", "psi_dev.h", "device_util.h", "kernels.h"]),
+    "motor": (os.path.join(ROOT, "profiles", "motor_step_f32_256x256x64x64_counters.txt"),
+              ["motor.hip", "motor_dev.h", "device_util.h", "kernels.h"]),
+}
 
 
 def log(*a):
@@ -40,17 +47,22 @@ def motor_bytes(p, b, with_m1):
     return b * (2 * n_psi * p.ns + n_psi * (2 if with_m1 else 1))
 
 
+def psi_bytes(p, b, out):
+    """Algorithmic HBM bytes of one psi step: read psi, m0, u, gradu, write psi [read m1,
+    write stress and moments]."""
+    n_psi = p.nx * p.ny * p.ntheta
+    nxy = p.nx * p.ny
+    return b * (3 * n_psi + 6 * nxy) + (b * (n_psi + 10 * nxy) if out else 0)
+
+
 def step_bytes(p, b, out):
     """Algorithmic HBM bytes of one micro-step: motor kernel (read M, write M, write m0
     [and m1]) + psi kernel (read psi, m0, u, gradu; write psi [read m1, write stress and
     moments])."""
-    n_psi = p.nx * p.ny * p.ntheta
-    nxy = p.nx * p.ny
-    psi = b * (3 * n_psi + 6 * nxy) + (b * (n_psi + 10 * nxy) if out else 0)
-    return motor_bytes(p, b, out) + psi
+    return motor_bytes(p, b, out) + psi_bytes(p, b, out)
 
 
-def run_forward(p, precision, steps, warmup, K, profile=True):
+def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1):
     import torch
     from paper_1908_04279_amd import inputs as gen
     from paper_1908_04279_amd import mmk
@@ -80,7 +92,7 @@ def run_forward(p, precision, steps, warmup, K, profile=True):
     e = advance(warmup, 0)
     torch.cuda.synchronize()
     if profile:
-        ctx.profile(True)
+        ctx.profile(True, every=event_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     advance(steps, e)
@@ -89,7 +101,7 @@ def run_forward(p, precision, steps, warmup, K, profile=True):
     elapsed = t1 - t0
     prof = {}
     if profile:
-        for name in ("motor_step", "psi_step", "global_sums"):
+        for name in ("motor_step", "psi_step", "global_sums", "step_fused"):
             ms, n = ctx.profile_read(name)
             prof[name] = (ms, n)
         ctx.profile(False)
@@ -175,19 +187,26 @@ def copy_calibration(nbytes, reps):
     print(json.dumps({"copy_calibration_bytes_each_way": nbytes, "reps": reps}), flush=True)
 
 
-def counters_traffic(n_plain, n_out):
-    """HBM bytes per motor-step launch (weighted like `achieved`: n_plain launches without and
-    n_out with the m1 output) from the committed rocprofv3 counter summary, or None when it is
-    missing or was taken on a different motor kernel source."""
-    if not os.path.exists(COUNTERS):
+def sources_sha(files):
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counters_traffic(kind, n_plain, n_out):
+    """HBM bytes per launch of the dominant kernel (weighted like `achieved`: n_plain launches
+    without and n_out with the m1 output) from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on different kernel sources."""
+    path, files = COUNTERS[kind]
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(COUNTERS):
+    for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.strip().split("=", 1)
             kv[k.strip()] = v.strip()
-    src_sha = hashlib.sha256(open(MOTOR_SRC, "rb").read()).hexdigest()[:16]
-    if kv.get("motor_hip_sha256_16") != src_sha:
+    if kv.get("sources_sha256_16") != sources_sha(files):
         return None
     try:
         t0 = float(kv["hbm_bytes_per_launch"])
@@ -224,9 +243,11 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint"], default="all",
+    ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64"], default="all",
                     help="restrict to one leg (used for profiler runs)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--event-every", type=int, default=1,
+                    help="bracket every N-th kernel launch with HIP events (measurements of the event cost)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -245,27 +266,45 @@ def main():
     if args.only == "adjoint":
         print(json.dumps({"adjoint_fp32": run_adjoint("c5_adjoint_fp32_256x256x64x32", mmk.FP32)}), flush=True)
         return
+    if args.only == "adjoint64":
+        print(json.dumps({"adjoint_fp64": run_adjoint("c4_adjoint_fp64_64x64x32x32", mmk.FP64)}), flush=True)
+        return
 
     p = gen.params_for("c3_fp32_256x256x64x64")
     K = 10
     res = {}
     if args.only in ("all", "fp32"):
-        res["fp32"] = run_forward(p, mmk.FP32, args.steps, args.warmup, K)
+        res["fp32"] = run_forward(p, mmk.FP32, args.steps, args.warmup, K, event_every=args.event_every)
     if args.only in ("all", "fp64"):
-        res["fp64"] = run_forward(p, mmk.FP64, args.fp64_steps, min(args.warmup, 20), K)
+        res["fp64"] = run_forward(p, mmk.FP64, args.fp64_steps, min(args.warmup, 20), K,
+                                  event_every=args.event_every)
 
     def summarise(r, b):
-        n_out = r["steps"] // K
+        """Whole-step rate and the roofline of the kernel that carries the motor stream: the
+        fused launch (motor step n+1 with psi step n) when the run used it, else the motor
+        step.  Per call of K steps: one motor launch, K-1 fused launches (the last with the
+        m1 output), one psi launch with the outputs; unfused: K motor + K psi launches."""
+        calls = r["steps"] // K
         sps = r["steps"] / r["elapsed"]
-        total = (r["steps"] - n_out) * step_bytes(p, b, False) + n_out * step_bytes(p, b, True)
-        ms, n = r["prof"]["motor_step"]
-        mb = ((n - n_out) * motor_bytes(p, b, False) + n_out * motor_bytes(p, b, True)) / max(n, 1)
-        r["n_motor"], r["n_out"] = n, n_out
-        motor_gbs = mb / (ms / n / 1e3) / 1e9
-        return dict(steps_per_s=sps, step_gbs=total / r["elapsed"] / 1e9,
-                    motor_avg_us=ms / n * 1e3, motor_gbs=motor_gbs, motor_bytes_per_launch=mb,
-                    psi_avg_us=r["prof"]["psi_step"][0] / r["prof"]["psi_step"][1] * 1e3,
-                    mass=r["mass"])
+        total = (r["steps"] - calls) * step_bytes(p, b, False) + calls * step_bytes(p, b, True)
+        ms_f, n_f = r["prof"]["step_fused"]
+        ms_m, n_m = r["prof"]["motor_step"]
+        ms_p, n_p = r["prof"]["psi_step"]
+        if n_f > 0:
+            kind, ms, n = "fused", ms_f, n_f
+            n_out = calls if K >= 2 else 0
+            per = lambda m1: motor_bytes(p, b, m1) + psi_bytes(p, b, False)
+            name = "fused launch: motor step n+1 + psi step n (LDS-free walk)"
+        else:
+            kind, ms, n = "motor", ms_m, n_m
+            n_out = calls
+            per = lambda m1: motor_bytes(p, b, m1)
+            name = "motor column step"
+        kb = ((n - n_out) * per(False) + n_out * per(True)) / max(n, 1)
+        return dict(steps_per_s=sps, step_gbs=total / r["elapsed"] / 1e9, kind=kind, kernel=name,
+                    avg_us=ms / n * 1e3, gbs=kb / (ms / n / 1e3) / 1e9, bytes_per_launch=kb,
+                    n_plain=n - n_out, n_out=n_out, motor_avg_us=ms_m / max(n_m, 1) * 1e3,
+                    psi_avg_us=ms_p / max(n_p, 1) * 1e3, launches=n_f + n_m + n_p, mass=r["mass"])
 
     out = {"metric": METRIC, "unit": "micro-steps/s", "n_gpus": 1, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
@@ -278,20 +317,20 @@ def main():
                                    f"{'FP32' if main_leg == 'fp32' else 'FP64'}, fluid exchange every 10 steps",
                        "nx": p.nx, "ny": p.ny, "ntheta": p.ntheta, "ns": p.ns,
                        "motor_cells": p.nx * p.ny * p.ntheta * p.ns, "K": K})
-    r0 = res[main_leg]
-    traffic = counters_traffic(r0["n_motor"] - r0["n_out"], r0["n_out"]) if main_leg == "fp32" else None
-    out["roofline"] = {"bound": "hbm", "achieved": s["motor_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": s["motor_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                       "kernel": "motor column step", "avg_launch_us": s["motor_avg_us"],
-                       "algorithmic_bytes_per_launch": s["motor_bytes_per_launch"]}
+    traffic = counters_traffic(s["kind"], s["n_plain"], s["n_out"]) if main_leg == "fp32" else None
+    out["roofline"] = {"bound": "hbm", "achieved": s["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": s["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                       "kernel": s["kernel"], "avg_launch_us": s["avg_us"],
+                       "algorithmic_bytes_per_launch": s["bytes_per_launch"]}
     out["step_hbm_gbs"] = s["step_gbs"]
     out["step_hbm_frac"] = s["step_gbs"] / HBM_PEAK_GBS
+    out["launches_per_step"] = s["launches"] / res[main_leg]["steps"]
     out["psi_step_avg_us"] = s["psi_avg_us"]
     if "fp32" in res and "fp64" in res:
         s64 = summarise(res["fp64"], 8)
         out["fp64"] = {"micro_steps_per_s": s64["steps_per_s"], "ms_per_step": 1e3 / s64["steps_per_s"],
-                       "step_hbm_gbs": s64["step_gbs"], "motor_gbs": s64["motor_gbs"],
-                       "motor_frac": s64["motor_gbs"] / HBM_PEAK_GBS, "motor_avg_us": s64["motor_avg_us"],
+                       "step_hbm_gbs": s64["step_gbs"], "kernel": s64["kernel"], "kernel_gbs": s64["gbs"],
+                       "kernel_frac": s64["gbs"] / HBM_PEAK_GBS, "kernel_avg_us": s64["avg_us"],
                        "steps": res["fp64"]["steps"]}
         out["fp32_over_fp64"] = s["steps_per_s"] / s64["steps_per_s"]
     out["adjoint_over_forward"] = None

@@ -202,9 +202,11 @@ static hipError_t rev_cfg(const T *M, const T *lam_in, const T *lam_m0, const T 
                           double *gpart, int gblocks, int64_t ncol, int ns, int limiter, const MotorConst<T> &c,
                           T inv_ds, hipStream_t s) {
     constexpr int COLS = 256 / LPC;
-    int64_t blocks = (ncol + COLS - 1) / COLS;
-    if (blocks > gblocks) blocks = gblocks;
-    if (blocks < 1) blocks = 1;
+    // one block per COLS columns (no grid-stride loop: the dispatcher balances the blocks);
+    // each block owns its row of gpart, so the FP64 accumulation across steps is race-free
+    const int64_t blocks = (ncol + COLS - 1) / COLS;
+    if (blocks < 1) return hipSuccess;
+    if (blocks > gblocks || blocks > 0x7fffffff) return hipErrorInvalidValue;
     if (limiter == 0)
         hipLaunchKernelGGL((k_motor_reverse<T, CPL, LPC, 0, RAGGED>), dim3((unsigned)blocks), dim3(256), 0, s, M,
                            lam_in, lam_m0, lam_m1, lam_out, gpart, ncol, ns, c, inv_ds);
@@ -214,6 +216,20 @@ static hipError_t rev_cfg(const T *M, const T *lam_in, const T *lam_m0, const T 
     return hipGetLastError();
 }
 
+// Lanes per column of the reverse tiling: 16 bytes of the column per lane as in the forward
+// kernel, or 0 for the masked 16-lane kernel of other lengths.
+static int rev_lpc(int ns, int elem) {
+    const int cpl = 16 / elem;
+    const int lpc = (ns >= 2 * cpl && ns % cpl == 0) ? ns / cpl : 0;
+    return (lpc >= 2 && lpc <= 64 && (lpc & (lpc - 1)) == 0) ? lpc : 0;
+}
+
+int64_t motor_reverse_blocks(int64_t ncol, int ns, int elem) {
+    const int lpc = rev_lpc(ns, elem);
+    const int cols = 256 / (lpc ? lpc : 16);
+    return (ncol + cols - 1) / cols;
+}
+
 template <typename T>
 hipError_t launch_motor_reverse(const T *M, const T *lam_in, const T *lam_m0, const T *lam_m1, T *lam_out,
                                 double *gpart, int gblocks, int64_t ncol, int ns, int limiter,
@@ -221,7 +237,7 @@ hipError_t launch_motor_reverse(const T *M, const T *lam_in, const T *lam_m0, co
     const T ids = (T)inv_ds;
     // 16 bytes of the column per lane, as in the forward kernel
     constexpr int CPL = 16 / sizeof(T);
-    const int lpc = (ns >= 2 * CPL && ns % CPL == 0) ? ns / CPL : 0;
+    const int lpc = rev_lpc(ns, (int)sizeof(T));
 #define MMK_REV_CASE(LPC)                                                                                      \
     if (lpc == LPC)                                                                                            \
         return rev_cfg<T, CPL, LPC, false>(M, lam_in, lam_m0, lam_m1, lam_out, gpart, gblocks, ncol, ns, limiter, \

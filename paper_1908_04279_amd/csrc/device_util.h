@@ -17,6 +17,7 @@ enum : int {
     DPP_ROW_MIRROR = 0x140,      // lane i <- lane 15-i
     DPP_ROW_HALF_MIRROR = 0x141, // lane i <- lane 7-i within each half row
     DPP_WAVE_SHL1 = 0x130,       // lane i <- lane i+1 across the whole wave
+    DPP_WAVE_ROL1 = 0x134,       // lane i <- lane i+1, lane 63 <- lane 0
     DPP_WAVE_SHR1 = 0x138,       // lane i <- lane i-1 across the whole wave
     DPP_WAVE_ROR1 = 0x13C        // lane i <- lane i-1, lane 0 <- lane 63
 };

@@ -23,7 +23,7 @@ namespace {
 thread_local std::string g_create_error;
 constexpr int kMaxTheta = 512;
 constexpr int kMaxS = 512;
-constexpr int kProfIds = 5;
+constexpr int kProfIds = 6;
 constexpr int kProfMax = 65536;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -69,7 +69,8 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     const size_t e = esize(p);
     const size_t nm = (size_t)n_m(p), np = (size_t)n_psi(p), nxy = (size_t)p.nx * p.ny;
     const PsiLaunch pl = plan_psi(p.nx, p.ny, p.ntheta, e, 2);
-    L.psi_blocks = pl.blocks;
+    const WalkPlan wp = plan_walk(p.nx, p.ny, p.ntheta);
+    L.psi_blocks = wp.ok && wp.blocks > pl.blocks ? wp.blocks : pl.blocks;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -88,7 +89,7 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.stress = take(3 * nxy * e);
     L.mom = take(7 * nxy * e);
     L.tab = take(TAB_N * (size_t)p.ntheta * e);
-    L.partials = take((size_t)pl.blocks * 4 * sizeof(double));
+    L.partials = take((size_t)L.psi_blocks * 4 * sizeof(double));
     L.sums = take(4 * sizeof(double));
     off = tape_layout(&L.tape, off, nm, np, nxy, e, ckpt_every, max_tape_steps);
     L.total = off;
@@ -107,17 +108,19 @@ struct mmk_ctx {
     PsiLaunch pl{}, pl_rev{};
     int cur = 0;    // index of the current M / psi buffers
     int m0cur = 0;  // index of the m0 buffer that belongs to the current M
-    // overlap of the psi step of micro-step n with the motor step of n+1 (side stream, same
-    // default priority as every stream here).  Off by default: on MI355X the motor step alone
-    // saturates HBM and the overlapped order measured slower; MMK_OVERLAP=1 turns it on.
-    bool overlap = false;
-    hipStream_t side = nullptr;
-    hipEvent_t ev_motor = nullptr, ev_psi[2] = {nullptr, nullptr};
+    // ntheta = 64, 128: the psi step runs as the LDS-free walking kernel (default in FP32, where
+    // it measured as fast as the LDS-tiled one; in FP64 the LDS-tiled kernel is faster;
+    // MMK_PSI_WALK=0/1 overrides).  MMK_FUSE=1 (with the walking kernel) puts the psi step of
+    // micro-step n and the motor step of n+1 in one launch; off by default, it measured slower.
+    WalkPlan wp{};
+    bool walk = false, fuse = false;
     bool have_state = false, have_fluid = false, have_out = false;
     std::string err;
     bool prof = false;
+    int prof_every = 1;              // time every prof_every-th launch of each kernel id
+    int64_t seen[kProfIds] = {0, 0, 0, 0, 0, 0};
     std::vector<hipEvent_t> ev[kProfIds];  // start/stop pairs
-    int nev[kProfIds] = {0, 0, 0, 0, 0};
+    int nev[kProfIds] = {0, 0, 0, 0, 0, 0};
     TapeState tape;
     std::vector<double> host_tab64;  // host copies of the angle tables (outlive the async copy)
     std::vector<float> host_tab32;
@@ -154,6 +157,7 @@ static mmk_status hipfail(mmk_ctx *c, hipError_t e, const char *what) {
 static hipError_t prof_begin_on(mmk_ctx *c, int id, int *slot, hipStream_t s) {
     *slot = -1;
     if (!c->prof || c->nev[id] >= kProfMax) return hipSuccess;
+    if (c->seen[id]++ % c->prof_every != 0) return hipSuccess;
     int i = c->nev[id];
     while ((int)c->ev[id].size() < 2 * (i + 1)) {
         hipEvent_t e;
@@ -189,10 +193,16 @@ static mmk_status psi_half(mmk_ctx *c, const T *psi_in, T *psi_out, const T *m0,
                            const T *G, double dt, bool out, hipStream_t s) {
     int slot;
     HIPCHK(c, prof_begin_on(c, 1, &slot, s), "hipEventRecord");
-    HIPCHK(c, launch_psi_step<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab),
-                                 out ? c->at<T>(c->L.stress) : nullptr, out ? c->at<T>(c->L.mom) : nullptr,
-                                 out ? c->at<double>(c->L.partials) : nullptr, psi_const<T>(c->p, dt), c->pl, s),
-           "psi step launch");
+    T *stress = out ? c->at<T>(c->L.stress) : nullptr, *mom = out ? c->at<T>(c->L.mom) : nullptr;
+    double *part = out ? c->at<double>(c->L.partials) : nullptr;
+    if (c->walk)
+        HIPCHK(c, launch_psi_walk<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part,
+                                     psi_const<T>(c->p, dt), c->wp, s),
+               "psi step launch");
+    else
+        HIPCHK(c, launch_psi_step<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part,
+                                     psi_const<T>(c->p, dt), c->pl, s),
+               "psi step launch");
     HIPCHK(c, prof_end_on(c, 1, slot, s), "hipEventRecord");
     return MMK_OK;
 }
@@ -214,7 +224,8 @@ static mmk_status global_sums(mmk_ctx *c) {
     const double dx = p.lx / p.nx, dy = p.ly / p.ny, dth = kTwoPi / p.ntheta;
     int slot;
     HIPCHK(c, prof_begin(c, 2, &slot), "hipEventRecord");
-    HIPCHK(c, launch_reduce_partials(c->at<double>(c->L.partials), c->pl.blocks, c->at<double>(c->L.sums),
+    HIPCHK(c, launch_reduce_partials(c->at<double>(c->L.partials), c->walk ? c->wp.blocks : c->pl.blocks,
+                                     c->at<double>(c->L.sums),
                                      dx * dy * dth, dx * dy, c->stream),
            "global sums launch");
     HIPCHK(c, prof_end(c, 2, slot), "hipEventRecord");
@@ -240,38 +251,43 @@ static mmk_status run_steps_serial(mmk_ctx *c, int K, double dt) {
     return MMK_OK;
 }
 
-// Overlapped order: the psi step of micro-step n (side stream) runs beside the motor step of
-// n+1 (context stream); they touch different fields.  m0 is double-buffered: the motor step
-// n writes the buffer the psi step n-2 read, so it waits for that psi step only.  The
-// context stream waits for the last psi step before returning, so every later call sees
-// the finished state.
+// Fused order: launch 0 is the motor step of micro-step 0; launch n (1 <= n < K) holds the
+// motor step of n and the psi step of n-1; launch K is the psi step of K-1 with the outputs.
+// Motor step n reads M[n], writes M[n+1] and m0 buffer (n+1) & 1; the psi step n-1 of the
+// same launch reads the other m0 buffer, written by the previous launch.  Same arithmetic as
+// the serial order, so the same bits.
 template <typename T>
-static mmk_status run_steps_overlap(mmk_ctx *c, int K, double dt) {
-    for (int n = 0; n < K; ++n) {
-        const bool last = (n == K - 1);
-        const int a = c->cur, b = 1 - c->cur;
-        const int mb = c->m0cur ^ 1;
-        if (n >= 2) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_psi[n & 1], 0), "hipStreamWaitEvent");
-        T *m0 = c->at<T>(c->L.m0[mb]);
-        T *m1 = last ? c->at<T>(c->L.m1) : nullptr;
-        mmk_status st = motor_half<T>(c, c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), m0, m1, dt, c->stream);
-        if (st != MMK_OK) return st;
-        HIPCHK(c, hipEventRecord(c->ev_motor, c->stream), "hipEventRecord");
-        HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_motor, 0), "hipStreamWaitEvent");
-        st = psi_half<T>(c, c->at<T>(c->L.psi[a]), c->at<T>(c->L.psi[b]), m0, m1, c->at<T>(c->L.u),
-                         c->at<T>(c->L.G), dt, last, c->side);
-        if (st != MMK_OK) return st;
-        HIPCHK(c, hipEventRecord(c->ev_psi[n & 1], c->side), "hipEventRecord");
-        c->cur = b;
-        c->m0cur = mb;
+static mmk_status run_steps_fused(mmk_ctx *c, int K, double dt) {
+    const mmk_params &p = c->p;
+    const int A = c->cur, m0a = c->m0cur;
+    auto Mb = [&](int n) { return c->at<T>(c->L.M[(A + n) & 1]); };
+    auto Pb = [&](int n) { return c->at<T>(c->L.psi[(A + n) & 1]); };
+    auto m0b = [&](int n) { return c->at<T>(c->L.m0[(m0a + n) & 1]); };  // m0 of M[n]
+    T *m1 = c->at<T>(c->L.m1);
+    const T *u = c->at<T>(c->L.u), *G = c->at<T>(c->L.G);
+    mmk_status st = motor_half<T>(c, Mb(0), Mb(1), m0b(1), K == 1 ? m1 : nullptr, dt, c->stream);
+    if (st != MMK_OK) return st;
+    const MotorConst<T> mc = motor_const<T>(p, dt);
+    const PsiConst<T> pc = psi_const<T>(p, dt);
+    for (int n = 1; n < K; ++n) {
+        int slot;
+        HIPCHK(c, prof_begin(c, 5, &slot), "hipEventRecord");
+        HIPCHK(c, launch_step_fused<T>(Mb(n), Mb(n + 1), m0b(n + 1), n == K - 1 ? m1 : nullptr, n_psi(p), p.ns,
+                                       p.limiter, mc, Pb(n - 1), Pb(n), m0b(n), u, G, c->at<T>(c->L.tab), pc, c->wp,
+                                       c->stream),
+               "fused step launch");
+        HIPCHK(c, prof_end(c, 5, slot), "hipEventRecord");
     }
-    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_psi[(K - 1) & 1], 0), "hipStreamWaitEvent");
+    st = psi_half<T>(c, Pb(K - 1), Pb(K), m0b(K), m1, u, G, dt, true, c->stream);
+    if (st != MMK_OK) return st;
+    c->cur = (A + K) & 1;
+    c->m0cur = (m0a + K) & 1;
     return MMK_OK;
 }
 
 template <typename T>
 static mmk_status run_steps(mmk_ctx *c, int K, double dt) {
-    mmk_status st = (c->overlap && !c->tape.active) ? run_steps_overlap<T>(c, K, dt) : run_steps_serial<T>(c, K, dt);
+    mmk_status st = (c->fuse && !c->tape.active && K > 0) ? run_steps_fused<T>(c, K, dt) : run_steps_serial<T>(c, K, dt);
     if (st != MMK_OK) return st;
     if (K > 0) {
         c->have_out = true;
@@ -388,17 +404,10 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
         return hipfail(nullptr, e, "copy of angle tables");
     }
     tape_init(&c->tape, ckpt_every, ckpt_every > 0 ? max_tape_steps : 0);
-    if (const char *ov = getenv("MMK_OVERLAP")) c->overlap = atoi(ov) != 0;
-    if (c->overlap) {
-        e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_motor, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_psi[0], hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_psi[1], hipEventDisableTiming);
-        if (e != hipSuccess) {
-            mmk_destroy(c);
-            return hipfail(nullptr, e, "side stream / events");
-        }
-    }
+    c->wp = plan_walk(p->nx, p->ny, p->ntheta);
+    const char *ew = getenv("MMK_PSI_WALK"), *ef = getenv("MMK_FUSE");
+    c->walk = c->wp.ok && (ew ? atoi(ew) != 0 : c->esz == 4);
+    c->fuse = c->walk && fused_supported(p->ns, (int)c->esz, p->limiter, p->ntheta) && ef && atoi(ef) != 0;
     *out = c;
     return MMK_OK;
 }
@@ -406,13 +415,8 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
 mmk_status mmk_destroy(mmk_ctx *c) {
     if (!c) return MMK_ERR_ARG;
     (void)hipStreamSynchronize(c->stream);
-    if (c->side) (void)hipStreamSynchronize(c->side);
     for (int i = 0; i < kProfIds; ++i)
         for (hipEvent_t e : c->ev[i]) (void)hipEventDestroy(e);
-    if (c->ev_motor) (void)hipEventDestroy(c->ev_motor);
-    for (hipEvent_t e : c->ev_psi)
-        if (e) (void)hipEventDestroy(e);
-    if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
     return MMK_OK;
 }
@@ -548,8 +552,10 @@ mmk_status mmk_tape_end(mmk_ctx *c) {
 mmk_status mmk_profile(mmk_ctx *c, int32_t enable) {
     if (!c) return MMK_ERR_ARG;
     HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (enable < 0) return fail(c, MMK_ERR_ARG, "enable must be >= 0");
     c->prof = enable != 0;
-    for (int i = 0; i < kProfIds; ++i) c->nev[i] = 0;
+    c->prof_every = enable > 0 ? enable : 1;
+    for (int i = 0; i < kProfIds; ++i) c->nev[i] = 0, c->seen[i] = 0;
     return MMK_OK;
 }
 

@@ -13,8 +13,7 @@
 // output step are shuffles inside that group.  Tiles are banded per XCD so the halo
 // re-reads of neighbouring tiles hit the same L2.
 #include "adjoint.h"
-#include "device_util.h"
-#include "kernels.h"
+#include "psi_dev.h"
 
 #include <cstdio>
 #include <cstdlib>
@@ -28,9 +27,13 @@ static size_t psi_lds(int ti, int tj, int nth, size_t elem, int nf) {
 }
 
 // Tile choice: the largest of the candidate tiles whose LDS footprint stays <= 40 KB (so
-// several blocks share a CU), else <= 64 KB.  MMK_PSI_TILE=TIxTJ overrides (measurements).
+// several blocks share a CU), else <= 64 KB, that still gives at least kMinTiles blocks; a grid
+// too small for that takes the fitting compiled tile with the most blocks (latency, not
+// bandwidth, bounds such grids).  MMK_PSI_TILE=TIxTJ overrides (measurements).
+static constexpr int kMinTiles = 1024;
 PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem, int nf) {
     static const int cand[][2] = {{8, 8}, {4, 8}, {4, 4}, {2, 4}, {2, 2}, {1, 2}, {1, 1}};
+    static const int ncompiled = 4;  // the first four have compile-time kernels
     PsiLaunch pl{};
     pl.group = nth <= 16 ? 16 : (nth <= 32 ? 32 : 64);
     bool chosen = false;
@@ -43,15 +46,33 @@ PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem, int nf) {
             chosen = true;
         }
     }
+    auto ntiles = [&](int ti, int tj) { return (long)((nx + ti - 1) / ti) * ((ny + tj - 1) / tj); };
     for (size_t limit : {(size_t)40 * 1024, (size_t)64 * 1024}) {
         if (chosen) break;
-        for (auto &c : cand)
+        int small = -1;  // fitting compiled tile with the most blocks
+        for (int i = 0; i < ncompiled; ++i) {
+            if (psi_lds(cand[i][0], cand[i][1], nth, elem, nf) > limit) continue;
+            if (ntiles(cand[i][0], cand[i][1]) >= kMinTiles) {
+                pl.ti = cand[i][0];
+                pl.tj = cand[i][1];
+                chosen = true;
+                break;
+            }
+            small = i;
+        }
+        if (!chosen && small >= 0) {
+            pl.ti = cand[small][0];
+            pl.tj = cand[small][1];
+            chosen = true;
+        }
+        for (auto &c : cand) {
+            if (chosen) break;
             if (psi_lds(c[0], c[1], nth, elem, nf) <= limit) {
                 pl.ti = c[0];
                 pl.tj = c[1];
                 chosen = true;
-                break;
             }
+        }
     }
     if (!chosen) {
         pl.ti = 1;
@@ -65,52 +86,6 @@ PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem, int nf) {
     pl.blocks = 8 * per;
     return pl;
 }
-
-template <typename T>
-__device__ __forceinline__ T donor(T A, T left, T right) {
-    return (A >= T(0)) ? A * left : A * right;
-}
-
-template <typename T>
-__device__ __forceinline__ T shfl_xor_t(T v, int mask, int width) {
-    return __shfl_xor(v, mask, width);
-}
-
-// sum over the G lanes of a pencil group (G = 16, 32, 64), result in every lane
-template <typename T>
-__device__ __forceinline__ T group_total(T v, int G) {
-    for (int m = G / 2; m >= 1; m >>= 1) v += shfl_xor_t(v, m, G);
-    return v;
-}
-#pragma clang fp contract(off)
-template <typename T>
-__device__ __forceinline__ T group_total_comp(CSum<T> c, int G) {
-    T s = c.hi, e = c.lo;
-    for (int m = G / 2; m >= 1; m >>= 1) {
-        const T s2 = shfl_xor_t(s, m, G), e2 = shfl_xor_t(e, m, G);
-        T t, err;
-        two_sum(s, s2, t, err);
-        s = t;
-        e = e + e2 + err;
-    }
-    return s + e;
-}
-#pragma clang fp contract(on)
-
-template <typename T>
-struct Acc;  // theta accumulators: plain in FP64, compensated in FP32
-template <>
-struct Acc<double> {
-    double v = 0;
-    __device__ void add(double x) { v += x; }
-    __device__ double total(int G) const { return group_total(v, G); }
-};
-template <>
-struct Acc<float> {
-    CSum<float> c;
-    __device__ void add(float x) { c.add(x); }
-    __device__ float total(int G) const { return group_total_comp(c, G); }
-};
 
 // Per-lane constants of one orientation k: p, the two theta faces and the moment weights.
 template <typename T>
@@ -137,13 +112,6 @@ __device__ __forceinline__ AngleK<T> angle_k(const T *s_tab, int nth, int k) {
     a.cs = s_tab[TAB_CS * nth + k];
     a.ss = s_tab[TAB_SS * nth + k];
     return a;
-}
-
-// periodic index for i in [-1, n + 16): a halo index is off by at most one tile
-__device__ __forceinline__ int wrap(int i, int n) {
-    if (i < 0) i += n;
-    while (i >= n) i -= n;
-    return i;
 }
 
 // Stages NF fields of a TI x TJ tile plus its one-pencil halo (cross stencil: corner pencils
@@ -363,7 +331,11 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
             if (k < nth) ak[j] = angle_k(s_tab, nth, k);
         }
     }
-    double acc_mass = 0, acc_s0 = 0, acc_s1 = 0, acc_s2 = 0;
+    // FP64 block partials: mass on every lane; each stress component on the lanes that hold it
+    double acc_mass = 0, acc_sig = 0;
+    int lane_q = -1;
+    constexpr bool COMP = std::is_same<T, float>::value;
+    const int lane = tid % 64;
 
     // WALK (one wave per pencil): wave grp takes TJ/4 tile columns and walks each along x, so
     // the flux through a pencil's upper x-face is carried into the next pencil as its lower
@@ -395,9 +367,11 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
         const T uy_c = s_u[NH + q], uy_m = s_u[NH + qym], uy_p = s_u[NH + qyp];
         const T Gxx = s_G[p], Gxy = s_G[TI * TJ + p], Gyx = s_G[2 * TI * TJ + p], Gyy = s_G[3 * TI * TJ + p];
         const int64_t pen = (int64_t)gi * ny + gj;
-        Acc<T> a_c, a_nx, a_ny, a_dxx, a_dxy, a_dyy, a_b, a_sxx, a_sxy, a_syy;
+        T ms[NMOM], me[NMOM];  // this lane's theta partial sums of the moments (output steps)
+#pragma unroll
+        for (int m = 0; m < NMOM; ++m) ms[m] = me[m] = T(0);
 
-        auto cell = [&](const AngleK<T> &a, int slot) {
+        auto cell = [&](const AngleK<T> &a, int slot, bool first) {
             const int k = a.k;
             const T ps = s_psi[q * nth + k];
             const T mc = s_m0[q * nth + k];
@@ -437,53 +411,58 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
             psi_out[pen * nth + k] = pn;
             if (out) {
                 const T fm = c.F * m1[pen * nth + k];
-                a_c.add(pn);
-                a_nx.add(pn * a.co);
-                a_ny.add(pn * a.si);
-                a_dxx.add(pn * a.cc);
-                a_dxy.add(pn * a.cs);
-                a_dyy.add(pn * a.ss);
-                a_b.add(pn * mc);
-                a_sxx.add(pn * (c.sigma_f * a.h1 + fm * a.cc));
-                a_sxy.add(pn * (c.sigma_f * a.h2 + fm * a.cs));
-                a_syy.add(pn * (-c.sigma_f * a.h1 + fm * a.ss));
+                const T terms[NMOM] = {pn,
+                                       pn * a.co,
+                                       pn * a.si,
+                                       pn * a.cc,
+                                       pn * a.cs,
+                                       pn * a.ss,
+                                       pn * mc,
+                                       pn * (c.sigma_f * a.h1 + fm * a.cc),
+                                       pn * (c.sigma_f * a.h2 + fm * a.cs),
+                                       pn * (-c.sigma_f * a.h1 + fm * a.ss)};
+#pragma unroll
+                for (int m = 0; m < NMOM; ++m) mom_add<COMP>(ms[m], me[m], terms[m], first);
                 acc_mass += (double)pn;
             }
         };
         if constexpr (FIXED) {
 #pragma unroll
             for (int j = 0; j < KMAX; ++j)
-                if (kk + j * G < nth) cell(ak[j], j);
+                if (kk + j * G < nth) cell(ak[j], j, j == 0);
         } else {
-            for (int k = kk; k < nth; k += G) cell(angle_k(s_tab, nth, k), 0);
+            for (int k = kk; k < nth; k += G) cell(angle_k(s_tab, nth, k), 0, k == kk);
         }
         if (out) {
-            const T dth = c.dth;
-            const T v0 = a_c.total(G) * dth, v1 = a_nx.total(G) * dth, v2 = a_ny.total(G) * dth;
-            const T v3 = a_dxx.total(G) * dth, v4 = a_dxy.total(G) * dth, v5 = a_dyy.total(G) * dth;
-            const T v6 = a_b.total(G) * dth;
-            const T s0 = a_sxx.total(G) * dth, s1 = a_sxy.total(G) * dth, s2 = a_syy.total(G) * dth;
-            if (kk == 0) {
-                mom[0 * nxy + pen] = v0;
-                mom[1 * nxy + pen] = v1;
-                mom[2 * nxy + pen] = v2;
-                mom[3 * nxy + pen] = v3;
-                mom[4 * nxy + pen] = v4;
-                mom[5 * nxy + pen] = v5;
-                mom[6 * nxy + pen] = v6;
-                stress[0 * nxy + pen] = s0;
-                stress[1 * nxy + pen] = s1;
-                stress[2 * nxy + pen] = s2;
-                acc_s0 += (double)s0;
-                acc_s1 += (double)s1;
-                acc_s2 += (double)s2;
+            // one lane per quantity stores its total (moments 0..6, stress 7..9)
+            int qm;
+            T tot;
+            if constexpr (FIXED) {
+                tot = group_moments<(NTH_C <= 16 ? 16 : (NTH_C <= 32 ? 32 : 64)), COMP, KMAX == 1>(ms, me, lane, qm);
+            } else if (G == 64) {
+                tot = group_moments<64, COMP, false>(ms, me, lane, qm);
+            } else if (G == 32) {
+                tot = group_moments<32, COMP, false>(ms, me, lane, qm);
+            } else {
+                tot = group_moments<16, COMP, false>(ms, me, lane, qm);
+            }
+            if (qm >= 0) {
+                const T v = tot * c.dth;
+                if (qm < 7) {
+                    mom[qm * nxy + pen] = v;
+                } else {
+                    stress[(qm - 7) * nxy + pen] = v;
+                    acc_sig += (double)v;
+                }
+                lane_q = qm;
             }
         }
     }
 
     if (out) {
         // fixed-order block reduction of the FP64 partials: wave butterfly, then waves 0..3
-        double v[4] = {acc_mass, acc_s0, acc_s1, acc_s2};
+        double v[4] = {acc_mass, lane_q == 7 ? acc_sig : 0.0, lane_q == 8 ? acc_sig : 0.0,
+                       lane_q == 9 ? acc_sig : 0.0};
 #pragma unroll
         for (int a = 0; a < 4; ++a)
             for (int m = 32; m >= 1; m >>= 1) v[a] += __shfl_xor(v[a], m, 64);
@@ -672,18 +651,27 @@ template hipError_t launch_psi_reverse<double>(const double *, const double *, c
 #pragma clang fp contract(off)
 __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ partials, int n,
                                                           double *__restrict__ out, double s0, double s1) {
+    // thread t takes rows t, t + 256, ... (four independent compensated chains per thread),
+    // then a fixed-order TwoSum tree over the threads: the same bits on every run
     __shared__ double sh[4][256], se[4][256];
     const int t = threadIdx.x;
-    for (int a = 0; a < 4; ++a) {
-        double s = 0, e = 0;
-        for (int i = t; i < n; i += 256) {
-            double x = partials[(size_t)i * 4 + a], hi, lo;
-            two_sum(s, x, hi, lo);
-            s = hi;
-            e += lo;
+    double s[4] = {0, 0, 0, 0}, e[4] = {0, 0, 0, 0};
+    for (int i = t; i < n; i += 256) {
+        const double2 x01 = reinterpret_cast<const double2 *>(partials)[(size_t)i * 2];
+        const double2 x23 = reinterpret_cast<const double2 *>(partials)[(size_t)i * 2 + 1];
+        const double x[4] = {x01.x, x01.y, x23.x, x23.y};
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            double hi, lo;
+            two_sum(s[a], x[a], hi, lo);
+            s[a] = hi;
+            e[a] += lo;
         }
-        sh[a][t] = s;
-        se[a][t] = e;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        sh[a][t] = s[a];
+        se[a][t] = e[a];
     }
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {

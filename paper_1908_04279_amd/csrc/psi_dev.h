@@ -1,0 +1,299 @@
+// Device code of the filament-density (psi) step shared by the LDS-tiled psi kernels and the
+// walking psi step of the fused micro-step kernel: the donor-cell flux, the split butterfly
+// for the theta-moments, and the LDS-free walking tile.
+#pragma once
+#include "device_util.h"
+#include "kernels.h"
+
+#include <type_traits>
+
+namespace mmk {
+
+// first-order upwind (donor-cell) flux through a face with velocity A; A = 0 takes the left cell
+template <typename T>
+__device__ __forceinline__ T donor(T A, T left, T right) {
+    return (A >= T(0)) ? A * left : A * right;
+}
+
+// ---- theta-moments of a pencil: NMOM per-lane partial sums reduced over the G lanes ----
+// Quantities: c, n_x, n_y, D_xx, D_xy, D_yy, B (moments 0..6) and sigma_xx, sigma_xy,
+// sigma_yy (7..9).
+constexpr int NMOM = 10;
+
+// Value of the partner lane across lane bit B (the butterfly partner of level B; the mirror
+// forms inside a row pair lanes that differ in bit B, which is all the reduction needs).
+template <int B, typename T>
+__device__ __forceinline__ T xchg(T v) {
+    if constexpr (B == 0) return dpp<DPP_QUAD_XOR1>(v, v);
+    else if constexpr (B == 1) return dpp<DPP_QUAD_XOR2>(v, v);
+    else if constexpr (B == 2) return dpp<DPP_ROW_HALF_MIRROR>(v, v);
+    else if constexpr (B == 3) return dpp<DPP_ROW_MIRROR>(v, v);
+    else return __shfl_xor(v, 1 << B, 64);
+}
+
+// One level of the split butterfly over lane bit B with N quantities still open in s[0..N)
+// (FP32: e carries the compensation).  A lane with bit B clear keeps the lower H = ceil(N/2)
+// quantities, a lane with the bit set the upper ones (padded with a zero), and each adds its
+// partner's copy of what it keeps, so the work halves at every level.  Once one quantity is
+// left the remaining levels are a plain butterfly.  [off, end) tracks which quantities the
+// lane's slots hold; the summation order is fixed by the lane index (reproducible).
+#pragma clang fp contract(off)
+template <int B, int N, bool COMP, bool E0, typename T>
+__device__ __forceinline__ void split_level(T (&s)[NMOM], T (&e)[NMOM], int lane, int &off, int &end) {
+    if constexpr (B >= 0) {
+        constexpr int H = (N + 1) / 2;
+        const bool up = N >= 2 && ((lane >> B) & 1);
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const T ls = s[j], hs = (N >= 2 && j + H < N) ? s[j + H] : T(0);
+            const T ks = up ? hs : ls, ss = up ? ls : hs;
+            const T rs = xchg<B>(N >= 2 ? ss : ls);
+            if constexpr (COMP) {
+                T ke = T(0), re = T(0);
+                if constexpr (!E0) {
+                    const T le = e[j], he = (N >= 2 && j + H < N) ? e[j + H] : T(0);
+                    ke = up ? he : le;
+                    re = xchg<B>(N >= 2 ? (up ? le : he) : le);
+                }
+                T t, err;
+                two_sum(ks, rs, t, err);
+                s[j] = t;
+                e[j] = E0 ? err : (ke + re) + err;
+            } else {
+                s[j] = ks + rs;
+            }
+        }
+        if constexpr (N >= 2) {
+            if (up) off += H;
+            else end = min(end, off + H);
+        }
+        split_level<B - 1, H, COMP, false>(s, e, lane, off, end);
+    }
+}
+
+// Totals of the NMOM quantities over a group of G lanes.  Returns the total held by this lane
+// and sets q to its quantity, or -1 for a lane that holds none or a duplicate.
+template <int G, bool COMP, bool E0, typename T>
+__device__ __forceinline__ T group_moments(T (&s)[NMOM], T (&e)[NMOM], int lane, int &q) {
+    constexpr int LB = G == 64 ? 5 : (G == 32 ? 4 : 3);  // top lane bit of the group
+    int off = 0, end = NMOM;
+    split_level<LB, NMOM, COMP, E0>(s, e, lane, off, end);
+    // the split levels are the top four bits; below them every lane of a sub-group holds the
+    // same total, the one with those low bits clear stores it
+    constexpr int LOW = (1 << (LB - 3)) - 1;
+    q = (off < end && (lane & LOW) == 0) ? off : -1;
+    if constexpr (COMP) return s[0] + e[0];
+    else return s[0];
+}
+#pragma clang fp contract(on)
+
+// per-lane partial sum of one quantity: the first term sets it, later terms add (compensated
+// in FP32)
+#pragma clang fp contract(off)
+template <bool COMP, typename T>
+__device__ __forceinline__ void mom_add(T &s, T &e, T v, bool first) {
+    if (first) {
+        s = v;
+        e = T(0);
+    } else if constexpr (COMP) {
+        T t, err;
+        two_sum(s, v, t, err);
+        s = t;
+        e += err;
+    } else {
+        s += v;
+    }
+}
+#pragma clang fp contract(on)
+
+// periodic index for i in [-1, n + 16): a halo index is off by at most one tile
+__device__ __forceinline__ int wrap(int i, int n) {
+    if (i < 0) i += n;
+    while (i >= n) i -= n;
+    return i;
+}
+
+
+// ---- LDS-free psi step: one wave walks a row of pencils along x ----------------------------
+// For ntheta = 64 KPL a pencil is one wave (lane k holds orientations k, k + 64, ...).  A block
+// of four waves owns a tile of TI x 4 pencils; wave w walks the pencils (i0 .. i0+TI-1, j0+w)
+// in x order.  The upper x-face flux of a pencil is the lower one of the next (the face
+// velocity is the symmetric mean of its two cells, so the carried value equals the one the
+// next pencil would compute), the theta neighbours are wave rotations, and the x-, y-halo
+// pencils are plain loads that the neighbouring waves of the block and of the XCD-banded
+// neighbouring tiles also read, so they hit in the caches.  Without LDS the step can share a
+// launch (and a CU) with the motor step.  u and gradu are wave-uniform per pencil.
+//
+// Same flux and update expressions as the LDS-tiled kernel; OUT adds the theta-moments, the
+// stress and the FP64 block partials (mass, sum sigma) of the new state.
+template <typename T, int KPL, int TI, bool OUT>
+__device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *__restrict__ psi_out,
+                                              const T *__restrict__ m0, const T *__restrict__ m1,
+                                              const T *__restrict__ u, const T *__restrict__ Gr,
+                                              const T *__restrict__ tab, T *__restrict__ stress,
+                                              T *__restrict__ mom, double *__restrict__ partials,
+                                              const PsiConst<T> &c, int tiles_i, int tiles_j, int per,
+                                              int vblock) {
+    constexpr int NTH = 64 * KPL;
+    constexpr bool COMP = std::is_same<T, float>::value;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nx = c.nx, ny = c.ny;
+    const int64_t nxy = (int64_t)nx * ny;
+    // XCD banding as in the LDS-tiled kernel: virtual block v runs on XCD v % 8
+    const int tile = (vblock & 7) * per + (vblock >> 3);
+    double acc_mass = 0, acc_sig = 0;
+    int lane_q = -1;
+    const int j = (tile % tiles_j) * 4 + w;
+    if (tile < tiles_i * tiles_j && j < ny) {
+        const int i0 = (tile / tiles_j) * TI;
+        const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j + 1 == ny) ? 0 : j + 1;
+        T co[KPL], si[KPL], chp[KPL], shp[KPL];
+#pragma unroll
+        for (int s = 0; s < KPL; ++s) {
+            const int k = lane + 64 * s;
+            co[s] = tab[TAB_C * NTH + k];
+            si[s] = tab[TAB_S * NTH + k];
+            chp[s] = tab[TAB_CH * NTH + k];
+            shp[s] = tab[TAB_SH * NTH + k];
+        }
+        // centre cells of the first pencil and the flux through its lower x-face
+        T Pc[KPL], Mc[KPL], fxc[KPL];
+        const int64_t pc0 = (int64_t)i0 * ny + j;
+        T ux_c = u[pc0];
+        {
+            const int im = (i0 == 0) ? nx - 1 : i0 - 1;
+            const int64_t pm = (int64_t)im * ny + j;
+            const T ux_m = u[pm];
+#pragma unroll
+            for (int s = 0; s < KPL; ++s) {
+                const int k = lane + 64 * s;
+                const T Pm = psi_in[pm * NTH + k], Mm = m0[pm * NTH + k];
+                Pc[s] = psi_in[pc0 * NTH + k];
+                Mc[s] = m0[pc0 * NTH + k];
+                const T ax_m = ux_m - c.F * Mm * co[s];
+                const T ax_c = ux_c - c.F * Mc[s] * co[s];
+                const T Axm = T(0.5) * (ax_m + ax_c);
+                fxc[s] = donor(Axm, Pm, Pc[s]);
+            }
+        }
+#pragma unroll 1
+        for (int t = 0; t < TI; ++t) {
+            const int i = i0 + t;
+            if (i >= nx) break;
+            const int ip = (i + 1 == nx) ? 0 : i + 1;
+            const int64_t pc = (int64_t)i * ny + j, pxp = (int64_t)ip * ny + j;
+            const int64_t pym = (int64_t)i * ny + jm, pyp = (int64_t)i * ny + jp;
+            T Pxp[KPL], Mxp[KPL], Pym[KPL], Mym[KPL], Pyp[KPL], Myp[KPL];
+#pragma unroll
+            for (int s = 0; s < KPL; ++s) {
+                const int k = lane + 64 * s;
+                Pxp[s] = psi_in[pxp * NTH + k];
+                Mxp[s] = m0[pxp * NTH + k];
+                Pym[s] = psi_in[pym * NTH + k];
+                Mym[s] = m0[pym * NTH + k];
+                Pyp[s] = psi_in[pyp * NTH + k];
+                Myp[s] = m0[pyp * NTH + k];
+            }
+            const T ux_p = u[pxp];
+            const T uy_c = u[nxy + pc], uy_m = u[nxy + pym], uy_p = u[nxy + pyp];
+            const T Gxx = Gr[pc], Gxy = Gr[nxy + pc], Gyx = Gr[2 * nxy + pc], Gyy = Gr[3 * nxy + pc];
+            // psi at orientation k+1: lane k+1, or lane 0 of the next slot for lane 63
+            T rp[KPL];
+#pragma unroll
+            for (int s = 0; s < KPL; ++s) rp[s] = dpp_any<DPP_WAVE_ROL1>(Pc[s]);
+            T fxp[KPL], fxm[KPL], fyp[KPL], fym[KPL], ftp[KPL];
+#pragma unroll
+            for (int s = 0; s < KPL; ++s) {
+                const T Pkp = (KPL == 1 || lane != 63) ? rp[s] : rp[(s + 1) % KPL];
+                const T ax_c = ux_c - c.F * Mc[s] * co[s];
+                const T ax_p = ux_p - c.F * Mxp[s] * co[s];
+                const T Axp = T(0.5) * (ax_c + ax_p);
+                fxp[s] = donor(Axp, Pc[s], Pxp[s]);
+                fxm[s] = fxc[s];
+                fxc[s] = fxp[s];
+                const T ay_c = uy_c - c.F * Mc[s] * si[s];
+                const T ay_m = uy_m - c.F * Mym[s] * si[s];
+                const T ay_p = uy_p - c.F * Myp[s] * si[s];
+                const T Ayp = T(0.5) * (ay_c + ay_p), Aym = T(0.5) * (ay_m + ay_c);
+                fyp[s] = donor(Ayp, Pc[s], Pyp[s]);
+                fym[s] = donor(Aym, Pym[s], Pc[s]);
+                const T wp = -shp[s] * (Gxx * chp[s] + Gxy * shp[s]) + chp[s] * (Gyx * chp[s] + Gyy * shp[s]);
+                ftp[s] = donor(wp, Pc[s], Pkp);
+            }
+            // flux through the lower theta face: lane k-1's upper one (lane 63 of the previous
+            // slot for lane 0)
+            T rm[KPL];
+#pragma unroll
+            for (int s = 0; s < KPL; ++s) rm[s] = dpp_any<DPP_WAVE_ROR1>(ftp[s]);
+            T ms[NMOM], me[NMOM];
+#pragma unroll
+            for (int m = 0; m < NMOM; ++m) ms[m] = me[m] = T(0);
+#pragma unroll
+            for (int s = 0; s < KPL; ++s) {
+                const int k = lane + 64 * s;
+                const T ftm = (KPL == 1 || lane != 0) ? rm[s] : rm[(s + KPL - 1) % KPL];
+                const T div = (fxp[s] - fxm[s]) * c.inv_dx + (fyp[s] - fym[s]) * c.inv_dy + (ftp[s] - ftm) * c.inv_dth;
+                const T pn = Pc[s] - c.dt * div;
+                psi_out[pc * NTH + k] = pn;
+                if constexpr (OUT) {
+                    const T fm = c.F * m1[pc * NTH + k];
+                    const T cc = tab[TAB_CC * NTH + k], cs = tab[TAB_CS * NTH + k], ss = tab[TAB_SS * NTH + k];
+                    const T h1 = tab[TAB_H1 * NTH + k], h2 = tab[TAB_H2 * NTH + k];
+                    const T terms[NMOM] = {pn,
+                                           pn * co[s],
+                                           pn * si[s],
+                                           pn * cc,
+                                           pn * cs,
+                                           pn * ss,
+                                           pn * Mc[s],
+                                           pn * (c.sigma_f * h1 + fm * cc),
+                                           pn * (c.sigma_f * h2 + fm * cs),
+                                           pn * (-c.sigma_f * h1 + fm * ss)};
+#pragma unroll
+                    for (int m = 0; m < NMOM; ++m) mom_add<COMP>(ms[m], me[m], terms[m], s == 0);
+                    acc_mass += (double)pn;
+                }
+            }
+            if constexpr (OUT) {
+                int qm;
+                const T tot = group_moments<64, COMP, KPL == 1>(ms, me, lane, qm);
+                if (qm >= 0) {
+                    const T v = tot * c.dth;
+                    if (qm < 7) {
+                        mom[qm * nxy + pc] = v;
+                    } else {
+                        stress[(qm - 7) * nxy + pc] = v;
+                        acc_sig += (double)v;
+                    }
+                    lane_q = qm;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < KPL; ++s) {
+                Pc[s] = Pxp[s];
+                Mc[s] = Mxp[s];
+            }
+            ux_c = ux_p;
+        }
+    }
+    if constexpr (OUT) {
+        // fixed-order block sum of the FP64 partials: wave butterfly, then waves 0..3
+        __shared__ double red[4][4];
+        double v[4] = {acc_mass, lane_q == 7 ? acc_sig : 0.0, lane_q == 8 ? acc_sig : 0.0,
+                       lane_q == 9 ? acc_sig : 0.0};
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            for (int m = 32; m >= 1; m >>= 1) v[a] += __shfl_xor(v[a], m, 64);
+        if (lane == 0)
+            for (int a = 0; a < 4; ++a) red[w][a] = v[a];
+        __syncthreads();
+        if (tid < 4) {
+            double sum = 0;
+            for (int q = 0; q < 4; ++q) sum += red[q][tid];
+            partials[(size_t)vblock * 4 + tid] = sum;
+        }
+    }
+}
+
+}  // namespace mmk

@@ -37,7 +37,7 @@ size_t tape_layout(TapeLayout *t, size_t off, size_t nm, size_t np, size_t nxy, 
     t->lam_m0 = take(t->psi_bytes);
     t->lam_m1 = take(t->psi_bytes);
     t->fluid = take(t->fluid_bytes * t->nfluid);
-    t->gpart_blocks = 2048;
+    t->gpart_blocks = (int)motor_reverse_blocks((int64_t)np, (int)(nm / np), (int)e);
     t->gpart = take((size_t)t->gpart_blocks * 4 * sizeof(double));
     t->gsum = take(4 * sizeof(double));
     return off;

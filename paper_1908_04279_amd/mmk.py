@@ -21,7 +21,7 @@ MMK_OK, MMK_ERR_ARG, MMK_ERR_NOMEM, MMK_ERR_HIP, MMK_ERR_STATE, MMK_ERR_UNSUPPOR
 FP64, FP32 = 0, 1
 SUPERBEE, UPWIND1 = 0, 1
 KERNEL_IDS = {"motor_step": 0, "psi_step": 1, "global_sums": 2, "psi_step_reverse": 3,
-              "motor_step_reverse": 4}
+              "motor_step_reverse": 4, "step_fused": 5}
 
 EXPORTS = ["mmk_workspace_bytes", "mmk_create", "mmk_destroy", "mmk_set_params", "mmk_set_state",
            "mmk_set_fluid", "mmk_step", "mmk_get_state", "mmk_get_stress", "mmk_get_moments",
@@ -222,8 +222,9 @@ class Context:
     def tape_end(self):
         self._check(lib().mmk_tape_end(self.h))
 
-    def profile(self, enable=True):
-        self._check(lib().mmk_profile(self.h, 1 if enable else 0))
+    def profile(self, enable=True, every=1):
+        """Time every `every`-th launch of each kernel with HIP events (enable=False: off)."""
+        self._check(lib().mmk_profile(self.h, int(every) if enable else 0))
 
     def profile_read(self, kernel):
         kid = KERNEL_IDS[kernel] if isinstance(kernel, str) else int(kernel)
