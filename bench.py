@@ -28,14 +28,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "micro-steps/s + HBM GB/s (% peak), FP32 vs FP64 at 256²×64×64; adjoint/fwd ratio"
 CSRC = os.path.join(ROOT, "paper_1908_04279_amd", "csrc")
-# rocprofv3 HBM byte counters of the dominant kernel, and the sources that kernel is built from
-# (the counters count only while those sources are unchanged)
-COUNTERS = {
-    "fused": (os.path.join(ROOT, "profiles", "fused_step_f32_256x256x64x64_counters.txt"),
-              ["fused.hip", "motor_dev.h", "psi_dev.h", "device_util.h", "kernels.h"]),
-    "motor": (os.path.join(ROOT, "profiles", "motor_step_f32_256x256x64x64_counters.txt"),
-              ["motor.hip", "motor_dev.h", "device_util.h", "kernels.h"]),
-}
+# rocprofv3 HBM byte counters of the motor kernel, and the sources it is built from (the
+# counters count only while those sources are unchanged)
+COUNTERS = (os.path.join(ROOT, "profiles", "motor_step_f32_256x256x64x64_counters.txt"),
+            ["motor.hip", "device_util.h", "kernels.h"])
+# kernel launches bracketed by HIP events inside the timed region: every EVENT_EVERY-th launch
+# of each kernel (an event pair on every launch costs ~14 us per micro-step on MI355X, ~4%)
+EVENT_EVERY = 13
 
 
 def log(*a):
@@ -101,13 +100,13 @@ def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1):
     elapsed = t1 - t0
     prof = {}
     if profile:
-        for name in ("motor_step", "psi_step", "global_sums", "step_fused"):
+        for name in ("motor_step", "psi_step", "global_sums"):
             ms, n = ctx.profile_read(name)
             prof[name] = (ms, n)
         ctx.profile(False)
     mass, ss = ctx.get_sums()
     ctx.close()
-    return dict(elapsed=elapsed, steps=steps, dt=dt, prof=prof, mass=mass)
+    return dict(elapsed=elapsed, steps=steps, dt=dt, prof=prof, mass=mass, event_every=event_every)
 
 
 def run_adjoint(name, precision):
@@ -143,7 +142,8 @@ def run_adjoint(name, precision):
         return ctx.get_stress()
 
     out = {}
-    for rep in range(2):       # the first pair is a warm-up
+    # pair 0: warm-up; pair 1: timed (no events); pair 2: HIP events on every reverse launch
+    for rep in range(3):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sigma = forward()
@@ -151,7 +151,7 @@ def run_adjoint(name, precision):
         t1 = time.perf_counter()
         d = sigma - target
         g_sigma = torch.stack([d[0], 2 * d[1], d[2]]) / torch.sqrt((d[0] ** 2 + 2 * d[1] ** 2 + d[2] ** 2).sum())
-        if rep == 1:
+        if rep == 2:
             ctx.profile(True)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -159,7 +159,8 @@ def run_adjoint(name, precision):
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         ctx.tape_end()
-        out = dict(forward_s=t1 - t0, backward_s=t3 - t2, g_params=g_par)
+        if rep == 1:
+            out = dict(forward_s=t1 - t0, backward_s=t3 - t2, g_params=g_par)
     ms_r, n_r = ctx.profile_read("motor_step_reverse")
     ms_p, n_p = ctx.profile_read("psi_step_reverse")
     b = 4 if precision == mmk.FP32 else 8
@@ -194,11 +195,11 @@ def sources_sha(files):
     return h.hexdigest()[:16]
 
 
-def counters_traffic(kind, n_plain, n_out):
-    """HBM bytes per launch of the dominant kernel (weighted like `achieved`: n_plain launches
-    without and n_out with the m1 output) from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on different kernel sources."""
-    path, files = COUNTERS[kind]
+def counters_traffic(n_plain, n_out):
+    """HBM bytes per motor launch (weighted like `achieved`: n_plain launches without and
+    n_out with the m1 output) from the committed rocprofv3 counter summary, or None when it
+    is missing or was taken on different kernel sources."""
+    path, files = COUNTERS
     if not os.path.exists(path):
         return None
     kv = {}
@@ -246,8 +247,8 @@ def main():
     ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64"], default="all",
                     help="restrict to one leg (used for profiler runs)")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--event-every", type=int, default=1,
-                    help="bracket every N-th kernel launch with HIP events (measurements of the event cost)")
+    ap.add_argument("--event-every", type=int, default=EVENT_EVERY,
+                    help="bracket every N-th launch of each kernel with HIP events")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -280,31 +281,21 @@ def main():
                                   event_every=args.event_every)
 
     def summarise(r, b):
-        """Whole-step rate and the roofline of the kernel that carries the motor stream: the
-        fused launch (motor step n+1 with psi step n) when the run used it, else the motor
-        step.  Per call of K steps: one motor launch, K-1 fused launches (the last with the
-        m1 output), one psi launch with the outputs; unfused: K motor + K psi launches."""
+        """Whole-step rate, and the motor kernel's roofline over its timed launches.  Launch j
+        of a kernel in the timed region (one per micro-step) is an output launch (m1, stress,
+        moments) when j % K == K - 1; launches j = 0, E, 2E, ... carry HIP events."""
         calls = r["steps"] // K
         sps = r["steps"] / r["elapsed"]
         total = (r["steps"] - calls) * step_bytes(p, b, False) + calls * step_bytes(p, b, True)
-        ms_f, n_f = r["prof"]["step_fused"]
+        timed = list(range(0, r["steps"], r["event_every"]))
+        n_out = sum(1 for j in timed if j % K == K - 1)
         ms_m, n_m = r["prof"]["motor_step"]
         ms_p, n_p = r["prof"]["psi_step"]
-        if n_f > 0:
-            kind, ms, n = "fused", ms_f, n_f
-            n_out = calls if K >= 2 else 0
-            per = lambda m1: motor_bytes(p, b, m1) + psi_bytes(p, b, False)
-            name = "fused launch: motor step n+1 + psi step n (LDS-free walk)"
-        else:
-            kind, ms, n = "motor", ms_m, n_m
-            n_out = calls
-            per = lambda m1: motor_bytes(p, b, m1)
-            name = "motor column step"
-        kb = ((n - n_out) * per(False) + n_out * per(True)) / max(n, 1)
-        return dict(steps_per_s=sps, step_gbs=total / r["elapsed"] / 1e9, kind=kind, kernel=name,
-                    avg_us=ms / n * 1e3, gbs=kb / (ms / n / 1e3) / 1e9, bytes_per_launch=kb,
-                    n_plain=n - n_out, n_out=n_out, motor_avg_us=ms_m / max(n_m, 1) * 1e3,
-                    psi_avg_us=ms_p / max(n_p, 1) * 1e3, launches=n_f + n_m + n_p, mass=r["mass"])
+        assert n_m == len(timed) and n_p == len(timed), (n_m, n_p, len(timed))
+        kb = ((n_m - n_out) * motor_bytes(p, b, False) + n_out * motor_bytes(p, b, True)) / n_m
+        return dict(steps_per_s=sps, step_gbs=total / r["elapsed"] / 1e9, avg_us=ms_m / n_m * 1e3,
+                    gbs=kb / (ms_m / n_m / 1e3) / 1e9, bytes_per_launch=kb, n_plain=n_m - n_out,
+                    n_out=n_out, psi_avg_us=ms_p / n_p * 1e3, timed_launches=n_m, mass=r["mass"])
 
     out = {"metric": METRIC, "unit": "micro-steps/s", "n_gpus": 1, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
@@ -317,20 +308,20 @@ def main():
                                    f"{'FP32' if main_leg == 'fp32' else 'FP64'}, fluid exchange every 10 steps",
                        "nx": p.nx, "ny": p.ny, "ntheta": p.ntheta, "ns": p.ns,
                        "motor_cells": p.nx * p.ny * p.ntheta * p.ns, "K": K})
-    traffic = counters_traffic(s["kind"], s["n_plain"], s["n_out"]) if main_leg == "fp32" else None
+    traffic = counters_traffic(s["n_plain"], s["n_out"]) if main_leg == "fp32" else None
     out["roofline"] = {"bound": "hbm", "achieved": s["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": s["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                       "kernel": s["kernel"], "avg_launch_us": s["avg_us"],
-                       "algorithmic_bytes_per_launch": s["bytes_per_launch"]}
+                       "kernel": "motor column step", "avg_launch_us": s["avg_us"],
+                       "algorithmic_bytes_per_launch": s["bytes_per_launch"],
+                       "timed_launches": s["timed_launches"], "output_launches_timed": s["n_out"]}
     out["step_hbm_gbs"] = s["step_gbs"]
     out["step_hbm_frac"] = s["step_gbs"] / HBM_PEAK_GBS
-    out["launches_per_step"] = s["launches"] / res[main_leg]["steps"]
     out["psi_step_avg_us"] = s["psi_avg_us"]
     if "fp32" in res and "fp64" in res:
         s64 = summarise(res["fp64"], 8)
         out["fp64"] = {"micro_steps_per_s": s64["steps_per_s"], "ms_per_step": 1e3 / s64["steps_per_s"],
-                       "step_hbm_gbs": s64["step_gbs"], "kernel": s64["kernel"], "kernel_gbs": s64["gbs"],
-                       "kernel_frac": s64["gbs"] / HBM_PEAK_GBS, "kernel_avg_us": s64["avg_us"],
+                       "step_hbm_gbs": s64["step_gbs"], "motor_gbs": s64["gbs"],
+                       "motor_frac": s64["gbs"] / HBM_PEAK_GBS, "motor_avg_us": s64["avg_us"],
                        "steps": res["fp64"]["steps"]}
         out["fp32_over_fp64"] = s["steps_per_s"] / s64["steps_per_s"]
     out["adjoint_over_forward"] = None

@@ -95,10 +95,7 @@ mmk_status mmk_set_fluid(mmk_ctx *ctx, const void *u, const void *gradu);
 
 /* Runs K >= 0 micro-steps of size dt (finite, > 0), motors first then Psi driven by the new
  * m0.  The last step also computes stress, moments and the FP64 global sums.  No host sync.
- * Two launches per micro-step; with MMK_FUSE=1 in the environment at mmk_create (ntheta = 64
- * or 128, superbee, ns = 16 .. 128, untaped runs) K+1 launches: the psi step of micro-step n
- * shares a launch with the motor step of n+1 (the motor field does not depend on Psi), with
- * the same bits as the two-launch order. */
+ * Two kernel launches per micro-step (motor, then psi). */
 mmk_status mmk_step(mmk_ctx *ctx, int32_t K, double dt);
 
 /* Copies the current state out (either pointer may be NULL). */
@@ -128,9 +125,8 @@ mmk_status mmk_tape_end(mmk_ctx *ctx);
 /* Kernel timing: with enable = N > 0 every N-th launch of each kernel is bracketed by HIP
  * events on the context's stream (enable = 0 turns timing off, < 0 is MMK_ERR_ARG).
  * mmk_profile_read (synchronizes) sums the elapsed times of the timed launches of `kernel_id`
- * (0 motor step, 1 psi step, 2 global sums, 3 reverse psi step, 4 reverse motor step,
- * 5 fused launch: motor step of micro-step n+1 with the psi step of n) since profiling was
- * enabled; up to 65536 launches per id are timed. */
+ * (0 motor step, 1 psi step, 2 global sums, 3 reverse psi step, 4 reverse motor step) since
+ * profiling was enabled; up to 65536 launches per id are timed. */
 mmk_status mmk_profile(mmk_ctx *ctx, int32_t enable);
 mmk_status mmk_profile_read(mmk_ctx *ctx, int32_t kernel_id, double *total_ms, int64_t *launches);
 

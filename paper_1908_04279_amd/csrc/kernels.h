@@ -21,10 +21,6 @@ template <typename T>
 hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                              int limiter, const MotorConst<T> &c, hipStream_t s);
 
-// Lanes per column of the exact (unmasked, unchunked) tiling launch_motor_step uses for this
-// column length and element size, 0 if it uses another kernel; *nt: nontemporal M access.
-int motor_plain_lpc(int ns, int elem, bool *nt);
-
 // Geometry and constants of the filament-density step.
 template <typename T>
 struct PsiConst {
@@ -68,18 +64,6 @@ template <typename T>
 hipError_t launch_psi_walk(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u, const T *G,
                            const T *tab, T *stress, T *mom, double *partials, const PsiConst<T> &c,
                            const WalkPlan &wp, hipStream_t s);
-
-// One launch holding the motor step of micro-step n+1 (M_in -> M_out, m0_new, m1 if non-null)
-// and the psi step of micro-step n (psi_in -> psi_out with m0_cur, no moments); the two touch
-// disjoint buffers.  Returns hipErrorInvalidValue (nothing launched) for a configuration
-// without a fused kernel: limiter != 0, a column length or tiling without one, or
-// motor_plain_lpc() == 0.
-template <typename T>
-hipError_t launch_step_fused(const T *M_in, T *M_out, T *m0_new, T *m1, int64_t ncol, int ns, int limiter,
-                             const MotorConst<T> &mc, const T *psi_in, T *psi_out, const T *m0_cur, const T *u,
-                             const T *G, const T *tab, const PsiConst<T> &pc, const WalkPlan &wp, hipStream_t s);
-// true if launch_step_fused has a kernel for this configuration
-bool fused_supported(int ns, int elem, int limiter, int nth);
 
 // Fixed-order compensated FP64 sum of partials[n][4] -> out[4] * scale[4].
 hipError_t launch_reduce_partials(const double *partials, int n, double *out, double s0,

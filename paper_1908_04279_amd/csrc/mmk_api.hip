@@ -23,13 +23,13 @@ namespace {
 thread_local std::string g_create_error;
 constexpr int kMaxTheta = 512;
 constexpr int kMaxS = 512;
-constexpr int kProfIds = 6;
+constexpr int kProfIds = 5;
 constexpr int kProfMax = 65536;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t M[2], psi[2], m0[2], m1, u, G, stress, mom, tab, partials, sums;
+    size_t M[2], psi[2], m0, m1, u, G, stress, mom, tab, partials, sums;
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -81,8 +81,7 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.M[1] = take(nm * e);
     L.psi[0] = take(np * e);
     L.psi[1] = take(np * e);
-    L.m0[0] = take(np * e);
-    L.m0[1] = take(np * e);
+    L.m0 = take(np * e);
     L.m1 = take(np * e);
     L.u = take(2 * nxy * e);
     L.G = take(4 * nxy * e);
@@ -107,20 +106,18 @@ struct mmk_ctx {
     Layout L{};
     PsiLaunch pl{}, pl_rev{};
     int cur = 0;    // index of the current M / psi buffers
-    int m0cur = 0;  // index of the m0 buffer that belongs to the current M
     // ntheta = 64, 128: the psi step runs as the LDS-free walking kernel (default in FP32, where
     // it measured as fast as the LDS-tiled one; in FP64 the LDS-tiled kernel is faster;
-    // MMK_PSI_WALK=0/1 overrides).  MMK_FUSE=1 (with the walking kernel) puts the psi step of
-    // micro-step n and the motor step of n+1 in one launch; off by default, it measured slower.
+    // MMK_PSI_WALK=0/1 overrides)
     WalkPlan wp{};
-    bool walk = false, fuse = false;
+    bool walk = false;
     bool have_state = false, have_fluid = false, have_out = false;
     std::string err;
     bool prof = false;
     int prof_every = 1;              // time every prof_every-th launch of each kernel id
-    int64_t seen[kProfIds] = {0, 0, 0, 0, 0, 0};
+    int64_t seen[kProfIds] = {0, 0, 0, 0, 0};
     std::vector<hipEvent_t> ev[kProfIds];  // start/stop pairs
-    int nev[kProfIds] = {0, 0, 0, 0, 0, 0};
+    int nev[kProfIds] = {0, 0, 0, 0, 0};
     TapeState tape;
     std::vector<double> host_tab64;  // host copies of the angle tables (outlive the async copy)
     std::vector<float> host_tab32;
@@ -241,7 +238,7 @@ static mmk_status run_steps_serial(mmk_ctx *c, int K, double dt) {
         mmk_status st = tape_before_step(c, &c->tape, dt);
         if (st != MMK_OK) return st;
         st = micro_step<T>(c, c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), c->at<T>(c->L.psi[a]),
-                           c->at<T>(c->L.psi[b]), c->at<T>(c->L.m0[c->m0cur]), c->at<T>(c->L.u), c->at<T>(c->L.G),
+                           c->at<T>(c->L.psi[b]), c->at<T>(c->L.m0), c->at<T>(c->L.u), c->at<T>(c->L.G),
                            dt, last);
         if (st != MMK_OK) return st;
         c->cur = b;
@@ -251,43 +248,9 @@ static mmk_status run_steps_serial(mmk_ctx *c, int K, double dt) {
     return MMK_OK;
 }
 
-// Fused order: launch 0 is the motor step of micro-step 0; launch n (1 <= n < K) holds the
-// motor step of n and the psi step of n-1; launch K is the psi step of K-1 with the outputs.
-// Motor step n reads M[n], writes M[n+1] and m0 buffer (n+1) & 1; the psi step n-1 of the
-// same launch reads the other m0 buffer, written by the previous launch.  Same arithmetic as
-// the serial order, so the same bits.
-template <typename T>
-static mmk_status run_steps_fused(mmk_ctx *c, int K, double dt) {
-    const mmk_params &p = c->p;
-    const int A = c->cur, m0a = c->m0cur;
-    auto Mb = [&](int n) { return c->at<T>(c->L.M[(A + n) & 1]); };
-    auto Pb = [&](int n) { return c->at<T>(c->L.psi[(A + n) & 1]); };
-    auto m0b = [&](int n) { return c->at<T>(c->L.m0[(m0a + n) & 1]); };  // m0 of M[n]
-    T *m1 = c->at<T>(c->L.m1);
-    const T *u = c->at<T>(c->L.u), *G = c->at<T>(c->L.G);
-    mmk_status st = motor_half<T>(c, Mb(0), Mb(1), m0b(1), K == 1 ? m1 : nullptr, dt, c->stream);
-    if (st != MMK_OK) return st;
-    const MotorConst<T> mc = motor_const<T>(p, dt);
-    const PsiConst<T> pc = psi_const<T>(p, dt);
-    for (int n = 1; n < K; ++n) {
-        int slot;
-        HIPCHK(c, prof_begin(c, 5, &slot), "hipEventRecord");
-        HIPCHK(c, launch_step_fused<T>(Mb(n), Mb(n + 1), m0b(n + 1), n == K - 1 ? m1 : nullptr, n_psi(p), p.ns,
-                                       p.limiter, mc, Pb(n - 1), Pb(n), m0b(n), u, G, c->at<T>(c->L.tab), pc, c->wp,
-                                       c->stream),
-               "fused step launch");
-        HIPCHK(c, prof_end(c, 5, slot), "hipEventRecord");
-    }
-    st = psi_half<T>(c, Pb(K - 1), Pb(K), m0b(K), m1, u, G, dt, true, c->stream);
-    if (st != MMK_OK) return st;
-    c->cur = (A + K) & 1;
-    c->m0cur = (m0a + K) & 1;
-    return MMK_OK;
-}
-
 template <typename T>
 static mmk_status run_steps(mmk_ctx *c, int K, double dt) {
-    mmk_status st = (c->fuse && !c->tape.active && K > 0) ? run_steps_fused<T>(c, K, dt) : run_steps_serial<T>(c, K, dt);
+    mmk_status st = run_steps_serial<T>(c, K, dt);
     if (st != MMK_OK) return st;
     if (K > 0) {
         c->have_out = true;
@@ -307,7 +270,7 @@ void *ctx_cur_M(const mmk_ctx *c) { return c->ws + c->L.M[c->cur]; }
 void *ctx_cur_psi(const mmk_ctx *c) { return c->ws + c->L.psi[c->cur]; }
 void *ctx_fluid_u(const mmk_ctx *c) { return c->ws + c->L.u; }
 void *ctx_fluid_G(const mmk_ctx *c) { return c->ws + c->L.G; }
-void *ctx_m0(const mmk_ctx *c) { return c->ws + c->L.m0[c->m0cur]; }
+void *ctx_m0(const mmk_ctx *c) { return c->ws + c->L.m0; }
 void *ctx_m1(const mmk_ctx *c) { return c->ws + c->L.m1; }
 void *ctx_tab(const mmk_ctx *c) { return c->ws + c->L.tab; }
 const PsiLaunch &ctx_psi_launch(const mmk_ctx *c) { return c->pl; }
@@ -405,9 +368,8 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     }
     tape_init(&c->tape, ckpt_every, ckpt_every > 0 ? max_tape_steps : 0);
     c->wp = plan_walk(p->nx, p->ny, p->ntheta);
-    const char *ew = getenv("MMK_PSI_WALK"), *ef = getenv("MMK_FUSE");
+    const char *ew = getenv("MMK_PSI_WALK");
     c->walk = c->wp.ok && (ew ? atoi(ew) != 0 : c->esz == 4);
-    c->fuse = c->walk && fused_supported(p->ns, (int)c->esz, p->limiter, p->ntheta) && ef && atoi(ef) != 0;
     *out = c;
     return MMK_OK;
 }
@@ -510,7 +472,7 @@ mmk_status mmk_get_motor_moments(mmk_ctx *c, void *m0, void *m1) {
     if (!c->have_out) return fail(c, MMK_ERR_STATE, "no outputs: run mmk_step with K > 0 first");
     const size_t np = (size_t)n_psi(c->p) * c->esz;
     if (m0)
-        HIPCHK(c, hipMemcpyAsync(m0, c->ws + c->L.m0[c->m0cur], np, hipMemcpyDeviceToDevice, c->stream), "copy of m0");
+        HIPCHK(c, hipMemcpyAsync(m0, c->ws + c->L.m0, np, hipMemcpyDeviceToDevice, c->stream), "copy of m0");
     if (m1) HIPCHK(c, hipMemcpyAsync(m1, c->ws + c->L.m1, np, hipMemcpyDeviceToDevice, c->stream), "copy of m1");
     return MMK_OK;
 }

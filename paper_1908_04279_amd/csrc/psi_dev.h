@@ -1,6 +1,6 @@
 // Device code of the filament-density (psi) step shared by the LDS-tiled psi kernels and the
-// walking psi step of the fused micro-step kernel: the donor-cell flux, the split butterfly
-// for the theta-moments, and the LDS-free walking tile.
+// LDS-free walking psi kernel: the donor-cell flux, the split butterfly for the
+// theta-moments, and the walking tile.
 #pragma once
 #include "device_util.h"
 #include "kernels.h"
@@ -121,8 +121,8 @@ __device__ __forceinline__ int wrap(int i, int n) {
 // velocity is the symmetric mean of its two cells, so the carried value equals the one the
 // next pencil would compute), the theta neighbours are wave rotations, and the x-, y-halo
 // pencils are plain loads that the neighbouring waves of the block and of the XCD-banded
-// neighbouring tiles also read, so they hit in the caches.  Without LDS the step can share a
-// launch (and a CU) with the motor step.  u and gradu are wave-uniform per pencil.
+// neighbouring tiles also read, so they hit in the caches.  u and gradu are wave-uniform per
+// pencil.
 //
 // Same flux and update expressions as the LDS-tiled kernel; OUT adds the theta-moments, the
 // stress and the FP64 block partials (mass, sum sigma) of the new state.

@@ -1,0 +1,55 @@
+// The LDS-free walking psi kernel for gfx950 (the tile walk itself is psi_walk_tile in
+// psi_dev.h): tiles of 8 x 4 pencils, one wave per row of 8 pencils, XCD-banded blocks.
+#include "psi_dev.h"
+
+namespace mmk {
+
+WalkPlan plan_walk(int nx, int ny, int nth) {
+    WalkPlan w{};
+    if (nth != 64 && nth != 128) return w;
+    w.ok = 1;
+    w.kpl = nth / 64;
+    w.ti = 8;
+    w.tiles_i = (nx + w.ti - 1) / w.ti;
+    w.tiles_j = (ny + 3) / 4;
+    w.per = (w.tiles_i * w.tiles_j + 7) / 8;
+    w.blocks = 8 * w.per;
+    return w;
+}
+
+template <typename T, int KPL, int TI, bool OUT>
+__global__ __launch_bounds__(256) void k_psi_walk(const T *__restrict__ psi_in, T *__restrict__ psi_out,
+                                                  const T *__restrict__ m0, const T *__restrict__ m1,
+                                                  const T *__restrict__ u, const T *__restrict__ G,
+                                                  const T *__restrict__ tab, T *__restrict__ stress,
+                                                  T *__restrict__ mom, double *__restrict__ partials,
+                                                  PsiConst<T> c, int tiles_i, int tiles_j, int per) {
+    psi_walk_tile<T, KPL, TI, OUT>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, c, tiles_i, tiles_j,
+                                   per, (int)blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_psi_walk(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u, const T *G,
+                           const T *tab, T *stress, T *mom, double *partials, const PsiConst<T> &c,
+                           const WalkPlan &wp, hipStream_t s) {
+    if (!wp.ok || wp.ti != 8) return hipErrorInvalidValue;
+    const bool out = stress != nullptr;
+#define MMK_WALK(KPL, OUT)                                                                                  \
+    hipLaunchKernelGGL((k_psi_walk<T, KPL, 8, OUT>), dim3(wp.blocks), dim3(256), 0, s, psi_in, psi_out, m0, m1, u, \
+                       G, tab, stress, mom, partials, c, wp.tiles_i, wp.tiles_j, wp.per)
+    if (wp.kpl == 1) {
+        if (out) MMK_WALK(1, true); else MMK_WALK(1, false);
+    } else {
+        if (out) MMK_WALK(2, true); else MMK_WALK(2, false);
+    }
+#undef MMK_WALK
+    return hipGetLastError();
+}
+template hipError_t launch_psi_walk<float>(const float *, float *, const float *, const float *, const float *,
+                                           const float *, const float *, float *, float *, double *,
+                                           const PsiConst<float> &, const WalkPlan &, hipStream_t);
+template hipError_t launch_psi_walk<double>(const double *, double *, const double *, const double *,
+                                            const double *, const double *, const double *, double *, double *,
+                                            double *, const PsiConst<double> &, const WalkPlan &, hipStream_t);
+
+}  // namespace mmk

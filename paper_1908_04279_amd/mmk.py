@@ -21,7 +21,7 @@ MMK_OK, MMK_ERR_ARG, MMK_ERR_NOMEM, MMK_ERR_HIP, MMK_ERR_STATE, MMK_ERR_UNSUPPOR
 FP64, FP32 = 0, 1
 SUPERBEE, UPWIND1 = 0, 1
 KERNEL_IDS = {"motor_step": 0, "psi_step": 1, "global_sums": 2, "psi_step_reverse": 3,
-              "motor_step_reverse": 4, "step_fused": 5}
+              "motor_step_reverse": 4}
 
 EXPORTS = ["mmk_workspace_bytes", "mmk_create", "mmk_destroy", "mmk_set_params", "mmk_set_state",
            "mmk_set_fluid", "mmk_step", "mmk_get_state", "mmk_get_stress", "mmk_get_moments",
