@@ -123,6 +123,15 @@ struct KahanT {
 };
 using Kahan = KahanT<float>;
 
+// One Kahan step on a (sum, comp) pair held in registers.
+template <typename T>
+__device__ __forceinline__ void kahan_add(T &sum, T &comp, T x) {
+    const T y = x - comp;
+    const T t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+}
+
 // Compensated butterfly over the G lanes of a group, starting from a Kahan pair
 // (value = s - e).  Every lane of the group gets the total.
 template <int G, typename T>
@@ -150,6 +159,39 @@ __device__ __forceinline__ T group_sum_comp(T s, T kahan_comp) {
     if constexpr (G >= 32) cross(16);
     if constexpr (G >= 64) cross(32);
     return s + e;
+}
+
+// Value of the partner lane across the top bit of a group of G lanes (G = 2 .. 64).
+template <int G, typename T>
+__device__ __forceinline__ T top_xchg(T v) {
+    if constexpr (G == 2) return dpp<DPP_QUAD_XOR1>(v, v);
+    else if constexpr (G == 4) return dpp<DPP_QUAD_XOR2>(v, v);
+    else if constexpr (G == 8) return dpp<DPP_ROW_HALF_MIRROR>(v, v);
+    else if constexpr (G == 16) return dpp<DPP_ROW_MIRROR>(v, v);
+    else return __shfl_xor(v, G / 2, 64);
+}
+
+// Totals of two per-lane quantities q0, q1 over a group of G lanes (G a power of two, 2 .. 64).
+// The top level hands q0 to the lower half of the group and q1 to the upper half, each lane
+// adding its partner's copy; the remaining levels are a butterfly inside each half.  Lane g of
+// the group returns the total of q0 (g < G/2) or q1 (g >= G/2).  COMP (FP32): the inputs are
+// Kahan pairs (value = sum - comp) and every level is a TwoSum with the errors carried along;
+// otherwise plain sums.  PAIR = false reduces q0 alone in the same order (every lane ends with
+// the q0 total, the same bits as lane 0 of the paired form).
+template <int G, bool COMP, bool PAIR, typename T>
+__device__ __forceinline__ T group_sum_pair(T s0, T c0, T s1, T c1, int g) {
+    const bool up = PAIR && (g & (G / 2)) != 0;
+    const T ks = up ? s1 : s0, ss = PAIR ? (up ? s0 : s1) : s0;
+    const T rs = top_xchg<G>(ss);
+    if constexpr (COMP) {
+        const T ke = up ? -c1 : -c0, se = PAIR ? (up ? -c0 : -c1) : -c0;
+        const T re = top_xchg<G>(se);
+        T t, err;
+        two_sum(ks, rs, t, err);
+        return group_sum_comp<G / 2>(t, -((ke + re) + err));
+    } else {
+        return group_sum<G / 2>(ks + rs);
+    }
 }
 #pragma clang fp contract(on)
 

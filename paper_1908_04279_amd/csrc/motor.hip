@@ -112,38 +112,33 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     }
 
     // s-moments of the new column: m0 = ds sum M, m1 = ds^2 sum (l + 1/2 - ns/2) M, the
-    // weights being exact half-integers.  FP32: Kahan inside the lane, TwoSum butterfly.
-    if constexpr (std::is_same<T, float>::value) {
-        Kahan a0, a1;
+    // weights being exact half-integers.  FP32: Kahan inside the lane, TwoSum butterfly.  On
+    // output steps one paired butterfly serves both: lane 0 of the group ends with m0, lane
+    // LPC/2 with m1; m0 has the same bits on every step.
+    constexpr bool COMP = std::is_same<T, float>::value;
+    const T wb = T(0.5) * (T)(2 * l0 + 1 - ns);  // weight of this lane's first cell
+    T a0s = T(0), a0c = T(0), a1s = T(0), a1c = T(0);
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-            const bool in = !RAGGED || (l0 + j < ns);
-            const float v = in ? y[j] : 0.0f;
-            a0.add(v);
-            if constexpr (WANT_M1) a1.add(v * (0.5f * (float)(2 * (l0 + j) + 1 - ns)));
-        }
-        const float s0 = group_sum_comp<LPC>(a0.sum, a0.comp);
-        if (active && g == 0) m0[col] = s0 * c.ds;
-        if constexpr (WANT_M1) {
-            const float s1 = group_sum_comp<LPC>(a1.sum, a1.comp);
-            if (active && g == 0) m1[col] = s1 * c.ds2;
-        }
-    } else {
-        T a0 = 0, a1 = 0;
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-            const bool in = !RAGGED || (l0 + j < ns);
-            const T v = in ? y[j] : T(0);
-            a0 += v;
-            if constexpr (WANT_M1) a1 += v * (T(0.5) * (T)(2 * (l0 + j) + 1 - ns));
-        }
-        const T s0 = group_sum<LPC>(a0);
-        if (active && g == 0) m0[col] = s0 * c.ds;
-        if constexpr (WANT_M1) {
-            const T s1 = group_sum<LPC>(a1);
-            if (active && g == 0) m1[col] = s1 * c.ds2;
+    for (int j = 0; j < CPL; ++j) {
+        const bool in = !RAGGED || (l0 + j < ns);
+        const T v = in ? y[j] : T(0);
+        if constexpr (COMP) {
+            if (j == 0) {
+                a0s = v;
+                if constexpr (WANT_M1) a1s = v * wb;
+            } else {
+                kahan_add(a0s, a0c, v);
+                if constexpr (WANT_M1) kahan_add(a1s, a1c, v * (wb + T(j)));
+            }
+        } else {
+            a0s += v;
+            if constexpr (WANT_M1) a1s += v * (wb + T(j));
         }
     }
+    const T tot = group_sum_pair<LPC, COMP, WANT_M1>(a0s, a0c, a1s, a1c, g);
+    if (active && g == 0) m0[col] = tot * c.ds;
+    if constexpr (WANT_M1)
+        if (active && g == LPC / 2) m1[col] = tot * c.ds2;
 }
 
 // ---------------------------------------------------------------------------------------
