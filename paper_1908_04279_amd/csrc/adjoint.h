@@ -6,8 +6,8 @@ namespace mmk {
 
 // lam_out = (dM'/dM)^T lam', lam' = lam_in (NULL = 0) + lam_m0 ds + lam_m1 (s - L/2) ds
 // (lam_m1 may be NULL); adds this step's k_on, k_off, v0 gradient terms to gpart[block][0..2].
-// The grid has motor_reverse_blocks(ncol, ns, sizeof(T)) blocks; gblocks (rows of gpart) must
-// be at least that (hipErrorInvalidValue otherwise, nothing launched).
+// The grid is the device's resident block count, at most gblocks (rows of gpart) and at most
+// one block per chunk of columns; motor_reverse_blocks() bounds it for sizing gpart.
 template <typename T>
 hipError_t launch_motor_reverse(const T *M, const T *lam_in, const T *lam_m0, const T *lam_m1, T *lam_out,
                                 double *gpart, int gblocks, int64_t ncol, int ns, int limiter,
@@ -27,7 +27,7 @@ hipError_t launch_seed(const T *g_sigma, const T *g_mom, const T *psi, const T *
 
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 
-// grid size of launch_motor_reverse
+// upper bound of the grid of launch_motor_reverse (rows of gpart it may touch)
 int64_t motor_reverse_blocks(int64_t ncol, int ns, int elem);
 
 }  // namespace mmk

@@ -14,6 +14,7 @@
 #include "adjoint.h"
 #include "device_util.h"
 
+#include <mutex>
 #include <type_traits>
 
 namespace mmk {
@@ -51,7 +52,7 @@ struct Faces {
 // Limiter branches and face values h of a column state z (this lane's CPL cells).
 template <typename T, int CPL, int LPC, int LIM, bool RAGGED>
 __device__ __forceinline__ void faces(const T (&z)[CPL], Faces<T, CPL> &f, int g, int l0, int ns) {
-    const T zl = from_prev<LPC>(z[CPL - 1], T(0), g);
+    const T zl = from_prev0<LPC>(z[CPL - 1], g);
     const T zr = from_next<LPC>(z[0], z[CPL - 1], g);
     T d[CPL + 1];
     d[0] = z[0] - zl;
@@ -73,7 +74,7 @@ __device__ __forceinline__ void faces(const T (&z)[CPL], Faces<T, CPL> &f, int g
         }
         f.h[j] = z[j] + T(0.5) * (f.ca[j] * d[j] + f.cb[j] * d[j + 1]);
     }
-    f.hl = from_prev<LPC>(f.h[CPL - 1], T(0), g);
+    f.hl = from_prev0<LPC>(f.h[CPL - 1], g);
 }
 
 // out = (dR/dz)^T mu at the state with faces f, and the parameter terms of mu . R(z):
@@ -90,12 +91,12 @@ __device__ __forceinline__ void rhs_vjp(const T (&z)[CPL], const Faces<T, CPL> &
         s_koff -= mu[j] * z[j];
         s_v0 -= mu[j] * (f.h[j] - (j == 0 ? f.hl : f.h[j - 1]));
     }
-    const T mu_next = from_next<LPC>(mu[0], T(0), g);  // mu_{ns} = 0
+    const T mu_next = from_next0<LPC>(mu[0], g);  // mu_{ns} = 0
     T nu[CPL];
 #pragma unroll
     for (int j = 0; j < CPL; ++j) nu[j] = v0_ds * ((j + 1 < CPL ? mu[j + 1] : mu_next) - mu[j]);
-    const T cbnu_prev = from_prev<LPC>(f.cb[CPL - 1] * nu[CPL - 1], T(0), g);
-    const T canu_next = from_next<LPC>(f.ca[0] * nu[0], T(0), g);
+    const T cbnu_prev = from_prev0<LPC>(f.cb[CPL - 1] * nu[CPL - 1], g);
+    const T canu_next = from_next0<LPC>(f.ca[0] * nu[0], g);
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
         const T left = (j == 0) ? cbnu_prev : f.cb[j - 1] * nu[j - 1];
@@ -113,39 +114,52 @@ __global__ __launch_bounds__(256) void k_motor_reverse(const T *__restrict__ M, 
     const int g = threadIdx.x % LPC;
     const int l0 = g * CPL;
     RevAcc acc;
-    for (int64_t col0 = (int64_t)blockIdx.x * COLS; col0 < ncol; col0 += (int64_t)gridDim.x * COLS) {
+    // inputs of one chunk of COLS columns: M, lam' (NULL = 0) and the column cotangents
+    struct Chunk {
+        T x[CPL], lam[CPL], a0, a1;
+    };
+    auto load_chunk = [&](int64_t col0, Chunk &ch) {
         const int64_t col = col0 + threadIdx.x / LPC;
         const bool active = col < ncol;
         const int64_t base = col * (int64_t)ns + l0;
-        T x[CPL], lam[CPL];
-        const T a0 = active ? lam_m0[col] * c.ds : T(0);
-        const T a1 = (active && lam_m1) ? lam_m1[col] * c.ds2 : T(0);
+        ch.a0 = active ? lam_m0[col] * c.ds : T(0);
+        ch.a1 = (active && lam_m1) ? lam_m1[col] * c.ds2 : T(0);
         if constexpr (!RAGGED) {
             if (active) {
-                load_cells<T, CPL, false>(M + base, x);
+                load_cells<T, CPL, false>(M + base, ch.x);
                 if (lam_in) {
-                    load_cells<T, CPL, false>(lam_in + base, lam);
+                    load_cells<T, CPL, false>(lam_in + base, ch.lam);
                 } else {
 #pragma unroll
-                    for (int j = 0; j < CPL; ++j) lam[j] = T(0);
+                    for (int j = 0; j < CPL; ++j) ch.lam[j] = T(0);
                 }
             } else {
 #pragma unroll
-                for (int j = 0; j < CPL; ++j) x[j] = lam[j] = T(0);
+                for (int j = 0; j < CPL; ++j) ch.x[j] = ch.lam[j] = T(0);
             }
         } else {
 #pragma unroll
             for (int j = 0; j < CPL; ++j) {
                 const bool in = active && l0 + j < ns;
-                x[j] = in ? M[base + j] : T(0);
-                lam[j] = (in && lam_in) ? lam_in[base + j] : T(0);
+                ch.x[j] = in ? M[base + j] : T(0);
+                ch.lam[j] = (in && lam_in) ? lam_in[base + j] : T(0);
             }
         }
+    };
+    // one chunk: recompute the midpoint stage and both stages' limiter branches, then the
+    // transposed stages; parameter terms go to this thread's FP64 accumulators
+    auto process = [&](const Chunk &cur, int64_t col0) {
+        const int64_t col = col0 + threadIdx.x / LPC;
+        const bool active = col < ncol;
+        const int64_t base = col * (int64_t)ns + l0;
+        T lam[CPL];
+        const T(&x)[CPL] = cur.x;
+        const T a0 = cur.a0, a1 = cur.a1;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
             const bool in = active && (!RAGGED || l0 + j < ns);
             const T w = T(0.5) * (T)(2 * (l0 + j) + 1 - ns);  // (s_l - L/2) / ds
-            lam[j] = in ? lam[j] + a0 + a1 * w : T(0);
+            lam[j] = in ? cur.lam[j] + a0 + a1 * w : T(0);
         }
         // recompute the midpoint stage; the faces of x serve the recompute and the first stage
         Faces<T, CPL> fx, fy;
@@ -179,6 +193,21 @@ __global__ __launch_bounds__(256) void k_motor_reverse(const T *__restrict__ M, 
         acc.kon += (double)s_kon;
         acc.koff += (double)s_koff;
         acc.v0 += (double)s_v0 * (double)inv_ds;
+    };
+    // grid-stride over chunks, two register sets: the next chunk's loads are in flight while
+    // this chunk computes
+    const int64_t stride = (int64_t)gridDim.x * COLS;
+    Chunk A, B;
+    int64_t col0 = (int64_t)blockIdx.x * COLS;
+    load_chunk(col0, A);
+    while (col0 < ncol) {
+        if (col0 + stride < ncol) load_chunk(col0 + stride, B);
+        process(A, col0);
+        col0 += stride;
+        if (col0 >= ncol) break;
+        if (col0 + stride < ncol) load_chunk(col0 + stride, A);
+        process(B, col0);
+        col0 += stride;
     }
     // fixed-order block sum, added to this block's running FP64 partials
     __shared__ double red[4][3];
@@ -197,16 +226,51 @@ __global__ __launch_bounds__(256) void k_motor_reverse(const T *__restrict__ M, 
     }
 }
 
+// Blocks of 256 threads of `kern` the current device runs at once (occupancy x CUs), cached
+// per device and kernel.
+static hipError_t resident_blocks(const void *kern, int *out) {
+    struct Entry {
+        int dev;
+        const void *kern;
+        int blocks;
+    };
+    static Entry cache[64];
+    static int n = 0;
+    static std::mutex mu;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < n; ++i)
+        if (cache[i].dev == dev && cache[i].kern == kern) {
+            *out = cache[i].blocks;
+            return hipSuccess;
+        }
+    int cus = 0, per = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 256, 0);
+    if (e != hipSuccess) return e;
+    *out = per * cus > 0 ? per * cus : 1;
+    if (n < 64) cache[n++] = Entry{dev, kern, *out};
+    return hipSuccess;
+}
+
 template <typename T, int CPL, int LPC, bool RAGGED>
 static hipError_t rev_cfg(const T *M, const T *lam_in, const T *lam_m0, const T *lam_m1, T *lam_out,
                           double *gpart, int gblocks, int64_t ncol, int ns, int limiter, const MotorConst<T> &c,
                           T inv_ds, hipStream_t s) {
     constexpr int COLS = 256 / LPC;
-    // one block per COLS columns (no grid-stride loop: the dispatcher balances the blocks);
-    // each block owns its row of gpart, so the FP64 accumulation across steps is race-free
-    const int64_t blocks = (ncol + COLS - 1) / COLS;
-    if (blocks < 1) return hipSuccess;
-    if (blocks > gblocks || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    // persistent grid: as many blocks as the device holds at once (at most gblocks), each
+    // owning its row of gpart, so the FP64 accumulation across steps is race-free
+    const int64_t chunks = (ncol + COLS - 1) / COLS;
+    if (chunks < 1) return hipSuccess;
+    const void *kern = limiter == 0 ? reinterpret_cast<const void *>(&k_motor_reverse<T, CPL, LPC, 0, RAGGED>)
+                                    : reinterpret_cast<const void *>(&k_motor_reverse<T, CPL, LPC, 1, RAGGED>);
+    int res = 0;
+    hipError_t e = resident_blocks(kern, &res);
+    if (e != hipSuccess) return e;
+    int64_t blocks = chunks < res ? chunks : res;
+    if (blocks > gblocks) blocks = gblocks;
     if (limiter == 0)
         hipLaunchKernelGGL((k_motor_reverse<T, CPL, LPC, 0, RAGGED>), dim3((unsigned)blocks), dim3(256), 0, s, M,
                            lam_in, lam_m0, lam_m1, lam_out, gpart, ncol, ns, c, inv_ds);
@@ -215,6 +279,10 @@ static hipError_t rev_cfg(const T *M, const T *lam_in, const T *lam_m0, const T 
                            lam_in, lam_m0, lam_m1, lam_out, gpart, ncol, ns, c, inv_ds);
     return hipGetLastError();
 }
+
+// Upper bound of the persistent reverse grid (a device holds at most 8 blocks of 256 threads
+// per CU; MI355X has 256 CUs).
+static constexpr int64_t kRevMaxBlocks = 2048;
 
 // Lanes per column of the reverse tiling: 16 bytes of the column per lane as in the forward
 // kernel, or 0 for the masked 16-lane kernel of other lengths.
@@ -227,7 +295,8 @@ static int rev_lpc(int ns, int elem) {
 int64_t motor_reverse_blocks(int64_t ncol, int ns, int elem) {
     const int lpc = rev_lpc(ns, elem);
     const int cols = 256 / (lpc ? lpc : 16);
-    return (ncol + cols - 1) / cols;
+    const int64_t chunks = (ncol + cols - 1) / cols;
+    return chunks < kRevMaxBlocks ? chunks : kRevMaxBlocks;
 }
 
 template <typename T>

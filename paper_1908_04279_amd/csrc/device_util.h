@@ -54,34 +54,62 @@ __device__ __forceinline__ double dpp_any(double v) {
 // Lane moves inside groups of G consecutive lanes (G a power of two, 1 .. 64; a group of up to
 // 16 lanes sits inside one DPP row, larger groups use the wave-wide shifts).  from_prev: value
 // of lane g-1 of the group, `edge` on lane 0.  from_next: value of lane g+1, `edge` on lane G-1.
+// A group that fills its row (16) or the wave (64) gets the edge from the DPP old value;
+// smaller groups select it (the shift would read the neighbouring group there).
 template <int G, typename T>
 __device__ __forceinline__ T from_prev(T v, T edge, int g) {
     if constexpr (G == 1) {
         return edge;
+    } else if constexpr (G == 16 || G == 64) {
+        return dpp<(G == 16 ? DPP_ROW_SHR1 : DPP_WAVE_SHR1)>(v, edge);
     } else {
-        T r = dpp<(G <= 16 ? DPP_ROW_SHR1 : DPP_WAVE_SHR1)>(v, edge);
-        if constexpr (G != 16 && G != 64) r = (g == 0) ? edge : r;
-        return r;
+        const T r = dpp_any<(G < 16 ? DPP_ROW_SHR1 : DPP_WAVE_SHR1)>(v);
+        return (g == 0) ? edge : r;
     }
 }
 template <int G, typename T>
 __device__ __forceinline__ T from_next(T v, T edge, int g) {
     if constexpr (G == 1) {
         return edge;
+    } else if constexpr (G == 16 || G == 64) {
+        return dpp<(G == 16 ? DPP_ROW_SHL1 : DPP_WAVE_SHL1)>(v, edge);
     } else {
-        T r = dpp<(G <= 16 ? DPP_ROW_SHL1 : DPP_WAVE_SHL1)>(v, edge);
-        if constexpr (G != 16 && G != 64) r = (g == G - 1) ? edge : r;
-        return r;
+        const T r = dpp_any<(G < 16 ? DPP_ROW_SHL1 : DPP_WAVE_SHL1)>(v);
+        return (g == G - 1) ? edge : r;
+    }
+}
+// The same with a zero edge: a full row or wave takes the zero that a shift with bound_ctrl
+// writes where its source lane is outside the row, with no register holding the old value.
+template <int G, typename T>
+__device__ __forceinline__ T from_prev0(T v, int g) {
+    if constexpr (G == 1) {
+        return T(0);
+    } else if constexpr (G == 16 || G == 64) {
+        return dpp_any<(G == 16 ? DPP_ROW_SHR1 : DPP_WAVE_SHR1)>(v);
+    } else {
+        const T r = dpp_any<(G < 16 ? DPP_ROW_SHR1 : DPP_WAVE_SHR1)>(v);
+        return (g == 0) ? T(0) : r;
+    }
+}
+template <int G, typename T>
+__device__ __forceinline__ T from_next0(T v, int g) {
+    if constexpr (G == 1) {
+        return T(0);
+    } else if constexpr (G == 16 || G == 64) {
+        return dpp_any<(G == 16 ? DPP_ROW_SHL1 : DPP_WAVE_SHL1)>(v);
+    } else {
+        const T r = dpp_any<(G < 16 ? DPP_ROW_SHL1 : DPP_WAVE_SHL1)>(v);
+        return (g == G - 1) ? T(0) : r;
     }
 }
 
 // Sum over the G lanes of a group (butterfly); every lane of the group gets the total.
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
-    if constexpr (G >= 2) v += dpp<DPP_QUAD_XOR1>(v, v);
-    if constexpr (G >= 4) v += dpp<DPP_QUAD_XOR2>(v, v);
-    if constexpr (G >= 8) v += dpp<DPP_ROW_HALF_MIRROR>(v, v);
-    if constexpr (G >= 16) v += dpp<DPP_ROW_MIRROR>(v, v);
+    if constexpr (G >= 2) v += dpp_any<DPP_QUAD_XOR1>(v);
+    if constexpr (G >= 4) v += dpp_any<DPP_QUAD_XOR2>(v);
+    if constexpr (G >= 8) v += dpp_any<DPP_ROW_HALF_MIRROR>(v);
+    if constexpr (G >= 16) v += dpp_any<DPP_ROW_MIRROR>(v);
     if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
     if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
     return v;
@@ -139,7 +167,7 @@ __device__ __forceinline__ T group_sum_comp(T s, T kahan_comp) {
     T e = -kahan_comp;
     auto level = [&](auto tag) {
         constexpr int CTRL = decltype(tag)::value;
-        T s2 = dpp<CTRL>(s, s), e2 = dpp<CTRL>(e, e);
+        T s2 = dpp_any<CTRL>(s), e2 = dpp_any<CTRL>(e);
         T t, err;
         two_sum(s, s2, t, err);
         s = t;
@@ -164,10 +192,10 @@ __device__ __forceinline__ T group_sum_comp(T s, T kahan_comp) {
 // Value of the partner lane across the top bit of a group of G lanes (G = 2 .. 64).
 template <int G, typename T>
 __device__ __forceinline__ T top_xchg(T v) {
-    if constexpr (G == 2) return dpp<DPP_QUAD_XOR1>(v, v);
-    else if constexpr (G == 4) return dpp<DPP_QUAD_XOR2>(v, v);
-    else if constexpr (G == 8) return dpp<DPP_ROW_HALF_MIRROR>(v, v);
-    else if constexpr (G == 16) return dpp<DPP_ROW_MIRROR>(v, v);
+    if constexpr (G == 2) return dpp_any<DPP_QUAD_XOR1>(v);
+    else if constexpr (G == 4) return dpp_any<DPP_QUAD_XOR2>(v);
+    else if constexpr (G == 8) return dpp_any<DPP_ROW_HALF_MIRROR>(v);
+    else if constexpr (G == 16) return dpp_any<DPP_ROW_MIRROR>(v);
     else return __shfl_xor(v, G / 2, 64);
 }
 

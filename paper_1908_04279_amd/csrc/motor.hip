@@ -44,7 +44,7 @@ __device__ __forceinline__ float superbee<float>(float a, float b) {
 template <typename T, int CPL, int LPC, int LIM, bool RAGGED>
 __device__ __forceinline__ void motor_rhs(const T (&z)[CPL], T (&R)[CPL], const MotorConst<T> &c,
                                           int g, int l0, int ns) {
-    const T zl = from_prev<LPC>(z[CPL - 1], T(0), g);        // z_{l0-1}; ghost 0 at s = 0
+    const T zl = from_prev0<LPC>(z[CPL - 1], g);             // z_{l0-1}; ghost 0 at s = 0
     const T zr = from_next<LPC>(z[0], z[CPL - 1], g);        // z_{l0+CPL}; ghost at s = L
     T d[CPL + 1];                                             // d[j] = z_{l0+j} - z_{l0+j-1}
     d[0] = z[0] - zl;
@@ -63,7 +63,7 @@ __device__ __forceinline__ void motor_rhs(const T (&z)[CPL], T (&R)[CPL], const 
         const T sig = (LIM == 0) ? superbee(d[j], d[j + 1]) : T(0);
         h[j] = z[j] + T(0.5) * sig;
     }
-    const T hl = from_prev<LPC>(h[CPL - 1], T(0), g);        // h_{-1} = 0: no influx
+    const T hl = from_prev0<LPC>(h[CPL - 1], g);             // h_{-1} = 0: no influx
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
         const T left = (j == 0) ? hl : h[j - 1];

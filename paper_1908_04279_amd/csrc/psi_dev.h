@@ -24,10 +24,10 @@ constexpr int NMOM = 10;
 // forms inside a row pair lanes that differ in bit B, which is all the reduction needs).
 template <int B, typename T>
 __device__ __forceinline__ T xchg(T v) {
-    if constexpr (B == 0) return dpp<DPP_QUAD_XOR1>(v, v);
-    else if constexpr (B == 1) return dpp<DPP_QUAD_XOR2>(v, v);
-    else if constexpr (B == 2) return dpp<DPP_ROW_HALF_MIRROR>(v, v);
-    else if constexpr (B == 3) return dpp<DPP_ROW_MIRROR>(v, v);
+    if constexpr (B == 0) return dpp_any<DPP_QUAD_XOR1>(v);
+    else if constexpr (B == 1) return dpp_any<DPP_QUAD_XOR2>(v);
+    else if constexpr (B == 2) return dpp_any<DPP_ROW_HALF_MIRROR>(v);
+    else if constexpr (B == 3) return dpp_any<DPP_ROW_MIRROR>(v);
     else return __shfl_xor(v, 1 << B, 64);
 }
 
