@@ -17,6 +17,8 @@
  *     velocity p_perp . grad(u) . p.  Discretised here as first-order upwind (donor-cell)
  *     fluxes, forward Euler, periodic in x, y and th.
  *   - Sec. 2, Eq. (5) and the extra-stress step of Alg. 1: moments of Psi.
+ *   - Optional depletion (m_total > 0): Eqs. (5)-(6) and the over-binding clamp of Alg. 2,
+ *     applied at the start of each micro-step from the current state.
  * Where the paper leaves the discretisation open, the reading is written next to the code.
  */
 #include "oracle.h"
@@ -66,6 +68,10 @@ double oracle_superbee(double a, double b) {
  *   Phi_{ns-1/2} = v0 z_{ns-1}          first-order free outflow at the plus end s = L
  * sigma_l = superbee(z_l - z_{l-1}, z_{l+1} - z_l) with ghosts z_{-1} = 0, z_{ns} = z_{ns-1}. */
 void oracle_motor_rhs(const oracle_params *p, const double *z, double *R) {
+    oracle_motor_rhs_src(p, z, p->k_on, R);
+}
+
+void oracle_motor_rhs_src(const oracle_params *p, const double *z, double src, double *R) {
     const int ns = p->ns;
     const double ds = p->L / ns;
     double phi[ns + 1]; /* phi[l] = Phi_{l-1/2} */
@@ -81,18 +87,22 @@ void oracle_motor_rhs(const oracle_params *p, const double *z, double *R) {
             phi[l + 1] = p->v0 * (zl + 0.5 * sig);
     }
     for (int l = 0; l < ns; ++l)
-        R[l] = -(phi[l + 1] - phi[l]) / ds + p->k_on - p->k_off * z[l];
+        R[l] = -(phi[l + 1] - phi[l]) / ds + src - p->k_off * z[l];
 }
 
 /* Explicit midpoint: M* = M + (dt/2) R(M), Mout = M + dt R(M*). */
 void oracle_column_step(const oracle_params *p, double dt, const double *M, double *Mout) {
+    oracle_column_step_src(p, dt, M, p->k_on, Mout);
+}
+
+void oracle_column_step_src(const oracle_params *p, double dt, const double *M, double src, double *Mout) {
     const int ns = p->ns;
     if (ns <= 0) return;
     double R[ns], Ms[ns];
     for (int l = 0; l < ns; ++l) Ms[l] = 0.0;
-    oracle_motor_rhs(p, M, R);
+    oracle_motor_rhs_src(p, M, src, R);
     for (int l = 0; l < ns; ++l) Ms[l] = M[l] + 0.5 * dt * R[l];
-    oracle_motor_rhs(p, Ms, R);
+    oracle_motor_rhs_src(p, Ms, src, R);
     for (int l = 0; l < ns; ++l) Mout[l] = M[l] + dt * R[l];
 }
 
@@ -279,16 +289,84 @@ void oracle_global_sums(const oracle_params *p, const double *psi, const double 
         for (int c = 0; c < 3; ++c) sum_sigma[c] = neumaier(stress + c * nxy, nxy) * (dx * dy);
 }
 
+/* Coarse bound-motor density: Eq. (5) integrates the bound motors of every filament over
+ * s, x and th at an anchor r0; in the anchor-marginal reading the bound motors per unit area
+ * at (x, y) are sum over th of psi times the motors per filament m0. */
+void oracle_coarse_bound(const oracle_params *p, const double *psi, const double *m0, double *B) {
+    const long nx = p->nx, ny = p->ny, nth = p->nth;
+    const double dth = TWO_PI / nth;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) {
+            double b = 0.0;
+            for (int k = 0; k < nth; ++k) b += psi[IDX3(i, j, k)] * m0[IDX3(i, j, k)];
+            B[IDX2(i, j)] = b * dth;
+        }
+}
+
+/* Eq. (6): free motors M_f = M_total - B.  Alg. 2: where the bound motors exceed the total,
+ * every bound-motor column at that point is scaled down to the total (then M_f = 0). */
+void oracle_depletion(const oracle_params *p, const double *B, double *scale, double *src) {
+    const long nxy = (long)p->nx * p->ny;
+    for (long o = 0; o < nxy; ++o) {
+        if (B[o] > p->m_total) {
+            scale[o] = p->m_total / B[o];
+            src[o] = 0.0;
+        } else {
+            scale[o] = 1.0;
+            src[o] = p->k_on * (p->m_total - B[o]);
+        }
+    }
+}
+
+/* One motor step with depletion: each column of (x, y) is first scaled by scale[x, y],
+ * then stepped with the attachment source src[x, y] held over the step. */
+static void motor_step_depleted(const oracle_params *p, double dt, const double *M, double *Mout, double *m0,
+                                const double *scale, const double *src) {
+    const int ns = p->ns;
+    const long ny = p->ny, nth = p->nth;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < p->nx; ++i) {
+        double Mc[ns];
+        for (int j = 0; j < ny; ++j) {
+            const long o = IDX2(i, j);
+            for (int k = 0; k < nth; ++k) {
+                const long col = IDX3(i, j, k);
+                for (int l = 0; l < ns; ++l) Mc[l] = scale[o] * M[col * ns + l];
+                oracle_column_step_src(p, dt, Mc, src[o], Mout + col * ns);
+                double a, b;
+                oracle_column_moments(p, Mout + col * ns, &a, &b);
+                m0[col] = a;
+            }
+        }
+    }
+}
+
 void oracle_run(const oracle_params *p, double dt, int nsteps, double *psi, double *M,
                 const double *u, const double *gradu, double *m0_out, double *m1_out) {
-    const long npsi = (long)p->nx * p->ny * p->nth, nm = npsi * p->ns;
+    const long npsi = (long)p->nx * p->ny * p->nth, nm = npsi * p->ns, nxy = (long)p->nx * p->ny;
+    const int depl = p->m_total > 0.0;
     double *M2 = (double *)malloc(sizeof(double) * (size_t)nm);
     double *psi2 = (double *)malloc(sizeof(double) * (size_t)npsi);
     double *m0 = (double *)malloc(sizeof(double) * (size_t)npsi);
+    double *B = depl ? (double *)malloc(sizeof(double) * (size_t)(3 * nxy)) : NULL;
     double *Ma = M, *Mb = M2, *pa = psi, *pb = psi2;
+    if (depl) /* m0 of the current state, for its coarse bound density */
+        for (long c = 0; c < npsi; ++c) {
+            double a, b;
+            oracle_column_moments(p, M + c * p->ns, &a, &b);
+            m0[c] = a;
+        }
     for (int n = 0; n < nsteps; ++n) {
-        /* order within a micro-step: motors first, then psi driven by the new m0 */
-        oracle_motor_step(p, dt, Ma, Mb, m0, NULL);
+        /* order within a micro-step: [depletion of the current state,] motors, then psi
+         * driven by the new m0 */
+        if (depl) {
+            double *scale = B + nxy, *src = B + 2 * nxy;
+            oracle_coarse_bound(p, pa, m0, B);
+            oracle_depletion(p, B, scale, src);
+            motor_step_depleted(p, dt, Ma, Mb, m0, scale, src);
+        } else {
+            oracle_motor_step(p, dt, Ma, Mb, m0, NULL);
+        }
         oracle_psi_step(p, dt, pa, m0, u, gradu, pb);
         double *t = Ma; Ma = Mb; Mb = t;
         t = pa; pa = pb; pb = t;
@@ -308,4 +386,5 @@ void oracle_run(const oracle_params *p, double dt, int nsteps, double *psi, doub
     free(M2);
     free(psi2);
     free(m0);
+    free(B);
 }

@@ -19,6 +19,7 @@ typedef struct {
     double k_on, k_off, v0;
     double F, sigma_f;
     int limiter;              /* 0: superbee MUSCL, 1: first-order upwind (sigma = 0) */
+    double m_total;           /* total motor density per unit area; 0: free pool taken as 1 */
 } oracle_params;
 
 /* superbee slope of the two one-sided differences a (left) and b (right) */
@@ -26,9 +27,19 @@ double oracle_superbee(double a, double b);
 
 /* right-hand side of the motor walk + attach/detach equation on one column of ns cells */
 void oracle_motor_rhs(const oracle_params *p, const double *z, double *R);
+/* the same with the attachment source `src` (k_on times the free-motor density) */
+void oracle_motor_rhs_src(const oracle_params *p, const double *z, double src, double *R);
 
 /* one explicit-midpoint step of one column: Mout = M + dt R(M + dt/2 R(M)) */
 void oracle_column_step(const oracle_params *p, double dt, const double *M, double *Mout);
+void oracle_column_step_src(const oracle_params *p, double dt, const double *M, double src, double *Mout);
+
+/* coarse bound-motor density B [nx][ny] = sum_th psi m0 dth (Eq. (5), anchor-marginal) */
+void oracle_coarse_bound(const oracle_params *p, const double *psi, const double *m0, double *B);
+
+/* free-motor pool of Eq. (6) with the over-binding clamp of Alg. 2, per (x, y):
+ * scale = M_total / B where B > M_total (else 1), src = k_on (M_total - min(B, M_total)). */
+void oracle_depletion(const oracle_params *p, const double *B, double *scale, double *src);
 
 /* zeroth and first arclength moments of one column */
 void oracle_column_moments(const oracle_params *p, const double *M, double *m0, double *m1);
@@ -50,7 +61,8 @@ void oracle_global_sums(const oracle_params *p, const double *psi, const double 
                         double *mass, double *sum_sigma);
 
 /* nsteps micro-steps with one fluid field; psi and M are updated in place.
- * m0/m1 receive the moments of the final M (either may be NULL). */
+ * m0/m1 receive the moments of the final M (either may be NULL).  With m_total > 0 each
+ * micro-step starts with the depletion of oracle_depletion on the current state. */
 void oracle_run(const oracle_params *p, double dt, int nsteps, double *psi, double *M,
                 const double *u, const double *gradu, double *m0, double *m1);
 

@@ -19,7 +19,8 @@ class _Params(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nth", C.c_int), ("ns", C.c_int),
                 ("lx", C.c_double), ("ly", C.c_double), ("L", C.c_double),
                 ("k_on", C.c_double), ("k_off", C.c_double), ("v0", C.c_double),
-                ("F", C.c_double), ("sigma_f", C.c_double), ("limiter", C.c_int)]
+                ("F", C.c_double), ("sigma_f", C.c_double), ("limiter", C.c_int),
+                ("m_total", C.c_double)]
 
 
 _lib = None
@@ -37,7 +38,11 @@ def lib():
         L.oracle_superbee.argtypes = [C.c_double, C.c_double]
         L.oracle_superbee.restype = C.c_double
         L.oracle_motor_rhs.argtypes = [P, _dp, _dp]
+        L.oracle_motor_rhs_src.argtypes = [P, _dp, C.c_double, _dp]
         L.oracle_column_step.argtypes = [P, C.c_double, _dp, _dp]
+        L.oracle_column_step_src.argtypes = [P, C.c_double, _dp, C.c_double, _dp]
+        L.oracle_coarse_bound.argtypes = [P, _dp, _dp, _dp]
+        L.oracle_depletion.argtypes = [P, _dp, _dp, _dp]
         L.oracle_column_moments.argtypes = [P, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.oracle_motor_step.argtypes = [P, C.c_double, _dp, _dp, C.c_void_p, C.c_void_p]
         L.oracle_psi_step.argtypes = [P, C.c_double, _dp, _dp, _dp, _dp, _dp]
@@ -53,7 +58,7 @@ def lib():
 def cparams(p) -> _Params:
     """Accepts any object with the ModelParams attribute names."""
     return _Params(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, p.k_on, p.k_off, p.v0,
-                   p.F, p.sigma_f, int(getattr(p, "limiter", 0)))
+                   p.F, p.sigma_f, int(getattr(p, "limiter", 0)), float(getattr(p, "m_total", 0.0)))
 
 
 def _f64(a):
@@ -80,6 +85,35 @@ def column_step(p, dt, M):
     out = np.empty_like(M)
     lib().oracle_column_step(C.byref(cparams(p)), float(dt), M, out)
     return out
+
+
+def motor_rhs_src(p, z, src):
+    z = _f64(z)
+    R = np.empty_like(z)
+    lib().oracle_motor_rhs_src(C.byref(cparams(p)), z, float(src), R)
+    return R
+
+
+def column_step_src(p, dt, M, src):
+    M = _f64(M)
+    out = np.empty_like(M)
+    lib().oracle_column_step_src(C.byref(cparams(p)), float(dt), M, float(src), out)
+    return out
+
+
+def coarse_bound(p, psi, m0):
+    B = np.empty((p.nx, p.ny))
+    lib().oracle_coarse_bound(C.byref(cparams(p)), _f64(psi), _f64(m0), B)
+    return B
+
+
+def depletion(p, B):
+    """(scale, src) per (x, y): the over-binding clamp factor and k_on times the free pool."""
+    B = _f64(B)
+    scale = np.empty_like(B)
+    src = np.empty_like(B)
+    lib().oracle_depletion(C.byref(cparams(p)), B, scale, src)
+    return scale, src
 
 
 def column_moments(p, M):

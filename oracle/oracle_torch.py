@@ -10,7 +10,7 @@ Kinks use one fixed branch rule, the same the hand-written adjoint has to follow
 takes the zero branch, and a donor-cell face with velocity exactly 0 takes the left cell.
 `torch.where` routes the whole gradient to the chosen branch.
 
-Model: Cook & Shinar, Sec. 2 Eqs. (1)-(5), Alg. 1 and Alg. 2 (see oracle.c for the readings
+Model: Cook & Shinar, Sec. 2 Eqs. (1)-(6), Alg. 1 and Alg. 2 (see oracle.c for the readings
 of the discretisation, which are the same here).
 """
 from __future__ import annotations
@@ -115,8 +115,24 @@ class Problem:
         self.p = p
         self.ds = p.L / p.ns
 
+    def depletion(self, psi, M, k_on):
+        """Eqs. (5)-(6) with the over-binding clamp of Alg. 2 on the current state: the coarse
+        bound density B = sum_th psi m0 dth per (x, y); where B > m_total every column there
+        is scaled by m_total / B and the free pool is 0, elsewhere the pool is m_total - B.
+        Returns the scaled M and the attachment source k_on * pool, shaped to broadcast."""
+        p = self.p
+        dth = TWO_PI / p.ntheta
+        m0, _ = s_moments(M, p.L)
+        B = (psi * m0).sum(-1) * dth
+        over = B > p.m_total
+        scale = torch.where(over, p.m_total / B, torch.ones_like(B))
+        src = torch.where(over, torch.zeros_like(B), k_on * (p.m_total - B))
+        return M * scale[:, :, None, None], src[:, :, None, None]
+
     def step(self, psi, M, k_on, k_off, v0, u, G, dt):
         p = self.p
+        if getattr(p, "m_total", 0.0) > 0.0:
+            M, k_on = self.depletion(psi, M, k_on)
         M1 = motor_step(M, k_on, k_off, v0, dt, self.ds, p.limiter)
         m0, _ = s_moments(M1, p.L)
         psi1 = psi_step(psi, m0, u, G, p.F, dt, p.lx, p.ly)

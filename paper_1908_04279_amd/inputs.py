@@ -48,6 +48,7 @@ class ModelParams:
     F: float = 1.0
     sigma_f: float = 1.0
     limiter: int = 0          # 0: superbee-limited MUSCL flux in s, 1: first-order upwind
+    m_total: float = 0.0      # total motors per unit area (free-motor depletion); 0: pool of 1
 
     def as_dict(self):
         return asdict(self)
@@ -173,12 +174,14 @@ def cfl_dt(p: ModelParams, fluids, cfl=0.4):
 
     rate_M   = v0/ds + k_off                            (motor walk + detachment)
     rate_Psi = (max|u_x| + F m_bar)/dx + (max|u_y| + F m_bar)/dy + max sum|gradu|/dth
-    with m_bar = L k_on / k_off the largest steady bound-motor count per filament.
+    with m_bar = L k_on P / k_off the largest steady bound-motor count per filament, P the
+    free-motor pool (1, or m_total if larger under depletion).
     dt = cfl / max(rate_M, rate_Psi), minimised over every fluid field of the run.
     """
     ds = p.L / p.ns
     dx, dy, dth = p.lx / p.nx, p.ly / p.ny, TWO_PI / p.ntheta
-    m_bar = p.L * p.k_on / p.k_off if p.k_off > 0 else 0.0
+    pool = max(1.0, getattr(p, "m_total", 0.0))
+    m_bar = p.L * p.k_on * pool / p.k_off if p.k_off > 0 else 0.0
     rate_m = p.v0 / ds + p.k_off
     best = math.inf
     for u, g in fluids:
