@@ -60,12 +60,19 @@ typedef struct {
     int32_t ns;            /* arclength cells s_l = (l + 1/2) L / ns, 1 .. 512 */
     double lx, ly;         /* box size (> 0) */
     double L;              /* filament length (> 0) */
-    double k_on, k_off;    /* attachment rate (free pool taken as 1) and detachment rate */
+    double k_on, k_off;    /* attachment rate (per free motor) and detachment rate */
     double v0;             /* motor walking speed along +s, >= 0 */
     double F;              /* motor force coefficient: gliding speed F m0 along -p */
     double sigma_f;        /* filament extra-stress coefficient */
     int32_t precision;     /* mmk_precision: storage AND arithmetic of every field */
     int32_t limiter;       /* mmk_limiter; MMK_UPWIND1 sets the superbee slope to 0 */
+    double m_total;        /* total motors per unit area, >= 0.  0: the free-motor pool is 1
+                            * everywhere (linear attachment).  > 0: free-motor depletion
+                            * (Eqs. (5)-(6)) and the over-binding clamp of Alg. 2: each
+                            * micro-step starts from B(x, y) = sum_th psi m0 dth of the
+                            * current state; where B > m_total every motor column at (x, y)
+                            * is scaled by m_total / B and none attach, elsewhere they
+                            * attach at rate k_on (m_total - B).  Not supported by the tape. */
 } mmk_params;
 
 /* Bytes of device workspace a context needs.  ckpt_every > 0 reserves the adjoint tape:

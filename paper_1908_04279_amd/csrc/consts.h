@@ -19,6 +19,11 @@ inline MotorConst<T> motor_const(const mmk_params &p, double dt) {
     c.half_dt = (T)(0.5 * dt);
     c.ds = (T)ds;
     c.ds2 = (T)(ds * ds);
+    c.m_total = (T)p.m_total;
+    c.nth = p.ntheta;
+    c.nth_shift = -1;
+    for (int k = 0; k < 31; ++k)
+        if ((1 << k) == p.ntheta) c.nth_shift = k;
     return c;
 }
 

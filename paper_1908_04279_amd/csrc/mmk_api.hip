@@ -29,7 +29,7 @@ constexpr int kProfMax = 65536;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t M[2], psi[2], m0, m1, u, G, stress, mom, tab, partials, sums;
+    size_t M[2], psi[2], m0, m1, Bxy, u, G, stress, mom, tab, partials, sums;
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -47,11 +47,12 @@ std::string check_params(const mmk_params *p) {
     if (p->ns < 1) return "ns must be >= 1";
     if (p->precision != MMK_FP32 && p->precision != MMK_FP64) return "precision must be MMK_FP64 or MMK_FP32";
     if (p->limiter != MMK_SUPERBEE && p->limiter != MMK_UPWIND1) return "limiter must be MMK_SUPERBEE or MMK_UPWIND1";
-    const double vals[] = {p->lx, p->ly, p->L, p->k_on, p->k_off, p->v0, p->F, p->sigma_f};
+    const double vals[] = {p->lx, p->ly, p->L, p->k_on, p->k_off, p->v0, p->F, p->sigma_f, p->m_total};
     for (double v : vals)
         if (!std::isfinite(v)) return "non-finite model parameter";
     if (p->lx <= 0 || p->ly <= 0 || p->L <= 0) return "lx, ly and L must be > 0";
     if (p->v0 < 0) return "v0 must be >= 0 (motors walk towards s = L)";
+    if (p->m_total < 0) return "m_total must be >= 0 (0: no depletion)";
     if ((int64_t)p->nx * p->ny > ((int64_t)1 << 31)) return "nx * ny too large";
     return "";
 }
@@ -83,6 +84,7 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.psi[1] = take(np * e);
     L.m0 = take(np * e);
     L.m1 = take(np * e);
+    L.Bxy = take(nxy * e);
     L.u = take(2 * nxy * e);
     L.G = take(4 * nxy * e);
     L.stress = take(3 * nxy * e);
@@ -179,7 +181,8 @@ static mmk_status motor_half(mmk_ctx *c, const T *M_in, T *M_out, T *m0, T *m1, 
     const mmk_params &p = c->p;
     int slot;
     HIPCHK(c, prof_begin_on(c, 0, &slot, s), "hipEventRecord");
-    HIPCHK(c, launch_motor_step<T>(M_in, M_out, m0, m1, n_psi(p), p.ns, p.limiter, motor_const<T>(p, dt), s),
+    const T *Bxy = p.m_total > 0 ? c->at<T>(c->L.Bxy) : nullptr;
+    HIPCHK(c, launch_motor_step<T>(M_in, M_out, m0, m1, n_psi(p), p.ns, p.limiter, motor_const<T>(p, dt), Bxy, s),
            "motor step launch");
     HIPCHK(c, prof_end_on(c, 0, slot, s), "hipEventRecord");
     return MMK_OK;
@@ -192,12 +195,13 @@ static mmk_status psi_half(mmk_ctx *c, const T *psi_in, T *psi_out, const T *m0,
     HIPCHK(c, prof_begin_on(c, 1, &slot, s), "hipEventRecord");
     T *stress = out ? c->at<T>(c->L.stress) : nullptr, *mom = out ? c->at<T>(c->L.mom) : nullptr;
     double *part = out ? c->at<double>(c->L.partials) : nullptr;
+    T *Bxy = c->p.m_total > 0 ? c->at<T>(c->L.Bxy) : nullptr;  // coarse bound density of the new state
     if (c->walk)
-        HIPCHK(c, launch_psi_walk<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part,
+        HIPCHK(c, launch_psi_walk<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part, Bxy,
                                      psi_const<T>(c->p, dt), c->wp, s),
                "psi step launch");
     else
-        HIPCHK(c, launch_psi_step<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part,
+        HIPCHK(c, launch_psi_step<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part, Bxy,
                                      psi_const<T>(c->p, dt), c->pl, s),
                "psi step launch");
     HIPCHK(c, prof_end_on(c, 1, slot, s), "hipEventRecord");
@@ -410,6 +414,20 @@ mmk_status mmk_set_state(mmk_ctx *c, const void *psi, const void *M) {
     } else {
         HIPCHK(c, launch_zero<double>(c->at<double>(c->L.M[c->cur]), n_m(c->p), c->stream), "zero M");
     }
+    if (c->p.m_total > 0) {  // coarse bound density of the new state, for the first step's depletion
+        const double ds = c->p.L / c->p.ns, dth = kTwoPi / c->p.ntheta;
+        const int64_t nxy = (int64_t)c->p.nx * c->p.ny;
+        hipError_t e;
+        if (c->esz == 4)
+            e = launch_coarse_bound<float>(M ? c->at<float>(c->L.M[c->cur]) : nullptr, c->at<float>(c->L.psi[c->cur]),
+                                           c->at<float>(c->L.Bxy), nxy, c->p.ntheta, c->p.ns, (float)ds, (float)dth,
+                                           c->stream);
+        else
+            e = launch_coarse_bound<double>(M ? c->at<double>(c->L.M[c->cur]) : nullptr,
+                                            c->at<double>(c->L.psi[c->cur]), c->at<double>(c->L.Bxy), nxy,
+                                            c->p.ntheta, c->p.ns, ds, dth, c->stream);
+        HIPCHK(c, e, "coarse bound density launch");
+    }
     c->have_state = true;
     c->have_out = false;
     return MMK_OK;
@@ -494,6 +512,8 @@ mmk_status mmk_get_sums(mmk_ctx *c, double *mass, double sum_sigma[3]) {
 
 mmk_status mmk_tape_begin(mmk_ctx *c, int32_t ckpt_every) {
     if (!c) return MMK_ERR_ARG;
+    if (c->p.m_total > 0)
+        return fail(c, MMK_ERR_UNSUPPORTED, "the adjoint covers linear attachment only (m_total = 0)");
     return tape_begin(c, &c->tape, ckpt_every, c->have_state, c->have_fluid, c->cur);
 }
 

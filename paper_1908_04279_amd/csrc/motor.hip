@@ -40,9 +40,9 @@ __device__ __forceinline__ float superbee<float>(float a, float b) {
 // R(z) on this lane's CPL cells.  g: lane index inside the column group; l0 = g * CPL.
 // With the face value h_l = z_l + sigma_l / 2 (flux v0 h_l; h_{-1} = 0 carries the zero
 // influx, and the zero last slope makes h_{ns-1} = z_{ns-1}, the first-order outflow):
-//   R_l = -(v0/ds) (h_l - h_{l-1}) + (k_on - k_off z_l).
+//   R_l = -(v0/ds) (h_l - h_{l-1}) + (src - k_off z_l),  src = k_on times the free pool.
 template <typename T, int CPL, int LPC, int LIM, bool RAGGED>
-__device__ __forceinline__ void motor_rhs(const T (&z)[CPL], T (&R)[CPL], const MotorConst<T> &c,
+__device__ __forceinline__ void motor_rhs(const T (&z)[CPL], T (&R)[CPL], const MotorConst<T> &c, T src,
                                           int g, int l0, int ns) {
     const T zl = from_prev0<LPC>(z[CPL - 1], g);             // z_{l0-1}; ghost 0 at s = 0
     const T zr = from_next<LPC>(z[0], z[CPL - 1], g);        // z_{l0+CPL}; ghost at s = L
@@ -67,14 +67,15 @@ __device__ __forceinline__ void motor_rhs(const T (&z)[CPL], T (&R)[CPL], const 
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
         const T left = (j == 0) ? hl : h[j - 1];
-        R[j] = c.nv_ds * (h[j] - left) + (c.k_on - c.k_off * z[j]);
+        R[j] = c.nv_ds * (h[j] - left) + (src - c.k_off * z[j]);
     }
 }
 
 template <typename T, int CPL, int LPC, int LIM, bool RAGGED, bool WANT_M1, bool NT>
 __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, T *__restrict__ M_out,
                                                     T *__restrict__ m0, T *__restrict__ m1,
-                                                    int64_t ncol, int ns, MotorConst<T> c) {
+                                                    int64_t ncol, int ns, MotorConst<T> c,
+                                                    const T *__restrict__ Bxy) {
     constexpr int COLS = 256 / LPC;
     const int g = threadIdx.x % LPC;
     const int64_t col = (int64_t)blockIdx.x * COLS + threadIdx.x / LPC;
@@ -95,11 +96,27 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
         for (int j = 0; j < CPL; ++j) x[j] = (active && l0 + j < ns) ? M_in[base + j] : T(0);
     }
 
+    // free-motor depletion (Eq. (6)) with the over-binding clamp of Alg. 2, from the coarse
+    // bound density of the current state at this column's (x, y)
+    T src = c.k_on;
+    if (Bxy) {
+        const int64_t xy = c.nth_shift >= 0 ? (col >> c.nth_shift) : col / c.nth;
+        const T B = active ? Bxy[xy] : T(0);
+        if (B > c.m_total) {
+            const T scale = c.m_total / B;
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) x[j] *= scale;
+            src = T(0);
+        } else {
+            src = c.k_on * (c.m_total - B);
+        }
+    }
+
     T R[CPL], y[CPL];
-    motor_rhs<T, CPL, LPC, LIM, RAGGED>(x, R, c, g, l0, ns);
+    motor_rhs<T, CPL, LPC, LIM, RAGGED>(x, R, c, src, g, l0, ns);
 #pragma unroll
     for (int j = 0; j < CPL; ++j) y[j] = x[j] + c.half_dt * R[j];
-    motor_rhs<T, CPL, LPC, LIM, RAGGED>(y, R, c, g, l0, ns);
+    motor_rhs<T, CPL, LPC, LIM, RAGGED>(y, R, c, src, g, l0, ns);
 #pragma unroll
     for (int j = 0; j < CPL; ++j) y[j] = x[j] + c.dt * R[j];
 
@@ -286,13 +303,13 @@ static hipError_t launch_chunked(const T *M_in, T *M_out, T *m0, T *m1, int64_t 
 
 template <typename T, int CPL, int LPC, bool RAGGED, int LIM, bool NT>
 static hipError_t launch_nt(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
-                            const MotorConst<T> &c, hipStream_t s, unsigned blocks) {
+                            const MotorConst<T> &c, const T *Bxy, hipStream_t s, unsigned blocks) {
     if (m1)
         hipLaunchKernelGGL((k_motor_step<T, CPL, LPC, LIM, RAGGED, true, NT>), dim3(blocks), dim3(256), 0, s,
-                           M_in, M_out, m0, m1, ncol, ns, c);
+                           M_in, M_out, m0, m1, ncol, ns, c, Bxy);
     else
         hipLaunchKernelGGL((k_motor_step<T, CPL, LPC, LIM, RAGGED, false, NT>), dim3(blocks), dim3(256), 0, s,
-                           M_in, M_out, m0, m1, ncol, ns, c);
+                           M_in, M_out, m0, m1, ncol, ns, c, Bxy);
     return hipGetLastError();
 }
 
@@ -308,21 +325,22 @@ static bool motor_nontemporal(int elem) {
 
 template <typename T, int CPL, int LPC, bool RAGGED, int LIM>
 static hipError_t launch_lim(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
-                             const MotorConst<T> &c, hipStream_t s, unsigned blocks) {
+                             const MotorConst<T> &c, const T *Bxy, hipStream_t s, unsigned blocks) {
     if (!RAGGED && motor_nontemporal((int)sizeof(T)))
-        return launch_nt<T, CPL, LPC, RAGGED, LIM, true>(M_in, M_out, m0, m1, ncol, ns, c, s, blocks);
-    return launch_nt<T, CPL, LPC, RAGGED, LIM, false>(M_in, M_out, m0, m1, ncol, ns, c, s, blocks);
+        return launch_nt<T, CPL, LPC, RAGGED, LIM, true>(M_in, M_out, m0, m1, ncol, ns, c, Bxy, s, blocks);
+    return launch_nt<T, CPL, LPC, RAGGED, LIM, false>(M_in, M_out, m0, m1, ncol, ns, c, Bxy, s, blocks);
 }
 
 template <typename T, int CPL, int LPC, bool RAGGED>
 static hipError_t launch_cfg(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
-                             int limiter, const MotorConst<T> &c, hipStream_t s) {
+                             int limiter, const MotorConst<T> &c, const T *Bxy, hipStream_t s) {
     constexpr int COLS = 256 / LPC;
     const int64_t blocks = (ncol + COLS - 1) / COLS;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    if (limiter == 0) return launch_lim<T, CPL, LPC, RAGGED, 0>(M_in, M_out, m0, m1, ncol, ns, c, s, (unsigned)blocks);
-    return launch_lim<T, CPL, LPC, RAGGED, 1>(M_in, M_out, m0, m1, ncol, ns, c, s, (unsigned)blocks);
+    if (limiter == 0)
+        return launch_lim<T, CPL, LPC, RAGGED, 0>(M_in, M_out, m0, m1, ncol, ns, c, Bxy, s, (unsigned)blocks);
+    return launch_lim<T, CPL, LPC, RAGGED, 1>(M_in, M_out, m0, m1, ncol, ns, c, Bxy, s, (unsigned)blocks);
 }
 
 // Lanes per column for the exact tilings (0: use the masked generic kernel).  Default: 16
@@ -357,8 +375,8 @@ static int chunks_per_lane(int ns, int elem) {
 
 template <typename T>
 hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
-                             int limiter, const MotorConst<T> &c, hipStream_t s) {
-    const int nch = chunks_per_lane(ns, (int)sizeof(T));
+                             int limiter, const MotorConst<T> &c, const T *Bxy, hipStream_t s) {
+    const int nch = Bxy ? 1 : chunks_per_lane(ns, (int)sizeof(T));  // chunked: no depletion
     if (nch > 1) {
         const bool nt = motor_nontemporal((int)sizeof(T));
         const int lpc = ns / (nch * (16 / (int)sizeof(T)));
@@ -371,7 +389,7 @@ hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
     const int lpc = lanes_per_column(ns, (int)sizeof(T));
 #define MMK_MOTOR_CASE(NS, LPC)                                                                   \
     if (ns == NS && lpc == LPC)                                                                   \
-        return launch_cfg<T, NS / LPC, LPC, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
+        return launch_cfg<T, NS / LPC, LPC, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
     if constexpr (sizeof(T) == 4) {
         MMK_MOTOR_CASE(8, 2) MMK_MOTOR_CASE(16, 4) MMK_MOTOR_CASE(32, 8) MMK_MOTOR_CASE(64, 16)
         MMK_MOTOR_CASE(64, 8) MMK_MOTOR_CASE(128, 32) MMK_MOTOR_CASE(128, 16) MMK_MOTOR_CASE(256, 64)
@@ -383,18 +401,18 @@ hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
     }
 #undef MMK_MOTOR_CASE
     // any other length: 16 lanes per column, masked tail cells, scalar loads
-    if (ns <= 16) return launch_cfg<T, 1, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-    if (ns <= 32) return launch_cfg<T, 2, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-    if (ns <= 64) return launch_cfg<T, 4, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-    if (ns <= 128) return launch_cfg<T, 8, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-    if (ns <= 256) return launch_cfg<T, 16, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
-    if (ns <= 512) return launch_cfg<T, 32, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s);
+    if (ns <= 16) return launch_cfg<T, 1, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
+    if (ns <= 32) return launch_cfg<T, 2, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
+    if (ns <= 64) return launch_cfg<T, 4, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
+    if (ns <= 128) return launch_cfg<T, 8, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
+    if (ns <= 256) return launch_cfg<T, 16, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
+    if (ns <= 512) return launch_cfg<T, 32, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
     return hipErrorInvalidValue;
 }
 
 template hipError_t launch_motor_step<float>(const float *, float *, float *, float *, int64_t, int, int,
-                                             const MotorConst<float> &, hipStream_t);
+                                             const MotorConst<float> &, const float *, hipStream_t);
 template hipError_t launch_motor_step<double>(const double *, double *, double *, double *, int64_t, int,
-                                              int, const MotorConst<double> &, hipStream_t);
+                                              int, const MotorConst<double> &, const double *, hipStream_t);
 
 }  // namespace mmk

@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
                                                   const T *__restrict__ u, const T *__restrict__ Gr,
                                                   const T *__restrict__ tab, T *__restrict__ stress,
                                                   T *__restrict__ mom, double *__restrict__ partials,
-                                                  PsiConst<T> c, PsiLaunch pl) {
+                                                  T *__restrict__ Bxy, PsiConst<T> c, PsiLaunch pl) {
     constexpr bool FIXED = NTH_C > 0 && TI_C > 0 && TJ_C > 0;
     extern __shared__ __align__(16) unsigned char smem[];
     const int nx = c.nx, ny = c.ny;
@@ -370,6 +370,7 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
         T ms[NMOM], me[NMOM];  // this lane's theta partial sums of the moments (output steps)
 #pragma unroll
         for (int m = 0; m < NMOM; ++m) ms[m] = me[m] = T(0);
+        T bs = T(0), bc = T(0);  // coarse bound density: sum psi_out m0 over this lane
 
         auto cell = [&](const AngleK<T> &a, int slot, bool first) {
             const int k = a.k;
@@ -409,6 +410,10 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
             const T div = (fxp - fxm) * c.inv_dx + (fyp - fym) * c.inv_dy + (ftp - ftm) * c.inv_dth;
             const T pn = ps - c.dt * div;
             psi_out[pen * nth + k] = pn;
+            if (Bxy) {
+                if (first) bs = pn * mc;
+                else kahan_add(bs, bc, pn * mc);
+            }
             if (out) {
                 const T fm = c.F * m1[pen * nth + k];
                 const T terms[NMOM] = {pn,
@@ -432,6 +437,19 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
                 if (kk + j * G < nth) cell(ak[j], j, j == 0);
         } else {
             for (int k = kk; k < nth; k += G) cell(angle_k(s_tab, nth, k), 0, k == kk);
+        }
+        if (Bxy) {
+            T tb;
+            if constexpr (FIXED) {
+                tb = pencil_total<(NTH_C <= 16 ? 16 : (NTH_C <= 32 ? 32 : 64))>(bs, bc);
+            } else if (G == 64) {
+                tb = pencil_total<64>(bs, bc);
+            } else if (G == 32) {
+                tb = pencil_total<32>(bs, bc);
+            } else {
+                tb = pencil_total<16>(bs, bc);
+            }
+            if (kk == 0) Bxy[pen] = tb * c.dth;
         }
         if (out) {
             // one lane per quantity stores its total (moments 0..6, stress 7..9)
@@ -480,19 +498,19 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
 
 template <typename T, int NTH, int TI, int TJ>
 static void launch_fixed(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u, const T *G,
-                         const T *tab, T *stress, T *mom, double *partials, const PsiConst<T> &c,
+                         const T *tab, T *stress, T *mom, double *partials, T *Bxy, const PsiConst<T> &c,
                          const PsiLaunch &pl, hipStream_t s) {
     hipLaunchKernelGGL((k_psi_step<T, NTH, TI, TJ>), dim3(pl.blocks), dim3(256), pl.lds_bytes, s, psi_in,
-                       psi_out, m0, m1, u, G, tab, stress, mom, partials, c, pl);
+                       psi_out, m0, m1, u, G, tab, stress, mom, partials, Bxy, c, pl);
 }
 
 template <typename T>
 hipError_t launch_psi_step(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u,
-                           const T *G, const T *tab, T *stress, T *mom, double *partials,
+                           const T *G, const T *tab, T *stress, T *mom, double *partials, T *Bxy,
                            const PsiConst<T> &c, const PsiLaunch &pl, hipStream_t s) {
-#define MMK_PSI_CASE(N, A, B)                                                                        \
-    if (c.nth == N && pl.ti == A && pl.tj == B) {                                                    \
-        launch_fixed<T, N, A, B>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, c, pl, s); \
+#define MMK_PSI_CASE(N, A, B)                                                                             \
+    if (c.nth == N && pl.ti == A && pl.tj == B) {                                                         \
+        launch_fixed<T, N, A, B>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, Bxy, c, pl, s); \
         return hipGetLastError();                                                                    \
     }
 #define MMK_PSI_TILES(N) MMK_PSI_CASE(N, 8, 8) MMK_PSI_CASE(N, 4, 8) MMK_PSI_CASE(N, 4, 4) MMK_PSI_CASE(N, 2, 4)
@@ -503,16 +521,17 @@ hipError_t launch_psi_step(const T *psi_in, T *psi_out, const T *m0, const T *m1
 #undef MMK_PSI_TILES
 #undef MMK_PSI_CASE
     hipLaunchKernelGGL((k_psi_step<T, 0, 0, 0>), dim3(pl.blocks), dim3(256), pl.lds_bytes, s, psi_in, psi_out,
-                       m0, m1, u, G, tab, stress, mom, partials, c, pl);
+                       m0, m1, u, G, tab, stress, mom, partials, Bxy, c, pl);
     return hipGetLastError();
 }
 
 template hipError_t launch_psi_step<float>(const float *, float *, const float *, const float *, const float *,
-                                           const float *, const float *, float *, float *, double *,
+                                           const float *, const float *, float *, float *, double *, float *,
                                            const PsiConst<float> &, const PsiLaunch &, hipStream_t);
 template hipError_t launch_psi_step<double>(const double *, double *, const double *, const double *,
                                             const double *, const double *, const double *, double *, double *,
-                                            double *, const PsiConst<double> &, const PsiLaunch &, hipStream_t);
+                                            double *, double *, const PsiConst<double> &, const PsiLaunch &,
+                                            hipStream_t);
 
 // ---------------------------------------------------------------------------------------
 // Reverse of the donor-cell step.  LDS tile of lam', psi and m0 with the same halo.
@@ -693,6 +712,53 @@ hipError_t launch_reduce_partials(const double *partials, int n, double *out, do
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials, n, out, s0, s1);
     return hipGetLastError();
 }
+
+// Coarse bound density of a state (start of a depleted run): one block per (x, y) point sums
+// psi[th] M[th][s] over the point's nth * ns cells, Kahan per thread and a TwoSum tree over
+// the block, times ds dth.
+#pragma clang fp contract(off)
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_bound(const T *__restrict__ M, const T *__restrict__ psi,
+                                                      T *__restrict__ Bxy, int64_t nxy, int nth, int ns, T ds,
+                                                      T dth) {
+    __shared__ T sh[256], se[256];
+    const int t = threadIdx.x;
+    const int64_t n = (int64_t)nth * ns;
+    for (int64_t xy = blockIdx.x; xy < nxy; xy += gridDim.x) {
+        T s = 0, cmp = 0;
+        if (M)
+            for (int64_t i = t; i < n; i += 256) kahan_add(s, cmp, psi[xy * nth + i / ns] * M[xy * n + i]);
+        sh[t] = s;
+        se[t] = -cmp;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (t < w) {
+                T hi, lo;
+                two_sum(sh[t], sh[t + w], hi, lo);
+                sh[t] = hi;
+                se[t] = se[t] + se[t + w] + lo;
+            }
+            __syncthreads();
+        }
+        if (t == 0) Bxy[xy] = (sh[0] + se[0]) * ds * dth;
+        __syncthreads();
+    }
+}
+#pragma clang fp contract(on)
+
+template <typename T>
+hipError_t launch_coarse_bound(const T *M, const T *psi, T *Bxy, int64_t nxy, int nth, int ns, T ds, T dth,
+                               hipStream_t s) {
+    if (nxy <= 0) return hipSuccess;
+    const int64_t blocks = nxy < 65536 ? nxy : 65536;
+    hipLaunchKernelGGL(k_coarse_bound<T>, dim3((unsigned)blocks), dim3(256), 0, s, M, psi, Bxy, nxy, nth, ns, ds,
+                       dth);
+    return hipGetLastError();
+}
+template hipError_t launch_coarse_bound<float>(const float *, const float *, float *, int64_t, int, int, float,
+                                               float, hipStream_t);
+template hipError_t launch_coarse_bound<double>(const double *, const double *, double *, int64_t, int, int,
+                                                double, double, hipStream_t);
 
 template <typename T>
 __global__ void k_zero(T *out, int64_t n) {

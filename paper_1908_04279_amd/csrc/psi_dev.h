@@ -87,6 +87,14 @@ __device__ __forceinline__ T group_moments(T (&s)[NMOM], T (&e)[NMOM], int lane,
 }
 #pragma clang fp contract(on)
 
+// Total over the G lanes of a pencil group of a per-lane Kahan pair (FP32: compensated
+// butterfly) or plain sum (FP64); every lane of the group gets it.
+template <int G, typename T>
+__device__ __forceinline__ T pencil_total(T s, T comp) {
+    if constexpr (std::is_same<T, float>::value) return group_sum_comp<G>(s, comp);
+    else return group_sum<G>(s);
+}
+
 // per-lane partial sum of one quantity: the first term sets it, later terms add (compensated
 // in FP32)
 #pragma clang fp contract(off)
@@ -132,8 +140,8 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
                                               const T *__restrict__ u, const T *__restrict__ Gr,
                                               const T *__restrict__ tab, T *__restrict__ stress,
                                               T *__restrict__ mom, double *__restrict__ partials,
-                                              const PsiConst<T> &c, int tiles_i, int tiles_j, int per,
-                                              int vblock) {
+                                              T *__restrict__ Bxy, const PsiConst<T> &c, int tiles_i,
+                                              int tiles_j, int per, int vblock) {
     constexpr int NTH = 64 * KPL;
     constexpr bool COMP = std::is_same<T, float>::value;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -229,6 +237,7 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
             T ms[NMOM], me[NMOM];
 #pragma unroll
             for (int m = 0; m < NMOM; ++m) ms[m] = me[m] = T(0);
+            T bs = T(0), bc = T(0);  // coarse bound density: sum psi_out m0 over this lane
 #pragma unroll
             for (int s = 0; s < KPL; ++s) {
                 const int k = lane + 64 * s;
@@ -236,6 +245,10 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
                 const T div = (fxp[s] - fxm[s]) * c.inv_dx + (fyp[s] - fym[s]) * c.inv_dy + (ftp[s] - ftm) * c.inv_dth;
                 const T pn = Pc[s] - c.dt * div;
                 psi_out[pc * NTH + k] = pn;
+                if (Bxy) {
+                    if (s == 0) bs = pn * Mc[s];
+                    else kahan_add(bs, bc, pn * Mc[s]);
+                }
                 if constexpr (OUT) {
                     const T fm = c.F * m1[pc * NTH + k];
                     const T cc = tab[TAB_CC * NTH + k], cs = tab[TAB_CS * NTH + k], ss = tab[TAB_SS * NTH + k];
@@ -254,6 +267,10 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
                     for (int m = 0; m < NMOM; ++m) mom_add<COMP>(ms[m], me[m], terms[m], s == 0);
                     acc_mass += (double)pn;
                 }
+            }
+            if (Bxy) {
+                const T tb = pencil_total<64>(bs, bc);
+                if (lane == 0) Bxy[pc] = tb * c.dth;
             }
             if constexpr (OUT) {
                 int qm;

@@ -23,20 +23,21 @@ __global__ __launch_bounds__(256) void k_psi_walk(const T *__restrict__ psi_in, 
                                                   const T *__restrict__ u, const T *__restrict__ G,
                                                   const T *__restrict__ tab, T *__restrict__ stress,
                                                   T *__restrict__ mom, double *__restrict__ partials,
-                                                  PsiConst<T> c, int tiles_i, int tiles_j, int per) {
-    psi_walk_tile<T, KPL, TI, OUT>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, c, tiles_i, tiles_j,
-                                   per, (int)blockIdx.x);
+                                                  T *__restrict__ Bxy, PsiConst<T> c, int tiles_i, int tiles_j,
+                                                  int per) {
+    psi_walk_tile<T, KPL, TI, OUT>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, Bxy, c, tiles_i,
+                                   tiles_j, per, (int)blockIdx.x);
 }
 
 template <typename T>
 hipError_t launch_psi_walk(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u, const T *G,
-                           const T *tab, T *stress, T *mom, double *partials, const PsiConst<T> &c,
+                           const T *tab, T *stress, T *mom, double *partials, T *Bxy, const PsiConst<T> &c,
                            const WalkPlan &wp, hipStream_t s) {
     if (!wp.ok || wp.ti != 8) return hipErrorInvalidValue;
     const bool out = stress != nullptr;
 #define MMK_WALK(KPL, OUT)                                                                                  \
     hipLaunchKernelGGL((k_psi_walk<T, KPL, 8, OUT>), dim3(wp.blocks), dim3(256), 0, s, psi_in, psi_out, m0, m1, u, \
-                       G, tab, stress, mom, partials, c, wp.tiles_i, wp.tiles_j, wp.per)
+                       G, tab, stress, mom, partials, Bxy, c, wp.tiles_i, wp.tiles_j, wp.per)
     if (wp.kpl == 1) {
         if (out) MMK_WALK(1, true); else MMK_WALK(1, false);
     } else {
@@ -46,10 +47,11 @@ hipError_t launch_psi_walk(const T *psi_in, T *psi_out, const T *m0, const T *m1
     return hipGetLastError();
 }
 template hipError_t launch_psi_walk<float>(const float *, float *, const float *, const float *, const float *,
-                                           const float *, const float *, float *, float *, double *,
+                                           const float *, const float *, float *, float *, double *, float *,
                                            const PsiConst<float> &, const WalkPlan &, hipStream_t);
 template hipError_t launch_psi_walk<double>(const double *, double *, const double *, const double *,
                                             const double *, const double *, const double *, double *, double *,
-                                            double *, const PsiConst<double> &, const WalkPlan &, hipStream_t);
+                                            double *, double *, const PsiConst<double> &, const WalkPlan &,
+                                            hipStream_t);
 
 }  // namespace mmk
