@@ -5,8 +5,9 @@ arclength cells (268M bound-motor cells), FP32 storage and arithmetic, a new see
 field every K = 10 micro-steps, stress/moments/global sums on every exchange.  A "step" is
 one micro-step of the whole path: motor column step, s-moments, psi donor-cell update,
 and (every 10th) theta-moments, stress and FP64 global sums.  Inputs are resident in HBM
-before the timed region.  Also measured: the same grid in FP64, and the oracle (FP64 C,
-OpenMP) on a bounded sample of the same grid on the host cores.
+before the timed region.  Also measured: the same grid in FP64, the same grid in FP32 with
+free-motor depletion, the adjoint/forward time ratios, and the oracle (FP64 C, OpenMP) on a
+bounded sample of the same grid on the host cores.
 
 Prints one JSON line.  --gpus N > 1 is refused: this path runs on one GPU.
 """
@@ -35,6 +36,9 @@ COUNTERS = (os.path.join(ROOT, "profiles", "motor_step_f32_256x256x64x64_counter
 # kernel launches bracketed by HIP events inside the timed region: every EVENT_EVERY-th launch
 # of each kernel (an event pair on every launch costs ~14 us per micro-step on MI355X, ~4%)
 EVENT_EVERY = 13
+# total motors per unit area of the depletion leg: about twice the coarse bound density the
+# linear model settles to on this workload, so the free pool is roughly halved
+M_TOTAL_BENCH = 0.02
 
 
 def log(*a):
@@ -244,9 +248,10 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64"], default="all",
+    ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64", "depletion"], default="all",
                     help="restrict to one leg (used for profiler runs)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--depletion-steps", type=int, default=200)
     ap.add_argument("--event-every", type=int, default=EVENT_EVERY,
                     help="bracket every N-th launch of each kernel with HIP events")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -274,6 +279,11 @@ def main():
     p = gen.params_for("c3_fp32_256x256x64x64")
     K = 10
     res = {}
+    if args.only in ("all", "depletion"):
+        # the same grid with free-motor depletion and the over-binding clamp
+        pd = gen.params_for("c3_fp32_256x256x64x64", m_total=M_TOTAL_BENCH)
+        res["depletion"] = run_forward(pd, mmk.FP32, args.depletion_steps, min(args.warmup, 20), K,
+                                       event_every=args.event_every)
     if args.only in ("all", "fp32"):
         res["fp32"] = run_forward(p, mmk.FP32, args.steps, args.warmup, K, event_every=args.event_every)
     if args.only in ("all", "fp64"):
@@ -296,6 +306,18 @@ def main():
         return dict(steps_per_s=sps, step_gbs=total / r["elapsed"] / 1e9, avg_us=ms_m / n_m * 1e3,
                     gbs=kb / (ms_m / n_m / 1e3) / 1e9, bytes_per_launch=kb, n_plain=n_m - n_out,
                     n_out=n_out, psi_avg_us=ms_p / n_p * 1e3, timed_launches=n_m, mass=r["mass"])
+
+    def depletion_summary():
+        sd = summarise(res["depletion"], 4)
+        d = {"m_total": M_TOTAL_BENCH, "micro_steps_per_s": sd["steps_per_s"],
+             "ms_per_step": 1e3 / sd["steps_per_s"], "motor_avg_us": sd["avg_us"], "motor_gbs": sd["gbs"],
+             "motor_frac": sd["gbs"] / HBM_PEAK_GBS, "psi_avg_us": sd["psi_avg_us"],
+             "steps": res["depletion"]["steps"]}
+        return d
+
+    if args.only == "depletion":
+        print(json.dumps({"depletion_fp32": depletion_summary()}), flush=True)
+        return
 
     out = {"metric": METRIC, "unit": "micro-steps/s", "n_gpus": 1, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
@@ -324,6 +346,9 @@ def main():
                        "motor_frac": s64["gbs"] / HBM_PEAK_GBS, "motor_avg_us": s64["avg_us"],
                        "steps": res["fp64"]["steps"]}
         out["fp32_over_fp64"] = s["steps_per_s"] / s64["steps_per_s"]
+    if "depletion" in res:
+        out["depletion_fp32"] = depletion_summary()
+        out["depletion_fp32"]["relative_to_linear"] = out["depletion_fp32"]["micro_steps_per_s"] / s["steps_per_s"]
     out["adjoint_over_forward"] = None
     if args.only == "all" and not args.no_adjoint:
         log("[bench] adjoint legs")

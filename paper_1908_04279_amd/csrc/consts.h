@@ -19,7 +19,6 @@ inline MotorConst<T> motor_const(const mmk_params &p, double dt) {
     c.half_dt = (T)(0.5 * dt);
     c.ds = (T)ds;
     c.ds2 = (T)(ds * ds);
-    c.m_total = (T)p.m_total;
     c.nth = p.ntheta;
     c.nth_shift = -1;
     for (int k = 0; k < 31; ++k)
@@ -40,6 +39,7 @@ inline PsiConst<T> psi_const(const mmk_params &p, double dt) {
     c.F = (T)p.F;
     c.sigma_f = (T)p.sigma_f;
     c.dth = (T)(kTwoPi / p.ntheta);
+    c.m_total = (T)p.m_total;
     return c;
 }
 

@@ -13,26 +13,41 @@ struct MotorConst {
     T nv_ds;       // -v0 / ds
     T dt, half_dt; // step and midpoint stage
     T ds, ds2;     // m0 = ds * sum M,  m1 = ds^2 * sum (l + 1/2 - ns/2) M
-    T m_total;     // depletion: total motors per unit area
     int nth;       // columns per (x, y) point, and log2 of it when a power of two (else -1)
     int nth_shift;
 };
 
 // Forward motor step over `ncol` independent columns of `ns` cells.
 //   M_out = M + dt R(M + dt/2 R(M));  m0 = sum M_out ds;  m1 (if non-null) likewise.
-// Bxy (non-null: depletion) is the coarse bound density [nx][ny] of the current state; the
-// columns of point xy = col / nth are first scaled by m_total / B where B > m_total, and the
-// attachment source is k_on (m_total - min(B, m_total)) instead of k_on.
+// Dxy (non-null: depletion) holds [nx][ny][2] = (clamp factor, free-motor pool) of the
+// current state (depletion_of() of its coarse bound density); the columns of point
+// xy = col / nth are first scaled by the factor, and the attachment source is k_on times the
+// pool instead of k_on.
 template <typename T>
 hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
-                             int limiter, const MotorConst<T> &c, const T *Bxy, hipStream_t s);
+                             int limiter, const MotorConst<T> &c, const T *Dxy, hipStream_t s);
 
 // Geometry and constants of the filament-density step.
 template <typename T>
 struct PsiConst {
     int nx, ny, nth;
     T dt, inv_dx, inv_dy, inv_dth, F, sigma_f, dth;
+    T m_total;  // depletion: total motors per unit area
 };
+
+// Free-motor pool (Eq. (6)) and over-binding clamp factor (Alg. 2) of one (x, y) point from
+// its coarse bound density B: B > m_total scales the point's motor columns by m_total / B and
+// leaves no free motors; otherwise factor 1 and pool m_total - B.
+template <typename T>
+__host__ __device__ inline void depletion_of(T B, T m_total, T &scale, T &pool) {
+    if (B > m_total) {
+        scale = m_total / B;
+        pool = T(0);
+    } else {
+        scale = T(1);
+        pool = m_total - B;
+    }
+}
 
 // Precomputed angle tables: [9][nth] = cos th_k, sin th_k, cos th_{k+1/2}, sin th_{k+1/2},
 // cos(2 th_k)/2, sin(2 th_k)/2, cos^2, cos sin, sin^2.
@@ -51,12 +66,13 @@ PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem, int nfields);
 // Donor-cell update psi_out = psi_in - dt div(flux).  If `stress` is non-null, also writes
 // stress[3][nx][ny], mom[7][nx][ny] of (psi_out, m0, m1) and per-block FP64 partials
 // partials[blocks][4] = (sum psi_out, sum sxx, sum sxy, sum syy).
-// Bxy (non-null) receives the coarse bound density sum_th psi_out m0 dth per (x, y) on every
-// step (one fixed-order reduction, the same on output and plain steps).
+// Dxy (non-null) receives depletion_of(B) per (x, y) of the new state on every step, with the
+// coarse bound density B = sum_th psi_out m0 dth (one fixed-order reduction, the same on
+// output and plain steps).
 template <typename T>
 hipError_t launch_psi_step(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u,
                            const T *G, const T *tab, T *stress, T *mom, double *partials,
-                           T *Bxy, const PsiConst<T> &c, const PsiLaunch &pl, hipStream_t s);
+                           T *Dxy, const PsiConst<T> &c, const PsiLaunch &pl, hipStream_t s);
 
 // LDS-free psi step for ntheta = 64 or 128: tiles of ti x 4 pencils, one wave walking each
 // row of ti pencils along x; XCD-banded blocks (8 * per).
@@ -70,14 +86,15 @@ WalkPlan plan_walk(int nx, int ny, int nth);
 // Same update and outputs as launch_psi_step, with the walking kernel.
 template <typename T>
 hipError_t launch_psi_walk(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u, const T *G,
-                           const T *tab, T *stress, T *mom, double *partials, T *Bxy, const PsiConst<T> &c,
+                           const T *tab, T *stress, T *mom, double *partials, T *Dxy, const PsiConst<T> &c,
                            const WalkPlan &wp, hipStream_t s);
 
-// Coarse bound density of a state: Bxy[x][y] = dth ds sum_{th, s} psi[x][y][th] M[x][y][th][s]
-// (M NULL: zero).  Compensated sums in FP32.
+// depletion_of() of the coarse bound density of a state,
+// B[x][y] = dth ds sum_{th, s} psi[x][y][th] M[x][y][th][s] (M NULL: zero), into Dxy[x][y][2].
+// Compensated sums in FP32.
 template <typename T>
-hipError_t launch_coarse_bound(const T *M, const T *psi, T *Bxy, int64_t nxy, int nth, int ns, T ds, T dth,
-                               hipStream_t s);
+hipError_t launch_coarse_bound(const T *M, const T *psi, T *Dxy, int64_t nxy, int nth, int ns, T ds, T dth,
+                               T m_total, hipStream_t s);
 
 // Fixed-order compensated FP64 sum of partials[n][4] -> out[4] * scale[4].
 hipError_t launch_reduce_partials(const double *partials, int n, double *out, double s0,

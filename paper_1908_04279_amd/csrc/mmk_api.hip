@@ -29,7 +29,7 @@ constexpr int kProfMax = 65536;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t M[2], psi[2], m0, m1, Bxy, u, G, stress, mom, tab, partials, sums;
+    size_t M[2], psi[2], m0, m1, Dxy, u, G, stress, mom, tab, partials, sums;
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -84,7 +84,7 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.psi[1] = take(np * e);
     L.m0 = take(np * e);
     L.m1 = take(np * e);
-    L.Bxy = take(nxy * e);
+    L.Dxy = take(2 * nxy * e);
     L.u = take(2 * nxy * e);
     L.G = take(4 * nxy * e);
     L.stress = take(3 * nxy * e);
@@ -181,8 +181,8 @@ static mmk_status motor_half(mmk_ctx *c, const T *M_in, T *M_out, T *m0, T *m1, 
     const mmk_params &p = c->p;
     int slot;
     HIPCHK(c, prof_begin_on(c, 0, &slot, s), "hipEventRecord");
-    const T *Bxy = p.m_total > 0 ? c->at<T>(c->L.Bxy) : nullptr;
-    HIPCHK(c, launch_motor_step<T>(M_in, M_out, m0, m1, n_psi(p), p.ns, p.limiter, motor_const<T>(p, dt), Bxy, s),
+    const T *Dxy = p.m_total > 0 ? c->at<T>(c->L.Dxy) : nullptr;
+    HIPCHK(c, launch_motor_step<T>(M_in, M_out, m0, m1, n_psi(p), p.ns, p.limiter, motor_const<T>(p, dt), Dxy, s),
            "motor step launch");
     HIPCHK(c, prof_end_on(c, 0, slot, s), "hipEventRecord");
     return MMK_OK;
@@ -195,13 +195,13 @@ static mmk_status psi_half(mmk_ctx *c, const T *psi_in, T *psi_out, const T *m0,
     HIPCHK(c, prof_begin_on(c, 1, &slot, s), "hipEventRecord");
     T *stress = out ? c->at<T>(c->L.stress) : nullptr, *mom = out ? c->at<T>(c->L.mom) : nullptr;
     double *part = out ? c->at<double>(c->L.partials) : nullptr;
-    T *Bxy = c->p.m_total > 0 ? c->at<T>(c->L.Bxy) : nullptr;  // coarse bound density of the new state
+    T *Dxy = c->p.m_total > 0 ? c->at<T>(c->L.Dxy) : nullptr;  // depletion factors of the new state
     if (c->walk)
-        HIPCHK(c, launch_psi_walk<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part, Bxy,
+        HIPCHK(c, launch_psi_walk<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part, Dxy,
                                      psi_const<T>(c->p, dt), c->wp, s),
                "psi step launch");
     else
-        HIPCHK(c, launch_psi_step<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part, Bxy,
+        HIPCHK(c, launch_psi_step<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part, Dxy,
                                      psi_const<T>(c->p, dt), c->pl, s),
                "psi step launch");
     HIPCHK(c, prof_end_on(c, 1, slot, s), "hipEventRecord");
@@ -414,18 +414,18 @@ mmk_status mmk_set_state(mmk_ctx *c, const void *psi, const void *M) {
     } else {
         HIPCHK(c, launch_zero<double>(c->at<double>(c->L.M[c->cur]), n_m(c->p), c->stream), "zero M");
     }
-    if (c->p.m_total > 0) {  // coarse bound density of the new state, for the first step's depletion
+    if (c->p.m_total > 0) {  // depletion factors of the new state, for the first step
         const double ds = c->p.L / c->p.ns, dth = kTwoPi / c->p.ntheta;
         const int64_t nxy = (int64_t)c->p.nx * c->p.ny;
         hipError_t e;
         if (c->esz == 4)
             e = launch_coarse_bound<float>(M ? c->at<float>(c->L.M[c->cur]) : nullptr, c->at<float>(c->L.psi[c->cur]),
-                                           c->at<float>(c->L.Bxy), nxy, c->p.ntheta, c->p.ns, (float)ds, (float)dth,
-                                           c->stream);
+                                           c->at<float>(c->L.Dxy), nxy, c->p.ntheta, c->p.ns, (float)ds, (float)dth,
+                                           (float)c->p.m_total, c->stream);
         else
             e = launch_coarse_bound<double>(M ? c->at<double>(c->L.M[c->cur]) : nullptr,
-                                            c->at<double>(c->L.psi[c->cur]), c->at<double>(c->L.Bxy), nxy,
-                                            c->p.ntheta, c->p.ns, ds, dth, c->stream);
+                                            c->at<double>(c->L.psi[c->cur]), c->at<double>(c->L.Dxy), nxy,
+                                            c->p.ntheta, c->p.ns, ds, dth, c->p.m_total, c->stream);
         HIPCHK(c, e, "coarse bound density launch");
     }
     c->have_state = true;

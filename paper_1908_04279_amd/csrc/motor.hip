@@ -75,13 +75,23 @@ template <typename T, int CPL, int LPC, int LIM, bool RAGGED, bool WANT_M1, bool
 __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, T *__restrict__ M_out,
                                                     T *__restrict__ m0, T *__restrict__ m1,
                                                     int64_t ncol, int ns, MotorConst<T> c,
-                                                    const T *__restrict__ Bxy) {
+                                                    const T *__restrict__ Dxy) {
     constexpr int COLS = 256 / LPC;
     const int g = threadIdx.x % LPC;
     const int64_t col = (int64_t)blockIdx.x * COLS + threadIdx.x / LPC;
     const bool active = col < ncol;
     const int l0 = g * CPL;
     const int64_t base = col * (int64_t)ns + l0;
+
+    // free-motor depletion (Eq. (6)) with the over-binding clamp of Alg. 2: the clamp factor
+    // and the free pool of this column's (x, y), loaded beside the column
+    T scale = T(1), pool = T(0);
+    if (Dxy) {
+        const int64_t cc = active ? col : 0;
+        const int64_t xy = c.nth_shift >= 0 ? (cc >> c.nth_shift) : cc / c.nth;
+        scale = Dxy[2 * xy];
+        pool = Dxy[2 * xy + 1];
+    }
 
     T x[CPL];
     if constexpr (!RAGGED) {
@@ -96,20 +106,11 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
         for (int j = 0; j < CPL; ++j) x[j] = (active && l0 + j < ns) ? M_in[base + j] : T(0);
     }
 
-    // free-motor depletion (Eq. (6)) with the over-binding clamp of Alg. 2, from the coarse
-    // bound density of the current state at this column's (x, y)
     T src = c.k_on;
-    if (Bxy) {
-        const int64_t xy = c.nth_shift >= 0 ? (col >> c.nth_shift) : col / c.nth;
-        const T B = active ? Bxy[xy] : T(0);
-        if (B > c.m_total) {
-            const T scale = c.m_total / B;
+    if (Dxy) {
 #pragma unroll
-            for (int j = 0; j < CPL; ++j) x[j] *= scale;
-            src = T(0);
-        } else {
-            src = c.k_on * (c.m_total - B);
-        }
+        for (int j = 0; j < CPL; ++j) x[j] *= scale;
+        src = c.k_on * pool;
     }
 
     T R[CPL], y[CPL];
@@ -303,13 +304,13 @@ static hipError_t launch_chunked(const T *M_in, T *M_out, T *m0, T *m1, int64_t 
 
 template <typename T, int CPL, int LPC, bool RAGGED, int LIM, bool NT>
 static hipError_t launch_nt(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
-                            const MotorConst<T> &c, const T *Bxy, hipStream_t s, unsigned blocks) {
+                            const MotorConst<T> &c, const T *Dxy, hipStream_t s, unsigned blocks) {
     if (m1)
         hipLaunchKernelGGL((k_motor_step<T, CPL, LPC, LIM, RAGGED, true, NT>), dim3(blocks), dim3(256), 0, s,
-                           M_in, M_out, m0, m1, ncol, ns, c, Bxy);
+                           M_in, M_out, m0, m1, ncol, ns, c, Dxy);
     else
         hipLaunchKernelGGL((k_motor_step<T, CPL, LPC, LIM, RAGGED, false, NT>), dim3(blocks), dim3(256), 0, s,
-                           M_in, M_out, m0, m1, ncol, ns, c, Bxy);
+                           M_in, M_out, m0, m1, ncol, ns, c, Dxy);
     return hipGetLastError();
 }
 
@@ -325,22 +326,22 @@ static bool motor_nontemporal(int elem) {
 
 template <typename T, int CPL, int LPC, bool RAGGED, int LIM>
 static hipError_t launch_lim(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
-                             const MotorConst<T> &c, const T *Bxy, hipStream_t s, unsigned blocks) {
+                             const MotorConst<T> &c, const T *Dxy, hipStream_t s, unsigned blocks) {
     if (!RAGGED && motor_nontemporal((int)sizeof(T)))
-        return launch_nt<T, CPL, LPC, RAGGED, LIM, true>(M_in, M_out, m0, m1, ncol, ns, c, Bxy, s, blocks);
-    return launch_nt<T, CPL, LPC, RAGGED, LIM, false>(M_in, M_out, m0, m1, ncol, ns, c, Bxy, s, blocks);
+        return launch_nt<T, CPL, LPC, RAGGED, LIM, true>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, blocks);
+    return launch_nt<T, CPL, LPC, RAGGED, LIM, false>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, blocks);
 }
 
 template <typename T, int CPL, int LPC, bool RAGGED>
 static hipError_t launch_cfg(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
-                             int limiter, const MotorConst<T> &c, const T *Bxy, hipStream_t s) {
+                             int limiter, const MotorConst<T> &c, const T *Dxy, hipStream_t s) {
     constexpr int COLS = 256 / LPC;
     const int64_t blocks = (ncol + COLS - 1) / COLS;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
     if (limiter == 0)
-        return launch_lim<T, CPL, LPC, RAGGED, 0>(M_in, M_out, m0, m1, ncol, ns, c, Bxy, s, (unsigned)blocks);
-    return launch_lim<T, CPL, LPC, RAGGED, 1>(M_in, M_out, m0, m1, ncol, ns, c, Bxy, s, (unsigned)blocks);
+        return launch_lim<T, CPL, LPC, RAGGED, 0>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, (unsigned)blocks);
+    return launch_lim<T, CPL, LPC, RAGGED, 1>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, (unsigned)blocks);
 }
 
 // Lanes per column for the exact tilings (0: use the masked generic kernel).  Default: 16
@@ -375,8 +376,8 @@ static int chunks_per_lane(int ns, int elem) {
 
 template <typename T>
 hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
-                             int limiter, const MotorConst<T> &c, const T *Bxy, hipStream_t s) {
-    const int nch = Bxy ? 1 : chunks_per_lane(ns, (int)sizeof(T));  // chunked: no depletion
+                             int limiter, const MotorConst<T> &c, const T *Dxy, hipStream_t s) {
+    const int nch = Dxy ? 1 : chunks_per_lane(ns, (int)sizeof(T));  // chunked: no depletion
     if (nch > 1) {
         const bool nt = motor_nontemporal((int)sizeof(T));
         const int lpc = ns / (nch * (16 / (int)sizeof(T)));
@@ -389,7 +390,7 @@ hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
     const int lpc = lanes_per_column(ns, (int)sizeof(T));
 #define MMK_MOTOR_CASE(NS, LPC)                                                                   \
     if (ns == NS && lpc == LPC)                                                                   \
-        return launch_cfg<T, NS / LPC, LPC, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
+        return launch_cfg<T, NS / LPC, LPC, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Dxy, s);
     if constexpr (sizeof(T) == 4) {
         MMK_MOTOR_CASE(8, 2) MMK_MOTOR_CASE(16, 4) MMK_MOTOR_CASE(32, 8) MMK_MOTOR_CASE(64, 16)
         MMK_MOTOR_CASE(64, 8) MMK_MOTOR_CASE(128, 32) MMK_MOTOR_CASE(128, 16) MMK_MOTOR_CASE(256, 64)
@@ -401,12 +402,12 @@ hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
     }
 #undef MMK_MOTOR_CASE
     // any other length: 16 lanes per column, masked tail cells, scalar loads
-    if (ns <= 16) return launch_cfg<T, 1, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
-    if (ns <= 32) return launch_cfg<T, 2, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
-    if (ns <= 64) return launch_cfg<T, 4, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
-    if (ns <= 128) return launch_cfg<T, 8, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
-    if (ns <= 256) return launch_cfg<T, 16, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
-    if (ns <= 512) return launch_cfg<T, 32, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Bxy, s);
+    if (ns <= 16) return launch_cfg<T, 1, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Dxy, s);
+    if (ns <= 32) return launch_cfg<T, 2, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Dxy, s);
+    if (ns <= 64) return launch_cfg<T, 4, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Dxy, s);
+    if (ns <= 128) return launch_cfg<T, 8, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Dxy, s);
+    if (ns <= 256) return launch_cfg<T, 16, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Dxy, s);
+    if (ns <= 512) return launch_cfg<T, 32, 16, true>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Dxy, s);
     return hipErrorInvalidValue;
 }
 

@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
                                                   const T *__restrict__ u, const T *__restrict__ Gr,
                                                   const T *__restrict__ tab, T *__restrict__ stress,
                                                   T *__restrict__ mom, double *__restrict__ partials,
-                                                  T *__restrict__ Bxy, PsiConst<T> c, PsiLaunch pl) {
+                                                  T *__restrict__ Dxy, PsiConst<T> c, PsiLaunch pl) {
     constexpr bool FIXED = NTH_C > 0 && TI_C > 0 && TJ_C > 0;
     extern __shared__ __align__(16) unsigned char smem[];
     const int nx = c.nx, ny = c.ny;
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
             const T div = (fxp - fxm) * c.inv_dx + (fyp - fym) * c.inv_dy + (ftp - ftm) * c.inv_dth;
             const T pn = ps - c.dt * div;
             psi_out[pen * nth + k] = pn;
-            if (Bxy) {
+            if (Dxy) {
                 if (first) bs = pn * mc;
                 else kahan_add(bs, bc, pn * mc);
             }
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
         } else {
             for (int k = kk; k < nth; k += G) cell(angle_k(s_tab, nth, k), 0, k == kk);
         }
-        if (Bxy) {
+        if (Dxy) {
             T tb;
             if constexpr (FIXED) {
                 tb = pencil_total<(NTH_C <= 16 ? 16 : (NTH_C <= 32 ? 32 : 64))>(bs, bc);
@@ -449,7 +449,12 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
             } else {
                 tb = pencil_total<16>(bs, bc);
             }
-            if (kk == 0) Bxy[pen] = tb * c.dth;
+            if (kk == 0) {
+                T sc, pool;
+                depletion_of(tb * c.dth, c.m_total, sc, pool);
+                Dxy[2 * pen] = sc;
+                Dxy[2 * pen + 1] = pool;
+            }
         }
         if (out) {
             // one lane per quantity stores its total (moments 0..6, stress 7..9)
@@ -498,19 +503,19 @@ __global__ __launch_bounds__(256) void k_psi_step(const T *__restrict__ psi_in, 
 
 template <typename T, int NTH, int TI, int TJ>
 static void launch_fixed(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u, const T *G,
-                         const T *tab, T *stress, T *mom, double *partials, T *Bxy, const PsiConst<T> &c,
+                         const T *tab, T *stress, T *mom, double *partials, T *Dxy, const PsiConst<T> &c,
                          const PsiLaunch &pl, hipStream_t s) {
     hipLaunchKernelGGL((k_psi_step<T, NTH, TI, TJ>), dim3(pl.blocks), dim3(256), pl.lds_bytes, s, psi_in,
-                       psi_out, m0, m1, u, G, tab, stress, mom, partials, Bxy, c, pl);
+                       psi_out, m0, m1, u, G, tab, stress, mom, partials, Dxy, c, pl);
 }
 
 template <typename T>
 hipError_t launch_psi_step(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u,
-                           const T *G, const T *tab, T *stress, T *mom, double *partials, T *Bxy,
+                           const T *G, const T *tab, T *stress, T *mom, double *partials, T *Dxy,
                            const PsiConst<T> &c, const PsiLaunch &pl, hipStream_t s) {
 #define MMK_PSI_CASE(N, A, B)                                                                             \
     if (c.nth == N && pl.ti == A && pl.tj == B) {                                                         \
-        launch_fixed<T, N, A, B>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, Bxy, c, pl, s); \
+        launch_fixed<T, N, A, B>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, Dxy, c, pl, s); \
         return hipGetLastError();                                                                    \
     }
 #define MMK_PSI_TILES(N) MMK_PSI_CASE(N, 8, 8) MMK_PSI_CASE(N, 4, 8) MMK_PSI_CASE(N, 4, 4) MMK_PSI_CASE(N, 2, 4)
@@ -521,7 +526,7 @@ hipError_t launch_psi_step(const T *psi_in, T *psi_out, const T *m0, const T *m1
 #undef MMK_PSI_TILES
 #undef MMK_PSI_CASE
     hipLaunchKernelGGL((k_psi_step<T, 0, 0, 0>), dim3(pl.blocks), dim3(256), pl.lds_bytes, s, psi_in, psi_out,
-                       m0, m1, u, G, tab, stress, mom, partials, Bxy, c, pl);
+                       m0, m1, u, G, tab, stress, mom, partials, Dxy, c, pl);
     return hipGetLastError();
 }
 
@@ -715,12 +720,12 @@ hipError_t launch_reduce_partials(const double *partials, int n, double *out, do
 
 // Coarse bound density of a state (start of a depleted run): one block per (x, y) point sums
 // psi[th] M[th][s] over the point's nth * ns cells, Kahan per thread and a TwoSum tree over
-// the block, times ds dth.
+// the block, times ds dth; stores depletion_of() of it.
 #pragma clang fp contract(off)
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_bound(const T *__restrict__ M, const T *__restrict__ psi,
-                                                      T *__restrict__ Bxy, int64_t nxy, int nth, int ns, T ds,
-                                                      T dth) {
+                                                      T *__restrict__ Dxy, int64_t nxy, int nth, int ns, T ds,
+                                                      T dth, T m_total) {
     __shared__ T sh[256], se[256];
     const int t = threadIdx.x;
     const int64_t n = (int64_t)nth * ns;
@@ -740,25 +745,30 @@ __global__ __launch_bounds__(256) void k_coarse_bound(const T *__restrict__ M, c
             }
             __syncthreads();
         }
-        if (t == 0) Bxy[xy] = (sh[0] + se[0]) * ds * dth;
+        if (t == 0) {
+            T sc, pool;
+            depletion_of((sh[0] + se[0]) * ds * dth, m_total, sc, pool);
+            Dxy[2 * xy] = sc;
+            Dxy[2 * xy + 1] = pool;
+        }
         __syncthreads();
     }
 }
 #pragma clang fp contract(on)
 
 template <typename T>
-hipError_t launch_coarse_bound(const T *M, const T *psi, T *Bxy, int64_t nxy, int nth, int ns, T ds, T dth,
-                               hipStream_t s) {
+hipError_t launch_coarse_bound(const T *M, const T *psi, T *Dxy, int64_t nxy, int nth, int ns, T ds, T dth,
+                               T m_total, hipStream_t s) {
     if (nxy <= 0) return hipSuccess;
     const int64_t blocks = nxy < 65536 ? nxy : 65536;
-    hipLaunchKernelGGL(k_coarse_bound<T>, dim3((unsigned)blocks), dim3(256), 0, s, M, psi, Bxy, nxy, nth, ns, ds,
-                       dth);
+    hipLaunchKernelGGL(k_coarse_bound<T>, dim3((unsigned)blocks), dim3(256), 0, s, M, psi, Dxy, nxy, nth, ns, ds,
+                       dth, m_total);
     return hipGetLastError();
 }
 template hipError_t launch_coarse_bound<float>(const float *, const float *, float *, int64_t, int, int, float,
-                                               float, hipStream_t);
+                                               float, float, hipStream_t);
 template hipError_t launch_coarse_bound<double>(const double *, const double *, double *, int64_t, int, int,
-                                                double, double, hipStream_t);
+                                                double, double, double, hipStream_t);
 
 template <typename T>
 __global__ void k_zero(T *out, int64_t n) {

@@ -133,14 +133,15 @@ __device__ __forceinline__ int wrap(int i, int n) {
 // pencil.
 //
 // Same flux and update expressions as the LDS-tiled kernel; OUT adds the theta-moments, the
-// stress and the FP64 block partials (mass, sum sigma) of the new state.
-template <typename T, int KPL, int TI, bool OUT>
+// stress and the FP64 block partials (mass, sum sigma) of the new state; DEPL adds the
+// depletion factors of the new state (Dxy).
+template <typename T, int KPL, int TI, bool OUT, bool DEPL>
 __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *__restrict__ psi_out,
                                               const T *__restrict__ m0, const T *__restrict__ m1,
                                               const T *__restrict__ u, const T *__restrict__ Gr,
                                               const T *__restrict__ tab, T *__restrict__ stress,
                                               T *__restrict__ mom, double *__restrict__ partials,
-                                              T *__restrict__ Bxy, const PsiConst<T> &c, int tiles_i,
+                                              T *__restrict__ Dxy, const PsiConst<T> &c, int tiles_i,
                                               int tiles_j, int per, int vblock) {
     constexpr int NTH = 64 * KPL;
     constexpr bool COMP = std::is_same<T, float>::value;
@@ -245,7 +246,7 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
                 const T div = (fxp[s] - fxm[s]) * c.inv_dx + (fyp[s] - fym[s]) * c.inv_dy + (ftp[s] - ftm) * c.inv_dth;
                 const T pn = Pc[s] - c.dt * div;
                 psi_out[pc * NTH + k] = pn;
-                if (Bxy) {
+                if constexpr (DEPL) {
                     if (s == 0) bs = pn * Mc[s];
                     else kahan_add(bs, bc, pn * Mc[s]);
                 }
@@ -268,9 +269,14 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
                     acc_mass += (double)pn;
                 }
             }
-            if (Bxy) {
+            if constexpr (DEPL) {
                 const T tb = pencil_total<64>(bs, bc);
-                if (lane == 0) Bxy[pc] = tb * c.dth;
+                if (lane == 0) {
+                    T sc, pool;
+                    depletion_of(tb * c.dth, c.m_total, sc, pool);
+                    Dxy[2 * pc] = sc;
+                    Dxy[2 * pc + 1] = pool;
+                }
             }
             if constexpr (OUT) {
                 int qm;

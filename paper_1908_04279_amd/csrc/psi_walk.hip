@@ -17,32 +17,36 @@ WalkPlan plan_walk(int nx, int ny, int nth) {
     return w;
 }
 
-template <typename T, int KPL, int TI, bool OUT>
+template <typename T, int KPL, int TI, bool OUT, bool DEPL>
 __global__ __launch_bounds__(256) void k_psi_walk(const T *__restrict__ psi_in, T *__restrict__ psi_out,
                                                   const T *__restrict__ m0, const T *__restrict__ m1,
                                                   const T *__restrict__ u, const T *__restrict__ G,
                                                   const T *__restrict__ tab, T *__restrict__ stress,
                                                   T *__restrict__ mom, double *__restrict__ partials,
-                                                  T *__restrict__ Bxy, PsiConst<T> c, int tiles_i, int tiles_j,
+                                                  T *__restrict__ Dxy, PsiConst<T> c, int tiles_i, int tiles_j,
                                                   int per) {
-    psi_walk_tile<T, KPL, TI, OUT>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, Bxy, c, tiles_i,
+    psi_walk_tile<T, KPL, TI, OUT, DEPL>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, Dxy, c, tiles_i,
                                    tiles_j, per, (int)blockIdx.x);
 }
 
 template <typename T>
 hipError_t launch_psi_walk(const T *psi_in, T *psi_out, const T *m0, const T *m1, const T *u, const T *G,
-                           const T *tab, T *stress, T *mom, double *partials, T *Bxy, const PsiConst<T> &c,
+                           const T *tab, T *stress, T *mom, double *partials, T *Dxy, const PsiConst<T> &c,
                            const WalkPlan &wp, hipStream_t s) {
     if (!wp.ok || wp.ti != 8) return hipErrorInvalidValue;
     const bool out = stress != nullptr;
-#define MMK_WALK(KPL, OUT)                                                                                  \
-    hipLaunchKernelGGL((k_psi_walk<T, KPL, 8, OUT>), dim3(wp.blocks), dim3(256), 0, s, psi_in, psi_out, m0, m1, u, \
-                       G, tab, stress, mom, partials, Bxy, c, wp.tiles_i, wp.tiles_j, wp.per)
+#define MMK_WALK(KPL, OUT, DEPL)                                                                           \
+    hipLaunchKernelGGL((k_psi_walk<T, KPL, 8, OUT, DEPL>), dim3(wp.blocks), dim3(256), 0, s, psi_in, psi_out, m0, \
+                       m1, u, G, tab, stress, mom, partials, Dxy, c, wp.tiles_i, wp.tiles_j, wp.per)
+#define MMK_WALK_D(KPL, OUT)                 \
+    if (Dxy) MMK_WALK(KPL, OUT, true);       \
+    else MMK_WALK(KPL, OUT, false);
     if (wp.kpl == 1) {
-        if (out) MMK_WALK(1, true); else MMK_WALK(1, false);
+        if (out) { MMK_WALK_D(1, true) } else { MMK_WALK_D(1, false) }
     } else {
-        if (out) MMK_WALK(2, true); else MMK_WALK(2, false);
+        if (out) { MMK_WALK_D(2, true) } else { MMK_WALK_D(2, false) }
     }
+#undef MMK_WALK_D
 #undef MMK_WALK
     return hipGetLastError();
 }
