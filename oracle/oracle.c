@@ -289,6 +289,41 @@ void oracle_global_sums(const oracle_params *p, const double *psi, const double 
         for (int c = 0; c < 3; ++c) sum_sigma[c] = neumaier(stress + c * nxy, nxy) * (dx * dy);
 }
 
+/* Eq. (10) with the delta function of the immersed-boundary spreading taken as the two-point
+ * hat in each direction: a point force at x_h lands on the four cell centres around it with
+ * the bilinear weights (1 - a)(1 - b), a(1 - b), (1 - a)b, ab.  The y-integral's dx dy cancels
+ * the hat's 1/(dx dy), so each motor cell adds F p psi M ds dth times its weights. */
+void oracle_motor_force(const oracle_params *p, const double *psi, const double *M, double *force) {
+    const long nx = p->nx, ny = p->ny, nth = p->nth;
+    const int ns = p->ns;
+    const long nxy = nx * ny;
+    const double dx = p->lx / nx, dy = p->ly / ny, dth = TWO_PI / nth, ds = p->L / ns;
+    for (long o = 0; o < 2 * nxy; ++o) force[o] = 0.0;
+    for (long i = 0; i < nx; ++i)
+        for (long j = 0; j < ny; ++j)
+            for (long k = 0; k < nth; ++k) {
+                const double th = k * dth, co = cos(th), si = sin(th);
+                const double ps = psi[IDX3(i, j, k)];
+                for (int l = 0; l < ns; ++l) {
+                    const double lever = (l + 0.5) * ds - 0.5 * p->L;
+                    const double hx = (i + 0.5) * dx + lever * co, hy = (j + 0.5) * dy + lever * si;
+                    /* fractional cell-centre index of the head, its lower neighbour and weight */
+                    const double fx = hx / dx - 0.5, fy = hy / dy - 0.5;
+                    const double ix = floor(fx), iy = floor(fy);
+                    const double ax = fx - ix, ay = fy - iy;
+                    const long i0 = (((long)ix % nx) + nx) % nx, j0 = (((long)iy % ny) + ny) % ny;
+                    const long i1 = (i0 + 1) % nx, j1 = (j0 + 1) % ny;
+                    const double v = p->F * ps * M[IDX3(i, j, k) * ns + l] * ds * dth;
+                    const double w[4] = {(1 - ax) * (1 - ay), ax * (1 - ay), (1 - ax) * ay, ax * ay};
+                    const long cell[4] = {IDX2(i0, j0), IDX2(i1, j0), IDX2(i0, j1), IDX2(i1, j1)};
+                    for (int q = 0; q < 4; ++q) {
+                        force[cell[q]] += v * co * w[q];
+                        force[nxy + cell[q]] += v * si * w[q];
+                    }
+                }
+            }
+}
+
 /* Coarse bound-motor density: Eq. (5) integrates the bound motors of every filament over
  * s, x and th at an anchor r0; in the anchor-marginal reading the bound motors per unit area
  * at (x, y) are sum over th of psi times the motors per filament m0. */

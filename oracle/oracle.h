@@ -60,6 +60,12 @@ void oracle_moments(const oracle_params *p, const double *psi, const double *m0,
 void oracle_global_sums(const oracle_params *p, const double *psi, const double *stress,
                         double *mass, double *sum_sigma);
 
+/* Motor force density F2 [2][nx][ny] of the state (psi, M), Eq. (10): the bound motors of cell l
+ * of a filament centred at (x_i, y_j) with orientation p_k push with F p_k psi M_l ds dth; each
+ * acts at the motor head x_h = (x_i, y_j) + (s_l - L/2) p_k and is spread onto the grid with the
+ * two-point hat (bilinear) kernel, periodic in x and y.  Sequential loops (scatter). */
+void oracle_motor_force(const oracle_params *p, const double *psi, const double *M, double *force);
+
 /* nsteps micro-steps with one fluid field; psi and M are updated in place.
  * m0/m1 receive the moments of the final M (either may be NULL).  With m_total > 0 each
  * micro-step starts with the depletion of oracle_depletion on the current state. */

@@ -43,6 +43,7 @@ def lib():
         L.oracle_column_step_src.argtypes = [P, C.c_double, _dp, C.c_double, _dp]
         L.oracle_coarse_bound.argtypes = [P, _dp, _dp, _dp]
         L.oracle_depletion.argtypes = [P, _dp, _dp, _dp]
+        L.oracle_motor_force.argtypes = [P, _dp, _dp, _dp]
         L.oracle_column_moments.argtypes = [P, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.oracle_motor_step.argtypes = [P, C.c_double, _dp, _dp, C.c_void_p, C.c_void_p]
         L.oracle_psi_step.argtypes = [P, C.c_double, _dp, _dp, _dp, _dp, _dp]
@@ -114,6 +115,13 @@ def depletion(p, B):
     src = np.empty_like(B)
     lib().oracle_depletion(C.byref(cparams(p)), B, scale, src)
     return scale, src
+
+
+def motor_force(p, psi, M):
+    """Motor force density [2][nx][ny] of (psi, M), Eq. (10) with the bilinear hat spreading."""
+    f = np.empty((2, p.nx, p.ny))
+    lib().oracle_motor_force(C.byref(cparams(p)), _f64(psi), _f64(M), f)
+    return f
 
 
 def column_moments(p, M):

@@ -108,6 +108,34 @@ def theta_moments(psi, m0, m1, F, sigma_f):
     return stress, mom
 
 
+def motor_force(psi, M, F, L, lx, ly):
+    """Eq. (10): F p psi M ds dth of every motor cell spread from its head position
+    (x, y) + (s - L/2) p onto the cell centres with the bilinear hat, periodic."""
+    nx, ny, nth, ns = M.shape
+    dx, dy, dth, ds = lx / nx, ly / ny, TWO_PI / nth, L / ns
+    th = torch.arange(nth, dtype=f64) * dth
+    co, si = torch.cos(th), torch.sin(th)
+    lever = (torch.arange(ns, dtype=f64) + 0.5) * ds - 0.5 * L
+    xc = (torch.arange(nx, dtype=f64) + 0.5) * dx
+    yc = (torch.arange(ny, dtype=f64) + 0.5) * dy
+    hx = xc[:, None, None, None] + lever[None, None, None, :] * co[None, None, :, None]
+    hy = yc[None, :, None, None] + lever[None, None, None, :] * si[None, None, :, None]
+    fx, fy = hx / dx - 0.5, hy / dy - 0.5
+    ix, iy = torch.floor(fx), torch.floor(fy)
+    ax, ay = fx - ix, fy - iy
+    i0 = torch.remainder(ix.long(), nx)
+    j0 = torch.remainder(iy.long(), ny)
+    i0, j0 = torch.broadcast_to(i0, M.shape), torch.broadcast_to(j0, M.shape)
+    v = F * psi[..., None] * M * (ds * dth)
+    out = torch.zeros(2, nx * ny, dtype=f64)
+    for di, dj, w in ((0, 0, (1 - ax) * (1 - ay)), (1, 0, ax * (1 - ay)), (0, 1, (1 - ax) * ay), (1, 1, ax * ay)):
+        cell = ((i0 + di) % nx) * ny + (j0 + dj) % ny
+        vw = torch.broadcast_to(v * w, M.shape)
+        out[0].index_add_(0, cell.reshape(-1), (vw * co[None, None, :, None]).reshape(-1))
+        out[1].index_add_(0, cell.reshape(-1), (vw * si[None, None, :, None]).reshape(-1))
+    return out.reshape(2, nx, ny)
+
+
 class Problem:
     """Grid constants of one run (plain attributes, float64 everywhere)."""
 
