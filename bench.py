@@ -6,8 +6,8 @@ field every K = 10 micro-steps, stress/moments/global sums on every exchange.  A
 one micro-step of the whole path: motor column step, s-moments, psi donor-cell update,
 and (every 10th) theta-moments, stress and FP64 global sums.  Inputs are resident in HBM
 before the timed region.  Also measured: the same grid in FP64, the same grid in FP32 with
-free-motor depletion, the adjoint/forward time ratios, and the oracle (FP64 C, OpenMP) on a
-bounded sample of the same grid on the host cores.
+free-motor depletion, the motor force density of the grid, the adjoint/forward time ratios,
+and the oracle (FP64 C, OpenMP) on a bounded sample of the same grid on the host cores.
 
 Prints one JSON line.  --gpus N > 1 is refused: this path runs on one GPU.
 """
@@ -181,6 +181,37 @@ def run_adjoint(name, precision):
     return out
 
 
+def run_force(p, precision, reps):
+    """Motor force density of a seeded state (Eq. (10)), timed over `reps` calls with HIP
+    events on the library's stream."""
+    import torch
+    from paper_1908_04279_amd import inputs as gen
+    from paper_1908_04279_amd import mmk
+    ctx = mmk.Context(p, precision=precision)
+    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0)
+    M0 = torch.rand(p.nx, p.ny, p.ntheta, p.ns, dtype=ctx.dtype, device=ctx.device,
+                    generator=torch.Generator(device=ctx.device).manual_seed(5)) * (p.k_on / p.k_off)
+    ctx.set_state(torch.as_tensor(psi0), M0)
+    for _ in range(2):
+        ctx.get_force()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.get_force()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, n = ctx.profile_read("motor_force")
+    ctx.profile(False)
+    ctx.close()
+    b = 4 if precision == mmk.FP32 else 8
+    n_psi = p.nx * p.ny * p.ntheta
+    alg = b * (n_psi * p.ns + n_psi + 2 * p.nx * p.ny)   # read M and psi, write the force
+    us = ms / n * 1e3
+    return {"avg_us": us, "wall_us_per_call": el / reps * 1e6, "algorithmic_bytes": alg,
+            "gbs": alg / (us * 1e-6) / 1e9, "frac": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "calls": n}
+
+
 def copy_calibration(nbytes, reps):
     """A plain device copy of known size (for scaling the HBM byte counters)."""
     import torch
@@ -248,7 +279,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64", "depletion"], default="all",
+    ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64", "depletion", "force"],
+                    default="all",
                     help="restrict to one leg (used for profiler runs)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--depletion-steps", type=int, default=200)
@@ -274,6 +306,10 @@ def main():
         return
     if args.only == "adjoint64":
         print(json.dumps({"adjoint_fp64": run_adjoint("c4_adjoint_fp64_64x64x32x32", mmk.FP64)}), flush=True)
+        return
+    if args.only == "force":
+        print(json.dumps({"force_fp32": run_force(gen.params_for("c3_fp32_256x256x64x64"), mmk.FP32, 10)}),
+              flush=True)
         return
 
     p = gen.params_for("c3_fp32_256x256x64x64")
@@ -346,6 +382,9 @@ def main():
                        "motor_frac": s64["gbs"] / HBM_PEAK_GBS, "motor_avg_us": s64["avg_us"],
                        "steps": res["fp64"]["steps"]}
         out["fp32_over_fp64"] = s["steps_per_s"] / s64["steps_per_s"]
+    if args.only == "all":
+        log("[bench] motor force leg")
+        out["force_fp32"] = run_force(p, mmk.FP32, 10)
     if "depletion" in res:
         out["depletion_fp32"] = depletion_summary()
         out["depletion_fp32"]["relative_to_linear"] = out["depletion_fp32"]["micro_steps_per_s"] / s["steps_per_s"]

@@ -112,6 +112,15 @@ mmk_status mmk_get_stress(mmk_ctx *ctx, void *sigma);
 mmk_status mmk_get_moments(mmk_ctx *ctx, void *moments);
 /* s-moments of the current M: m0 always, m1 as of the last step that produced outputs. */
 mmk_status mmk_get_motor_moments(mmk_ctx *ctx, void *m0, void *m1);
+/* Motor force density of the current state (Eq. (10)), force [2][nx][ny] = (f_x, f_y): every
+ * bound-motor cell l of a filament at (x_i, y_j) with orientation p_k adds F p_k psi M_l ds dth
+ * at its head (x_i, y_j) + (s_l - L/2) p_k, spread onto the cell centres with the two-point
+ * hat (bilinear) in x and y, periodic.  The filament length L is in the units of lx, ly.
+ * Same bits on every run (each spreading window is private to one wave and summed in a fixed
+ * order).  Needs state; MMK_ERR_UNSUPPORTED if the filament's reach makes the spreading window
+ * larger than 3072 cells ((8 + 2 rx + 1)(8 + 2 ry + 1), rx = ceil(L nx / (2 lx)) + 1) or the
+ * device's LDS per block.  No host sync. */
+mmk_status mmk_get_force(mmk_ctx *ctx, void *force);
 /* host outputs, synchronizes: mass = sum Psi dx dy dth and sum_sigma[c] = sum sigma_c dx dy,
  * both accumulated in FP64 in a fixed order (bitwise reproducible). */
 mmk_status mmk_get_sums(mmk_ctx *ctx, double *mass, double sum_sigma[3]);
@@ -132,8 +141,9 @@ mmk_status mmk_tape_end(mmk_ctx *ctx);
 /* Kernel timing: with enable = N > 0 every N-th launch of each kernel is bracketed by HIP
  * events on the context's stream (enable = 0 turns timing off, < 0 is MMK_ERR_ARG).
  * mmk_profile_read (synchronizes) sums the elapsed times of the timed launches of `kernel_id`
- * (0 motor step, 1 psi step, 2 global sums, 3 reverse psi step, 4 reverse motor step) since
- * profiling was enabled; up to 65536 launches per id are timed. */
+ * (0 motor step, 1 psi step, 2 global sums, 3 reverse psi step, 4 reverse motor step, 5 motor
+ * force: spreading and merge) since profiling was enabled; up to 65536 launches per id are
+ * timed. */
 mmk_status mmk_profile(mmk_ctx *ctx, int32_t enable);
 mmk_status mmk_profile_read(mmk_ctx *ctx, int32_t kernel_id, double *total_ms, int64_t *launches);
 

@@ -5,6 +5,7 @@
 #include "consts.h"
 #include "kernels.h"
 #include "tape.h"
+#include "force.h"
 
 #include <hip/hip_runtime.h>
 
@@ -23,13 +24,13 @@ namespace {
 thread_local std::string g_create_error;
 constexpr int kMaxTheta = 512;
 constexpr int kMaxS = 512;
-constexpr int kProfIds = 5;
+constexpr int kProfIds = 6;
 constexpr int kProfMax = 65536;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t M[2], psi[2], m0, m1, Dxy, u, G, stress, mom, tab, partials, sums;
+    size_t M[2], psi[2], m0, m1, Dxy, fpart, frec, fexy, fw, fcs, u, G, stress, mom, tab, partials, sums;
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -85,6 +86,13 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.m0 = take(np * e);
     L.m1 = take(np * e);
     L.Dxy = take(2 * nxy * e);
+    L.fpart = take(plan_force(p.nx, p.ny, p.ns, p.lx, p.ly, p.L, e).part_elems * sizeof(double));
+    const int fch = force_chunk(e);  // spreading records of the force, per (orientation, cell)
+    const size_t nrec = (size_t)p.ntheta * ((p.ns + fch - 1) / fch) * fch;
+    L.frec = take(2 * nrec * sizeof(int));
+    L.fexy = take(2 * (size_t)p.ntheta * sizeof(int));
+    L.fw = take(4 * nrec * e);
+    L.fcs = take(2 * (size_t)p.ntheta * sizeof(double));
     L.u = take(2 * nxy * e);
     L.G = take(4 * nxy * e);
     L.stress = take(3 * nxy * e);
@@ -117,12 +125,15 @@ struct mmk_ctx {
     std::string err;
     bool prof = false;
     int prof_every = 1;              // time every prof_every-th launch of each kernel id
-    int64_t seen[kProfIds] = {0, 0, 0, 0, 0};
+    int64_t seen[kProfIds] = {0, 0, 0, 0, 0, 0};
     std::vector<hipEvent_t> ev[kProfIds];  // start/stop pairs
-    int nev[kProfIds] = {0, 0, 0, 0, 0};
+    int nev[kProfIds] = {0, 0, 0, 0, 0, 0};
     TapeState tape;
     std::vector<double> host_tab64;  // host copies of the angle tables (outlive the async copy)
     std::vector<float> host_tab32;
+    ForceRecords frec;  // host copy of the force spreading records
+    std::vector<float> host_fw32;
+    bool frec_ok = false;
 
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -365,6 +376,24 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     } else {
         e = hipMemcpyAsync(c->ws + L.tab, c->host_tab64.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream);
     }
+    // spreading records of the motor force (needed only by mmk_get_force)
+    const ForcePlan fp = plan_force(p->nx, p->ny, p->ns, p->lx, p->ly, p->L, c->esz);
+    ForceRecords &fr = c->frec;
+    c->frec_ok = force_records(nth, p->ns, p->lx, p->ly, p->L, p->nx, p->ny, fp, force_chunk(c->esz), &fr);
+    if (c->frec_ok) {
+        auto up = [&](size_t off, const void *src, size_t bytes) {
+            if (e == hipSuccess) e = hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+        };
+        up(L.frec, fr.rec.data(), fr.rec.size() * sizeof(int));
+        up(L.fexy, fr.exy.data(), fr.exy.size() * sizeof(int));
+        up(L.fcs, fr.cs.data(), fr.cs.size() * sizeof(double));
+        if (c->esz == 4) {
+            c->host_fw32.assign(fr.w.begin(), fr.w.end());
+            up(L.fw, c->host_fw32.data(), c->host_fw32.size() * 4);
+        } else {
+            up(L.fw, fr.w.data(), fr.w.size() * 8);
+        }
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         delete c;
@@ -492,6 +521,34 @@ mmk_status mmk_get_motor_moments(mmk_ctx *c, void *m0, void *m1) {
     if (m0)
         HIPCHK(c, hipMemcpyAsync(m0, c->ws + c->L.m0, np, hipMemcpyDeviceToDevice, c->stream), "copy of m0");
     if (m1) HIPCHK(c, hipMemcpyAsync(m1, c->ws + c->L.m1, np, hipMemcpyDeviceToDevice, c->stream), "copy of m1");
+    return MMK_OK;
+}
+
+mmk_status mmk_get_force(mmk_ctx *c, void *force) {
+    if (!c) return MMK_ERR_ARG;
+    if (!force) return fail(c, MMK_ERR_ARG, "force is NULL");
+    if (!c->have_state) return fail(c, MMK_ERR_STATE, "mmk_get_force before mmk_set_state");
+    const mmk_params &p = c->p;
+    const ForcePlan fp = plan_force(p.nx, p.ny, p.ns, p.lx, p.ly, p.L, c->esz);
+    if (!c->frec_ok || fp.nt == 0)
+        return fail(c, MMK_ERR_UNSUPPORTED, "spreading window of %d x %d cells is too large", fp.wx, fp.wy);
+    int slot;
+    HIPCHK(c, prof_begin(c, 5, &slot), "hipEventRecord");
+    hipError_t e;
+    const int *rec = c->at<int>(c->L.frec), *exy = c->at<int>(c->L.fexy);
+    const double *cs = c->at<double>(c->L.fcs);
+    if (c->esz == 4)
+        e = launch_motor_force<float>(c->at<float>(c->L.M[c->cur]), c->at<float>(c->L.psi[c->cur]), rec, exy,
+                                      c->at<float>(c->L.fw), cs, c->at<double>(c->L.fpart), (float *)force, p.nx,
+                                      p.ny, p.ntheta, p.ns, p.F, p.L, fp, c->stream);
+    else
+        e = launch_motor_force<double>(c->at<double>(c->L.M[c->cur]), c->at<double>(c->L.psi[c->cur]), rec, exy,
+                                       c->at<double>(c->L.fw), cs, c->at<double>(c->L.fpart), (double *)force, p.nx,
+                                       p.ny, p.ntheta, p.ns, p.F, p.L, fp, c->stream);
+    if (e == hipErrorInvalidValue)
+        return fail(c, MMK_ERR_UNSUPPORTED, "spreading window of %zu bytes exceeds the LDS per block", fp.lds_bytes);
+    HIPCHK(c, e, "motor force launch");
+    HIPCHK(c, prof_end(c, 5, slot), "hipEventRecord");
     return MMK_OK;
 }
 

@@ -21,11 +21,11 @@ MMK_OK, MMK_ERR_ARG, MMK_ERR_NOMEM, MMK_ERR_HIP, MMK_ERR_STATE, MMK_ERR_UNSUPPOR
 FP64, FP32 = 0, 1
 SUPERBEE, UPWIND1 = 0, 1
 KERNEL_IDS = {"motor_step": 0, "psi_step": 1, "global_sums": 2, "psi_step_reverse": 3,
-              "motor_step_reverse": 4}
+              "motor_step_reverse": 4, "motor_force": 5}
 
 EXPORTS = ["mmk_workspace_bytes", "mmk_create", "mmk_destroy", "mmk_set_params", "mmk_set_state",
            "mmk_set_fluid", "mmk_step", "mmk_get_state", "mmk_get_stress", "mmk_get_moments",
-           "mmk_get_motor_moments", "mmk_get_sums", "mmk_tape_begin", "mmk_tape_backward",
+           "mmk_get_motor_moments", "mmk_get_force", "mmk_get_sums", "mmk_tape_begin", "mmk_tape_backward",
            "mmk_tape_end", "mmk_profile", "mmk_profile_read", "mmk_last_error"]
 
 
@@ -67,6 +67,7 @@ def lib():
             "mmk_get_stress": ([vp, vp], C.c_int),
             "mmk_get_moments": ([vp, vp], C.c_int),
             "mmk_get_motor_moments": ([vp, vp, vp], C.c_int),
+            "mmk_get_force": ([vp, vp], C.c_int),
             "mmk_get_sums": ([vp, C.POINTER(d), C.POINTER(d)], C.c_int),
             "mmk_tape_begin": ([vp, i32], C.c_int),
             "mmk_tape_backward": ([vp, vp, vp, vp, C.POINTER(d)], C.c_int),
@@ -202,6 +203,12 @@ class Context:
         m0, m1 = self.empty(self.shape_psi), self.empty(self.shape_psi)
         self._check(lib().mmk_get_motor_moments(self.h, _ptr(m0), _ptr(m1)))
         return m0, m1
+
+    def get_force(self):
+        """Motor force density [2][nx][ny] of the current state."""
+        f = self.empty((2, self.p.nx, self.p.ny))
+        self._check(lib().mmk_get_force(self.h, _ptr(f)))
+        return f
 
     def get_sums(self):
         mass = C.c_double()

@@ -1,0 +1,95 @@
+"""Motor force density (Eq. (10), bilinear-hat spreading) on the GPU against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle_a as A
+from paper_1908_04279_amd import inputs as gen
+from paper_1908_04279_amd.inputs import ModelParams
+from tests.conftest import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_force(p, psi, M, precision=0):
+    import torch
+    from paper_1908_04279_amd import mmk
+    ctx = mmk.Context(p, precision=precision)
+    ctx.set_state(torch.as_tensor(psi), torch.as_tensor(M))
+    f = ctx.get_force().double().cpu().numpy()
+    ctx.close()
+    return f
+
+
+def case(shape, seed=0, **kw):
+    nx, ny, nt, ns = shape
+    p = ModelParams(nx=nx, ny=ny, ntheta=nt, ns=ns, **kw)
+    psi = gen.make_psi0(nx, ny, nt, p.lx, p.ly, seed=seed)
+    M = gen.make_M0_random(nx, ny, nt, ns, seed=5 + seed)
+    return p, psi, M
+
+
+@pytest.mark.parametrize("shape,kw", [
+    ((16, 16, 16, 16), {}),                                 # C1 grid: window 2 rings wider than a tile
+    ((21, 13, 32, 20), {"L": 1.7}),                         # ragged tiles, window wider than the grid
+    ((5, 7, 12, 8), {}),                                    # window wraps the box several times
+    ((40, 24, 64, 128), {"lx": 3.0, "ly": 2.0, "L": 0.8}),  # two staging passes per row
+    ((33, 9, 8, 100), {"L": 0.3}),                          # short filaments
+])
+def test_fp64_against_oracle(shape, kw):
+    p, psi, M = case(shape, **kw)
+    g = gpu_force(p, psi, M)
+    o = A.motor_force(p, psi, M)
+    err = rel_err(g, o)
+    print(f"{shape} {kw}: {err:.2e}", flush=True)
+    assert err <= 1e-12
+
+
+def test_fp32_against_fp64_oracle():
+    p, psi, M = case((48, 40, 64, 64))
+    psi32, M32 = psi.astype(np.float32), M.astype(np.float32)
+    g = gpu_force(p, psi32, M32, precision=1)
+    o = A.motor_force(p, psi32.astype(np.float64), M32.astype(np.float64))
+    err = rel_err(g, o)
+    print(f"fp32: {err:.2e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_c3_size_fp32_and_repeatability():
+    """256^2 x 64 x 64 FP32 (the benchmark grid) against the oracle, and the same bits twice."""
+    p, psi, M = case((256, 256, 64, 64))
+    psi32, M32 = psi.astype(np.float32), M.astype(np.float32)
+    g1 = gpu_force(p, psi32, M32, precision=1)
+    g2 = gpu_force(p, psi32, M32, precision=1)
+    assert np.array_equal(g1, g2)
+    o = A.motor_force(p, psi32.astype(np.float64), M32.astype(np.float64))
+    err = rel_err(g1, o)
+    print(f"c3 fp32: {err:.2e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_total_force_on_the_gpu_matches_the_motor_sum():
+    """sum F2 dx dy = F sum p psi m0 dth dx dy, with m0 from the GPU's own motor moments."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    p, psi, M = case((24, 20, 32, 16))
+    ctx = mmk.Context(p)
+    ctx.set_state(torch.as_tensor(psi), torch.as_tensor(M))
+    f = ctx.get_force().cpu().numpy()
+    ctx.close()
+    dx, dy, dth, ds = p.lx / p.nx, p.ly / p.ny, 2 * np.pi / p.ntheta, p.L / p.ns
+    th = np.arange(p.ntheta) * dth
+    m0 = M.sum(-1) * ds
+    want = p.F * np.array([(psi * m0 * np.cos(th)).sum(), (psi * m0 * np.sin(th)).sum()]) * dth
+    np.testing.assert_allclose(f.sum(axis=(1, 2)), want, rtol=1e-12)
+
+
+def test_window_too_large_is_unsupported():
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=2048, ny=8, ntheta=1, ns=1, lx=1.0, ly=100.0, L=1.0)
+    ctx = mmk.Context(p)
+    ctx.set_state(torch.ones(2048, 8, 1, dtype=torch.float64))
+    with pytest.raises(mmk.MMKError) as ei:
+        ctx.get_force()
+    assert ei.value.status == mmk.MMK_ERR_UNSUPPORTED
+    ctx.close()
