@@ -3,32 +3,36 @@
 // head (x_i, y_j) + (s_l - L/2) p_k; the delta function is the two-point hat (bilinear) in x
 // and y, periodic.
 //
-// For a fixed orientation k the push is along p_k for every term, so the spreading first
-// builds the scalar density G_k = sum over points and cells of F psi M ds dth hat, then adds
-// cos(th_k) G_k and sin(th_k) G_k to the force.  The head offset (s_l - L/2) p_k is the same
-// for every point and moves monotonically with l, so the bilinear corners of consecutive
-// cells l are mostly shared: a lane keeps the four corners of its current head in registers,
-// adds each cell's weighted motors to them, and spreads a corner only when the head has moved
-// past it.  Spreading is a scatter, done in a fixed order so that the result has the same
-// bits on every run:
+// For a fixed orientation k the push is along p_k for every term, so the spreading builds the
+// scalar density G_k = sum over points and cells of F psi M ds dth hat and adds cos(th_k) G_k,
+// sin(th_k) G_k to the force.  Orientation k + nth/2 pushes along -p_k, and its cell
+// ns - 1 - l sits where cell l of orientation k does (s_{ns-1-l} - L/2 = -(s_l - L/2)), so for
+// even nth one pass spreads u = F ds dth (psi_k M_k[l] - psi_k' M_k'[ns-1-l]), k' = k + nth/2,
+// with orientation k's stencil and adds cos(th_k), sin(th_k) times the result: half the
+// spreading of one pass per orientation.  The head offset is the same for every point and
+// moves monotonically with l, so the bilinear corners of consecutive cells are mostly shared:
+// a lane keeps the four corners of its current head in registers, adds each cell's weighted
+// u to them, and spreads a corner only when the head has moved past it.  Spreading is a
+// scatter, done in a fixed order so that the result has the same bits on every run:
 //   k_motor_force: one wave per 8 x 8 tile of filament points.  The wave owns a private LDS
-//     window of G_k around its tile (the tile plus the filament's reach) in FP64, and keeps
-//     the window's running (fx, fy) in FP64 registers, NT cells per lane: the x and y sums
-//     cancel strongly over the orientations (by a factor ~150 on a near-isotropic state),
-//     and FP32 sums lost ~1e-4 relative there.  For each orientation it stages the tile's 64
-//     motor columns in LDS (coalesced row loads, the next chunk prefetched) and reads its own
-//     column back into registers, then walks the cells with the host-built records (corner
-//     move code, corner cell, four weights; wave-uniform scalar loads).  A spread corner goes
-//     to window cell point + corner with one LDS atomic add: for a fixed corner the lanes'
-//     cells are distinct, no other wave touches the window and the LDS applies one wave's
-//     operations in issue order, so each cell's terms are summed in the fixed order.  After
-//     the orientation the window is folded into the registers and cleared; at the end the
-//     (fx, fy) window goes to a partial array.
-//   k_force_merge: each grid cell sums, in tile order, the window cells of every tile whose
-//     window covers it (periodic).
+//     window of the pass's density around its tile (the corners its heads reach) in FP64,
+//     and keeps the window's running (fx, fy) in FP64 registers, NT cells per lane: the x
+//     and y sums cancel strongly over the orientations (by a factor ~150 on a near-isotropic
+//     state), and FP32 sums lost ~1e-4 relative there.  For each pass it stages the tile's
+//     64 motor columns of both orientations in LDS (coalesced row loads, the next chunk
+//     prefetched) and reads its own u back into registers, then walks the cells with the
+//     host-built records (corner move code, corner cell, four weights; wave-uniform scalar
+//     loads).  A spread corner goes to window cell point + corner with one LDS atomic add:
+//     for a fixed corner the lanes' cells are distinct, no other wave touches the window and
+//     the LDS applies one wave's operations in issue order, so each cell's terms are summed
+//     in the fixed order.  After the pass the window is folded into the registers and
+//     cleared; at the end the (fx, fy) window goes to a partial array.
+//   k_force_merge: each grid cell sums, in a fixed order, the window cells of every tile
+//     whose window covers it (periodic).
 #include "force.h"
 #include "device_util.h"
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -36,18 +40,45 @@ namespace mmk {
 
 namespace {
 constexpr int kNt[] = {4, 8, 16, 24, 32, 40, 44, 48};  // compiled register-window sizes, cells per lane
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// head of arclength cell l of orientation k, in cells from its point: integer and fraction
+struct Head {
+    int a, b;
+    double ax, ay;
+};
+Head head(int k, int l, int nth, int ns, double lx, double ly, double L, int nx, int ny) {
+    const double dx = lx / nx, dy = ly / ny, ds = L / ns, dth = kTwoPi / nth;
+    const double lever = (l + 0.5) * ds - 0.5 * L;
+    const double ox = lever * std::cos(k * dth) / dx, oy = lever * std::sin(k * dth) / dy;
+    const double fa = std::floor(ox), fb = std::floor(oy);
+    return {(int)fa, (int)fb, ox - fa, oy - fb};
+}
 }  // namespace
 
-ForcePlan plan_force(int nx, int ny, int ns, double lx, double ly, double L, size_t elem) {
+ForcePlan plan_force(int nx, int ny, int nth, int ns, double lx, double ly, double L, size_t elem) {
     ForcePlan f{};
-    const double reach_x = 0.5 * L / (lx / nx), reach_y = 0.5 * L / (ly / ny);
-    f.rx = (int)std::ceil(reach_x) + 1;
-    f.ry = (int)std::ceil(reach_y) + 1;
-    f.wx = 8 + 2 * f.rx + 1;
-    f.wy = 8 + 2 * f.ry + 1;
     f.tiles_i = (nx + 7) / 8;
     f.tiles_j = (ny + 7) / 8;
-    (void)ns;
+    f.paired = nth % 2 == 0;
+    f.npass = f.paired ? nth / 2 : nth;
+    f.chunk = elem == 4 ? 32 : 16;
+    // the corners a, a + 1 (b, b + 1) of every head, over all orientations and cells
+    int xmin = 0, xmax = 0, ymin = 0, ymax = 0;
+    const double reach_x = 0.5 * L / (lx / nx), reach_y = 0.5 * L / (ly / ny);
+    if (reach_x > 4096.0 || reach_y > 4096.0) return f;  // far beyond any window: nt = 0
+    for (int k = 0; k < nth; ++k)
+        for (int l = 0; l < ns; ++l) {
+            const Head h = head(k, l, nth, ns, lx, ly, L, nx, ny);
+            xmin = std::min(xmin, h.a);
+            xmax = std::max(xmax, h.a + 1);
+            ymin = std::min(ymin, h.b);
+            ymax = std::max(ymax, h.b + 1);
+        }
+    f.rx = -xmin;
+    f.ry = -ymin;
+    f.wx = xmax - xmin + 8;
+    f.wy = ymax - ymin + 8;
     const double cells = (double)f.wx * f.wy;
     f.nt = 0;
     for (int nt : kNt)
@@ -55,49 +86,44 @@ ForcePlan plan_force(int nx, int ny, int ns, double lx, double ly, double L, siz
             f.nt = nt;
             break;
         }
-    const int ch = force_chunk(elem);
-    f.lds_bytes = f.nt ? sizeof(double) * ((size_t)f.wx * f.wy + 1) / 2 * 2 + elem * 64 * (ch + 4) : 0;
+    f.lds_bytes = f.nt ? sizeof(double) * ((size_t)f.wx * f.wy + 1) / 2 * 2 + elem * 2 * 64 * (f.chunk + 4) : 0;
     f.part_elems = f.nt ? (size_t)f.tiles_i * f.tiles_j * 2 * f.wx * f.wy : 0;
     return f;
 }
 
-bool force_records(int nth, int ns, double lx, double ly, double L, int nx, int ny, const ForcePlan &fp, int chunk,
+bool force_records(int nth, int ns, double lx, double ly, double L, int nx, int ny, const ForcePlan &fp,
                    ForceRecords *out) {
-    const double dx = lx / nx, dy = ly / ny, ds = L / ns, dth = 6.283185307179586476925286766559 / nth;
     ForceRecords &r = *out;
-    r.chunk = chunk;
-    r.nchunk = (ns + chunk - 1) / chunk;
-    r.lpad = r.nchunk * chunk;
-    r.rec.assign((size_t)nth * r.lpad * 2, 0);
-    r.w.assign((size_t)nth * r.lpad * 4, 0.0);
-    r.exy.resize(2 * (size_t)nth);
-    r.cs.resize(2 * (size_t)nth);
-    bool ok = fp.nt > 0;
-    for (int k = 0; k < nth; ++k) {
-        const double co = std::cos(k * dth), si = std::sin(k * dth);
+    if (fp.nt == 0) return false;
+    const int npass = fp.npass;
+    r.lpad = (ns + fp.chunk - 1) / fp.chunk * fp.chunk;
+    r.rec.assign((size_t)npass * r.lpad, 0);
+    r.w.assign((size_t)npass * r.lpad * 4, 0.0);
+    r.exy.resize(2 * (size_t)npass);
+    r.cs.resize(2 * (size_t)npass);
+    bool ok = true;
+    for (int k = 0; k < npass; ++k) {
+        const double co = std::cos(k * kTwoPi / nth), si = std::sin(k * kTwoPi / nth);
         r.cs[k] = co;
-        r.cs[nth + k] = si;
+        r.cs[npass + k] = si;
         const int sx = co < 0.0 ? -1 : 1, sy = si < 0.0 ? -1 : 1;
         r.exy[2 * k] = sx * fp.wy;
         r.exy[2 * k + 1] = sy;
         int pa = 0, pb = 0, cell = 0;
         for (int l = 0; l < ns; ++l) {
-            const double lever = (l + 0.5) * ds - 0.5 * L;
-            const double ox = lever * co / dx, oy = lever * si / dy;
-            const double fa = std::floor(ox), fb = std::floor(oy), ax = ox - fa, ay = oy - fb;
-            const int a = (int)fa, b = (int)fb;
+            const Head h = head(k, l, nth, ns, lx, ly, L, nx, ny);
             // trailing corner coordinates and the weights in (trailing, leading) order
-            const int xt = sx > 0 ? a : a + 1, yt = sy > 0 ? b : b + 1;
-            const double wxt = sx > 0 ? 1.0 - ax : ax, wxl = 1.0 - wxt;
-            const double wyt = sy > 0 ? 1.0 - ay : ay, wyl = 1.0 - wyt;
+            const int xt = sx > 0 ? h.a : h.a + 1, yt = sy > 0 ? h.b : h.b + 1;
+            const double wxt = sx > 0 ? 1.0 - h.ax : h.ax, wxl = 1.0 - wxt;
+            const double wyt = sy > 0 ? 1.0 - h.ay : h.ay, wyl = 1.0 - wyt;
             int code = 0;
             if (l > 0) {
-                const int mx = (a - pa) * sx, my = (b - pb) * sy;
+                const int mx = (h.a - pa) * sx, my = (h.b - pb) * sy;
                 code = (mx == 0 && my == 0) ? 0 : (mx == 1 && my == 0) ? 1 : (mx == 0 && my == 1) ? 2
                                                : (mx == 1 && my == 1) ? 3 : 7;
             }
-            pa = a;
-            pb = b;
+            pa = h.a;
+            pb = h.b;
             // every lane's corners (li + x + rx, lj + y + ry), x in {xt, xt + sx}, must lie in the window
             for (int x : {xt, xt + sx})
                 if (x + fp.rx < 0 || x + fp.rx + 7 >= fp.wx) ok = false;
@@ -105,14 +131,13 @@ bool force_records(int nth, int ns, double lx, double ly, double L, int nx, int 
                 if (y + fp.ry < 0 || y + fp.ry + 7 >= fp.wy) ok = false;
             cell = (xt + fp.rx) * fp.wy + yt + fp.ry;
             const size_t q = (size_t)k * r.lpad + l;
-            r.rec[2 * q] = code;
-            r.rec[2 * q + 1] = cell;
+            r.rec[q] = cell * 8 + code;
             r.w[4 * q + 0] = wxt * wyt;
             r.w[4 * q + 1] = wxl * wyt;
             r.w[4 * q + 2] = wxt * wyl;
             r.w[4 * q + 3] = wxl * wyl;
         }
-        for (int l = ns; l < r.lpad; ++l) r.rec[2 * ((size_t)k * r.lpad + l) + 1] = cell;  // padding: no move
+        for (int l = ns; l < r.lpad; ++l) r.rec[(size_t)k * r.lpad + l] = cell * 8;  // padding: no move
     }
     return ok;
 }
@@ -123,15 +148,15 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
                                                     const T *__restrict__ wts, const double *__restrict__ cs,
                                                     double *__restrict__ part, int nx, int ny, int nth, int ns,
                                                     T cF, ForcePlan fp) {
-    constexpr int SR = CH + 4;        // staging row: one point's CH cells, 16-byte aligned
-    constexpr int PPL = 64 / CH;      // points per row load
+    constexpr int SR = CH + 4;          // staging row: one point's CH cells, 16-byte aligned
+    constexpr int PPL = 64 / CH;        // points per row load
     constexpr int LB = 32 / sizeof(T);  // records per batch of scalar loads
     using V = typename std::conditional<std::is_same<T, float>::value, float4, double2>::type;
     constexpr int VW = sizeof(V) / sizeof(T);
     extern __shared__ __align__(16) unsigned char smem[];
     const int ncells = fp.wx * fp.wy;
-    double *G = reinterpret_cast<double *>(smem);              // [wx][wy] density of the current orientation
-    T *stg = reinterpret_cast<T *>(G + (ncells + 1) / 2 * 2);  // [64 points][SR], 16-byte aligned
+    double *G = reinterpret_cast<double *>(smem);              // [wx][wy] density of the current pass
+    T *stg = reinterpret_cast<T *>(G + (ncells + 1) / 2 * 2);  // [2 orientations][64 points][SR]
     const int lane = threadIdx.x;
     const int ti = blockIdx.x / fp.tiles_j, tj = blockIdx.x % fp.tiles_j;
     const int li = lane >> 3, lj = lane & 7;
@@ -142,102 +167,104 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
     double tx[NT], ty[NT];
 #pragma unroll
     for (int q = 0; q < NT; ++q) tx[q] = ty[q] = 0.0;
-    // staging: cells s0 .. s0+CH-1 of the tile's 64 columns of one orientation; a row load
-    // covers PPL points, lane % CH = cell.  Points past the grid edge and cells past ns load
-    // clamped (finite) values: the former spread with psi = 0, the latter have zero weights.
+    // staging of one chunk: cells s0 .. s0+CH-1 of orientation k and cells ns-s0-CH ..
+    // ns-s0-1 of its partner k2, for the tile's 64 points; a row load covers PPL points,
+    // lane % CH = cell.  Points past the grid edge and cells outside [0, ns) load clamped
+    // (finite) values: the former spread with psi = 0, the latter have zero weights.
     const int nchunk = (ns + CH - 1) / CH;
     const int64_t pstride = (int64_t)nth * ns;
-    const int lc = lane % CH;
-    T rows[CH];
+    const int lc = lane % CH, lq = lane / CH;
+    T rows[2][CH];
     auto load_rows = [&](int k, int s0) {
-        const T *Mk = M + (int64_t)k * ns + (s0 + lc < ns ? s0 + lc : ns - 1);
+        const int k2 = fp.paired ? k + nth / 2 : k;
+        const int la = min(s0 + lc, ns - 1), lb = max(ns - s0 - CH + lc, 0);
+        const T *Ma = M + (int64_t)k * ns + la, *Mb = M + (int64_t)k2 * ns + lb;
 #pragma unroll
         for (int r = 0; r < CH; ++r) {
-            const int q = r * PPL + lane / CH;
+            const int q = r * PPL + lq;
             const int pi = min(ti * 8 + (q >> 3), nx - 1), pj = min(tj * 8 + (q & 7), ny - 1);
-            rows[r] = Mk[((int64_t)pi * ny + pj) * pstride];
+            const int64_t po = ((int64_t)pi * ny + pj) * pstride;
+            rows[0][r] = Ma[po];
+            rows[1][r] = Mb[po];
         }
     };
     load_rows(0, 0);
-    const double *csk = cs;
-    for (int k = 0; k < nth; ++k) {
-        const T cps = mine ? cF * psi[((int64_t)gi * ny + gj) * nth + k] : T(0);
+    for (int k = 0; k < fp.npass; ++k) {
+        const int k2 = fp.paired ? k + nth / 2 : k;
+        const T ca = mine ? cF * psi[((int64_t)gi * ny + gj) * nth + k] : T(0);
+        const T cb = mine && fp.paired ? cF * psi[((int64_t)gi * ny + gj) * nth + k2] : T(0);
         const int ex = exy[2 * k], ey = exy[2 * k + 1];
         T att = T(0), alt = T(0), atl = T(0), all = T(0);  // corners of the current head
         int pc = 0;
-        auto spread = [&](T v, int c) { atomicAdd(G + c + lcell, (double)(v * cps)); };
+        auto spread = [&](T v, int c) { atomicAdd(G + c + lcell, (double)v); };
         for (int ch = 0; ch < nchunk; ++ch) {
             __syncthreads();  // the previous chunk's reads of the staging rows (and the fold) are done
 #pragma unroll
-            for (int r = 0; r < CH; ++r) stg[(r * PPL + lane / CH) * SR + lc] = rows[r];
+            for (int r = 0; r < CH; ++r) {
+                stg[(r * PPL + lq) * SR + lc] = rows[0][r];
+                stg[(64 + r * PPL + lq) * SR + lc] = rows[1][r];
+            }
             __syncthreads();  // staging rows (and the cleared window) visible to every lane
             {
-                const int nx_it = k * nchunk + ch + 1;
-                if (nx_it < nth * nchunk) load_rows(nx_it / nchunk, (nx_it % nchunk) * CH);
+                const int nit = k * nchunk + ch + 1;
+                if (nit < fp.npass * nchunk) load_rows(nit / nchunk, (nit % nchunk) * CH);
             }
+            // u of cell s0 + j: this orientation's cell and the partner's mirror cell
             T u[CH];
 #pragma unroll
             for (int v = 0; v < CH / VW; ++v) {
-                const V x = *reinterpret_cast<const V *>(stg + lane * SR + v * VW);
+                const V a = *reinterpret_cast<const V *>(stg + lane * SR + v * VW);
+                const V b = *reinterpret_cast<const V *>(stg + (64 + lane) * SR + CH - VW - v * VW);
                 if constexpr (VW == 4) {
-                    u[4 * v] = x.x;
-                    u[4 * v + 1] = x.y;
-                    u[4 * v + 2] = x.z;
-                    u[4 * v + 3] = x.w;
+                    u[4 * v] = ca * a.x - cb * b.w;
+                    u[4 * v + 1] = ca * a.y - cb * b.z;
+                    u[4 * v + 2] = ca * a.z - cb * b.y;
+                    u[4 * v + 3] = ca * a.w - cb * b.x;
                 } else {
-                    u[2 * v] = x.x;
-                    u[2 * v + 1] = x.y;
+                    u[2 * v] = ca * a.x - cb * b.y;
+                    u[2 * v + 1] = ca * a.y - cb * b.x;
                 }
             }
             const size_t r0 = (size_t)k * nchunk * CH + (size_t)ch * CH;
-            const int *rk = rec + 2 * r0;
+            const int *rk = rec + r0;
             const T *wk = wts + 4 * r0;
 #pragma unroll
             for (int b = 0; b < CH; b += LB) {
                 // one batch of wave-uniform records, all loaded before its first atomic
-                int code[LB], cell[LB];
+                int rc[LB];
                 T w[LB][4];
 #pragma unroll
                 for (int q = 0; q < LB; ++q) {
-                    code[q] = rk[2 * (b + q)];
-                    cell[q] = rk[2 * (b + q) + 1];
+                    rc[q] = rk[b + q];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) w[q][c] = wk[4 * (b + q) + c];
                 }
 #pragma unroll
                 for (int q = 0; q < LB; ++q) {
-                    switch (code[q]) {
-                    case 0: break;
-                    case 1:  // one step along x: the trailing x column is done
-                        spread(att, pc);
-                        spread(atl, pc + ey);
-                        att = alt;
-                        atl = all;
-                        alt = all = T(0);
-                        break;
-                    case 2:  // one step along y: the trailing y row is done
-                        spread(att, pc);
+                    // Corners the head has moved past are spread before the move: tt on any
+                    // move, tl on a step along x, lt on a step along y (a spread of 0 on the
+                    // current corner when there is none: adding +0 changes no sum), lt and ll
+                    // as well on the rare diagonal step or jump.  Branch-free but for those.
+                    const int code = rc[q] & 7;
+                    const bool sx = code & 1, sy = code & 2;
+                    spread(code ? att : T(0), pc);
+                    spread(sx ? atl : sy ? alt : T(0), sx ? pc + ey : pc + ex);
+                    if (sx && sy) {
                         spread(alt, pc + ex);
-                        att = atl;
-                        alt = all;
-                        atl = all = T(0);
-                        break;
-                    case 3:  // one step along both: only the leading-leading corner stays
-                        spread(att, pc);
-                        spread(alt, pc + ex);
-                        spread(atl, pc + ey);
-                        att = all;
-                        alt = atl = all = T(0);
-                        break;
-                    default:  // a jump: no corner stays
-                        spread(att, pc);
-                        spread(alt, pc + ex);
-                        spread(atl, pc + ey);
-                        spread(all, pc + ex + ey);
-                        att = alt = atl = all = T(0);
-                        break;
+                        if (code == 7) spread(all, pc + ex + ey);
                     }
-                    pc = cell[q];
+                    // the survivors move to their new roles, the rest restart from 0 (selects)
+                    const bool jump = code == 7;
+                    const T x1 = sy ? all : alt, x0 = sy ? atl : att;
+                    const T ntt = jump ? T(0) : sx ? x1 : x0;
+                    const T nlt = sx ? T(0) : x1;
+                    const T ntl = sy ? T(0) : sx ? all : atl;
+                    const T nll = code ? T(0) : all;
+                    att = ntt;
+                    alt = nlt;
+                    atl = ntl;
+                    all = nll;
+                    pc = rc[q] >> 3;
                     const T m = u[b + q];
                     att += w[q][0] * m;
                     alt += w[q][1] * m;
@@ -250,8 +277,8 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
         spread(alt, pc + ex);
         spread(atl, pc + ey);
         spread(all, pc + ex + ey);
-        __syncthreads();  // the orientation's window is complete
-        const double co = csk[k], si = csk[nth + k];
+        __syncthreads();  // the pass's window is complete
+        const double co = cs[k], si = cs[fp.npass + k];
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             const int c = lane + 64 * q;
@@ -274,7 +301,13 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
     }
 }
 
-// force[c][x][y] = sum over tiles t (in order) and window cells w of t that land on (x, y)
+__device__ __forceinline__ int floor_div8(int a) { return a >= 0 ? a / 8 : -((-a + 7) / 8); }
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// force[c][x][y] = sum of window cell (x - o_t, y - o_t') of every tile (t, t') whose window
+// covers (x, y) modulo the grid, o the window origin 8 t - rx; in the fixed order (image of x,
+// t, image of y, t').  For an image X = x + m nx, the tiles whose window [8t - rx, 8t - rx +
+// wx) holds X are t in [ceil((X + rx - wx + 1) / 8), floor((X + rx) / 8)].
 template <typename T>
 __global__ __launch_bounds__(256) void k_force_merge(const double *__restrict__ part, T *__restrict__ force, int nx,
                                                      int ny, ForcePlan fp) {
@@ -284,21 +317,25 @@ __global__ __launch_bounds__(256) void k_force_merge(const double *__restrict__ 
          cell += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(cell / ny), y = (int)(cell % ny);
         double fx = 0.0, fy = 0.0;
-        for (int ti = 0; ti < fp.tiles_i; ++ti) {
-            // window x-offset of this cell in tile ti's window (origin ti*8 - rx), periodic
-            int wx0 = (x - (ti * 8 - fp.rx)) % nx;
-            if (wx0 < 0) wx0 += nx;
-            if (wx0 >= fp.wx) continue;
-            for (int tj = 0; tj < fp.tiles_j; ++tj) {
-                int wy0 = (y - (tj * 8 - fp.ry)) % ny;
-                if (wy0 < 0) wy0 += ny;
-                if (wy0 >= fp.wy) continue;
-                const double *w = part + ((size_t)ti * fp.tiles_j + tj) * nwin;
-                for (int wx = wx0; wx < fp.wx; wx += nx)
-                    for (int wy = wy0; wy < fp.wy; wy += ny) {
-                        fx += w[2 * (wx * fp.wy + wy)];
-                        fy += w[2 * (wx * fp.wy + wy) + 1];
+        // images X of x that some window can hold: -rx <= X <= 8 (tiles_i - 1) - rx + wx - 1
+        const int mx0 = -floor_div(x + fp.rx, nx), mx1 = floor_div(8 * (fp.tiles_i - 1) - fp.rx + fp.wx - 1 - x, nx);
+        const int my0 = -floor_div(y + fp.ry, ny), my1 = floor_div(8 * (fp.tiles_j - 1) - fp.ry + fp.wy - 1 - y, ny);
+        for (int mx = mx0; mx <= mx1; ++mx) {
+            const int X = x + mx * nx;
+            const int t0 = max(floor_div8(X + fp.rx - fp.wx + 8), 0), t1 = min(floor_div8(X + fp.rx), fp.tiles_i - 1);
+            for (int ti = t0; ti <= t1; ++ti) {
+                const int wxc = X - (8 * ti - fp.rx);
+                for (int my = my0; my <= my1; ++my) {
+                    const int Y = y + my * ny;
+                    const int u0 = max(floor_div8(Y + fp.ry - fp.wy + 8), 0);
+                    const int u1 = min(floor_div8(Y + fp.ry), fp.tiles_j - 1);
+                    for (int tj = u0; tj <= u1; ++tj) {
+                        const int wyc = Y - (8 * tj - fp.ry);
+                        const double *w = part + ((size_t)ti * fp.tiles_j + tj) * nwin + 2 * (wxc * fp.wy + wyc);
+                        fx += w[0];
+                        fy += w[1];
                     }
+                }
             }
         }
         force[cell] = (T)fx;
@@ -314,10 +351,10 @@ hipError_t launch_motor_force(const T *M, const T *psi, const int *rec, const in
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return e;
-    if (fp.nt == 0 || fp.lds_bytes > (size_t)max_lds) return hipErrorInvalidValue;
+    constexpr int CH = std::is_same<T, float>::value ? 32 : 16;
+    if (fp.nt == 0 || fp.chunk != CH || fp.lds_bytes > (size_t)max_lds) return hipErrorInvalidValue;
     const int tiles = fp.tiles_i * fp.tiles_j;
-    const T cF = (T)(F * (L / ns) * (6.283185307179586476925286766559 / nth));
-    constexpr int CH = std::is_same<T, float>::value ? 64 : 32;
+    const T cF = (T)(F * (L / ns) * (kTwoPi / nth));
 #define MMK_FORCE_LAUNCH(NT_)                                                                                    \
     hipLaunchKernelGGL((k_motor_force<T, NT_, CH>), dim3(tiles), dim3(64), fp.lds_bytes, s, M, psi, rec, exy, w, \
                        cs, part, nx, ny, nth, ns, cF, fp)

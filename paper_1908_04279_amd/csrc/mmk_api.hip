@@ -86,13 +86,14 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.m0 = take(np * e);
     L.m1 = take(np * e);
     L.Dxy = take(2 * nxy * e);
-    L.fpart = take(plan_force(p.nx, p.ny, p.ns, p.lx, p.ly, p.L, e).part_elems * sizeof(double));
-    const int fch = force_chunk(e);  // spreading records of the force, per (orientation, cell)
-    const size_t nrec = (size_t)p.ntheta * ((p.ns + fch - 1) / fch) * fch;
-    L.frec = take(2 * nrec * sizeof(int));
-    L.fexy = take(2 * (size_t)p.ntheta * sizeof(int));
+    // motor force: partial windows and the spreading records per (pass, cell)
+    const ForcePlan fpl = plan_force(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, e);
+    const size_t nrec = (size_t)fpl.npass * ((p.ns + fpl.chunk - 1) / fpl.chunk) * fpl.chunk;
+    L.fpart = take(fpl.part_elems * sizeof(double));
+    L.frec = take(nrec * sizeof(int));
+    L.fexy = take(2 * (size_t)fpl.npass * sizeof(int));
     L.fw = take(4 * nrec * e);
-    L.fcs = take(2 * (size_t)p.ntheta * sizeof(double));
+    L.fcs = take(2 * (size_t)fpl.npass * sizeof(double));
     L.u = take(2 * nxy * e);
     L.G = take(4 * nxy * e);
     L.stress = take(3 * nxy * e);
@@ -131,6 +132,7 @@ struct mmk_ctx {
     TapeState tape;
     std::vector<double> host_tab64;  // host copies of the angle tables (outlive the async copy)
     std::vector<float> host_tab32;
+    ForcePlan fplan;    // motor-force spreading geometry
     ForceRecords frec;  // host copy of the force spreading records
     std::vector<float> host_fw32;
     bool frec_ok = false;
@@ -377,9 +379,9 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
         e = hipMemcpyAsync(c->ws + L.tab, c->host_tab64.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream);
     }
     // spreading records of the motor force (needed only by mmk_get_force)
-    const ForcePlan fp = plan_force(p->nx, p->ny, p->ns, p->lx, p->ly, p->L, c->esz);
+    c->fplan = plan_force(p->nx, p->ny, nth, p->ns, p->lx, p->ly, p->L, c->esz);
     ForceRecords &fr = c->frec;
-    c->frec_ok = force_records(nth, p->ns, p->lx, p->ly, p->L, p->nx, p->ny, fp, force_chunk(c->esz), &fr);
+    c->frec_ok = force_records(nth, p->ns, p->lx, p->ly, p->L, p->nx, p->ny, c->fplan, &fr);
     if (c->frec_ok) {
         auto up = [&](size_t off, const void *src, size_t bytes) {
             if (e == hipSuccess) e = hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
@@ -529,7 +531,7 @@ mmk_status mmk_get_force(mmk_ctx *c, void *force) {
     if (!force) return fail(c, MMK_ERR_ARG, "force is NULL");
     if (!c->have_state) return fail(c, MMK_ERR_STATE, "mmk_get_force before mmk_set_state");
     const mmk_params &p = c->p;
-    const ForcePlan fp = plan_force(p.nx, p.ny, p.ns, p.lx, p.ly, p.L, c->esz);
+    const ForcePlan &fp = c->fplan;
     if (!c->frec_ok || fp.nt == 0)
         return fail(c, MMK_ERR_UNSUPPORTED, "spreading window of %d x %d cells is too large", fp.wx, fp.wy);
     int slot;

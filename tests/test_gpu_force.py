@@ -34,6 +34,9 @@ def case(shape, seed=0, **kw):
     ((5, 7, 12, 8), {}),                                    # window wraps the box several times
     ((40, 24, 64, 128), {"lx": 3.0, "ly": 2.0, "L": 0.8}),  # two staging passes per row
     ((33, 9, 8, 100), {"L": 0.3}),                          # short filaments
+    ((13, 11, 15, 24), {}),                                 # odd ntheta: no partner orientation
+    ((9, 10, 3, 7), {"L": 2.5}),                            # odd, window wider than the grid
+    ((12, 10, 6, 5), {"L": 6.0}),                           # heads jump > 1 cell per arclength cell
 ])
 def test_fp64_against_oracle(shape, kw):
     p, psi, M = case(shape, **kw)
@@ -84,9 +87,10 @@ def test_total_force_on_the_gpu_matches_the_motor_sum():
 
 
 def test_window_too_large_is_unsupported():
+    """Heads up to 768 cells from their point along x: a window far beyond the registers."""
     import torch
     from paper_1908_04279_amd import mmk
-    p = ModelParams(nx=2048, ny=8, ntheta=1, ns=1, lx=1.0, ly=100.0, L=1.0)
+    p = ModelParams(nx=2048, ny=8, ntheta=1, ns=4, lx=1.0, ly=100.0, L=1.0)
     ctx = mmk.Context(p)
     ctx.set_state(torch.ones(2048, 8, 1, dtype=torch.float64))
     with pytest.raises(mmk.MMKError) as ei:
