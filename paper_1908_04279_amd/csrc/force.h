@@ -43,13 +43,19 @@ struct ForceRecords {
 bool force_records(int nth, int ns, double lx, double ly, double L, int nx, int ny, const ForcePlan &fp,
                    ForceRecords *out);
 
+// Device image of the records: one block of 256 dwords per (pass, chunk), record j of the
+// chunk at dwords [j * 256 / chunk, ...): rec, then the four weights in the field precision
+// (FP32 at dwords 1..4; FP64 at dwords 2..9).
+constexpr int kForceBlock = 256;
+void force_record_blocks(const ForceRecords &r, const ForcePlan &fp, size_t elem, std::vector<uint32_t> *out);
+
 // force[2][nx][ny] (fx, fy) of the state (M, psi): Eq. (10) with the bilinear hat, periodic.
-// rec, exy, w, cs: the records of force_records() on the device (w in the field precision,
-// cs in FP64); part: scratch of plan.part_elems FP64 elements.
+// blk: force_record_blocks() on the device; exy, cs: the records' steps and angle table;
+// part: scratch of plan.part_elems FP64 elements.
 // hipErrorInvalidValue (nothing launched) if the window does not fit the registers or the
 // device's LDS per block.
 template <typename T>
-hipError_t launch_motor_force(const T *M, const T *psi, const int *rec, const int *exy, const T *w, const double *cs,
+hipError_t launch_motor_force(const T *M, const T *psi, const uint32_t *blk, const int *exy, const double *cs,
                               double *part, T *force, int nx, int ny, int nth, int ns, double F, double L,
                               const ForcePlan &fp, hipStream_t s);
 

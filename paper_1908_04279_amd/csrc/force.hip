@@ -16,13 +16,14 @@
 // scatter, done in a fixed order so that the result has the same bits on every run:
 //   k_motor_force: one wave per 8 x 8 tile of filament points.  The wave owns a private LDS
 //     window of the pass's density around its tile (the corners its heads reach) in FP64,
-//     and keeps the window's running (fx, fy) in FP64 registers, NT cells per lane: the x
-//     and y sums cancel strongly over the orientations (by a factor ~150 on a near-isotropic
-//     state), and FP32 sums lost ~1e-4 relative there.  For each pass it stages the tile's
-//     64 motor columns of both orientations in LDS (coalesced row loads, the next chunk
-//     prefetched) and reads its own u back into registers, then walks the cells with the
-//     host-built records (corner move code, corner cell, four weights; wave-uniform scalar
-//     loads).  A spread corner goes to window cell point + corner with one LDS atomic add:
+//     and keeps the window's running (fx, fy) in registers in the field precision, NT cells
+//     per lane.  (Unpaired, the sums over orientations cancel by a factor ~150 on a
+//     near-isotropic state and FP32 sums lost ~1e-4 relative; the paired differences cancel
+//     by a factor 1-4 on the same states, where FP32 sums cost ~2e-7.)  For each pass it
+//     stages the tile's 64 motor columns of both orientations in LDS (coalesced row loads,
+//     the next chunk prefetched) and reads its own u back into registers, then walks the
+//     cells with the host-built records (corner move code, corner cell, four weights;
+//     wave-uniform scalar loads).  A spread corner goes to window cell point + corner with one LDS atomic add:
 //     for a fixed corner the lanes' cells are distinct, no other wave touches the window and
 //     the LDS applies one wave's operations in issue order, so each cell's terms are summed
 //     in the fixed order.  After the pass the window is folded into the registers and
@@ -34,6 +35,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <type_traits>
 
 namespace mmk {
@@ -142,17 +144,37 @@ bool force_records(int nth, int ns, double lx, double ly, double L, int nx, int 
     return ok;
 }
 
-template <typename T, int NT, int CH>
+void force_record_blocks(const ForceRecords &r, const ForcePlan &fp, size_t elem, std::vector<uint32_t> *out) {
+    const int nchunk = r.lpad / fp.chunk, stride = kForceBlock / fp.chunk;
+    out->assign((size_t)fp.npass * nchunk * kForceBlock, 0u);
+    for (int k = 0; k < fp.npass; ++k)
+        for (int l = 0; l < r.lpad; ++l) {
+            const size_t q = (size_t)k * r.lpad + l;
+            uint32_t *d = out->data() + ((size_t)k * nchunk + l / fp.chunk) * kForceBlock + (l % fp.chunk) * stride;
+            d[0] = (uint32_t)r.rec[q];
+            for (int c = 0; c < 4; ++c) {
+                if (elem == 4) {
+                    const float v = (float)r.w[4 * q + c];
+                    std::memcpy(d + 1 + c, &v, 4);
+                } else {
+                    std::memcpy(d + 2 + 2 * c, &r.w[4 * q + c], 8);
+                }
+            }
+        }
+}
+
+template <typename T, int NT, int CH, bool VEC>
 __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, const T *__restrict__ psi,
-                                                    const int *__restrict__ rec, const int *__restrict__ exy,
-                                                    const T *__restrict__ wts, const double *__restrict__ cs,
+                                                    const uint32_t *__restrict__ blk, const int *__restrict__ exy,
+                                                    const double *__restrict__ cs,
                                                     double *__restrict__ part, int nx, int ny, int nth, int ns,
                                                     T cF, ForcePlan fp) {
-    constexpr int SR = CH + 4;          // staging row: one point's CH cells, 16-byte aligned
-    constexpr int PPL = 64 / CH;        // points per row load
-    constexpr int LB = 32 / sizeof(T);  // records per batch of scalar loads
     using V = typename std::conditional<std::is_same<T, float>::value, float4, double2>::type;
     constexpr int VW = sizeof(V) / sizeof(T);
+    constexpr int SR = CH + 4;                 // staging row: one point's CH cells, 16-byte aligned
+    constexpr int PPL = VEC ? 64 * VW / CH : 64 / CH;  // points per row load
+    constexpr int NR = 64 / PPL;               // row loads per orientation and chunk
+    constexpr int RS = kForceBlock / CH;       // dwords per record
     extern __shared__ __align__(16) unsigned char smem[];
     const int ncells = fp.wx * fp.wy;
     double *G = reinterpret_cast<double *>(smem);              // [wx][wy] density of the current pass
@@ -164,29 +186,40 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
     const bool mine = gi < nx && gj < ny;
     const int lcell = li * fp.wy + lj;
     for (int q = lane; q < ncells; q += 64) G[q] = 0.0;
-    double tx[NT], ty[NT];
+    T tx[NT], ty[NT];
 #pragma unroll
-    for (int q = 0; q < NT; ++q) tx[q] = ty[q] = 0.0;
+    for (int q = 0; q < NT; ++q) tx[q] = ty[q] = T(0);
     // staging of one chunk: cells s0 .. s0+CH-1 of orientation k and cells ns-s0-CH ..
-    // ns-s0-1 of its partner k2, for the tile's 64 points; a row load covers PPL points,
-    // lane % CH = cell.  Points past the grid edge and cells outside [0, ns) load clamped
-    // (finite) values: the former spread with psi = 0, the latter have zero weights.
+    // ns-s0-1 of its partner k2, for the tile's 64 points; a row load covers PPL points, each
+    // lane one cell (or, with VEC, a 16-byte vector of VW cells; ns is then a multiple of VW
+    // and every vector lies wholly inside or wholly outside [0, ns)).  Points past the grid
+    // edge and cells outside [0, ns) load clamped (finite) values: the former spread with
+    // psi = 0, the latter have zero weights.  The chunk's records come with it, 4 dwords a
+    // lane.
     const int nchunk = (ns + CH - 1) / CH;
     const int64_t pstride = (int64_t)nth * ns;
-    const int lc = lane % CH, lq = lane / CH;
-    T rows[2][CH];
-    auto load_rows = [&](int k, int s0) {
+    constexpr int LPP = 64 / PPL;  // lanes per point in a row load
+    const int lq = lane / LPP, lc = (lane % LPP) * (VEC ? VW : 1);
+    typedef T TV __attribute__((ext_vector_type(VW)));  // native vector: stays in registers
+    using R = typename std::conditional<VEC, TV, T>::type;
+    R rows[2][NR];
+    uint32_t rnext[4];
+    auto load_rows = [&](int k, int ch) {
+        const int s0 = ch * CH;
         const int k2 = fp.paired ? k + nth / 2 : k;
-        const int la = min(s0 + lc, ns - 1), lb = max(ns - s0 - CH + lc, 0);
+        const int la = min(s0 + lc, ns - (VEC ? VW : 1)), lb = max(ns - s0 - CH + lc, 0);
         const T *Ma = M + (int64_t)k * ns + la, *Mb = M + (int64_t)k2 * ns + lb;
 #pragma unroll
-        for (int r = 0; r < CH; ++r) {
+        for (int r = 0; r < NR; ++r) {
             const int q = r * PPL + lq;
             const int pi = min(ti * 8 + (q >> 3), nx - 1), pj = min(tj * 8 + (q & 7), ny - 1);
             const int64_t po = ((int64_t)pi * ny + pj) * pstride;
-            rows[0][r] = Ma[po];
-            rows[1][r] = Mb[po];
+            rows[0][r] = *reinterpret_cast<const R *>(Ma + po);
+            rows[1][r] = *reinterpret_cast<const R *>(Mb + po);
         }
+        const uint32_t *b = blk + ((size_t)k * nchunk + ch) * kForceBlock + lane;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rnext[j] = b[64 * j];
     };
     load_rows(0, 0);
     for (int k = 0; k < fp.npass; ++k) {
@@ -200,14 +233,17 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
         for (int ch = 0; ch < nchunk; ++ch) {
             __syncthreads();  // the previous chunk's reads of the staging rows (and the fold) are done
 #pragma unroll
-            for (int r = 0; r < CH; ++r) {
-                stg[(r * PPL + lq) * SR + lc] = rows[0][r];
-                stg[(64 + r * PPL + lq) * SR + lc] = rows[1][r];
+            for (int r = 0; r < NR; ++r) {
+                *reinterpret_cast<R *>(stg + (r * PPL + lq) * SR + lc) = rows[0][r];
+                *reinterpret_cast<R *>(stg + (64 + r * PPL + lq) * SR + lc) = rows[1][r];
             }
+            uint32_t rv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) rv[j] = rnext[j];
             __syncthreads();  // staging rows (and the cleared window) visible to every lane
             {
                 const int nit = k * nchunk + ch + 1;
-                if (nit < fp.npass * nchunk) load_rows(nit / nchunk, (nit % nchunk) * CH);
+                if (nit < fp.npass * nchunk) load_rows(nit / nchunk, nit % nchunk);
             }
             // u of cell s0 + j: this orientation's cell and the partner's mirror cell
             T u[CH];
@@ -225,27 +261,30 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
                     u[2 * v + 1] = ca * a.y - cb * b.x;
                 }
             }
-            const size_t r0 = (size_t)k * nchunk * CH + (size_t)ch * CH;
-            const int *rk = rec + r0;
-            const T *wk = wts + 4 * r0;
 #pragma unroll
-            for (int b = 0; b < CH; b += LB) {
-                // one batch of wave-uniform records, all loaded before its first atomic
-                int rc[LB];
-                T w[LB][4];
-#pragma unroll
-                for (int q = 0; q < LB; ++q) {
-                    rc[q] = rk[b + q];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) w[q][c] = wk[4 * (b + q) + c];
-                }
-#pragma unroll
-                for (int q = 0; q < LB; ++q) {
+            for (int j = 0; j < CH; ++j) {
+                {
                     // Corners the head has moved past are spread before the move: tt on any
                     // move, tl on a step along x, lt on a step along y (a spread of 0 on the
                     // current corner when there is none: adding +0 changes no sum), lt and ll
                     // as well on the rare diagonal step or jump.  Branch-free but for those.
-                    const int code = rc[q] & 7;
+                    // record j: wave-uniform, read out of the lanes that hold it
+                    const int d = j * RS;
+                    const int rc = (int)__builtin_amdgcn_readlane(rv[d >> 6], d & 63);
+                    T w[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if constexpr (sizeof(T) == 4) {
+                            const int e = d + 1 + c;
+                            w[c] = __uint_as_float(__builtin_amdgcn_readlane(rv[e >> 6], e & 63));
+                        } else {
+                            const int e = d + 2 + 2 * c;
+                            const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane(rv[e >> 6], e & 63);
+                            const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane(rv[(e + 1) >> 6], (e + 1) & 63);
+                            w[c] = __longlong_as_double((long long)(lo | hi << 32));
+                        }
+                    }
+                    const int code = rc & 7;
                     const bool sx = code & 1, sy = code & 2;
                     spread(code ? att : T(0), pc);
                     spread(sx ? atl : sy ? alt : T(0), sx ? pc + ey : pc + ex);
@@ -264,12 +303,12 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
                     alt = nlt;
                     atl = ntl;
                     all = nll;
-                    pc = rc[q] >> 3;
-                    const T m = u[b + q];
-                    att += w[q][0] * m;
-                    alt += w[q][1] * m;
-                    atl += w[q][2] * m;
-                    all += w[q][3] * m;
+                    pc = rc >> 3;
+                    const T m = u[j];
+                    att += w[0] * m;
+                    alt += w[1] * m;
+                    atl += w[2] * m;
+                    all += w[3] * m;
                 }
             }
         }
@@ -278,12 +317,12 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
         spread(atl, pc + ey);
         spread(all, pc + ex + ey);
         __syncthreads();  // the pass's window is complete
-        const double co = cs[k], si = cs[fp.npass + k];
+        const T co = (T)cs[k], si = (T)cs[fp.npass + k];
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             const int c = lane + 64 * q;
             if (c < ncells) {
-                const double g = G[c];
+                const T g = (T)G[c];
                 G[c] = 0.0;
                 tx[q] += co * g;
                 ty[q] += si * g;
@@ -295,8 +334,8 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
     for (int q = 0; q < NT; ++q) {
         const int c = lane + 64 * q;
         if (c < ncells) {
-            dst[2 * c] = tx[q];
-            dst[2 * c + 1] = ty[q];
+            dst[2 * c] = (double)tx[q];
+            dst[2 * c + 1] = (double)ty[q];
         }
     }
 }
@@ -343,20 +382,13 @@ __global__ __launch_bounds__(256) void k_force_merge(const double *__restrict__ 
     }
 }
 
-template <typename T>
-hipError_t launch_motor_force(const T *M, const T *psi, const int *rec, const int *exy, const T *w, const double *cs,
-                              double *part, T *force, int nx, int ny, int nth, int ns, double F, double L,
-                              const ForcePlan &fp, hipStream_t s) {
-    int dev = 0, max_lds = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (e != hipSuccess) return e;
+template <typename T, bool VEC>
+hipError_t launch_spread(const T *M, const T *psi, const uint32_t *blk, const int *exy, const double *cs,
+                         double *part, int nx, int ny, int nth, int ns, T cF, const ForcePlan &fp, hipStream_t s) {
     constexpr int CH = std::is_same<T, float>::value ? 32 : 16;
-    if (fp.nt == 0 || fp.chunk != CH || fp.lds_bytes > (size_t)max_lds) return hipErrorInvalidValue;
     const int tiles = fp.tiles_i * fp.tiles_j;
-    const T cF = (T)(F * (L / ns) * (kTwoPi / nth));
-#define MMK_FORCE_LAUNCH(NT_)                                                                                    \
-    hipLaunchKernelGGL((k_motor_force<T, NT_, CH>), dim3(tiles), dim3(64), fp.lds_bytes, s, M, psi, rec, exy, w, \
+#define MMK_FORCE_LAUNCH(NT_)                                                                                      \
+    hipLaunchKernelGGL((k_motor_force<T, NT_, CH, VEC>), dim3(tiles), dim3(64), fp.lds_bytes, s, M, psi, blk, exy, \
                        cs, part, nx, ny, nth, ns, cF, fp)
     switch (fp.nt) {
     case 4: MMK_FORCE_LAUNCH(4); break;
@@ -370,7 +402,24 @@ hipError_t launch_motor_force(const T *M, const T *psi, const int *rec, const in
     default: return hipErrorInvalidValue;
     }
 #undef MMK_FORCE_LAUNCH
-    e = hipGetLastError();
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_motor_force(const T *M, const T *psi, const uint32_t *blk, const int *exy, const double *cs,
+                              double *part, T *force, int nx, int ny, int nth, int ns, double F, double L,
+                              const ForcePlan &fp, hipStream_t s) {
+    int dev = 0, max_lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    constexpr int CH = std::is_same<T, float>::value ? 32 : 16;
+    if (fp.nt == 0 || fp.chunk != CH || fp.lds_bytes > (size_t)max_lds) return hipErrorInvalidValue;
+    const T cF = (T)(F * (L / ns) * (kTwoPi / nth));
+    // 16-byte row loads when every column starts on a 16-byte boundary
+    const bool vec = ns % (16 / sizeof(T)) == 0 && reinterpret_cast<uintptr_t>(M) % 16 == 0;
+    e = vec ? launch_spread<T, true>(M, psi, blk, exy, cs, part, nx, ny, nth, ns, cF, fp, s)
+            : launch_spread<T, false>(M, psi, blk, exy, cs, part, nx, ny, nth, ns, cF, fp, s);
     if (e != hipSuccess) return e;
     const int64_t nxy = (int64_t)nx * ny;
     int64_t blocks = (nxy + 255) / 256;
@@ -378,11 +427,11 @@ hipError_t launch_motor_force(const T *M, const T *psi, const int *rec, const in
     hipLaunchKernelGGL(k_force_merge<T>, dim3((unsigned)blocks), dim3(256), 0, s, part, force, nx, ny, fp);
     return hipGetLastError();
 }
-template hipError_t launch_motor_force<float>(const float *, const float *, const int *, const int *, const float *,
+template hipError_t launch_motor_force<float>(const float *, const float *, const uint32_t *, const int *,
                                               const double *, double *, float *, int, int, int, int, double, double,
                                               const ForcePlan &, hipStream_t);
-template hipError_t launch_motor_force<double>(const double *, const double *, const int *, const int *,
-                                               const double *, const double *, double *, double *, int, int, int,
-                                               int, double, double, const ForcePlan &, hipStream_t);
+template hipError_t launch_motor_force<double>(const double *, const double *, const uint32_t *, const int *,
+                                               const double *, double *, double *, int, int, int, int, double,
+                                               double, const ForcePlan &, hipStream_t);
 
 }  // namespace mmk

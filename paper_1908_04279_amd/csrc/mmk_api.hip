@@ -30,7 +30,7 @@ constexpr int kProfMax = 65536;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t M[2], psi[2], m0, m1, Dxy, fpart, frec, fexy, fw, fcs, u, G, stress, mom, tab, partials, sums;
+    size_t M[2], psi[2], m0, m1, Dxy, fpart, fblk, fexy, fcs, u, G, stress, mom, tab, partials, sums;
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -88,11 +88,10 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.Dxy = take(2 * nxy * e);
     // motor force: partial windows and the spreading records per (pass, cell)
     const ForcePlan fpl = plan_force(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, e);
-    const size_t nrec = (size_t)fpl.npass * ((p.ns + fpl.chunk - 1) / fpl.chunk) * fpl.chunk;
+    const size_t nblk = (size_t)fpl.npass * ((p.ns + fpl.chunk - 1) / fpl.chunk);
     L.fpart = take(fpl.part_elems * sizeof(double));
-    L.frec = take(nrec * sizeof(int));
+    L.fblk = take(nblk * kForceBlock * sizeof(uint32_t));
     L.fexy = take(2 * (size_t)fpl.npass * sizeof(int));
-    L.fw = take(4 * nrec * e);
     L.fcs = take(2 * (size_t)fpl.npass * sizeof(double));
     L.u = take(2 * nxy * e);
     L.G = take(4 * nxy * e);
@@ -134,7 +133,7 @@ struct mmk_ctx {
     std::vector<float> host_tab32;
     ForcePlan fplan;    // motor-force spreading geometry
     ForceRecords frec;  // host copy of the force spreading records
-    std::vector<float> host_fw32;
+    std::vector<uint32_t> host_fblk;
     bool frec_ok = false;
 
     template <typename T>
@@ -386,15 +385,10 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
         auto up = [&](size_t off, const void *src, size_t bytes) {
             if (e == hipSuccess) e = hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
         };
-        up(L.frec, fr.rec.data(), fr.rec.size() * sizeof(int));
+        force_record_blocks(fr, c->fplan, c->esz, &c->host_fblk);
+        up(L.fblk, c->host_fblk.data(), c->host_fblk.size() * sizeof(uint32_t));
         up(L.fexy, fr.exy.data(), fr.exy.size() * sizeof(int));
         up(L.fcs, fr.cs.data(), fr.cs.size() * sizeof(double));
-        if (c->esz == 4) {
-            c->host_fw32.assign(fr.w.begin(), fr.w.end());
-            up(L.fw, c->host_fw32.data(), c->host_fw32.size() * 4);
-        } else {
-            up(L.fw, fr.w.data(), fr.w.size() * 8);
-        }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -537,16 +531,17 @@ mmk_status mmk_get_force(mmk_ctx *c, void *force) {
     int slot;
     HIPCHK(c, prof_begin(c, 5, &slot), "hipEventRecord");
     hipError_t e;
-    const int *rec = c->at<int>(c->L.frec), *exy = c->at<int>(c->L.fexy);
+    const uint32_t *blk = c->at<uint32_t>(c->L.fblk);
+    const int *exy = c->at<int>(c->L.fexy);
     const double *cs = c->at<double>(c->L.fcs);
     if (c->esz == 4)
-        e = launch_motor_force<float>(c->at<float>(c->L.M[c->cur]), c->at<float>(c->L.psi[c->cur]), rec, exy,
-                                      c->at<float>(c->L.fw), cs, c->at<double>(c->L.fpart), (float *)force, p.nx,
-                                      p.ny, p.ntheta, p.ns, p.F, p.L, fp, c->stream);
+        e = launch_motor_force<float>(c->at<float>(c->L.M[c->cur]), c->at<float>(c->L.psi[c->cur]), blk, exy, cs,
+                                      c->at<double>(c->L.fpart), (float *)force, p.nx, p.ny, p.ntheta, p.ns, p.F,
+                                      p.L, fp, c->stream);
     else
-        e = launch_motor_force<double>(c->at<double>(c->L.M[c->cur]), c->at<double>(c->L.psi[c->cur]), rec, exy,
-                                       c->at<double>(c->L.fw), cs, c->at<double>(c->L.fpart), (double *)force, p.nx,
-                                       p.ny, p.ntheta, p.ns, p.F, p.L, fp, c->stream);
+        e = launch_motor_force<double>(c->at<double>(c->L.M[c->cur]), c->at<double>(c->L.psi[c->cur]), blk, exy, cs,
+                                       c->at<double>(c->L.fpart), (double *)force, p.nx, p.ny, p.ntheta, p.ns, p.F,
+                                       p.L, fp, c->stream);
     if (e == hipErrorInvalidValue)
         return fail(c, MMK_ERR_UNSUPPORTED, "spreading window of %zu bytes exceeds the LDS per block", fp.lds_bytes);
     HIPCHK(c, e, "motor force launch");
