@@ -118,8 +118,9 @@ mmk_status mmk_get_motor_moments(mmk_ctx *ctx, void *m0, void *m1);
  * hat (bilinear) in x and y, periodic.  The filament length L is in the units of lx, ly.
  * Same bits on every run (each spreading window is private to one wave and summed in a fixed
  * order).  Needs state; MMK_ERR_UNSUPPORTED if the filament's reach makes the spreading window
- * larger than 3072 cells ((8 + 2 rx + 1)(8 + 2 ry + 1), rx = ceil(L nx / (2 lx)) + 1) or the
- * device's LDS per block.  No host sync. */
+ * ((8 + 2 r)^2 cells for a reach of r = L nx / (2 lx) cells, 8 bytes each, plus 18 KB of
+ * staging) larger than the device's LDS per block; windows beyond 3072 cells cost one more
+ * read of M per 3072 cells.  No host sync. */
 mmk_status mmk_get_force(mmk_ctx *ctx, void *force);
 /* host outputs, synchronizes: mass = sum Psi dx dy dth and sum_sigma[c] = sum sigma_c dx dy,
  * both accumulated in FP64 in a fixed order (bitwise reproducible). */

@@ -14,6 +14,7 @@ struct ForcePlan {
     int rx, ry, wx, wy;
     int tiles_i, tiles_j;
     int nt;             // window cells per lane held in registers (0: the window is too large)
+    int nslice;         // launches, each folding 64 nt consecutive window cells (one M read each)
     int chunk;          // arclength cells staged at a time (32 for FP32, 16 for FP64)
     int npass;          // orientation passes: nth / 2 (paired) or nth
     bool paired;
@@ -52,8 +53,8 @@ void force_record_blocks(const ForceRecords &r, const ForcePlan &fp, size_t elem
 // force[2][nx][ny] (fx, fy) of the state (M, psi): Eq. (10) with the bilinear hat, periodic.
 // blk: force_record_blocks() on the device; exy, cs: the records' steps and angle table;
 // part: scratch of plan.part_elems FP64 elements.
-// hipErrorInvalidValue (nothing launched) if the window does not fit the registers or the
-// device's LDS per block.
+// hipErrorInvalidValue (nothing launched) if the window does not fit the device's LDS per
+// block.
 template <typename T>
 hipError_t launch_motor_force(const T *M, const T *psi, const uint32_t *blk, const int *exy, const double *cs,
                               double *part, T *force, int nx, int ny, int nth, int ns, double F, double L,

@@ -81,10 +81,14 @@ ForcePlan plan_force(int nx, int ny, int nth, int ns, double lx, double ly, doub
     f.ry = -ymin;
     f.wx = xmax - xmin + 8;
     f.wy = ymax - ymin + 8;
+    // the window's (fx, fy) sit in registers, at most 48 cells a lane: larger windows are
+    // folded in slices, one launch (and one read of M) per slice
     const double cells = (double)f.wx * f.wy;
     f.nt = 0;
+    f.nslice = (int)std::ceil(cells / (64.0 * 48));
+    const double per = std::ceil(cells / f.nslice);
     for (int nt : kNt)
-        if (cells <= 64.0 * nt) {
+        if (per <= 64.0 * nt) {
             f.nt = nt;
             break;
         }
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
                                                     const uint32_t *__restrict__ blk, const int *__restrict__ exy,
                                                     const double *__restrict__ cs,
                                                     double *__restrict__ part, int nx, int ny, int nth, int ns,
-                                                    T cF, ForcePlan fp) {
+                                                    T cF, int cbase, ForcePlan fp) {
     using V = typename std::conditional<std::is_same<T, float>::value, float4, double2>::type;
     constexpr int VW = sizeof(V) / sizeof(T);
     constexpr int SR = CH + 4;                 // staging row: one point's CH cells, 16-byte aligned
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
         const T co = (T)cs[k], si = (T)cs[fp.npass + k];
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
-            const int c = lane + 64 * q;
+            const int c = cbase + lane + 64 * q;
             if (c < ncells) {
                 const T g = (T)G[c];
                 G[c] = 0.0;
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
     double *dst = part + (size_t)blockIdx.x * 2 * ncells;
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
-        const int c = lane + 64 * q;
+        const int c = cbase + lane + 64 * q;
         if (c < ncells) {
             dst[2 * c] = (double)tx[q];
             dst[2 * c + 1] = (double)ty[q];
@@ -384,12 +388,13 @@ __global__ __launch_bounds__(256) void k_force_merge(const double *__restrict__ 
 
 template <typename T, bool VEC>
 hipError_t launch_spread(const T *M, const T *psi, const uint32_t *blk, const int *exy, const double *cs,
-                         double *part, int nx, int ny, int nth, int ns, T cF, const ForcePlan &fp, hipStream_t s) {
+                         double *part, int nx, int ny, int nth, int ns, T cF, int cbase, const ForcePlan &fp,
+                         hipStream_t s) {
     constexpr int CH = std::is_same<T, float>::value ? 32 : 16;
     const int tiles = fp.tiles_i * fp.tiles_j;
 #define MMK_FORCE_LAUNCH(NT_)                                                                                      \
     hipLaunchKernelGGL((k_motor_force<T, NT_, CH, VEC>), dim3(tiles), dim3(64), fp.lds_bytes, s, M, psi, blk, exy, \
-                       cs, part, nx, ny, nth, ns, cF, fp)
+                       cs, part, nx, ny, nth, ns, cF, cbase, fp)
     switch (fp.nt) {
     case 4: MMK_FORCE_LAUNCH(4); break;
     case 8: MMK_FORCE_LAUNCH(8); break;
@@ -418,8 +423,11 @@ hipError_t launch_motor_force(const T *M, const T *psi, const uint32_t *blk, con
     const T cF = (T)(F * (L / ns) * (kTwoPi / nth));
     // 16-byte row loads when every column starts on a 16-byte boundary
     const bool vec = ns % (16 / sizeof(T)) == 0 && reinterpret_cast<uintptr_t>(M) % 16 == 0;
-    e = vec ? launch_spread<T, true>(M, psi, blk, exy, cs, part, nx, ny, nth, ns, cF, fp, s)
-            : launch_spread<T, false>(M, psi, blk, exy, cs, part, nx, ny, nth, ns, cF, fp, s);
+    for (int sl = 0; sl < fp.nslice && e == hipSuccess; ++sl) {
+        const int cbase = sl * 64 * fp.nt;
+        e = vec ? launch_spread<T, true>(M, psi, blk, exy, cs, part, nx, ny, nth, ns, cF, cbase, fp, s)
+                : launch_spread<T, false>(M, psi, blk, exy, cs, part, nx, ny, nth, ns, cF, cbase, fp, s);
+    }
     if (e != hipSuccess) return e;
     const int64_t nxy = (int64_t)nx * ny;
     int64_t blocks = (nxy + 255) / 256;

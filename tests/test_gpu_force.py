@@ -86,13 +86,28 @@ def test_total_force_on_the_gpu_matches_the_motor_sum():
     np.testing.assert_allclose(f.sum(axis=(1, 2)), want, rtol=1e-12)
 
 
+@pytest.mark.parametrize("shape,kw,precision,tol", [
+    ((96, 96, 16, 32), {"L": 3.4}, 0, 1e-12),   # 60 x 60 window: folded in 2 slices
+    ((128, 128, 8, 32), {"L": 4.5}, 1, 1e-5),   # 100 x 100 window: 4 slices, ~100 KB of LDS
+])
+def test_sliced_windows(shape, kw, precision, tol):
+    p, psi, M = case(shape, **kw)
+    if precision:
+        psi, M = psi.astype(np.float32), M.astype(np.float32)
+    g = gpu_force(p, psi, M, precision=precision)
+    o = A.motor_force(p, psi.astype(np.float64), M.astype(np.float64))
+    err = rel_err(g, o)
+    print(f"{shape} {kw}: {err:.2e}", flush=True)
+    assert err <= tol
+
+
 def test_window_too_large_is_unsupported():
-    """Heads up to 768 cells from their point along x: a window far beyond the registers."""
+    """Heads up to 1536 cells from their point along x: a window beyond the LDS of a block."""
     import torch
     from paper_1908_04279_amd import mmk
-    p = ModelParams(nx=2048, ny=8, ntheta=1, ns=4, lx=1.0, ly=100.0, L=1.0)
+    p = ModelParams(nx=4096, ny=8, ntheta=1, ns=4, lx=1.0, ly=100.0, L=1.0)
     ctx = mmk.Context(p)
-    ctx.set_state(torch.ones(2048, 8, 1, dtype=torch.float64))
+    ctx.set_state(torch.ones(4096, 8, 1, dtype=torch.float64))
     with pytest.raises(mmk.MMKError) as ei:
         ctx.get_force()
     assert ei.value.status == mmk.MMK_ERR_UNSUPPORTED
