@@ -205,7 +205,9 @@ class Context:
         return m0, m1
 
     def get_force(self):
-        """Motor force density [2][nx][ny] of the current state."""
+        """Motor force density F2 [2][nx][ny] = (f_x, f_y) of the current state (Eq. (10)):
+        F p psi M ds dth of every bound-motor cell spread from its head, (x_i, y_j) +
+        (s_l - L/2) p, onto the four surrounding cell centres (bilinear hat, periodic)."""
         f = self.empty((2, self.p.nx, self.p.ny))
         self._check(lib().mmk_get_force(self.h, _ptr(f)))
         return f
