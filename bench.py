@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -39,15 +40,32 @@ EVENT_EVERY = 13
 # total motors per unit area of the depletion leg: about twice the coarse bound density the
 # linear model settles to on this workload, so the free pool is roughly halved
 M_TOTAL_BENCH = 0.02
+# Motor sub-cycling leg: motors walking 8x faster than the default (v0 = 8), whose stability
+# limit (v0/ds + k_off) is then stricter than the psi limit at 256^2, and a motor CFL of 0.4.
+SUBSTEP_V0 = 8.0
+MOTOR_CFL_BENCH = 0.4
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def motor_bytes(p, b, with_m1):
+def motor_bytes(p, b, with_m1, nstep=1):
+    """Algorithmic HBM bytes of one motor launch over nstep micro-steps: read M, write M, write
+    m0 of every micro-step [and m1 of the last]."""
     n_psi = p.nx * p.ny * p.ntheta
-    return b * (2 * n_psi * p.ns + n_psi * (2 if with_m1 else 1))
+    return b * (2 * n_psi * p.ns + n_psi * (nstep + (1 if with_m1 else 0)))
+
+
+MAX_BLOCK = 16  # micro-steps per temporally blocked motor launch (the library's block)
+
+
+def block_plan(p, K):
+    """Motor launches per K-step call and micro-steps in each: blocks of up to MAX_BLOCK for
+    the linear model (m_total = 0), unless MMK_MOTOR_BLOCK=0; else one per micro-step."""
+    if getattr(p, "m_total", 0.0) > 0 or os.environ.get("MMK_MOTOR_BLOCK", "1") == "0":
+        return [1] * K
+    return [min(MAX_BLOCK, K - d) for d in range(0, K, MAX_BLOCK)]
 
 
 def psi_bytes(p, b, out):
@@ -56,13 +74,6 @@ def psi_bytes(p, b, out):
     n_psi = p.nx * p.ny * p.ntheta
     nxy = p.nx * p.ny
     return b * (3 * n_psi + 6 * nxy) + (b * (n_psi + 10 * nxy) if out else 0)
-
-
-def step_bytes(p, b, out):
-    """Algorithmic HBM bytes of one micro-step: motor kernel (read M, write M, write m0
-    [and m1]) + psi kernel (read psi, m0, u, gradu; write psi [read m1, write stress and
-    moments])."""
-    return motor_bytes(p, b, out) + psi_bytes(p, b, out)
 
 
 def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1):
@@ -110,7 +121,8 @@ def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1):
         ctx.profile(False)
     mass, ss = ctx.get_sums()
     ctx.close()
-    return dict(elapsed=elapsed, steps=steps, dt=dt, prof=prof, mass=mass, event_every=event_every)
+    return dict(elapsed=elapsed, steps=steps, dt=dt, prof=prof, mass=mass, event_every=event_every,
+                blocks=block_plan(p, K))
 
 
 def run_adjoint(name, precision):
@@ -279,11 +291,13 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64", "depletion", "force"],
+    ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64", "depletion", "force",
+                                       "substeps"],
                     default="all",
                     help="restrict to one leg (used for profiler runs)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--depletion-steps", type=int, default=200)
+    ap.add_argument("--substep-steps", type=int, default=200)
     ap.add_argument("--event-every", type=int, default=EVENT_EVERY,
                     help="bracket every N-th launch of each kernel with HIP events")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -320,6 +334,13 @@ def main():
         pd = gen.params_for("c3_fp32_256x256x64x64", m_total=M_TOTAL_BENCH)
         res["depletion"] = run_forward(pd, mmk.FP32, args.depletion_steps, min(args.warmup, 20), K,
                                        event_every=args.event_every)
+    if args.only in ("all", "substeps"):
+        # fast motors on the same grid: one motor step per micro-step (dt at the motor limit)
+        # against motor sub-cycling (dt at the psi limit, n motor steps per launch)
+        pf = gen.params_for("c3_fp32_256x256x64x64", v0=SUBSTEP_V0)
+        ps = gen.params_for("c3_fp32_256x256x64x64", v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH)
+        res["fast_plain"] = run_forward(pf, mmk.FP32, args.substep_steps, 20, K, event_every=args.event_every)
+        res["fast_sub"] = run_forward(ps, mmk.FP32, args.substep_steps, 20, K, event_every=args.event_every)
     if args.only in ("all", "fp32"):
         res["fp32"] = run_forward(p, mmk.FP32, args.steps, args.warmup, K, event_every=args.event_every)
     if args.only in ("all", "fp64"):
@@ -327,21 +348,30 @@ def main():
                                   event_every=args.event_every)
 
     def summarise(r, b):
-        """Whole-step rate, and the motor kernel's roofline over its timed launches.  Launch j
-        of a kernel in the timed region (one per micro-step) is an output launch (m1, stress,
-        moments) when j % K == K - 1; launches j = 0, E, 2E, ... carry HIP events."""
+        """Whole-step rate, and the motor kernel's roofline over its timed launches.  A K-step
+        call runs the motor launches of r["blocks"] (micro-steps each); the last one of a call
+        carries the outputs (m1, stress, moments), as does the psi launch of the call's last
+        micro-step.  Launches j = 0, E, 2E, ... of each kernel in the timed region carry HIP
+        events."""
         calls = r["steps"] // K
+        blocks = r["blocks"]
         sps = r["steps"] / r["elapsed"]
-        total = (r["steps"] - calls) * step_bytes(p, b, False) + calls * step_bytes(p, b, True)
-        timed = list(range(0, r["steps"], r["event_every"]))
-        n_out = sum(1 for j in timed if j % K == K - 1)
+        launches = [(nb, i == len(blocks) - 1) for _ in range(calls) for i, nb in enumerate(blocks)]
+        total = sum(motor_bytes(p, b, out, nb) for nb, out in launches) \
+            + (r["steps"] - calls) * psi_bytes(p, b, False) + calls * psi_bytes(p, b, True)
+        timed_m = launches[::r["event_every"]]
+        timed_p = list(range(0, r["steps"], r["event_every"]))
         ms_m, n_m = r["prof"]["motor_step"]
         ms_p, n_p = r["prof"]["psi_step"]
-        assert n_m == len(timed) and n_p == len(timed), (n_m, n_p, len(timed))
-        kb = ((n_m - n_out) * motor_bytes(p, b, False) + n_out * motor_bytes(p, b, True)) / n_m
+        assert n_m == len(timed_m) and n_p == len(timed_p), (n_m, n_p, len(timed_m), len(timed_p))
+        n_out = sum(1 for _, out in timed_m if out)
+        kb = sum(motor_bytes(p, b, out, nb) for nb, out in timed_m) / n_m
+        steps_per_launch = sum(nb for nb, _ in timed_m) / n_m
         return dict(steps_per_s=sps, step_gbs=total / r["elapsed"] / 1e9, avg_us=ms_m / n_m * 1e3,
                     gbs=kb / (ms_m / n_m / 1e3) / 1e9, bytes_per_launch=kb, n_plain=n_m - n_out,
-                    n_out=n_out, psi_avg_us=ms_p / n_p * 1e3, timed_launches=n_m, mass=r["mass"])
+                    n_out=n_out, psi_avg_us=ms_p / n_p * 1e3, timed_launches=n_m, mass=r["mass"],
+                    steps_per_launch=steps_per_launch,
+                    motor_us_per_step=ms_m / n_m * 1e3 / steps_per_launch)
 
     def depletion_summary():
         sd = summarise(res["depletion"], 4)
@@ -351,8 +381,28 @@ def main():
              "steps": res["depletion"]["steps"]}
         return d
 
+    def substep_summary():
+        """Simulated time per wall second with and without motor sub-cycling (fast motors);
+        n per micro-step by the rule documented for mmk_params.motor_cfl."""
+        d = {"v0": SUBSTEP_V0, "motor_cfl": MOTOR_CFL_BENCH}
+        for key, name in (("fast_plain", "one_motor_step"), ("fast_sub", "subcycled")):
+            r = res[key]
+            sr = summarise(r, 4)
+            rate = SUBSTEP_V0 / (p.L / p.ns) + p.k_off
+            n = max(1, math.ceil(r["dt"] * rate / MOTOR_CFL_BENCH)) if key == "fast_sub" else 1
+            d[name] = {"dt": r["dt"], "motor_steps_per_micro_step": n, "micro_steps_per_s": sr["steps_per_s"],
+                       "simulated_time_per_s": r["dt"] * sr["steps_per_s"],
+                       "motor_us_per_micro_step": sr["motor_us_per_step"],
+                       "motor_us_per_motor_step": sr["motor_us_per_step"] / n, "psi_avg_us": sr["psi_avg_us"]}
+        d["speedup_simulated_time"] = (d["subcycled"]["simulated_time_per_s"]
+                                       / d["one_motor_step"]["simulated_time_per_s"])
+        return d
+
     if args.only == "depletion":
         print(json.dumps({"depletion_fp32": depletion_summary()}), flush=True)
+        return
+    if args.only == "substeps":
+        print(json.dumps({"substeps_fp32": substep_summary()}), flush=True)
         return
 
     out = {"metric": METRIC, "unit": "micro-steps/s", "n_gpus": 1, "higher_is_better": True,
@@ -371,7 +421,9 @@ def main():
                        "frac": s["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                        "kernel": "motor column step", "avg_launch_us": s["avg_us"],
                        "algorithmic_bytes_per_launch": s["bytes_per_launch"],
-                       "timed_launches": s["timed_launches"], "output_launches_timed": s["n_out"]}
+                       "timed_launches": s["timed_launches"], "output_launches_timed": s["n_out"],
+                       "micro_steps_per_launch": s["steps_per_launch"],
+                       "motor_us_per_micro_step": s["motor_us_per_step"]}
     out["step_hbm_gbs"] = s["step_gbs"]
     out["step_hbm_frac"] = s["step_gbs"] / HBM_PEAK_GBS
     out["psi_step_avg_us"] = s["psi_avg_us"]
@@ -385,6 +437,8 @@ def main():
     if args.only == "all":
         log("[bench] motor force leg")
         out["force_fp32"] = run_force(p, mmk.FP32, 10)
+    if "fast_sub" in res:
+        out["substeps_fp32"] = substep_summary()
     if "depletion" in res:
         out["depletion_fp32"] = depletion_summary()
         out["depletion_fp32"]["relative_to_linear"] = out["depletion_fp32"]["micro_steps_per_s"] / s["steps_per_s"]

@@ -73,6 +73,14 @@ typedef struct {
                             * current state; where B > m_total every motor column at (x, y)
                             * is scaled by m_total / B and none attach, elsewhere they
                             * attach at rate k_on (m_total - B).  Not supported by the tape. */
+    double motor_cfl;      /* >= 0.  0: one motor step per micro-step.  > 0: the motor step
+                            * sub-cycles (Alg. 2, local dt*): a micro-step of length dt
+                            * advances M by n = ceil(dt (v0 / ds + k_off) / motor_cfl)
+                            * steps of dt / n inside one launch (M is read and written once),
+                            * the s-moments taken after the last; n <= 4096.  The stability
+                            * limit is the same at every point here, so one n serves all.
+                            * Needs m_total = 0 (else MMK_ERR_UNSUPPORTED); not supported by
+                            * the tape. */
 } mmk_params;
 
 /* Bytes of device workspace a context needs.  ckpt_every > 0 reserves the adjoint tape:

@@ -19,6 +19,8 @@
  *   - Sec. 2, Eq. (5) and the extra-stress step of Alg. 1: moments of Psi.
  *   - Optional depletion (m_total > 0): Eqs. (5)-(6) and the over-binding clamp of Alg. 2,
  *     applied at the start of each micro-step from the current state.
+ *   - Optional motor sub-cycling (motor_cfl > 0, linear attachment): the inner loop of
+ *     Alg. 2, n steps of dt/n with n from the motor's stability limit.
  * Where the paper leaves the discretisation open, the reading is written next to the code.
  */
 #include "oracle.h"
@@ -137,6 +139,38 @@ void oracle_motor_step(const oracle_params *p, double dt, const double *M, doubl
             if (m0) m0[col] = a;
             if (m1) m1[col] = b;
         }
+    }
+}
+
+int oracle_motor_substeps(const oracle_params *p, double dt) {
+    if (!(p->motor_cfl > 0.0)) return 1;
+    const double rate = p->v0 / (p->L / p->ns) + p->k_off;
+    const double n = ceil(dt * rate / p->motor_cfl);
+    return n < 1.0 ? 1 : (int)n;
+}
+
+void oracle_motor_substepped(const oracle_params *p, double dt, const double *M, double *Mout,
+                             double *m0, double *m1) {
+    const int n = oracle_motor_substeps(p, dt), ns = p->ns;
+    const double h = dt / n;
+    const long ncol = (long)p->nx * p->ny * p->nth;
+#pragma omp parallel
+    {
+        double *tmp = (double *)malloc(sizeof(double) * (size_t)ns);
+#pragma omp for schedule(static)
+        for (long col = 0; col < ncol; ++col) {
+            double *dst = Mout + col * ns;
+            memcpy(dst, M + col * ns, sizeof(double) * (size_t)ns);
+            for (int q = 0; q < n; ++q) {
+                oracle_column_step(p, h, dst, tmp);
+                memcpy(dst, tmp, sizeof(double) * (size_t)ns);
+            }
+            double a, b;
+            oracle_column_moments(p, dst, &a, &b);
+            if (m0) m0[col] = a;
+            if (m1) m1[col] = b;
+        }
+        free(tmp);
     }
 }
 
@@ -399,6 +433,8 @@ void oracle_run(const oracle_params *p, double dt, int nsteps, double *psi, doub
             oracle_coarse_bound(p, pa, m0, B);
             oracle_depletion(p, B, scale, src);
             motor_step_depleted(p, dt, Ma, Mb, m0, scale, src);
+        } else if (p->motor_cfl > 0.0) {
+            oracle_motor_substepped(p, dt, Ma, Mb, m0, NULL);
         } else {
             oracle_motor_step(p, dt, Ma, Mb, m0, NULL);
         }

@@ -20,6 +20,7 @@ typedef struct {
     double F, sigma_f;
     int limiter;              /* 0: superbee MUSCL, 1: first-order upwind (sigma = 0) */
     double m_total;           /* total motor density per unit area; 0: free pool taken as 1 */
+    double motor_cfl;         /* > 0: motor sub-cycling (local dt*), see oracle_motor_substeps */
 } oracle_params;
 
 /* superbee slope of the two one-sided differences a (left) and b (right) */
@@ -45,6 +46,17 @@ void oracle_depletion(const oracle_params *p, const double *B, double *scale, do
 void oracle_column_moments(const oracle_params *p, const double *M, double *m0, double *m1);
 
 /* all columns: Mout, m0, m1 (m1 may be NULL) */
+/* Motor sub-steps of one micro-step of length dt (Alg. 2: the inner step dt* is limited by
+ * the motor's walking speed and detachment, a rate v0/ds + k_off that is the same at every
+ * point): 1 when motor_cfl <= 0, else the least n >= 1 with dt/n * rate <= motor_cfl, i.e.
+ * ceil(dt rate / motor_cfl).  Linear attachment only (m_total = 0). */
+int oracle_motor_substeps(const oracle_params *p, double dt);
+
+/* n explicit-midpoint steps of dt/n of every column (n from oracle_motor_substeps), then
+ * the s-moments of the result (either moment pointer may be NULL). */
+void oracle_motor_substepped(const oracle_params *p, double dt, const double *M, double *Mout,
+                             double *m0, double *m1);
+
 void oracle_motor_step(const oracle_params *p, double dt, const double *M, double *Mout,
                        double *m0, double *m1);
 

@@ -20,7 +20,7 @@ class _Params(C.Structure):
                 ("lx", C.c_double), ("ly", C.c_double), ("L", C.c_double),
                 ("k_on", C.c_double), ("k_off", C.c_double), ("v0", C.c_double),
                 ("F", C.c_double), ("sigma_f", C.c_double), ("limiter", C.c_int),
-                ("m_total", C.c_double)]
+                ("m_total", C.c_double), ("motor_cfl", C.c_double)]
 
 
 _lib = None
@@ -46,6 +46,9 @@ def lib():
         L.oracle_motor_force.argtypes = [P, _dp, _dp, _dp]
         L.oracle_column_moments.argtypes = [P, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.oracle_motor_step.argtypes = [P, C.c_double, _dp, _dp, C.c_void_p, C.c_void_p]
+        L.oracle_motor_substeps.argtypes = [P, C.c_double]
+        L.oracle_motor_substeps.restype = C.c_int
+        L.oracle_motor_substepped.argtypes = [P, C.c_double, _dp, _dp, C.c_void_p, C.c_void_p]
         L.oracle_psi_step.argtypes = [P, C.c_double, _dp, _dp, _dp, _dp, _dp]
         L.oracle_moments.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
         L.oracle_global_sums.argtypes = [P, _dp, _dp, C.POINTER(C.c_double), _dp]
@@ -59,7 +62,8 @@ def lib():
 def cparams(p) -> _Params:
     """Accepts any object with the ModelParams attribute names."""
     return _Params(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, p.k_on, p.k_off, p.v0,
-                   p.F, p.sigma_f, int(getattr(p, "limiter", 0)), float(getattr(p, "m_total", 0.0)))
+                   p.F, p.sigma_f, int(getattr(p, "limiter", 0)), float(getattr(p, "m_total", 0.0)),
+                   float(getattr(p, "motor_cfl", 0.0)))
 
 
 def _f64(a):
@@ -136,6 +140,21 @@ def motor_step(p, dt, M):
     m0 = np.empty(M.shape[:-1])
     m1 = np.empty(M.shape[:-1])
     lib().oracle_motor_step(C.byref(cparams(p)), float(dt), M, out, _ptr(m0), _ptr(m1))
+    return out, m0, m1
+
+
+def motor_substeps(p, dt):
+    """Sub-steps of one micro-step (the oracle's local dt* rule, Alg. 2)."""
+    return int(lib().oracle_motor_substeps(C.byref(cparams(p)), float(dt)))
+
+
+def motor_substepped(p, dt, M):
+    """motor_substeps(p, dt) midpoint steps of dt / n of every column, and the s-moments."""
+    M = _f64(M)
+    out = np.empty_like(M)
+    m0 = np.empty(M.shape[:-1])
+    m1 = np.empty(M.shape[:-1])
+    lib().oracle_motor_substepped(C.byref(cparams(p)), float(dt), M, out, _ptr(m0), _ptr(m1))
     return out, m0, m1
 
 

@@ -157,11 +157,24 @@ class Problem:
         src = torch.where(over, torch.zeros_like(B), k_on * (p.m_total - B))
         return M * scale[:, :, None, None], src[:, :, None, None]
 
+    def substeps(self, v0, k_off, dt):
+        """Alg. 2's inner loop: n steps of dt/n, n = ceil(dt (v0/ds + k_off) / motor_cfl) (at
+        least 1), the motor stability limit being the same at every point; 1 without
+        sub-cycling."""
+        cfl = getattr(self.p, "motor_cfl", 0.0)
+        if not cfl > 0.0:
+            return 1
+        rate = float(v0) / (self.p.L / self.p.ns) + float(k_off)
+        return max(1, int(math.ceil(dt * rate / cfl)))
+
     def step(self, psi, M, k_on, k_off, v0, u, G, dt):
         p = self.p
         if getattr(p, "m_total", 0.0) > 0.0:
             M, k_on = self.depletion(psi, M, k_on)
-        M1 = motor_step(M, k_on, k_off, v0, dt, self.ds, p.limiter)
+        n = self.substeps(v0, k_off, dt)
+        M1 = M
+        for _ in range(n):
+            M1 = motor_step(M1, k_on, k_off, v0, dt / n, self.ds, p.limiter)
         m0, _ = s_moments(M1, p.L)
         psi1 = psi_step(psi, m0, u, G, p.F, dt, p.lx, p.ly)
         return psi1, M1

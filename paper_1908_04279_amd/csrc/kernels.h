@@ -11,14 +11,20 @@ template <typename T>
 struct MotorConst {
     T k_on, k_off, v0;
     T nv_ds;       // -v0 / ds
-    T dt, half_dt; // step and midpoint stage
+    T dt, half_dt; // sub-step and its midpoint stage
+    int nsub;      // sub-steps per micro-step (>= 1)
+    int nstep;     // micro-steps per launch (>= 1): M stays in registers between them
+    T *m0_steps;   // [nstep - 1][ncol]: m0 after micro-steps 0 .. nstep-2 (nstep > 1)
     T ds, ds2;     // m0 = ds * sum M,  m1 = ds^2 * sum (l + 1/2 - ns/2) M
     int nth;       // columns per (x, y) point, and log2 of it when a power of two (else -1)
     int nth_shift;
 };
 
-// Forward motor step over `ncol` independent columns of `ns` cells.
-//   M_out = M + dt R(M + dt/2 R(M));  m0 = sum M_out ds;  m1 (if non-null) likewise.
+// Forward motor step over `ncol` independent columns of `ns` cells, in registers: c.nstep
+// micro-steps of c.nsub sub-steps each,
+//   M <- M + dt R(M + dt/2 R(M)),
+// with m0 after micro-step t < nstep-1 in c.m0_steps[t]; M_out = M after the last,
+// m0 = sum M_out ds, m1 (if non-null) likewise.
 // Dxy (non-null: depletion) holds [nx][ny][2] = (clamp factor, free-motor pool) of the
 // current state (depletion_of() of its coarse bound density); the columns of point
 // xy = col / nth are first scaled by the factor, and the attachment source is k_on times the

@@ -9,6 +9,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -25,12 +26,13 @@ thread_local std::string g_create_error;
 constexpr int kMaxTheta = 512;
 constexpr int kMaxS = 512;
 constexpr int kProfIds = 6;
+constexpr int kMaxBlock = 16;  // micro-steps per temporally blocked motor launch
 constexpr int kProfMax = 65536;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t M[2], psi[2], m0, m1, Dxy, fpart, fblk, fexy, fcs, u, G, stress, mom, tab, partials, sums;
+    size_t M[2], psi[2], psi_tmp, m0, m0s, m1, Dxy, fpart, fblk, fexy, fcs, u, G, stress, mom, tab, partials, sums;
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -48,12 +50,14 @@ std::string check_params(const mmk_params *p) {
     if (p->ns < 1) return "ns must be >= 1";
     if (p->precision != MMK_FP32 && p->precision != MMK_FP64) return "precision must be MMK_FP64 or MMK_FP32";
     if (p->limiter != MMK_SUPERBEE && p->limiter != MMK_UPWIND1) return "limiter must be MMK_SUPERBEE or MMK_UPWIND1";
-    const double vals[] = {p->lx, p->ly, p->L, p->k_on, p->k_off, p->v0, p->F, p->sigma_f, p->m_total};
+    const double vals[] = {p->lx, p->ly, p->L, p->k_on, p->k_off, p->v0, p->F, p->sigma_f, p->m_total,
+                           p->motor_cfl};
     for (double v : vals)
         if (!std::isfinite(v)) return "non-finite model parameter";
     if (p->lx <= 0 || p->ly <= 0 || p->L <= 0) return "lx, ly and L must be > 0";
     if (p->v0 < 0) return "v0 must be >= 0 (motors walk towards s = L)";
     if (p->m_total < 0) return "m_total must be >= 0 (0: no depletion)";
+    if (p->motor_cfl < 0) return "motor_cfl must be >= 0 (0: no sub-cycling)";
     if ((int64_t)p->nx * p->ny > ((int64_t)1 << 31)) return "nx * ny too large";
     return "";
 }
@@ -61,6 +65,8 @@ std::string check_params(const mmk_params *p) {
 std::string check_supported(const mmk_params *p) {
     if (p->ntheta > kMaxTheta) return "ntheta > 512 is not supported by the psi kernel";
     if (p->ns > kMaxS) return "ns > 512 is not supported by the motor kernel";
+    if (p->motor_cfl > 0 && p->m_total > 0)
+        return "motor sub-cycling (motor_cfl > 0) covers linear attachment only (m_total = 0)";
     if (plan_psi(p->nx, p->ny, p->ntheta, esize(*p), 2).lds_bytes > 64 * 1024)
         return "ntheta too large for the psi kernel's LDS tile at this precision";
     return "";
@@ -84,6 +90,10 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.psi[0] = take(np * e);
     L.psi[1] = take(np * e);
     L.m0 = take(np * e);
+    // temporal blocking of the linear motor step: m0 of the first kMaxBlock - 1 micro-steps
+    // of a block, and a third psi buffer so that a block of any length ends in the other one
+    L.m0s = p.m_total > 0 ? 0 : take((size_t)(kMaxBlock - 1) * np * e);
+    L.psi_tmp = p.m_total > 0 ? 0 : take(np * e);
     L.m1 = take(np * e);
     L.Dxy = take(2 * nxy * e);
     // motor force: partial windows and the spreading records per (pass, cell)
@@ -121,6 +131,7 @@ struct mmk_ctx {
     // MMK_PSI_WALK=0/1 overrides)
     WalkPlan wp{};
     bool walk = false;
+    bool block = false;  // temporal blocking of the linear motor step (MMK_MOTOR_BLOCK=0: off)
     bool have_state = false, have_fluid = false, have_out = false;
     std::string err;
     bool prof = false;
@@ -264,9 +275,50 @@ static mmk_status run_steps_serial(mmk_ctx *c, int K, double dt) {
     return MMK_OK;
 }
 
+// Temporal blocking of the linear motor step (m_total = 0, no tape): M does not depend on psi,
+// so one motor launch advances M through a block of up to kMaxBlock micro-steps, keeping each
+// column in registers and leaving m0 of every micro-step; then the block's psi steps run, each
+// with the m0 of its own micro-step.  Every micro-step is computed exactly as in the serial
+// order (the same bits); M is read and written once per block instead of once per step.
+template <typename T>
+static mmk_status run_steps_blocked(mmk_ctx *c, int K, double dt) {
+    const mmk_params &p = c->p;
+    const int64_t np = n_psi(p);
+    T *m0 = c->at<T>(c->L.m0), *m0s = c->at<T>(c->L.m0s), *m1 = c->at<T>(c->L.m1);
+    const T *u = c->at<T>(c->L.u), *G = c->at<T>(c->L.G);
+    for (int done = 0; done < K;) {
+        const int nb = std::min(kMaxBlock, K - done);
+        const bool out = done + nb == K;  // the call's last micro-step, with the outputs
+        const int a = c->cur, b = 1 - c->cur;
+        MotorConst<T> mc = motor_const<T>(p, dt);
+        mc.nstep = nb;
+        mc.m0_steps = m0s;
+        int slot;
+        HIPCHK(c, prof_begin_on(c, 0, &slot, c->stream), "hipEventRecord");
+        HIPCHK(c, launch_motor_step<T>(c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), m0, out ? m1 : nullptr, np, p.ns,
+                                       p.limiter, mc, nullptr, c->stream),
+               "motor step launch");
+        HIPCHK(c, prof_end_on(c, 0, slot, c->stream), "hipEventRecord");
+        // psi from buffer a to buffer b: the steps alternate between b and the third buffer,
+        // counted back from the last one, which writes b
+        const T *src = c->at<T>(c->L.psi[a]);
+        for (int t = 0; t < nb; ++t) {
+            T *dst = ((nb - 1 - t) % 2 == 0) ? c->at<T>(c->L.psi[b]) : c->at<T>(c->L.psi_tmp);
+            const T *m0t = t + 1 < nb ? m0s + (int64_t)t * np : m0;
+            mmk_status st = psi_half<T>(c, src, dst, m0t, m1, u, G, dt, out && t + 1 == nb, c->stream);
+            if (st != MMK_OK) return st;
+            src = dst;
+        }
+        c->cur = b;
+        done += nb;
+    }
+    return MMK_OK;
+}
+
 template <typename T>
 static mmk_status run_steps(mmk_ctx *c, int K, double dt) {
-    mmk_status st = run_steps_serial<T>(c, K, dt);
+    const bool blocked = c->block && c->p.m_total == 0 && !c->tape.active;
+    mmk_status st = blocked ? run_steps_blocked<T>(c, K, dt) : run_steps_serial<T>(c, K, dt);
     if (st != MMK_OK) return st;
     if (K > 0) {
         c->have_out = true;
@@ -399,6 +451,8 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     c->wp = plan_walk(p->nx, p->ny, p->ntheta);
     const char *ew = getenv("MMK_PSI_WALK");
     c->walk = c->wp.ok && (ew ? atoi(ew) != 0 : c->esz == 4);
+    const char *eb = getenv("MMK_MOTOR_BLOCK");
+    c->block = p->m_total == 0 && (eb ? atoi(eb) != 0 : true);
     *out = c;
     return MMK_OK;
 }
@@ -475,6 +529,9 @@ mmk_status mmk_step(mmk_ctx *c, int32_t K, double dt) {
     if (!c->have_state) return fail(c, MMK_ERR_STATE, "mmk_step before mmk_set_state");
     if (!c->have_fluid) return fail(c, MMK_ERR_STATE, "mmk_step before mmk_set_fluid");
     if (K == 0) return MMK_OK;
+    if (motor_substeps(c->p, dt) < 1)
+        return fail(c, MMK_ERR_ARG, "dt (v0/ds + k_off) / motor_cfl needs more than %d motor sub-steps",
+                    kMaxSubsteps);
     if (c->tape.active && c->tape.steps + K > c->tape.max_steps)
         return fail(c, MMK_ERR_ARG, "taped run would exceed max_tape_steps (%d)", c->tape.max_steps);
     return c->esz == 4 ? run_steps<float>(c, K, dt) : run_steps<double>(c, K, dt);
@@ -568,6 +625,8 @@ mmk_status mmk_tape_begin(mmk_ctx *c, int32_t ckpt_every) {
     if (!c) return MMK_ERR_ARG;
     if (c->p.m_total > 0)
         return fail(c, MMK_ERR_UNSUPPORTED, "the adjoint covers linear attachment only (m_total = 0)");
+    if (c->p.motor_cfl > 0)
+        return fail(c, MMK_ERR_UNSUPPORTED, "the adjoint covers one motor step per micro-step (motor_cfl = 0)");
     return tape_begin(c, &c->tape, ckpt_every, c->have_state, c->have_fluid, c->cur);
 }
 

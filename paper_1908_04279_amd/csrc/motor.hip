@@ -113,13 +113,49 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
         src = c.k_on * pool;
     }
 
+    // One micro-step: c.nsub explicit-midpoint steps of c.dt in registers (sub-cycling:
+    // the local dt* of Alg. 2); the first is outside the loop so that one step compiles as
+    // straight code.  x: the state before, y: after.
     T R[CPL], y[CPL];
-    motor_rhs<T, CPL, LPC, LIM, RAGGED>(x, R, c, src, g, l0, ns);
+    auto rk2 = [&]() {
+        motor_rhs<T, CPL, LPC, LIM, RAGGED>(x, R, c, src, g, l0, ns);
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) y[j] = x[j] + c.half_dt * R[j];
-    motor_rhs<T, CPL, LPC, LIM, RAGGED>(y, R, c, src, g, l0, ns);
+        for (int j = 0; j < CPL; ++j) y[j] = x[j] + c.half_dt * R[j];
+        motor_rhs<T, CPL, LPC, LIM, RAGGED>(y, R, c, src, g, l0, ns);
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) y[j] = x[j] + c.dt * R[j];
+        for (int j = 0; j < CPL; ++j) y[j] = x[j] + c.dt * R[j];
+    };
+    auto micro = [&]() {
+        rk2();
+        for (int q = 1; q < c.nsub; ++q) {
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) x[j] = y[j];
+            rk2();
+        }
+    };
+    constexpr bool COMP = std::is_same<T, float>::value;
+    // Temporal blocking (c.nstep > 1): the column stays in registers for nstep micro-steps;
+    // each but the last leaves its m0 for the psi step (the same bits as an unblocked step),
+    // and only the last is stored.
+    for (int t = 0; t + 1 < c.nstep; ++t) {
+        micro();
+        T s0 = T(0), e0 = T(0), s1 = T(0), e1 = T(0);
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            const T v = (!RAGGED || l0 + j < ns) ? y[j] : T(0);
+            if constexpr (COMP) {
+                if (j == 0) s0 = v;
+                else kahan_add(s0, e0, v);
+            } else {
+                s0 += v;
+            }
+        }
+        const T tot = group_sum_pair<LPC, COMP, false>(s0, e0, s1, e1, g);
+        if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = tot * c.ds;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) x[j] = y[j];
+    }
+    micro();
 
     if constexpr (!RAGGED) {
         if (active) store_cells<T, CPL, NT>(M_out + base, y);
@@ -133,7 +169,6 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     // weights being exact half-integers.  FP32: Kahan inside the lane, TwoSum butterfly.  On
     // output steps one paired butterfly serves both: lane 0 of the group ends with m0, lane
     // LPC/2 with m1; m0 has the same bits on every step.
-    constexpr bool COMP = std::is_same<T, float>::value;
     const T wb = T(0.5) * (T)(2 * l0 + 1 - ns);  // weight of this lane's first cell
     T a0s = T(0), a0c = T(0), a1s = T(0), a1c = T(0);
 #pragma unroll
@@ -377,7 +412,8 @@ static int chunks_per_lane(int ns, int elem) {
 template <typename T>
 hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                              int limiter, const MotorConst<T> &c, const T *Dxy, hipStream_t s) {
-    const int nch = Dxy ? 1 : chunks_per_lane(ns, (int)sizeof(T));  // chunked: no depletion
+    // the chunked tiling has neither depletion, sub-cycling nor temporal blocking
+    const int nch = (Dxy || c.nsub > 1 || c.nstep > 1) ? 1 : chunks_per_lane(ns, (int)sizeof(T));
     if (nch > 1) {
         const bool nt = motor_nontemporal((int)sizeof(T));
         const int lpc = ns / (nch * (16 / (int)sizeof(T)));

@@ -49,6 +49,7 @@ class ModelParams:
     sigma_f: float = 1.0
     limiter: int = 0          # 0: superbee-limited MUSCL flux in s, 1: first-order upwind
     m_total: float = 0.0      # total motors per unit area (free-motor depletion); 0: pool of 1
+    motor_cfl: float = 0.0    # > 0: the motor step sub-cycles at this CFL number; 0: one step
 
     def as_dict(self):
         return asdict(self)
@@ -176,13 +177,14 @@ def cfl_dt(p: ModelParams, fluids, cfl=0.4):
     rate_Psi = (max|u_x| + F m_bar)/dx + (max|u_y| + F m_bar)/dy + max sum|gradu|/dth
     with m_bar = L k_on P / k_off the largest steady bound-motor count per filament, P the
     free-motor pool (1, or m_total if larger under depletion).
-    dt = cfl / max(rate_M, rate_Psi), minimised over every fluid field of the run.
+    dt = cfl / max(rate_M, rate_Psi), minimised over every fluid field of the run; with
+    p.motor_cfl > 0 the motor step sub-cycles and rate_M is left out.
     """
     ds = p.L / p.ns
     dx, dy, dth = p.lx / p.nx, p.ly / p.ny, TWO_PI / p.ntheta
     pool = max(1.0, getattr(p, "m_total", 0.0))
     m_bar = p.L * p.k_on * pool / p.k_off if p.k_off > 0 else 0.0
-    rate_m = p.v0 / ds + p.k_off
+    rate_m = 0.0 if getattr(p, "motor_cfl", 0.0) > 0 else p.v0 / ds + p.k_off
     best = math.inf
     for u, g in fluids:
         rate_psi = ((np.abs(u[0]).max() + p.F * m_bar) / dx

@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("lx", C.c_double), ("ly", C.c_double), ("L", C.c_double),
                 ("k_on", C.c_double), ("k_off", C.c_double), ("v0", C.c_double),
                 ("F", C.c_double), ("sigma_f", C.c_double),
-                ("precision", C.c_int32), ("limiter", C.c_int32), ("m_total", C.c_double)]
+                ("precision", C.c_int32), ("limiter", C.c_int32), ("m_total", C.c_double),
+                ("motor_cfl", C.c_double)]
 
 
 _lib = None
@@ -89,7 +90,7 @@ def make_params(p, precision=FP64) -> Params:
     return Params(int(p.nx), int(p.ny), int(p.ntheta), int(p.ns), float(p.lx), float(p.ly),
                   float(p.L), float(p.k_on), float(p.k_off), float(p.v0), float(p.F),
                   float(p.sigma_f), int(precision), int(getattr(p, "limiter", 0)),
-                  float(getattr(p, "m_total", 0.0)))
+                  float(getattr(p, "m_total", 0.0)), float(getattr(p, "motor_cfl", 0.0)))
 
 
 def workspace_bytes(params: Params, ckpt_every=0, max_tape_steps=0) -> int:

@@ -47,7 +47,8 @@ def test_workspace_bytes_scales_with_fields_and_tape():
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(ntheta=0), dict(ns=0),
                                  dict(lx=0.0), dict(L=-1.0), dict(v0=-0.5), dict(k_on=float("nan")),
-                                 dict(limiter=7), dict(m_total=-1.0), dict(m_total=float("inf"))])
+                                 dict(limiter=7), dict(m_total=-1.0), dict(m_total=float("inf")),
+                                 dict(motor_cfl=-0.5), dict(motor_cfl=float("nan"))])
 def test_invalid_params_are_rejected(bad):
     n = mmk.lib().mmk_workspace_bytes(C.byref(mmk.make_params(params(**bad))), 0, 0)
     assert n == 0

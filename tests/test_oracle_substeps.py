@@ -1,0 +1,110 @@
+"""Pins of the oracle's motor sub-cycling (Alg. 2's inner loop with the local step dt*).
+
+Reading: the inner step is limited by the motor's walking speed and detachment, the rate
+v0/ds + k_off, which is the same at every point of this model; a micro-step of length dt
+takes n = ceil(dt (v0/ds + k_off) / motor_cfl) midpoint steps of dt/n (n = 1 when
+motor_cfl = 0), then the s-moments of the result feed the psi step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle_a as A
+from oracle import oracle_torch as B
+from paper_1908_04279_amd import inputs as gen
+from paper_1908_04279_amd.inputs import ModelParams
+from tests.conftest import rel_err
+
+
+@pytest.mark.parametrize("kw,dt,want", [
+    (dict(ns=64, v0=1.0, k_off=0.5, L=1.0, motor_cfl=0.4), 0.1, 17),   # 0.1 * 64.5 / 0.4 = 16.125
+    (dict(ns=4, v0=1.0, k_off=0.0, L=1.0, motor_cfl=0.5), 0.5, 4),     # exactly 4.0: no rounding up
+    (dict(ns=4, v0=1.0, k_off=0.0, L=1.0, motor_cfl=0.5), 0.5000001, 5),
+    (dict(ns=8, v0=0.0, k_off=2.0, L=1.0, motor_cfl=1.0), 0.01, 1),    # a step below the limit
+    (dict(ns=8, v0=3.0, k_off=2.0, L=1.0, motor_cfl=0.0), 10.0, 1),    # no sub-cycling
+])
+def test_substep_count(kw, dt, want):
+    p = ModelParams(nx=1, ny=1, ntheta=1, **kw)
+    assert A.motor_substeps(p, dt) == want
+    assert B.Problem(p).substeps(p.v0, p.k_off, dt) == want
+
+
+def test_no_walking_closed_form():
+    """v0 = 0: every cell is the ODE M' = k_on - k_off M; a midpoint step of h maps M - c to
+    (M - c) g, g = 1 - k_off h + (k_off h)^2 / 2, c = k_on / k_off, so n sub-steps give
+    c + (M - c) g^n with h = dt / n."""
+    p = ModelParams(nx=2, ny=3, ntheta=4, ns=12, v0=0.0, k_on=0.7, k_off=1.9, motor_cfl=0.3)
+    rng = np.random.default_rng(2)
+    M = rng.uniform(0.0, 3.0, (p.nx, p.ny, p.ntheta, p.ns))
+    dt = 0.5
+    n = A.motor_substeps(p, dt)
+    assert n == math.ceil(dt * p.k_off / 0.3) == 4
+    h = dt / n
+    g = 1.0 - p.k_off * h + 0.5 * (p.k_off * h) ** 2
+    c = p.k_on / p.k_off
+    want = c + (M - c) * g ** n
+    got, m0, _ = A.motor_substepped(p, dt, M)
+    assert np.max(np.abs(got - want)) <= 1e-14 * np.max(np.abs(want))
+    np.testing.assert_allclose(m0, want.sum(-1) * (p.L / p.ns), rtol=1e-14)
+
+
+def test_second_order_in_the_substep():
+    """At a fixed end time the error against the exact exp(-k_off t) decay falls 4x per halving
+    of the sub-step: the sub-steps really are dt / n."""
+    p = ModelParams(nx=1, ny=1, ntheta=1, ns=4, v0=0.0, k_on=0.0, k_off=3.0)
+    M = np.ones((1, 1, 1, 4))
+    dt = 0.4
+    errs = []
+    for cfl in [0.15, 0.075, 0.0375, 0.01875]:  # n = 8, 16, 32, 64
+        q = ModelParams(**{**p.as_dict(), "motor_cfl": cfl})
+        got, _, _ = A.motor_substepped(q, dt, M)
+        errs.append(abs(got[0, 0, 0, 0] - math.exp(-p.k_off * dt)))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(3.6 < r < 4.4 for r in ratios), ratios
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_steady_walking_profile_is_kept(limiter):
+    """First-order flux: the discrete steady column c (1 - rho^(l+1)), rho = v0 / (v0 +
+    k_off ds), has R = 0, so sub-cycled steps leave it unchanged (superbee: converge to a
+    steady column, and sub-cycling reaches the same one)."""
+    ns = 16
+    p = ModelParams(nx=1, ny=1, ntheta=1, ns=ns, v0=1.3, k_on=0.8, k_off=0.9, limiter=limiter, motor_cfl=0.35)
+    ds = p.L / ns
+    dt = 0.4 / (p.v0 / ds + p.k_off) * 5  # five times the plain limit: n = 6 sub-steps
+    assert A.motor_substeps(p, dt) == 6
+    M = np.zeros((1, 1, 1, ns))
+    for _ in range(3000):
+        M, _, _ = A.motor_substepped(p, dt, M)
+    if limiter == 1:
+        rho = p.v0 / (p.v0 + p.k_off * ds)
+        want = (p.k_on / p.k_off) * (1.0 - rho ** (np.arange(ns) + 1.0))
+        assert np.max(np.abs(M[0, 0, 0] - want)) <= 1e-12 * np.max(want)
+    q = ModelParams(**{**p.as_dict(), "motor_cfl": 0.0})
+    Mq = np.zeros((1, 1, 1, ns))
+    for _ in range(18000):
+        Mq, _, _ = A.motor_step(q, dt / 6, Mq)
+    assert np.max(np.abs(M - Mq)) <= 1e-12 * np.max(np.abs(Mq))
+
+
+def test_c_and_torch_oracles_agree_with_substeps():
+    """Random state, flow and two fluid fields, 9 micro-steps of 3 sub-steps, both limiters."""
+    for limiter in (0, 1):
+        p = ModelParams(nx=3, ny=4, ntheta=8, ns=8, limiter=limiter, k_on=0.9, k_off=0.6, v0=1.2, F=0.8)
+        psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, seed=0)
+        M0 = gen.make_M0_random(p.nx, p.ny, p.ntheta, p.ns, seed=5)
+        fl = gen.fluid_schedule(p.nx, p.ny, 2)
+        dt = gen.cfl_dt(p, fl) * 2.5
+        p.motor_cfl = dt * (p.v0 / (p.L / p.ns) + p.k_off) / 2.5
+        assert A.motor_substeps(p, dt) == 3
+        o = A.OracleA(p)
+        o.set_state(psi0, M0)
+        for e in range(2):
+            o.set_fluid(*fl[e])
+            o.step(5 if e == 0 else 4, dt)
+        psi_a, M_a = o.get_state()
+        s_a, mom_a = o.get_stress_moments()
+        psi_b, M_b, s_b, mom_b = B.forward(p, psi0, M0, fl, 5, 9, dt)
+        for x, y in [(psi_a, psi_b), (M_a, M_b), (s_a, s_b), (mom_a, mom_b)]:
+            assert rel_err(x, y.numpy()) <= 1e-13
