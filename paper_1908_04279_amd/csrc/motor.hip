@@ -71,6 +71,20 @@ __device__ __forceinline__ void motor_rhs(const T (&z)[CPL], T (&R)[CPL], const 
     }
 }
 
+// Column total of the lane partials (every lane of the group; with PAIR, the q0 total in the
+// lower half of the group and the q1 total in the upper half).  FP32: each partial is a Kahan
+// pair (value = s - c) summed in FP64 across the lanes and rounded once by the caller, as
+// accurate as a TwoSum butterfly and about half its instructions; FP64: plain sums.
+template <int LPC, bool PAIR, typename T>
+__device__ __forceinline__ double column_total(T s0, T c0, T s1, T c1, int g) {
+    if constexpr (std::is_same<T, float>::value) {
+        const double v0 = (double)s0 - (double)c0, v1 = (double)s1 - (double)c1;
+        return group_sum_pair<LPC, false, PAIR, double>(v0, 0.0, v1, 0.0, g);
+    } else {
+        return group_sum_pair<LPC, false, PAIR, double>(s0, c0, s1, c1, g);
+    }
+}
+
 template <typename T, int CPL, int LPC, int LIM, bool RAGGED, bool WANT_M1, bool NT>
 __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, T *__restrict__ M_out,
                                                     T *__restrict__ m0, T *__restrict__ m1,
@@ -150,8 +164,8 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
                 s0 += v;
             }
         }
-        const T tot = group_sum_pair<LPC, COMP, false>(s0, e0, s1, e1, g);
-        if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = tot * c.ds;
+        const double tot = column_total<LPC, false>(s0, e0, s1, e1, g);
+        if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = (T)(tot * (double)c.ds);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) x[j] = y[j];
     }
@@ -166,9 +180,9 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     }
 
     // s-moments of the new column: m0 = ds sum M, m1 = ds^2 sum (l + 1/2 - ns/2) M, the
-    // weights being exact half-integers.  FP32: Kahan inside the lane, TwoSum butterfly.  On
-    // output steps one paired butterfly serves both: lane 0 of the group ends with m0, lane
-    // LPC/2 with m1; m0 has the same bits on every step.
+    // weights being exact half-integers.  FP32: Kahan inside the lane, FP64 across the lanes
+    // (column_total).  On output steps one paired butterfly serves both: lane 0 of the group
+    // ends with m0, lane LPC/2 with m1; m0 has the same bits on every step.
     const T wb = T(0.5) * (T)(2 * l0 + 1 - ns);  // weight of this lane's first cell
     T a0s = T(0), a0c = T(0), a1s = T(0), a1c = T(0);
 #pragma unroll
@@ -188,10 +202,10 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
             if constexpr (WANT_M1) a1s += v * (wb + T(j));
         }
     }
-    const T tot = group_sum_pair<LPC, COMP, WANT_M1>(a0s, a0c, a1s, a1c, g);
-    if (active && g == 0) m0[col] = tot * c.ds;
+    const double tot = column_total<LPC, WANT_M1>(a0s, a0c, a1s, a1c, g);
+    if (active && g == 0) m0[col] = (T)(tot * (double)c.ds);
     if constexpr (WANT_M1)
-        if (active && g == LPC / 2) m1[col] = tot * c.ds2;
+        if (active && g == LPC / 2) m1[col] = (T)(tot * (double)c.ds2);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -267,16 +281,55 @@ __global__ __launch_bounds__(256) void k_motor_step_chunked(const T *__restrict_
             for (int j = 0; j < W; ++j) x[q][j] = T(0);
         }
     }
-    motor_rhs_chunked<T, NCH, LPC, LIM>(x, R, c, g);
+    // one micro-step of c.nsub midpoint steps (x before, y after), as in k_motor_step
+    auto rk2 = [&]() {
+        motor_rhs_chunked<T, NCH, LPC, LIM>(x, R, c, g);
 #pragma unroll
-    for (int q = 0; q < NCH; ++q)
+        for (int q = 0; q < NCH; ++q)
 #pragma unroll
-        for (int j = 0; j < W; ++j) y[q][j] = x[q][j] + c.half_dt * R[q][j];
-    motor_rhs_chunked<T, NCH, LPC, LIM>(y, R, c, g);
+            for (int j = 0; j < W; ++j) y[q][j] = x[q][j] + c.half_dt * R[q][j];
+        motor_rhs_chunked<T, NCH, LPC, LIM>(y, R, c, g);
 #pragma unroll
-    for (int q = 0; q < NCH; ++q)
+        for (int q = 0; q < NCH; ++q)
 #pragma unroll
-        for (int j = 0; j < W; ++j) y[q][j] = x[q][j] + c.dt * R[q][j];
+            for (int j = 0; j < W; ++j) y[q][j] = x[q][j] + c.dt * R[q][j];
+    };
+    auto keep = [&]() {
+#pragma unroll
+        for (int q = 0; q < NCH; ++q)
+#pragma unroll
+            for (int j = 0; j < W; ++j) x[q][j] = y[q][j];
+    };
+    auto micro = [&]() {
+        rk2();
+        for (int s = 1; s < c.nsub; ++s) {
+            keep();
+            rk2();
+        }
+    };
+    // temporal blocking: m0 of every micro-step but the last into c.m0_steps
+    for (int t = 0; t + 1 < c.nstep; ++t) {
+        micro();
+        if constexpr (std::is_same<T, float>::value) {
+            Kahan a0;
+#pragma unroll
+            for (int q = 0; q < NCH; ++q)
+#pragma unroll
+                for (int j = 0; j < W; ++j) a0.add(y[q][j]);
+            const float s0 = group_sum_comp<LPC>(a0.sum, a0.comp);
+            if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = s0 * c.ds;
+        } else {
+            T a0 = 0;
+#pragma unroll
+            for (int q = 0; q < NCH; ++q)
+#pragma unroll
+                for (int j = 0; j < W; ++j) a0 += y[q][j];
+            const T s0 = group_sum<LPC>(a0);
+            if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = s0 * c.ds;
+        }
+        keep();
+    }
+    micro();
     if (active)
 #pragma unroll
         for (int q = 0; q < NCH; ++q) store_cells<T, W, NT>(M_out + cbase + (q * LPC + g) * W, y[q]);
@@ -412,8 +465,8 @@ static int chunks_per_lane(int ns, int elem) {
 template <typename T>
 hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                              int limiter, const MotorConst<T> &c, const T *Dxy, hipStream_t s) {
-    // the chunked tiling has neither depletion, sub-cycling nor temporal blocking
-    const int nch = (Dxy || c.nsub > 1 || c.nstep > 1) ? 1 : chunks_per_lane(ns, (int)sizeof(T));
+    // the chunked tiling has no depletion
+    const int nch = Dxy ? 1 : chunks_per_lane(ns, (int)sizeof(T));
     if (nch > 1) {
         const bool nt = motor_nontemporal((int)sizeof(T));
         const int lpc = ns / (nch * (16 / (int)sizeof(T)));
