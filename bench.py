@@ -59,6 +59,21 @@ def motor_bytes(p, b, with_m1, nstep=1):
 
 MAX_BLOCK = 16  # micro-steps per temporally blocked motor launch (the library's block)
 
+# Algorithmic floating-point operations of one motor micro-step per cell (FMA = 2), counted on
+# the scheme: per Runge-Kutta stage the difference z_l - z_{l-1} (1), the superbee slope (2
+# doublings, 2 minima, 1 maximum, the sign test 1: 6), the face value z + sigma/2 (2), the flux
+# difference (1), R = -(v0/ds) dh + (src - k_off z) (4) and the stage update (2): 16; two
+# stages and the m0 sum (1): 33; m1 on output launches (2) more.
+MOTOR_FLOPS_PER_CELL = 33
+M1_FLOPS_PER_CELL = 2
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published peak (FP64: 78.6)
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def motor_flops(p, with_m1, nstep=1):
+    cells = p.nx * p.ny * p.ntheta * p.ns
+    return cells * (MOTOR_FLOPS_PER_CELL * nstep + (M1_FLOPS_PER_CELL if with_m1 else 0))
+
 
 def block_plan(p, K):
     """Motor launches per K-step call and micro-steps in each: blocks of up to MAX_BLOCK for
@@ -242,10 +257,11 @@ def sources_sha(files):
     return h.hexdigest()[:16]
 
 
-def counters_traffic(n_plain, n_out):
+def counters_traffic(n_plain, n_out, steps_per_launch=1):
     """HBM bytes per motor launch (weighted like `achieved`: n_plain launches without and
     n_out with the m1 output) from the committed rocprofv3 counter summary, or None when it
-    is missing or was taken on different kernel sources."""
+    is missing, was taken on different kernel sources or on launches of another number of
+    micro-steps."""
     path, files = COUNTERS
     if not os.path.exists(path):
         return None
@@ -257,8 +273,10 @@ def counters_traffic(n_plain, n_out):
     if kv.get("sources_sha256_16") != sources_sha(files):
         return None
     try:
-        t0 = float(kv["hbm_bytes_per_launch"])
+        if abs(float(kv.get("micro_steps_per_launch", "1")) - steps_per_launch) > 1e-9:
+            return None
         t1 = float(kv["hbm_bytes_per_output_launch"])
+        t0 = float(kv["hbm_bytes_per_launch"]) if n_plain else t1
     except (KeyError, ValueError):
         return None
     return (n_plain * t0 + n_out * t1) / max(n_plain + n_out, 1)
@@ -366,9 +384,11 @@ def main():
         assert n_m == len(timed_m) and n_p == len(timed_p), (n_m, n_p, len(timed_m), len(timed_p))
         n_out = sum(1 for _, out in timed_m if out)
         kb = sum(motor_bytes(p, b, out, nb) for nb, out in timed_m) / n_m
+        kf = sum(motor_flops(p, out, nb) for nb, out in timed_m) / n_m
         steps_per_launch = sum(nb for nb, _ in timed_m) / n_m
         return dict(steps_per_s=sps, step_gbs=total / r["elapsed"] / 1e9, avg_us=ms_m / n_m * 1e3,
                     gbs=kb / (ms_m / n_m / 1e3) / 1e9, bytes_per_launch=kb, n_plain=n_m - n_out,
+                    tflops=kf / (ms_m / n_m / 1e3) / 1e12, flops_per_launch=kf,
                     n_out=n_out, psi_avg_us=ms_p / n_p * 1e3, timed_launches=n_m, mass=r["mass"],
                     steps_per_launch=steps_per_launch,
                     motor_us_per_step=ms_m / n_m * 1e3 / steps_per_launch)
@@ -416,14 +436,23 @@ def main():
                                    f"{'FP32' if main_leg == 'fp32' else 'FP64'}, fluid exchange every 10 steps",
                        "nx": p.nx, "ny": p.ny, "ntheta": p.ntheta, "ns": p.ns,
                        "motor_cells": p.nx * p.ny * p.ntheta * p.ns, "K": K})
-    traffic = counters_traffic(s["n_plain"], s["n_out"]) if main_leg == "fp32" else None
-    out["roofline"] = {"bound": "hbm", "achieved": s["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": s["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                       "kernel": "motor column step", "avg_launch_us": s["avg_us"],
-                       "algorithmic_bytes_per_launch": s["bytes_per_launch"],
-                       "timed_launches": s["timed_launches"], "output_launches_timed": s["n_out"],
-                       "micro_steps_per_launch": s["steps_per_launch"],
-                       "motor_us_per_micro_step": s["motor_us_per_step"]}
+    traffic = counters_traffic(s["n_plain"], s["n_out"], s["steps_per_launch"]) if main_leg == "fp32" else None
+    # the motor launch against the roof it is closest to: HBM for one micro-step per launch,
+    # the FP32 vector ALU when the field is blocked over several micro-steps
+    alu_peak = FP32_VECTOR_PEAK_TFLOPS if main_leg == "fp32" else FP64_VECTOR_PEAK_TFLOPS
+    hbm_frac, alu_frac = s["gbs"] / HBM_PEAK_GBS, s["tflops"] / alu_peak
+    if alu_frac > hbm_frac:
+        roof = {"bound": "alu", "achieved": s["tflops"], "peak": alu_peak, "unit": "TFLOP/s", "frac": alu_frac}
+    else:
+        roof = {"bound": "hbm", "achieved": s["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_frac}
+    roof.update({"traffic": traffic, "kernel": "motor column step", "avg_launch_us": s["avg_us"],
+                 "micro_steps_per_launch": s["steps_per_launch"],
+                 "motor_us_per_micro_step": s["motor_us_per_step"],
+                 "algorithmic_bytes_per_launch": s["bytes_per_launch"], "hbm_gbs": s["gbs"],
+                 "hbm_frac": hbm_frac, "algorithmic_flops_per_launch": s["flops_per_launch"],
+                 "alu_tflops": s["tflops"], "alu_frac": alu_frac,
+                 "timed_launches": s["timed_launches"], "output_launches_timed": s["n_out"]})
+    out["roofline"] = roof
     out["step_hbm_gbs"] = s["step_gbs"]
     out["step_hbm_frac"] = s["step_gbs"] / HBM_PEAK_GBS
     out["psi_step_avg_us"] = s["psi_avg_us"]

@@ -54,6 +54,17 @@ def test_fp64_against_oracle(shape, limiter, n):
     compare(g, o, 1e-12)
 
 
+def test_chunked_blocked_against_oracle(monkeypatch):
+    """The chunked tiling (16 cells a lane) with sub-cycling inside blocks, FP64, against the
+    oracle."""
+    monkeypatch.setenv("MMK_MOTOR_NCH", "4")
+    p = ModelParams(nx=6, ny=5, ntheta=16, ns=64, k_on=0.9, k_off=0.6, v0=4.0, F=0.8)
+    psi0, M0, fl, dt = substep_case(p, 3)
+    g = run_gpu(p, psi0, M0, fl, 9, 18, dt)
+    o = run_oracle(p, psi0, M0, fl, 9, 18, dt)
+    compare(g, o, 1e-12)
+
+
 @pytest.mark.parametrize("shape,n", [((20, 18, 64, 64), 3), ((9, 7, 32, 32), 2), ((6, 5, 16, 100), 4)])
 def test_fp32_against_fp64_oracle(shape, n):
     nx, ny, nt, ns = shape
@@ -99,17 +110,21 @@ def test_refusals():
     ctx.close()
 
 
-@pytest.mark.parametrize("shape,precision,calls", [
-    ((8, 6, 16, 32), 0, [1, 7, 16, 17, 33]),   # blocks of 16 with every remainder kind
-    ((9, 5, 12, 20), 0, [10, 3]),              # masked generic kernel
-    ((12, 10, 64, 64), 1, [10, 10, 25]),       # FP32, compiled walk psi kernel
+@pytest.mark.parametrize("shape,precision,calls,nch", [
+    ((8, 6, 16, 32), 0, [1, 7, 16, 17, 33], None),   # blocks of 16 with every remainder kind
+    ((9, 5, 12, 20), 0, [10, 3], None),              # masked generic kernel
+    ((12, 10, 64, 64), 1, [10, 10, 25], None),       # FP32, compiled walk psi kernel
+    ((12, 10, 64, 64), 1, [10, 7], "2"),             # FP32, chunked tiling (8 cells a lane)
+    ((8, 6, 16, 64), 0, [12, 5], "2"),               # FP64, chunked tiling
 ])
-def test_temporal_blocking_is_bitwise_serial(monkeypatch, shape, precision, calls):
+def test_temporal_blocking_is_bitwise_serial(monkeypatch, shape, precision, calls, nch):
     """A run of several mmk_step calls gives the same bits with the motor field blocked over
     up to 16 micro-steps per launch (default for m_total = 0) and with one launch per
     micro-step (MMK_MOTOR_BLOCK=0); also with sub-cycling inside the blocks."""
     import torch
     from paper_1908_04279_amd import mmk
+    if nch:
+        monkeypatch.setenv("MMK_MOTOR_NCH", nch)
     nx, ny, nt, ns = shape
     for cfl in (0.0, 0.15):
         p = ModelParams(nx=nx, ny=ny, ntheta=nt, ns=ns, motor_cfl=cfl)
