@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 def build(verbose=False):
     cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fno-semantic-interposition",
            "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp",
-           os.path.join(HERE, "oracle.c"), "-lm"]
+           os.path.join(HERE, "oracle.c"), os.path.join(HERE, "oracle_r0.c"), "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

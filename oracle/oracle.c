@@ -74,21 +74,27 @@ void oracle_motor_rhs(const oracle_params *p, const double *z, double *R) {
 }
 
 void oracle_motor_rhs_src(const oracle_params *p, const double *z, double src, double *R) {
-    const int ns = p->ns;
-    const double ds = p->L / ns;
-    double phi[ns + 1]; /* phi[l] = Phi_{l-1/2} */
+    oracle_run_rhs(p, p->ns, z, src, R);
+}
+
+/* The same right-hand side on a run of n consecutive arclength cells (cell width ds = L/ns):
+ * the run's first cell takes the minus-end rules (no influx, ghost 0) and its last cell the
+ * plus-end rules (first-order outflow, ghost = itself).  n = ns is the whole column. */
+void oracle_run_rhs(const oracle_params *p, int n, const double *z, double src, double *R) {
+    const double ds = p->L / p->ns;
+    double phi[n + 1]; /* phi[l] = Phi_{l-1/2} */
     phi[0] = 0.0;
-    for (int l = 0; l < ns; ++l) {
+    for (int l = 0; l < n; ++l) {
         double zl = z[l];
         double zm = (l == 0) ? 0.0 : z[l - 1];
-        double zp = (l == ns - 1) ? z[ns - 1] : z[l + 1];
+        double zp = (l == n - 1) ? z[n - 1] : z[l + 1];
         double sig = (p->limiter == 0) ? oracle_superbee(zl - zm, zp - zl) : 0.0;
-        if (l == ns - 1)
+        if (l == n - 1)
             phi[l + 1] = p->v0 * zl;
         else
             phi[l + 1] = p->v0 * (zl + 0.5 * sig);
     }
-    for (int l = 0; l < ns; ++l)
+    for (int l = 0; l < n; ++l)
         R[l] = -(phi[l + 1] - phi[l]) / ds + src - p->k_off * z[l];
 }
 
@@ -98,14 +104,17 @@ void oracle_column_step(const oracle_params *p, double dt, const double *M, doub
 }
 
 void oracle_column_step_src(const oracle_params *p, double dt, const double *M, double src, double *Mout) {
-    const int ns = p->ns;
-    if (ns <= 0) return;
-    double R[ns], Ms[ns];
-    for (int l = 0; l < ns; ++l) Ms[l] = 0.0;
-    oracle_motor_rhs_src(p, M, src, R);
-    for (int l = 0; l < ns; ++l) Ms[l] = M[l] + 0.5 * dt * R[l];
-    oracle_motor_rhs_src(p, Ms, src, R);
-    for (int l = 0; l < ns; ++l) Mout[l] = M[l] + dt * R[l];
+    oracle_run_step(p, p->ns, dt, M, src, Mout);
+}
+
+void oracle_run_step(const oracle_params *p, int n, double dt, const double *M, double src, double *Mout) {
+    if (n <= 0) return;
+    double R[n], Ms[n];
+    for (int l = 0; l < n; ++l) Ms[l] = 0.0;
+    oracle_run_rhs(p, n, M, src, R);
+    for (int l = 0; l < n; ++l) Ms[l] = M[l] + 0.5 * dt * R[l];
+    oracle_run_rhs(p, n, Ms, src, R);
+    for (int l = 0; l < n; ++l) Mout[l] = M[l] + dt * R[l];
 }
 
 /* m0 = sum_l M_l ds (bound motors per filament, the gliding force magnitude up to F);

@@ -21,6 +21,7 @@ typedef struct {
     int limiter;              /* 0: superbee MUSCL, 1: first-order upwind (sigma = 0) */
     double m_total;           /* total motor density per unit area; 0: free pool taken as 1 */
     double motor_cfl;         /* > 0: motor sub-cycling (local dt*), see oracle_motor_substeps */
+    double rc;                /* > 0: capture radius of the anchor-resolved model (oracle_r0.c) */
 } oracle_params;
 
 /* superbee slope of the two one-sided differences a (left) and b (right) */
@@ -31,9 +32,14 @@ void oracle_motor_rhs(const oracle_params *p, const double *z, double *R);
 /* the same with the attachment source `src` (k_on times the free-motor density) */
 void oracle_motor_rhs_src(const oracle_params *p, const double *z, double src, double *R);
 
+/* the same on a run of n consecutive cells of width L/ns: minus-end rules at the run's
+ * first cell, plus-end rules at its last (n = ns: a whole column) */
+void oracle_run_rhs(const oracle_params *p, int n, const double *z, double src, double *R);
+
 /* one explicit-midpoint step of one column: Mout = M + dt R(M + dt/2 R(M)) */
 void oracle_column_step(const oracle_params *p, double dt, const double *M, double *Mout);
 void oracle_column_step_src(const oracle_params *p, double dt, const double *M, double src, double *Mout);
+void oracle_run_step(const oracle_params *p, int n, double dt, const double *M, double src, double *Mout);
 
 /* coarse bound-motor density B [nx][ny] = sum_th psi m0 dth (Eq. (5), anchor-marginal) */
 void oracle_coarse_bound(const oracle_params *p, const double *psi, const double *m0, double *B);
@@ -83,6 +89,38 @@ void oracle_motor_force(const oracle_params *p, const double *psi, const double 
  * micro-step starts with the depletion of oracle_depletion on the current state. */
 void oracle_run(const oracle_params *p, double dt, int nsteps, double *psi, double *M,
                 const double *u, const double *gradu, double *m0, double *m1);
+
+/* ---- anchor-resolved bound motors M_b(r0, x, th, s) with capture radius rc (oracle_r0.c) ----
+ * Anchors r0 sit on the cell centres.  A tracked cell is (a, b, k, l): the filament centred at
+ * x = r0 + (a dx, b dy) with angle th_k, arclength cell l, whose point x + (s_l - L/2) p_k lies
+ * within rc of r0.  Cells are listed in lexicographic order of (a, b, k, l); cells[4 c + 0..3]
+ * = (a, b, k, l).  M_b is stored [cell][i][j] with (i, j) the filament's cell x (the anchor is
+ * x - (a, b), periodic).  coarse, src, scale are per anchor [nx][ny]. */
+
+/* number of tracked cells (cells may be NULL); -1 when rc <= 0 or rc + L/2 >= lx/2 or ly/2 */
+long oracle_r0_cells(const oracle_params *p, int *cells);
+
+/* Eq. (5) at every anchor: coarse = sum over its tracked cells of M_b psi ds dx dy dth */
+void oracle_r0_coarse(const oracle_params *p, const int *cells, long ncell, const double *psi,
+                      const double *Mb, double *coarse);
+
+/* one motor step of every run of consecutive tracked cells (same a, b, k) as its own column;
+ * the anchor's scale (NULL: 1) multiplies the run first, its src (NULL: k_on) is the source */
+void oracle_r0_motor_step(const oracle_params *p, double dt, const int *cells, long ncell,
+                          const double *Mb, double *Mout, const double *scale, const double *src);
+
+/* anchor marginals of Eq. (10)'s r0 integral: m0[x][k] = sum over anchors and s of M_b ds dx dy,
+ * m1 the same with the lever arm (s_l - L/2) (either may be NULL) */
+void oracle_r0_marginal(const oracle_params *p, const int *cells, long ncell, const double *Mb,
+                        double *m0, double *m1);
+
+/* nsteps micro-steps of the anchor-resolved model; psi and Mb in place.  Each micro-step: with
+ * m_total > 0, the coarse density of the current state, the clamp and the free pool of
+ * oracle_depletion per anchor; the motor step; psi driven by the marginal m0.  m0, m1, coarse
+ * (each may be NULL) receive the marginals and the coarse density of the final state. */
+void oracle_r0_run(const oracle_params *p, double dt, int nsteps, const int *cells, long ncell,
+                   double *psi, double *Mb, const double *u, const double *gradu, double *m0,
+                   double *m1, double *coarse);
 
 int oracle_max_threads(void);
 void oracle_set_threads(int n);

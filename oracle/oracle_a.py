@@ -20,7 +20,7 @@ class _Params(C.Structure):
                 ("lx", C.c_double), ("ly", C.c_double), ("L", C.c_double),
                 ("k_on", C.c_double), ("k_off", C.c_double), ("v0", C.c_double),
                 ("F", C.c_double), ("sigma_f", C.c_double), ("limiter", C.c_int),
-                ("m_total", C.c_double), ("motor_cfl", C.c_double)]
+                ("m_total", C.c_double), ("motor_cfl", C.c_double), ("rc", C.c_double)]
 
 
 _lib = None
@@ -53,6 +53,14 @@ def lib():
         L.oracle_moments.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
         L.oracle_global_sums.argtypes = [P, _dp, _dp, C.POINTER(C.c_double), _dp]
         L.oracle_run.argtypes = [P, C.c_double, C.c_int, _dp, _dp, _dp, _dp, C.c_void_p, C.c_void_p]
+        _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+        L.oracle_r0_cells.argtypes = [P, C.c_void_p]
+        L.oracle_r0_cells.restype = C.c_long
+        L.oracle_r0_coarse.argtypes = [P, _ip, C.c_long, _dp, _dp, _dp]
+        L.oracle_r0_motor_step.argtypes = [P, C.c_double, _ip, C.c_long, _dp, _dp, C.c_void_p, C.c_void_p]
+        L.oracle_r0_marginal.argtypes = [P, _ip, C.c_long, _dp, C.c_void_p, C.c_void_p]
+        L.oracle_r0_run.argtypes = [P, C.c_double, C.c_int, _ip, C.c_long, _dp, _dp, _dp, _dp,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_max_threads.restype = C.c_int
         L.oracle_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -63,7 +71,7 @@ def cparams(p) -> _Params:
     """Accepts any object with the ModelParams attribute names."""
     return _Params(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, p.k_on, p.k_off, p.v0,
                    p.F, p.sigma_f, int(getattr(p, "limiter", 0)), float(getattr(p, "m_total", 0.0)),
-                   float(getattr(p, "motor_cfl", 0.0)))
+                   float(getattr(p, "motor_cfl", 0.0)), float(getattr(p, "rc", 0.0)))
 
 
 def _f64(a):
@@ -177,6 +185,77 @@ def global_sums(p, psi, stress):
     ss = np.empty(3)
     lib().oracle_global_sums(C.byref(cparams(p)), _f64(psi), _f64(stress), C.byref(mass), ss)
     return mass.value, ss
+
+
+# ---- anchor-resolved bound motors (oracle_r0.c) ----------------------------------------------
+def r0_cells(p):
+    """Tracked cells [n][4] = (a, b, k, l) in lexicographic order; raises if rc is unusable."""
+    n = lib().oracle_r0_cells(C.byref(cparams(p)), None)
+    if n < 0:
+        raise ValueError("rc must be > 0 with rc + L/2 < lx/2 and ly/2")
+    cells = np.empty((n, 4), dtype=np.int32)
+    lib().oracle_r0_cells(C.byref(cparams(p)), cells.ctypes.data_as(C.c_void_p))
+    return cells
+
+
+def r0_coarse(p, cells, psi, Mb):
+    out = np.empty((p.nx, p.ny))
+    lib().oracle_r0_coarse(C.byref(cparams(p)), cells, len(cells), _f64(psi), _f64(Mb), out)
+    return out
+
+
+def r0_motor_step(p, dt, cells, Mb, scale=None, src=None):
+    Mb = _f64(Mb)
+    out = np.empty_like(Mb)
+    scale = None if scale is None else _f64(scale)
+    src = None if src is None else _f64(src)
+    lib().oracle_r0_motor_step(C.byref(cparams(p)), float(dt), cells, len(cells), Mb, out, _ptr(scale), _ptr(src))
+    return out
+
+
+def r0_marginal(p, cells, Mb):
+    m0 = np.empty((p.nx, p.ny, p.ntheta))
+    m1 = np.empty((p.nx, p.ny, p.ntheta))
+    lib().oracle_r0_marginal(C.byref(cparams(p)), cells, len(cells), _f64(Mb), _ptr(m0), _ptr(m1))
+    return m0, m1
+
+
+class OracleR0:
+    """Host-side stepper of the anchor-resolved model, in the HIP library's call order."""
+
+    def __init__(self, p):
+        self.p = p
+        self.cells = r0_cells(p)
+        self.psi = self.Mb = self.u = self.gradu = None
+
+    def set_state(self, psi, Mb=None):
+        p = self.p
+        self.psi = _f64(psi).copy()
+        self.Mb = np.zeros((len(self.cells), p.nx, p.ny)) if Mb is None else _f64(Mb).copy()
+
+    def set_fluid(self, u, gradu):
+        self.u, self.gradu = _f64(u).copy(), _f64(gradu).copy()
+
+    def step(self, K, dt):
+        lib().oracle_r0_run(C.byref(cparams(self.p)), float(dt), int(K), self.cells, len(self.cells),
+                            self.psi, self.Mb, self.u, self.gradu, None, None, None)
+
+    def get_state(self):
+        return self.psi.copy(), self.Mb.copy()
+
+    def marginals(self):
+        return r0_marginal(self.p, self.cells, self.Mb)
+
+    def coarse(self):
+        return r0_coarse(self.p, self.cells, self.psi, self.Mb)
+
+    def get_stress_moments(self):
+        m0, m1 = self.marginals()
+        return moments(self.p, self.psi, m0, m1)
+
+    def get_sums(self):
+        stress, _ = self.get_stress_moments()
+        return global_sums(self.p, self.psi, stress)
 
 
 def max_threads():

@@ -50,6 +50,7 @@ class ModelParams:
     limiter: int = 0          # 0: superbee-limited MUSCL flux in s, 1: first-order upwind
     m_total: float = 0.0      # total motors per unit area (free-motor depletion); 0: pool of 1
     motor_cfl: float = 0.0    # > 0: the motor step sub-cycles at this CFL number; 0: one step
+    rc: float = 0.0           # > 0: anchor-resolved bound motors with this capture radius
 
     def as_dict(self):
         return asdict(self)
@@ -156,6 +157,12 @@ def make_M0_random(nx, ny, ntheta, ns, k_on=1.0, k_off=0.5, seed=5):
     """Random non-uniform bound-motor density, U[0, k_on/k_off], so columns differ."""
     rng = np.random.default_rng(seed)
     return np.ascontiguousarray(rng.uniform(0.0, k_on / k_off, (nx, ny, ntheta, ns)))
+
+
+def make_Mb0_random(ncell, nx, ny, k_on=1.0, k_off=0.5, seed=6):
+    """Random anchor-resolved bound-motor density [ncell][nx][ny], U[0, k_on/k_off]."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, k_on / k_off, (ncell, nx, ny))
 
 
 def make_target_stress(nx, ny, seed=3, scale=1e-3):
