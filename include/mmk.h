@@ -81,7 +81,37 @@ typedef struct {
                             * limit is the same at every point here, so one n serves all.
                             * Needs m_total = 0 (else MMK_ERR_UNSUPPORTED); not supported by
                             * the tape. */
+    double rc;             /* >= 0.  0: the anchor-marginal model above.  > 0: anchor-resolved
+                            * bound motors M_b(r0, x, th, s) (Sec. 2, Eqs. (4)-(6), Alg. 2) with
+                            * capture radius rc; needs rc + L/2 < lx/2 and < ly/2 (else
+                            * MMK_ERR_ARG).  Anchors r0 sit on the cell centres; the tracked
+                            * cells are listed by mmk_r0_cells.  M (set_state / get_state) is
+                            * then Mb [ncell][nx][ny]: cell c = (a, b, k, l) of the filament
+                            * centred at cell (i, j) with angle th_k, arclength cell l, bound to
+                            * the anchor at cell (i - a, j - b) (periodic).  Along a filament the
+                            * tracked cells form runs; each run walks as its own column (no
+                            * influx at its first cell, free outflow at its last: motors leave
+                            * the capture ball).  The attachment source of a run is k_on times
+                            * its anchor's free pool: 1 with m_total = 0, else m_total minus the
+                            * anchor's coarse density coarse(r0) = sum over its tracked cells of
+                            * M_b psi ds dx dy dth, with the clamp of Alg. 2 per anchor at the
+                            * start of each micro-step (where coarse > m_total the anchor's cells
+                            * are scaled by m_total / coarse and the pool is 0).  Psi is driven by,
+                            * and m0 / m1 / the moments report, the anchor marginals
+                            * m0(x, th) = sum over anchors and s of M_b ds dx dy (m1 with the lever
+                            * arm s - L/2).  Runs longer than 32 cells, motor_cfl > 0, the tape and
+                            * mmk_get_force give MMK_ERR_UNSUPPORTED.  Three launches per
+                            * micro-step with m_total > 0 (coarse + pool, motor, psi), two with
+                            * m_total = 0. */
 } mmk_params;
+
+/* Tracked cells of the anchor-resolved model (p->rc > 0), host: returns their number ncell
+ * (0 is possible for a tiny rc) and, when cells is not NULL, writes cells[4 c + 0..3] =
+ * (a, b, k, l) for c < ncell in lexicographic order of (a, b, k, l).  The motor point of the
+ * cell, relative to its anchor, is (a lx/nx, b ly/ny) + ((l + 1/2) L/ns - L/2) p_k, and the cell
+ * is tracked when its squared length (FP64, in that order) is at most rc^2.  Returns -1 on
+ * invalid params or an unusable rc (<= 0, or rc + L/2 not below lx/2 and ly/2). */
+int64_t mmk_r0_cells(const mmk_params *p, int32_t *cells);
 
 /* Bytes of device workspace a context needs.  ckpt_every > 0 reserves the adjoint tape:
  * checkpoints of (Psi, M) every ckpt_every steps for up to max_tape_steps taped steps, a
@@ -130,6 +160,11 @@ mmk_status mmk_get_motor_moments(mmk_ctx *ctx, void *m0, void *m1);
  * staging) larger than the device's LDS per block; windows beyond 3072 cells cost one more
  * read of M per 3072 cells.  No host sync. */
 mmk_status mmk_get_force(mmk_ctx *ctx, void *force);
+/* Anchor-resolved model only (rc > 0; else MMK_ERR_STATE): coarse [nx][ny] = the coarse density
+ * of Eq. (5) at every anchor of the current state, and free_pool [nx][ny] = its free motors of
+ * Eq. (6) before the next step's clamp, m_total - min(coarse, m_total) (1 with m_total = 0).
+ * Either pointer may be NULL.  Needs state.  No host sync. */
+mmk_status mmk_get_anchors(mmk_ctx *ctx, void *coarse, void *free_pool);
 /* host outputs, synchronizes: mass = sum Psi dx dy dth and sum_sigma[c] = sum sigma_c dx dy,
  * both accumulated in FP64 in a fixed order (bitwise reproducible). */
 mmk_status mmk_get_sums(mmk_ctx *ctx, double *mass, double sum_sigma[3]);
@@ -151,8 +186,8 @@ mmk_status mmk_tape_end(mmk_ctx *ctx);
  * events on the context's stream (enable = 0 turns timing off, < 0 is MMK_ERR_ARG).
  * mmk_profile_read (synchronizes) sums the elapsed times of the timed launches of `kernel_id`
  * (0 motor step, 1 psi step, 2 global sums, 3 reverse psi step, 4 reverse motor step, 5 motor
- * force: spreading and merge) since profiling was enabled; up to 65536 launches per id are
- * timed. */
+ * force: spreading and merge, 6 anchor-resolved motor step, 7 anchor coarse density and pool)
+ * since profiling was enabled; up to 65536 launches per id are timed. */
 mmk_status mmk_profile(mmk_ctx *ctx, int32_t enable);
 mmk_status mmk_profile_read(mmk_ctx *ctx, int32_t kernel_id, double *total_ms, int64_t *launches);
 

@@ -54,6 +54,7 @@ def lib():
         L.oracle_global_sums.argtypes = [P, _dp, _dp, C.POINTER(C.c_double), _dp]
         L.oracle_run.argtypes = [P, C.c_double, C.c_int, _dp, _dp, _dp, _dp, C.c_void_p, C.c_void_p]
         _ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+        L.oracle_run_step.argtypes = [P, C.c_int, C.c_double, _dp, C.c_double, _dp]
         L.oracle_r0_cells.argtypes = [P, C.c_void_p]
         L.oracle_r0_cells.restype = C.c_long
         L.oracle_r0_coarse.argtypes = [P, _ip, C.c_long, _dp, _dp, _dp]
@@ -185,6 +186,14 @@ def global_sums(p, psi, stress):
     ss = np.empty(3)
     lib().oracle_global_sums(C.byref(cparams(p)), _f64(psi), _f64(stress), C.byref(mass), ss)
     return mass.value, ss
+
+
+def run_step(p, dt, M, src):
+    """One midpoint step of a run of len(M) cells (minus-end rules first, plus-end rules last)."""
+    M = _f64(M)
+    out = np.empty_like(M)
+    lib().oracle_run_step(C.byref(cparams(p)), len(M), float(dt), M, float(src), out)
+    return out
 
 
 # ---- anchor-resolved bound motors (oracle_r0.c) ----------------------------------------------

@@ -6,6 +6,7 @@
 #include "kernels.h"
 #include "tape.h"
 #include "force.h"
+#include "r0.h"
 
 #include <hip/hip_runtime.h>
 
@@ -25,7 +26,7 @@ namespace {
 thread_local std::string g_create_error;
 constexpr int kMaxTheta = 512;
 constexpr int kMaxS = 512;
-constexpr int kProfIds = 6;
+constexpr int kProfIds = 8;
 constexpr int kMaxBlock = 16;  // micro-steps per temporally blocked motor launch
 constexpr int kProfMax = 65536;
 
@@ -33,6 +34,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t M[2], psi[2], psi_tmp, m0, m0s, m1, Dxy, fpart, fblk, fexy, fcs, u, G, stress, mom, tab, partials, sums;
+    size_t q0, r0part, r0scale, r0pool, r0seg, r0start;  // anchor-resolved model (rc > 0)
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -40,6 +42,9 @@ struct Layout {
 
 int64_t n_psi(const mmk_params &p) { return (int64_t)p.nx * p.ny * p.ntheta; }
 int64_t n_m(const mmk_params &p) { return n_psi(p) * p.ns; }
+R0Plan r0_plan_of(const mmk_params &p, bool cells_only = false) {
+    return plan_r0(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, p.rc, cells_only);
+}
 size_t esize(const mmk_params &p) { return p.precision == MMK_FP32 ? 4 : 8; }
 
 // Returns an error message, or empty when the parameters are usable.
@@ -51,13 +56,16 @@ std::string check_params(const mmk_params *p) {
     if (p->precision != MMK_FP32 && p->precision != MMK_FP64) return "precision must be MMK_FP64 or MMK_FP32";
     if (p->limiter != MMK_SUPERBEE && p->limiter != MMK_UPWIND1) return "limiter must be MMK_SUPERBEE or MMK_UPWIND1";
     const double vals[] = {p->lx, p->ly, p->L, p->k_on, p->k_off, p->v0, p->F, p->sigma_f, p->m_total,
-                           p->motor_cfl};
+                           p->motor_cfl, p->rc};
     for (double v : vals)
         if (!std::isfinite(v)) return "non-finite model parameter";
     if (p->lx <= 0 || p->ly <= 0 || p->L <= 0) return "lx, ly and L must be > 0";
     if (p->v0 < 0) return "v0 must be >= 0 (motors walk towards s = L)";
     if (p->m_total < 0) return "m_total must be >= 0 (0: no depletion)";
     if (p->motor_cfl < 0) return "motor_cfl must be >= 0 (0: no sub-cycling)";
+    if (p->rc < 0) return "rc must be >= 0 (0: anchor-marginal model)";
+    if (p->rc > 0 && !(p->rc + 0.5 * p->L < 0.5 * p->lx && p->rc + 0.5 * p->L < 0.5 * p->ly))
+        return "rc + L/2 must be below lx/2 and ly/2 (each anchor-filament pair has one offset)";
     if ((int64_t)p->nx * p->ny > ((int64_t)1 << 31)) return "nx * ny too large";
     return "";
 }
@@ -69,13 +77,22 @@ std::string check_supported(const mmk_params *p) {
         return "motor sub-cycling (motor_cfl > 0) covers linear attachment only (m_total = 0)";
     if (plan_psi(p->nx, p->ny, p->ntheta, esize(*p), 2).lds_bytes > 64 * 1024)
         return "ntheta too large for the psi kernel's LDS tile at this precision";
+    if (p->rc > 0) {
+        if (p->motor_cfl > 0) return "the anchor-resolved model (rc > 0) has no motor sub-cycling (motor_cfl = 0)";
+        const R0Plan rp = r0_plan_of(*p);
+        if (rp.lmax > kR0MaxRun) return "runs of tracked cells longer than 32 (rc too large for ns)";
+        if (rp.ncell > INT32_MAX || (double)rp.ncell * p->nx * p->ny > 9.0e18) return "too many tracked cells";
+    }
     return "";
 }
 
 Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     Layout L{};
     const size_t e = esize(p);
-    const size_t nm = (size_t)n_m(p), np = (size_t)n_psi(p), nxy = (size_t)p.nx * p.ny;
+    const bool r0 = p.rc > 0;
+    const R0Plan rp = r0 ? r0_plan_of(p) : R0Plan{};
+    const size_t np = (size_t)n_psi(p), nxy = (size_t)p.nx * p.ny;
+    const size_t nm = r0 ? (size_t)rp.ncell * nxy : (size_t)n_m(p);  // M, or Mb [ncell][nx][ny]
     const PsiLaunch pl = plan_psi(p.nx, p.ny, p.ntheta, e, 2);
     const WalkPlan wp = plan_walk(p.nx, p.ny, p.ntheta);
     L.psi_blocks = wp.ok && wp.blocks > pl.blocks ? wp.blocks : pl.blocks;
@@ -92,17 +109,27 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.m0 = take(np * e);
     // temporal blocking of the linear motor step: m0 of the first kMaxBlock - 1 micro-steps
     // of a block, and a third psi buffer so that a block of any length ends in the other one
-    L.m0s = p.m_total > 0 ? 0 : take((size_t)(kMaxBlock - 1) * np * e);
-    L.psi_tmp = p.m_total > 0 ? 0 : take(np * e);
+    L.m0s = (p.m_total > 0 || r0) ? 0 : take((size_t)(kMaxBlock - 1) * np * e);
+    L.psi_tmp = (p.m_total > 0 || r0) ? 0 : take(np * e);
     L.m1 = take(np * e);
-    L.Dxy = take(2 * nxy * e);
-    // motor force: partial windows and the spreading records per (pass, cell)
-    const ForcePlan fpl = plan_force(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, e);
-    const size_t nblk = (size_t)fpl.npass * ((p.ns + fpl.chunk - 1) / fpl.chunk);
-    L.fpart = take(fpl.part_elems * sizeof(double));
-    L.fblk = take(nblk * kForceBlock * sizeof(uint32_t));
-    L.fexy = take(2 * (size_t)fpl.npass * sizeof(int));
-    L.fcs = take(2 * (size_t)fpl.npass * sizeof(double));
+    L.Dxy = r0 ? 0 : take(2 * nxy * e);
+    if (!r0) {
+        // motor force: partial windows and the spreading records per (pass, cell)
+        const ForcePlan fpl = plan_force(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, e);
+        const size_t nblk = (size_t)fpl.npass * ((p.ns + fpl.chunk - 1) / fpl.chunk);
+        L.fpart = take(fpl.part_elems * sizeof(double));
+        L.fblk = take(nblk * kForceBlock * sizeof(uint32_t));
+        L.fexy = take(2 * (size_t)fpl.npass * sizeof(int));
+        L.fcs = take(2 * (size_t)fpl.npass * sizeof(double));
+    } else {
+        // run totals, coarse partial rows, per-anchor clamp factor and pool, run table
+        L.q0 = take((size_t)rp.nseg * nxy * e);
+        L.r0part = take((size_t)4 * rp.nsplit * nxy * sizeof(double));
+        L.r0scale = take(nxy * e);
+        L.r0pool = take(nxy * e);
+        L.r0seg = take((size_t)rp.nseg * sizeof(R0Seg));
+        L.r0start = take(((size_t)p.ntheta + 1) * sizeof(int32_t));
+    }
     L.u = take(2 * nxy * e);
     L.G = take(4 * nxy * e);
     L.stress = take(3 * nxy * e);
@@ -142,6 +169,7 @@ struct mmk_ctx {
     TapeState tape;
     std::vector<double> host_tab64;  // host copies of the angle tables (outlive the async copy)
     std::vector<float> host_tab32;
+    R0Plan r0;          // anchor-resolved model: tracked cells and runs (rc > 0)
     ForcePlan fplan;    // motor-force spreading geometry
     ForceRecords frec;  // host copy of the force spreading records
     std::vector<uint32_t> host_fblk;
@@ -151,6 +179,11 @@ struct mmk_ctx {
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
     void *vat(size_t off) const { return ws + off; }
 };
+
+// elements of the motor state: M [nx][ny][nth][ns], or Mb [ncell][nx][ny] when rc > 0
+static int64_t n_state(const mmk_ctx *c) {
+    return c->p.rc > 0 ? c->r0.ncell * (int64_t)c->p.nx * c->p.ny : n_m(c->p);
+}
 
 static mmk_status fail(mmk_ctx *c, mmk_status st, const char *fmt, ...) {
     char buf[512];
@@ -218,7 +251,8 @@ static mmk_status psi_half(mmk_ctx *c, const T *psi_in, T *psi_out, const T *m0,
     HIPCHK(c, prof_begin_on(c, 1, &slot, s), "hipEventRecord");
     T *stress = out ? c->at<T>(c->L.stress) : nullptr, *mom = out ? c->at<T>(c->L.mom) : nullptr;
     double *part = out ? c->at<double>(c->L.partials) : nullptr;
-    T *Dxy = c->p.m_total > 0 ? c->at<T>(c->L.Dxy) : nullptr;  // depletion factors of the new state
+    // depletion factors of the new state (anchor-marginal model)
+    T *Dxy = c->p.m_total > 0 && c->p.rc == 0 ? c->at<T>(c->L.Dxy) : nullptr;
     if (c->walk)
         HIPCHK(c, launch_psi_walk<T>(psi_in, psi_out, m0, m1, u, G, c->at<T>(c->L.tab), stress, mom, part, Dxy,
                                      psi_const<T>(c->p, dt), c->wp, s),
@@ -315,10 +349,85 @@ static mmk_status run_steps_blocked(mmk_ctx *c, int K, double dt) {
     return MMK_OK;
 }
 
+// ---- anchor-resolved model -----------------------------------------------------------------
+template <typename T>
+static R0Const<T> r0_const(const mmk_params &p, double dt, int advance) {
+    const double ds = p.L / p.ns;
+    R0Const<T> c;
+    c.k_on = (T)p.k_on;
+    c.k_off = (T)p.k_off;
+    c.nv_ds = (T)(-p.v0 / ds);
+    c.dt = (T)dt;
+    c.half_dt = (T)(0.5 * dt);
+    c.ds = ds;
+    c.ds2 = ds * ds;
+    c.dA = (p.lx / p.nx) * (p.ly / p.ny);
+    c.half_ns = 0.5 * p.ns;
+    c.nx = p.nx;
+    c.ny = p.ny;
+    c.nth = p.ntheta;
+    c.nxy = (int64_t)p.nx * p.ny;
+    c.advance = advance;
+    return c;
+}
+
+// Motor step of every run (advance = 0: only the run totals and marginals of the current state).
+template <typename T>
+static mmk_status r0_motor(mmk_ctx *c, const T *M_in, T *M_out, double dt, int advance, bool clamp) {
+    const mmk_params &p = c->p;
+    int slot;
+    HIPCHK(c, prof_begin(c, 6, &slot), "hipEventRecord");
+    HIPCHK(c, launch_r0_motor<T>(M_in, M_out, c->at<T>(c->L.q0), c->at<T>(c->L.m0), c->at<T>(c->L.m1),
+                                 c->at<R0Seg>(c->L.r0seg), c->at<int32_t>(c->L.r0start),
+                                 clamp ? c->at<T>(c->L.r0scale) : nullptr, clamp ? c->at<T>(c->L.r0pool) : nullptr,
+                                 r0_const<T>(p, dt, advance), c->r0.lmax, p.limiter, c->stream),
+           "anchor-resolved motor launch");
+    HIPCHK(c, prof_end(c, 6, slot), "hipEventRecord");
+    return MMK_OK;
+}
+
+// Coarse density of every anchor of the current state; with clamp, the factor and pool of the
+// next motor step; coarse_out / free_out (may be NULL) in the field precision.
+template <typename T>
+static mmk_status r0_anchors(mmk_ctx *c, bool clamp, T *coarse_out, T *free_out) {
+    const mmk_params &p = c->p;
+    int slot;
+    HIPCHK(c, prof_begin(c, 7, &slot), "hipEventRecord");
+    HIPCHK(c, launch_r0_coarse<T>(c->at<T>(c->L.q0), c->at<T>(c->L.psi[c->cur]), c->at<R0Seg>(c->L.r0seg),
+                                  c->at<double>(c->L.r0part), clamp ? c->at<T>(c->L.r0scale) : nullptr,
+                                  clamp ? c->at<T>(c->L.r0pool) : nullptr, coarse_out, free_out,
+                                  r0_const<T>(p, 0.0, 0), c->r0.nseg, c->r0.nsplit, kTwoPi / p.ntheta, p.m_total,
+                                  p.k_on, c->stream),
+           "anchor coarse density launch");
+    HIPCHK(c, prof_end(c, 7, slot), "hipEventRecord");
+    return MMK_OK;
+}
+
+// Each micro-step: [coarse density, clamp and pool of the current state (m_total > 0),] the
+// motor step of every run with the anchor marginals, then psi driven by the marginal m0.
+template <typename T>
+static mmk_status run_steps_r0(mmk_ctx *c, int K, double dt) {
+    const bool depl = c->p.m_total > 0;
+    for (int n = 0; n < K; ++n) {
+        const int a = c->cur, b = 1 - c->cur;
+        mmk_status st = MMK_OK;
+        if (depl) st = r0_anchors<T>(c, true, nullptr, nullptr);
+        if (st == MMK_OK) st = r0_motor<T>(c, c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), dt, 1, depl);
+        if (st == MMK_OK)
+            st = psi_half<T>(c, c->at<T>(c->L.psi[a]), c->at<T>(c->L.psi[b]), c->at<T>(c->L.m0), c->at<T>(c->L.m1),
+                             c->at<T>(c->L.u), c->at<T>(c->L.G), dt, n == K - 1, c->stream);
+        if (st != MMK_OK) return st;
+        c->cur = b;
+    }
+    return MMK_OK;
+}
+
 template <typename T>
 static mmk_status run_steps(mmk_ctx *c, int K, double dt) {
     const bool blocked = c->block && c->p.m_total == 0 && !c->tape.active;
-    mmk_status st = blocked ? run_steps_blocked<T>(c, K, dt) : run_steps_serial<T>(c, K, dt);
+    mmk_status st = c->p.rc > 0 ? run_steps_r0<T>(c, K, dt)
+                    : blocked   ? run_steps_blocked<T>(c, K, dt)
+                                : run_steps_serial<T>(c, K, dt);
     if (st != MMK_OK) return st;
     if (K > 0) {
         c->have_out = true;
@@ -384,6 +493,8 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     if (!m.empty()) return fail(nullptr, MMK_ERR_UNSUPPORTED, "%s", m.c_str());
     if (ckpt_every < 0 || (ckpt_every > 0 && max_tape_steps < 0))
         return fail(nullptr, MMK_ERR_ARG, "ckpt_every and max_tape_steps must be >= 0");
+    if (ckpt_every > 0 && p->rc > 0)
+        return fail(nullptr, MMK_ERR_UNSUPPORTED, "the adjoint tape covers the anchor-marginal model only (rc = 0)");
     if (ckpt_every > 0 && plan_psi(p->nx, p->ny, p->ntheta, esize(*p), 3).lds_bytes > 64 * 1024)
         return fail(nullptr, MMK_ERR_UNSUPPORTED, "ntheta too large for the reverse psi kernel at this precision");
     if (!workspace) return fail(nullptr, MMK_ERR_ARG, "workspace is NULL");
@@ -429,10 +540,19 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     } else {
         e = hipMemcpyAsync(c->ws + L.tab, c->host_tab64.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream);
     }
-    // spreading records of the motor force (needed only by mmk_get_force)
+    // spreading records of the motor force (needed only by mmk_get_force; anchor-marginal model)
     c->fplan = plan_force(p->nx, p->ny, nth, p->ns, p->lx, p->ly, p->L, c->esz);
     ForceRecords &fr = c->frec;
-    c->frec_ok = force_records(nth, p->ns, p->lx, p->ly, p->L, p->nx, p->ny, c->fplan, &fr);
+    c->frec_ok = p->rc == 0 && force_records(nth, p->ns, p->lx, p->ly, p->L, p->nx, p->ny, c->fplan, &fr);
+    if (p->rc > 0) {  // tracked cells and runs of the anchor-resolved model
+        c->r0 = r0_plan_of(*p);
+        if (e == hipSuccess && c->r0.nseg > 0)
+            e = hipMemcpyAsync(c->ws + L.r0seg, c->r0.seg.data(), c->r0.seg.size() * sizeof(R0Seg),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->ws + L.r0start, c->r0.seg_start.data(), c->r0.seg_start.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, c->stream);
+    }
     if (c->frec_ok) {
         auto up = [&](size_t off, const void *src, size_t bytes) {
             if (e == hipSuccess) e = hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
@@ -452,7 +572,7 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     const char *ew = getenv("MMK_PSI_WALK");
     c->walk = c->wp.ok && (ew ? atoi(ew) != 0 : c->esz == 4);
     const char *eb = getenv("MMK_MOTOR_BLOCK");
-    c->block = p->m_total == 0 && (eb ? atoi(eb) != 0 : true);
+    c->block = p->m_total == 0 && p->rc == 0 && (eb ? atoi(eb) != 0 : true);
     *out = c;
     return MMK_OK;
 }
@@ -483,17 +603,22 @@ mmk_status mmk_set_state(mmk_ctx *c, const void *psi, const void *M) {
     if (!c) return MMK_ERR_ARG;
     if (!psi) return fail(c, MMK_ERR_ARG, "psi is NULL");
     if (c->tape.active) return fail(c, MMK_ERR_STATE, "set_state during a taped run");
-    const size_t np = (size_t)n_psi(c->p) * c->esz, nm = (size_t)n_m(c->p) * c->esz;
+    const int64_t nme = n_state(c);
+    const size_t np = (size_t)n_psi(c->p) * c->esz, nm = (size_t)nme * c->esz;
     HIPCHK(c, hipMemcpyAsync(c->ws + c->L.psi[c->cur], psi, np, hipMemcpyDeviceToDevice, c->stream),
            "copy of psi");
-    if (M) {
+    if (M && nm > 0) {
         HIPCHK(c, hipMemcpyAsync(c->ws + c->L.M[c->cur], M, nm, hipMemcpyDeviceToDevice, c->stream), "copy of M");
     } else if (c->esz == 4) {
-        HIPCHK(c, launch_zero<float>(c->at<float>(c->L.M[c->cur]), n_m(c->p), c->stream), "zero M");
+        HIPCHK(c, launch_zero<float>(c->at<float>(c->L.M[c->cur]), nme, c->stream), "zero M");
     } else {
-        HIPCHK(c, launch_zero<double>(c->at<double>(c->L.M[c->cur]), n_m(c->p), c->stream), "zero M");
+        HIPCHK(c, launch_zero<double>(c->at<double>(c->L.M[c->cur]), nme, c->stream), "zero M");
     }
-    if (c->p.m_total > 0) {  // depletion factors of the new state, for the first step
+    if (c->p.rc > 0) {  // run totals and anchor marginals of the new state, for the first step
+        mmk_status st = c->esz == 4 ? r0_motor<float>(c, c->at<float>(c->L.M[c->cur]), c->at<float>(c->L.M[c->cur]), 0.0, 0, false)
+                                    : r0_motor<double>(c, c->at<double>(c->L.M[c->cur]), c->at<double>(c->L.M[c->cur]), 0.0, 0, false);
+        if (st != MMK_OK) return st;
+    } else if (c->p.m_total > 0) {  // depletion factors of the new state, for the first step
         const double ds = c->p.L / c->p.ns, dth = kTwoPi / c->p.ntheta;
         const int64_t nxy = (int64_t)c->p.nx * c->p.ny;
         hipError_t e;
@@ -543,8 +668,8 @@ mmk_status mmk_get_state(mmk_ctx *c, void *psi, void *M) {
     if (psi)
         HIPCHK(c, hipMemcpyAsync(psi, c->ws + c->L.psi[c->cur], (size_t)n_psi(c->p) * c->esz,
                                  hipMemcpyDeviceToDevice, c->stream), "copy of psi");
-    if (M)
-        HIPCHK(c, hipMemcpyAsync(M, c->ws + c->L.M[c->cur], (size_t)n_m(c->p) * c->esz, hipMemcpyDeviceToDevice,
+    if (M && n_state(c) > 0)
+        HIPCHK(c, hipMemcpyAsync(M, c->ws + c->L.M[c->cur], (size_t)n_state(c) * c->esz, hipMemcpyDeviceToDevice,
                                  c->stream), "copy of M");
     return MMK_OK;
 }
@@ -581,6 +706,7 @@ mmk_status mmk_get_force(mmk_ctx *c, void *force) {
     if (!c) return MMK_ERR_ARG;
     if (!force) return fail(c, MMK_ERR_ARG, "force is NULL");
     if (!c->have_state) return fail(c, MMK_ERR_STATE, "mmk_get_force before mmk_set_state");
+    if (c->p.rc > 0) return fail(c, MMK_ERR_UNSUPPORTED, "the motor force covers the anchor-marginal model (rc = 0)");
     const mmk_params &p = c->p;
     const ForcePlan &fp = c->fplan;
     if (!c->frec_ok || fp.nt == 0)
@@ -606,6 +732,23 @@ mmk_status mmk_get_force(mmk_ctx *c, void *force) {
     return MMK_OK;
 }
 
+mmk_status mmk_get_anchors(mmk_ctx *c, void *coarse, void *free_pool) {
+    if (!c) return MMK_ERR_ARG;
+    if (c->p.rc == 0) return fail(c, MMK_ERR_STATE, "mmk_get_anchors needs the anchor-resolved model (rc > 0)");
+    if (!c->have_state) return fail(c, MMK_ERR_STATE, "mmk_get_anchors before mmk_set_state");
+    if (!coarse && !free_pool) return MMK_OK;
+    return c->esz == 4 ? r0_anchors<float>(c, false, (float *)coarse, (float *)free_pool)
+                       : r0_anchors<double>(c, false, (double *)coarse, (double *)free_pool);
+}
+
+int64_t mmk_r0_cells(const mmk_params *p, int32_t *cells) {
+    if (!check_params(p).empty() || !(p->rc > 0)) return -1;
+    const R0Plan rp = r0_plan_of(*p, true);
+    if (!rp.ok) return -1;
+    if (cells && rp.ncell > 0) std::memcpy(cells, rp.cells.data(), rp.cells.size() * sizeof(int32_t));
+    return rp.ncell;
+}
+
 mmk_status mmk_get_sums(mmk_ctx *c, double *mass, double sum_sigma[3]) {
     if (!c) return MMK_ERR_ARG;
     if (!c->have_out) return fail(c, MMK_ERR_STATE, "no outputs: run mmk_step with K > 0 first");
@@ -623,6 +766,8 @@ mmk_status mmk_get_sums(mmk_ctx *c, double *mass, double sum_sigma[3]) {
 
 mmk_status mmk_tape_begin(mmk_ctx *c, int32_t ckpt_every) {
     if (!c) return MMK_ERR_ARG;
+    if (c->p.rc > 0)
+        return fail(c, MMK_ERR_UNSUPPORTED, "the adjoint covers the anchor-marginal model only (rc = 0)");
     if (c->p.m_total > 0)
         return fail(c, MMK_ERR_UNSUPPORTED, "the adjoint covers linear attachment only (m_total = 0)");
     if (c->p.motor_cfl > 0)

@@ -19,24 +19,6 @@
 
 namespace mmk {
 
-// Superbee slope of the one-sided differences a (left) and b (right): zero unless a and b
-// have the same strict sign, else sgn(b) max(min(2|a|,|b|), min(|a|,2|b|)).
-template <typename T>
-__device__ __forceinline__ T superbee(T a, T b) {
-    const T aa = fabs(a), ab = fabs(b);
-    const T m = fmax(fmin(aa + aa, ab), fmin(aa, ab + ab));
-    return (a * b > T(0)) ? copysign(m, b) : T(0);
-}
-// FP32: minmod(x, y) = med3(x, y, 0), and superbee = maxmod(minmod(2a, b), minmod(a, 2b)).
-// Both minmods carry the sign of b (or are 0), so their maxmod is med3(p, q, sgn(b) inf).
-// Every operation is exact (doubling, median, sign copy): the value equals the definition.
-template <>
-__device__ __forceinline__ float superbee<float>(float a, float b) {
-    const float p = __builtin_amdgcn_fmed3f(a + a, b, 0.0f);
-    const float q = __builtin_amdgcn_fmed3f(a, b + b, 0.0f);
-    return __builtin_amdgcn_fmed3f(p, q, copysignf(__builtin_inff(), b));
-}
-
 // R(z) on this lane's CPL cells.  g: lane index inside the column group; l0 = g * CPL.
 // With the face value h_l = z_l + sigma_l / 2 (flux v0 h_l; h_{-1} = 0 carries the zero
 // influx, and the zero last slope makes h_{ns-1} = z_{ns-1}, the first-order outflow):

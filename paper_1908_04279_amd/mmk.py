@@ -21,11 +21,11 @@ MMK_OK, MMK_ERR_ARG, MMK_ERR_NOMEM, MMK_ERR_HIP, MMK_ERR_STATE, MMK_ERR_UNSUPPOR
 FP64, FP32 = 0, 1
 SUPERBEE, UPWIND1 = 0, 1
 KERNEL_IDS = {"motor_step": 0, "psi_step": 1, "global_sums": 2, "psi_step_reverse": 3,
-              "motor_step_reverse": 4, "motor_force": 5}
+              "motor_step_reverse": 4, "motor_force": 5, "r0_motor_step": 6, "r0_coarse": 7}
 
 EXPORTS = ["mmk_workspace_bytes", "mmk_create", "mmk_destroy", "mmk_set_params", "mmk_set_state",
            "mmk_set_fluid", "mmk_step", "mmk_get_state", "mmk_get_stress", "mmk_get_moments",
-           "mmk_get_motor_moments", "mmk_get_force", "mmk_get_sums", "mmk_tape_begin", "mmk_tape_backward",
+           "mmk_get_motor_moments", "mmk_get_force", "mmk_get_anchors", "mmk_r0_cells", "mmk_get_sums", "mmk_tape_begin", "mmk_tape_backward",
            "mmk_tape_end", "mmk_profile", "mmk_profile_read", "mmk_last_error"]
 
 
@@ -41,7 +41,7 @@ class Params(C.Structure):
                 ("k_on", C.c_double), ("k_off", C.c_double), ("v0", C.c_double),
                 ("F", C.c_double), ("sigma_f", C.c_double),
                 ("precision", C.c_int32), ("limiter", C.c_int32), ("m_total", C.c_double),
-                ("motor_cfl", C.c_double)]
+                ("motor_cfl", C.c_double), ("rc", C.c_double)]
 
 
 _lib = None
@@ -69,6 +69,8 @@ def lib():
             "mmk_get_moments": ([vp, vp], C.c_int),
             "mmk_get_motor_moments": ([vp, vp, vp], C.c_int),
             "mmk_get_force": ([vp, vp], C.c_int),
+            "mmk_get_anchors": ([vp, vp, vp], C.c_int),
+            "mmk_r0_cells": ([P, vp], i64),
             "mmk_get_sums": ([vp, C.POINTER(d), C.POINTER(d)], C.c_int),
             "mmk_tape_begin": ([vp, i32], C.c_int),
             "mmk_tape_backward": ([vp, vp, vp, vp, C.POINTER(d)], C.c_int),
@@ -90,7 +92,8 @@ def make_params(p, precision=FP64) -> Params:
     return Params(int(p.nx), int(p.ny), int(p.ntheta), int(p.ns), float(p.lx), float(p.ly),
                   float(p.L), float(p.k_on), float(p.k_off), float(p.v0), float(p.F),
                   float(p.sigma_f), int(precision), int(getattr(p, "limiter", 0)),
-                  float(getattr(p, "m_total", 0.0)), float(getattr(p, "motor_cfl", 0.0)))
+                  float(getattr(p, "m_total", 0.0)), float(getattr(p, "motor_cfl", 0.0)),
+                  float(getattr(p, "rc", 0.0)))
 
 
 def workspace_bytes(params: Params, ckpt_every=0, max_tape_steps=0) -> int:
@@ -98,6 +101,19 @@ def workspace_bytes(params: Params, ckpt_every=0, max_tape_steps=0) -> int:
     if n == 0:
         raise MMKError(MMK_ERR_ARG, lib().mmk_last_error(None).decode())
     return n
+
+
+def r0_cells(p):
+    """Tracked cells of the anchor-resolved model (p.rc > 0): int32 array [ncell][4] = (a, b, k, l)."""
+    import numpy as np
+    params = make_params(p)
+    n = lib().mmk_r0_cells(C.byref(params), None)
+    if n < 0:
+        raise MMKError(MMK_ERR_ARG, "rc must be > 0 with rc + L/2 below lx/2 and ly/2")
+    cells = np.zeros((n, 4), dtype=np.int32)
+    if n > 0:
+        lib().mmk_r0_cells(C.byref(params), C.c_void_p(cells.ctypes.data))
+    return cells
 
 
 def _ptr(t):
@@ -134,7 +150,11 @@ class Context:
         self.h = h
         nx, ny, nt, ns = p.nx, p.ny, p.ntheta, p.ns
         self.shape_psi = (nx, ny, nt)
-        self.shape_M = (nx, ny, nt, ns)
+        if getattr(p, "rc", 0.0) > 0:   # anchor-resolved: Mb [ncell][nx][ny]
+            self.ncell = int(lib().mmk_r0_cells(C.byref(self.params), None))
+            self.shape_M = (self.ncell, nx, ny)
+        else:
+            self.shape_M = (nx, ny, nt, ns)
 
     # -- helpers ------------------------------------------------------------------------
     def _check(self, st):
@@ -212,6 +232,13 @@ class Context:
         f = self.empty((2, self.p.nx, self.p.ny))
         self._check(lib().mmk_get_force(self.h, _ptr(f)))
         return f
+
+    def get_anchors(self):
+        """Anchor-resolved model: (coarse, free) [nx][ny], the coarse bound-motor density of Eq. (5)
+        at every anchor of the current state and its free pool of Eq. (6) before the next clamp."""
+        co, fr = self.empty((self.p.nx, self.p.ny)), self.empty((self.p.nx, self.p.ny))
+        self._check(lib().mmk_get_anchors(self.h, _ptr(co), _ptr(fr)))
+        return co, fr
 
     def get_sums(self):
         mass = C.c_double()

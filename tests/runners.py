@@ -83,3 +83,36 @@ def seeded_case(p, n_exchanges=1, new_each=True, M0_kind="zero"):
     else:
         M0 = gen.make_M0_random(p.nx, p.ny, p.ntheta, p.ns, p.k_on, p.k_off, seed=5)
     return psi0, M0, fluids, dt
+
+
+def run_r0_oracle(p, psi0, Mb0, fluids, K, n, dt):
+    """FP64 oracle of the anchor-resolved model through the same call sequence."""
+    o = A.OracleR0(p)
+    o.set_state(psi0, Mb0)
+    done, e = 0, 0
+    while done < n:
+        o.set_fluid(*fluids[min(e, len(fluids) - 1)])
+        k = min(K, n - done)
+        o.step(k, dt)
+        done += k
+        e += 1
+    stress, mom = o.get_stress_moments()
+    mass, ss = A.global_sums(p, o.psi, stress)
+    m0, m1 = o.marginals()
+    coarse = o.coarse()
+    free = (p.m_total - np.minimum(coarse, p.m_total)) if p.m_total > 0 else np.ones_like(coarse)
+    return dict(psi=o.psi, M=o.Mb, m0=m0, m1=m1, stress=stress, mom=mom, mass=mass, sum_sigma=ss,
+                coarse=coarse, free=free)
+
+
+def run_r0_gpu(p, psi0, Mb0, fluids, K, n, dt, precision=0):
+    """The HIP library on the anchor-resolved model, with the per-anchor outputs."""
+    import torch
+    out = run_gpu(p, psi0, Mb0, fluids, K, n, dt, precision=precision, keep_ctx=True)
+    ctx = out.pop("ctx")
+    coarse, free = ctx.get_anchors()
+    out["coarse"] = coarse.double().cpu().numpy()
+    out["free"] = free.double().cpu().numpy()
+    torch.cuda.synchronize()
+    ctx.close()
+    return out

@@ -48,7 +48,8 @@ def test_workspace_bytes_scales_with_fields_and_tape():
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(ntheta=0), dict(ns=0),
                                  dict(lx=0.0), dict(L=-1.0), dict(v0=-0.5), dict(k_on=float("nan")),
                                  dict(limiter=7), dict(m_total=-1.0), dict(m_total=float("inf")),
-                                 dict(motor_cfl=-0.5), dict(motor_cfl=float("nan"))])
+                                 dict(motor_cfl=-0.5), dict(motor_cfl=float("nan")), dict(rc=-0.1),
+                                 dict(rc=float("nan")), dict(rc=2.7)])
 def test_invalid_params_are_rejected(bad):
     n = mmk.lib().mmk_workspace_bytes(C.byref(mmk.make_params(params(**bad))), 0, 0)
     assert n == 0
@@ -90,3 +91,28 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(mmk, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         mmk.lib()
+
+
+@pytest.mark.parametrize("kw", [dict(nx=12, ny=12, ntheta=8, ns=8, rc=0.45),
+                                dict(nx=9, ny=14, ntheta=6, ns=5, rc=0.8, lx=5.0, ly=7.0),
+                                dict(nx=128, ny=128, ntheta=32, ns=32, rc=0.1),
+                                dict(nx=8, ny=8, ntheta=8, ns=4, rc=0.01)])
+def test_r0_cells_match_the_oracle(kw):
+    """The library's tracked-cell table (host code) equals the oracle's, entry for entry."""
+    import numpy as np
+    from oracle import oracle_a as A
+    p = ModelParams(**kw)
+    assert np.array_equal(mmk.r0_cells(p), A.r0_cells(p))
+
+
+def test_r0_cells_refusals_and_workspace():
+    assert mmk.lib().mmk_r0_cells(C.byref(mmk.make_params(params())), None) == -1          # rc = 0
+    assert mmk.lib().mmk_r0_cells(C.byref(mmk.make_params(params(rc=3.0))), None) == -1    # too large
+    p = params(nx=32, ny=32, ntheta=16, ns=16, rc=0.3)
+    n = mmk.lib().mmk_r0_cells(C.byref(mmk.make_params(p)), None)
+    ws = mmk.workspace_bytes(mmk.make_params(p, mmk.FP64))
+    assert ws >= 2 * n * 32 * 32 * 8
+    for bad, msg in [(dict(ns=64, rc=0.5), "longer than 32"), (dict(rc=0.3, motor_cfl=0.4), "sub-cycling")]:
+        q = params(**bad)
+        assert mmk.lib().mmk_workspace_bytes(C.byref(mmk.make_params(q)), 0, 0) == 0
+        assert msg in mmk.lib().mmk_last_error(None).decode()
