@@ -44,6 +44,14 @@ M_TOTAL_BENCH = 0.02
 # limit (v0/ds + k_off) is then stricter than the psi limit at 256^2, and a motor CFL of 0.4.
 SUBSTEP_V0 = 8.0
 MOTOR_CFL_BENCH = 0.4
+# Anchor-resolved leg (M_b(r0, x, th, s) on the capture ball): 128^2 anchors and filament cells,
+# 32 orientations, 32 arclength cells, capture radius 0.1 (13216 tracked cells per filament cell,
+# 216.5M in all, runs of at most 7 cells), with depletion: m_total about the median coarse
+# density of the seeded state (M_b ~ U[0, k_on/k_off]), so the clamp is active at the start.
+R0_BENCH = dict(nx=128, ny=128, ntheta=32, ns=32, rc=0.1)
+R0_M_TOTAL = 8.0e-4
+R0_COUNTERS = (os.path.join(ROOT, "profiles", "r0_motor_f32_128x128x32x32_counters.txt"),
+               ["r0.hip", "r0.h", "device_util.h"])
 
 
 def log(*a):
@@ -239,6 +247,113 @@ def run_force(p, precision, reps):
             "gbs": alg / (us * 1e-6) / 1e9, "frac": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "calls": n}
 
 
+def r0_runs(cells):
+    """Number of runs (consecutive l with the same a, b, k) in a tracked-cell table."""
+    if len(cells) == 0:
+        return 0
+    brk = (np.diff(cells[:, 3]) != 1) | np.any(np.diff(cells[:, :3], axis=0) != 0, axis=1)
+    return int(np.sum(brk)) + 1
+
+
+def r0_motor_bytes(p, b, ncell, nrun, depl):
+    """Algorithmic HBM bytes of one anchor-resolved motor launch: read and write M_b, write the
+    run totals and the marginals m0, m1 [read the anchors' clamp factor and pool]."""
+    nxy = p.nx * p.ny
+    return b * (2 * ncell * nxy + nrun * nxy + 2 * nxy * p.ntheta + (2 * nxy if depl else 0))
+
+
+def r0_coarse_bytes(p, b, nrun, nsplit):
+    """Coarse density, clamp and pool: read the run totals and psi, write and read the FP64
+    partial rows, write the clamp factor and pool."""
+    nxy = p.nx * p.ny
+    return b * (nrun * nxy + nxy * p.ntheta + 2 * nxy) + 2 * 8 * 4 * nsplit * nxy
+
+
+def r0_counters_traffic():
+    """HBM bytes per FP32 anchor-resolved motor launch from the committed rocprofv3 counter
+    summary, or None when it is missing or was taken on other kernel sources."""
+    path, files = R0_COUNTERS
+    if not os.path.exists(path):
+        return None
+    kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
+    if kv.get("sources_sha256_16") != sources_sha(files):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def run_r0(precision, steps, warmup, K, event_every):
+    """The anchor-resolved micro-step (coarse + pool, motor, psi) on the R0_BENCH workload."""
+    import torch
+    from paper_1908_04279_amd import inputs as gen
+    from paper_1908_04279_amd import mmk
+    p = gen.ModelParams(**R0_BENCH, m_total=R0_M_TOTAL)
+    cells = mmk.r0_cells(p)
+    ncell, nrun = len(cells), r0_runs(cells)
+    n_ex = (warmup + steps) // K + 2
+    fluids_np = [gen.make_fluid(p.nx, p.ny, p.lx, p.ly, seed=1 + e) for e in range(n_ex)]
+    dt = gen.cfl_dt(p, fluids_np)
+    ctx = mmk.Context(p, precision=precision)
+    fl = [(torch.as_tensor(u).to(ctx.device, ctx.dtype), torch.as_tensor(g).to(ctx.device, ctx.dtype))
+          for u, g in fluids_np]
+    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0)
+    Mb0 = torch.rand(ncell, p.nx, p.ny, dtype=ctx.dtype, device=ctx.device,
+                     generator=torch.Generator(device=ctx.device).manual_seed(6)) * (p.k_on / p.k_off)
+    ctx.set_state(torch.as_tensor(psi0), Mb0)
+    del Mb0
+    co0, _ = ctx.get_anchors()
+    clamped0 = float((co0 > p.m_total).float().mean())
+
+    def advance(nsteps, e0):
+        done, e = 0, e0
+        while done < nsteps:
+            ctx.set_fluid(*fl[e])
+            k = min(K, nsteps - done)
+            ctx.step(k, dt)
+            done += k
+            e += 1
+        return e
+
+    log(f"[bench] anchor-resolved {'FP32' if precision == mmk.FP32 else 'FP64'}: {ncell} cells per filament "
+        f"cell, {nrun} runs, warmup {warmup}")
+    e = advance(warmup, 0)
+    torch.cuda.synchronize()
+    ctx.profile(True, every=event_every)
+    t0 = time.perf_counter()
+    advance(steps, e)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = {name: ctx.profile_read(name) for name in ("r0_motor_step", "r0_coarse", "psi_step")}
+    ctx.profile(False)
+    co, _ = ctx.get_anchors()
+    clamped = float((co > p.m_total).float().mean())
+    mass, _ = ctx.get_sums()
+    ctx.close()
+    b = 4 if precision == mmk.FP32 else 8
+    # the library's coarse split: about 1024 blocks of 64 lanes, 16 bytes of run totals per lane
+    vc = (16 // b) if (p.nx * p.ny) % (16 // b) == 0 else 1
+    gx = -(-(p.nx * p.ny) // (64 * vc))
+    nsplit = max(1, min(-(-1024 // gx), 64, -(-nrun // 4)))
+    mb = r0_motor_bytes(p, b, ncell, nrun, True)
+    cb = r0_coarse_bytes(p, b, nrun, nsplit)
+    ms_m, n_m = prof["r0_motor_step"]
+    ms_c, n_c = prof["r0_coarse"]
+    ms_p, n_p = prof["psi_step"]
+    us_m, us_c, us_p = ms_m / n_m * 1e3, ms_c / n_c * 1e3, ms_p / n_p * 1e3
+    flops = ncell * p.nx * p.ny * (MOTOR_FLOPS_PER_CELL + M1_FLOPS_PER_CELL)
+    alu_peak = FP32_VECTOR_PEAK_TFLOPS if b == 4 else FP64_VECTOR_PEAK_TFLOPS
+    return {"workload": f"{p.nx}x{p.ny} anchors and filament cells, {p.ntheta} orientations, {p.ns} arclength "
+                        f"cells, capture radius {p.rc}, m_total {p.m_total}",
+            "tracked_cells_per_filament_cell": ncell, "Mb_cells": ncell * p.nx * p.ny, "runs": nrun,
+            "steps": steps, "micro_steps_per_s": steps / el, "ms_per_step": el / steps * 1e3,
+            "motor_avg_us": us_m, "motor_algorithmic_bytes": mb, "motor_gbs": mb / (us_m * 1e-6) / 1e9,
+            "motor_frac": mb / (us_m * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "motor_alu_frac": flops / (us_m * 1e-6) / 1e12 / alu_peak,
+            "motor_traffic": r0_counters_traffic() if b == 4 else None,
+            "coarse_avg_us": us_c, "coarse_algorithmic_bytes": cb, "coarse_gbs": cb / (us_c * 1e-6) / 1e9,
+            "psi_avg_us": us_p, "clamped_anchor_fraction_start": clamped0, "clamped_anchor_fraction_end": clamped,
+            "mass": mass, "timed_launches": [n_m, n_c, n_p]}
+
+
 def copy_calibration(nbytes, reps):
     """A plain device copy of known size (for scaling the HBM byte counters)."""
     import torch
@@ -310,12 +425,13 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64", "depletion", "force",
-                                       "substeps"],
+                                       "substeps", "r0", "r0_fp32"],
                     default="all",
                     help="restrict to one leg (used for profiler runs)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--depletion-steps", type=int, default=200)
     ap.add_argument("--substep-steps", type=int, default=200)
+    ap.add_argument("--r0-steps", type=int, default=200)
     ap.add_argument("--event-every", type=int, default=EVENT_EVERY,
                     help="bracket every N-th launch of each kernel with HIP events")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -342,6 +458,13 @@ def main():
     if args.only == "force":
         print(json.dumps({"force_fp32": run_force(gen.params_for("c3_fp32_256x256x64x64"), mmk.FP32, 10)}),
               flush=True)
+        return
+
+    if args.only in ("r0", "r0_fp32"):
+        r0 = {"anchor_resolved_fp32": run_r0(mmk.FP32, args.r0_steps, 20, 10, args.event_every)}
+        if args.only == "r0":
+            r0["anchor_resolved_fp64"] = run_r0(mmk.FP64, args.r0_steps, 20, 10, args.event_every)
+        print(json.dumps(r0), flush=True)
         return
 
     p = gen.params_for("c3_fp32_256x256x64x64")
@@ -468,6 +591,9 @@ def main():
         out["force_fp32"] = run_force(p, mmk.FP32, 10)
     if "fast_sub" in res:
         out["substeps_fp32"] = substep_summary()
+    if args.only == "all":
+        out["anchor_resolved_fp32"] = run_r0(mmk.FP32, args.r0_steps, 20, K, args.event_every)
+        out["anchor_resolved_fp64"] = run_r0(mmk.FP64, args.r0_steps, 20, K, args.event_every)
     if "depletion" in res:
         out["depletion_fp32"] = depletion_summary()
         out["depletion_fp32"]["relative_to_linear"] = out["depletion_fp32"]["micro_steps_per_s"] / s["steps_per_s"]

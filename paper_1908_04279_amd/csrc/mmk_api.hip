@@ -34,7 +34,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t M[2], psi[2], psi_tmp, m0, m0s, m1, Dxy, fpart, fblk, fexy, fcs, u, G, stress, mom, tab, partials, sums;
-    size_t q0, r0part, r0scale, r0pool, r0seg, r0start;  // anchor-resolved model (rc > 0)
+    size_t q0, r0part, r0scale, r0pool, r0seg, r0start, psiT;  // anchor-resolved model (rc > 0)
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -92,7 +92,8 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     const bool r0 = p.rc > 0;
     const R0Plan rp = r0 ? r0_plan_of(p) : R0Plan{};
     const size_t np = (size_t)n_psi(p), nxy = (size_t)p.nx * p.ny;
-    const size_t nm = r0 ? (size_t)rp.ncell * nxy : (size_t)n_m(p);  // M, or Mb [ncell][nx][ny]
+    // M, or the tiled anchor-resolved state (M[tile][cell][64 vx])
+    const size_t nm = r0 ? (size_t)r0_tiled_elems(rp.ncell, (int64_t)nxy, r0_vx(e, rp.lmax)) : (size_t)n_m(p);
     const PsiLaunch pl = plan_psi(p.nx, p.ny, p.ntheta, e, 2);
     const WalkPlan wp = plan_walk(p.nx, p.ny, p.ntheta);
     L.psi_blocks = wp.ok && wp.blocks > pl.blocks ? wp.blocks : pl.blocks;
@@ -124,11 +125,12 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     } else {
         // run totals, coarse partial rows, per-anchor clamp factor and pool, run table
         L.q0 = take((size_t)rp.nseg * nxy * e);
-        L.r0part = take((size_t)4 * rp.nsplit * nxy * sizeof(double));
+        L.r0part = take((size_t)4 * r0_coarse_split((int64_t)nxy, rp.nseg, e) * nxy * sizeof(double));
         L.r0scale = take(nxy * e);
         L.r0pool = take(nxy * e);
         L.r0seg = take((size_t)rp.nseg * sizeof(R0Seg));
         L.r0start = take(((size_t)p.ntheta + 1) * sizeof(int32_t));
+        L.psiT = take(np * e);
     }
     L.u = take(2 * nxy * e);
     L.G = take(4 * nxy * e);
@@ -180,9 +182,14 @@ struct mmk_ctx {
     void *vat(size_t off) const { return ws + off; }
 };
 
-// elements of the motor state: M [nx][ny][nth][ns], or Mb [ncell][nx][ny] when rc > 0
+// elements of the motor state: M [nx][ny][nth][ns], or Mb [ncell][nx][ny] when rc > 0 (the
+// caller's layout; the context holds it tiled, r0_tiled_elems)
 static int64_t n_state(const mmk_ctx *c) {
     return c->p.rc > 0 ? c->r0.ncell * (int64_t)c->p.nx * c->p.ny : n_m(c->p);
+}
+static int64_t n_state_held(const mmk_ctx *c) {
+    return c->p.rc > 0 ? r0_tiled_elems(c->r0.ncell, (int64_t)c->p.nx * c->p.ny, r0_vx(c->esz, c->r0.lmax))
+                       : n_m(c->p);
 }
 
 static mmk_status fail(mmk_ctx *c, mmk_status st, const char *fmt, ...) {
@@ -367,8 +374,18 @@ static R0Const<T> r0_const(const mmk_params &p, double dt, int advance) {
     c.ny = p.ny;
     c.nth = p.ntheta;
     c.nxy = (int64_t)p.nx * p.ny;
+    c.ncell = 0;
+    c.vx = 1;
     c.advance = advance;
     return c;
+}
+
+template <typename T>
+static R0Const<T> r0_cst(const mmk_ctx *c, double dt, int advance) {
+    R0Const<T> k = r0_const<T>(c->p, dt, advance);
+    k.ncell = c->r0.ncell;
+    k.vx = r0_vx(sizeof(T), c->r0.lmax);
+    return k;
 }
 
 // Motor step of every run (advance = 0: only the run totals and marginals of the current state).
@@ -380,7 +397,7 @@ static mmk_status r0_motor(mmk_ctx *c, const T *M_in, T *M_out, double dt, int a
     HIPCHK(c, launch_r0_motor<T>(M_in, M_out, c->at<T>(c->L.q0), c->at<T>(c->L.m0), c->at<T>(c->L.m1),
                                  c->at<R0Seg>(c->L.r0seg), c->at<int32_t>(c->L.r0start),
                                  clamp ? c->at<T>(c->L.r0scale) : nullptr, clamp ? c->at<T>(c->L.r0pool) : nullptr,
-                                 r0_const<T>(p, dt, advance), c->r0.lmax, p.limiter, c->stream),
+                                 r0_cst<T>(c, dt, advance), c->r0.lmax, p.limiter, c->stream),
            "anchor-resolved motor launch");
     HIPCHK(c, prof_end(c, 6, slot), "hipEventRecord");
     return MMK_OK;
@@ -393,10 +410,11 @@ static mmk_status r0_anchors(mmk_ctx *c, bool clamp, T *coarse_out, T *free_out)
     const mmk_params &p = c->p;
     int slot;
     HIPCHK(c, prof_begin(c, 7, &slot), "hipEventRecord");
-    HIPCHK(c, launch_r0_coarse<T>(c->at<T>(c->L.q0), c->at<T>(c->L.psi[c->cur]), c->at<R0Seg>(c->L.r0seg),
+    HIPCHK(c, launch_r0_coarse<T>(c->at<T>(c->L.q0), c->at<T>(c->L.psi[c->cur]), c->at<T>(c->L.psiT),
+                                  c->at<R0Seg>(c->L.r0seg),
                                   c->at<double>(c->L.r0part), clamp ? c->at<T>(c->L.r0scale) : nullptr,
                                   clamp ? c->at<T>(c->L.r0pool) : nullptr, coarse_out, free_out,
-                                  r0_const<T>(p, 0.0, 0), c->r0.nseg, c->r0.nsplit, kTwoPi / p.ntheta, p.m_total,
+                                  r0_cst<T>(c, 0.0, 0), c->r0.nseg, c->r0.nsplit, kTwoPi / p.ntheta, p.m_total,
                                   p.k_on, c->stream),
            "anchor coarse density launch");
     HIPCHK(c, prof_end(c, 7, slot), "hipEventRecord");
@@ -546,6 +564,7 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     c->frec_ok = p->rc == 0 && force_records(nth, p->ns, p->lx, p->ly, p->L, p->nx, p->ny, c->fplan, &fr);
     if (p->rc > 0) {  // tracked cells and runs of the anchor-resolved model
         c->r0 = r0_plan_of(*p);
+        c->r0.nsplit = r0_coarse_split((int64_t)p->nx * p->ny, c->r0.nseg, c->esz);
         if (e == hipSuccess && c->r0.nseg > 0)
             e = hipMemcpyAsync(c->ws + L.r0seg, c->r0.seg.data(), c->r0.seg.size() * sizeof(R0Seg),
                                hipMemcpyHostToDevice, c->stream);
@@ -603,16 +622,22 @@ mmk_status mmk_set_state(mmk_ctx *c, const void *psi, const void *M) {
     if (!c) return MMK_ERR_ARG;
     if (!psi) return fail(c, MMK_ERR_ARG, "psi is NULL");
     if (c->tape.active) return fail(c, MMK_ERR_STATE, "set_state during a taped run");
-    const int64_t nme = n_state(c);
+    const int64_t nme = n_state(c), held = n_state_held(c);
     const size_t np = (size_t)n_psi(c->p) * c->esz, nm = (size_t)nme * c->esz;
+    const int64_t nxy = (int64_t)c->p.nx * c->p.ny;
+    const int vx = r0_vx(c->esz, c->r0.lmax);
     HIPCHK(c, hipMemcpyAsync(c->ws + c->L.psi[c->cur], psi, np, hipMemcpyDeviceToDevice, c->stream),
            "copy of psi");
-    if (M && nm > 0) {
+    if (M && nm > 0 && c->p.rc > 0) {  // caller layout -> tiled
+        HIPCHK(c, c->esz == 4 ? launch_r0_layout<float>((const float *)M, c->at<float>(c->L.M[c->cur]), c->r0.ncell, nxy, vx, true, c->stream)
+                              : launch_r0_layout<double>((const double *)M, c->at<double>(c->L.M[c->cur]), c->r0.ncell, nxy, vx, true, c->stream),
+               "layout of Mb");
+    } else if (M && nm > 0) {
         HIPCHK(c, hipMemcpyAsync(c->ws + c->L.M[c->cur], M, nm, hipMemcpyDeviceToDevice, c->stream), "copy of M");
     } else if (c->esz == 4) {
-        HIPCHK(c, launch_zero<float>(c->at<float>(c->L.M[c->cur]), nme, c->stream), "zero M");
+        HIPCHK(c, launch_zero<float>(c->at<float>(c->L.M[c->cur]), held, c->stream), "zero M");
     } else {
-        HIPCHK(c, launch_zero<double>(c->at<double>(c->L.M[c->cur]), nme, c->stream), "zero M");
+        HIPCHK(c, launch_zero<double>(c->at<double>(c->L.M[c->cur]), held, c->stream), "zero M");
     }
     if (c->p.rc > 0) {  // run totals and anchor marginals of the new state, for the first step
         mmk_status st = c->esz == 4 ? r0_motor<float>(c, c->at<float>(c->L.M[c->cur]), c->at<float>(c->L.M[c->cur]), 0.0, 0, false)
@@ -668,9 +693,16 @@ mmk_status mmk_get_state(mmk_ctx *c, void *psi, void *M) {
     if (psi)
         HIPCHK(c, hipMemcpyAsync(psi, c->ws + c->L.psi[c->cur], (size_t)n_psi(c->p) * c->esz,
                                  hipMemcpyDeviceToDevice, c->stream), "copy of psi");
-    if (M && n_state(c) > 0)
+    if (M && n_state(c) > 0 && c->p.rc > 0) {  // tiled -> caller layout
+        const int64_t nxy = (int64_t)c->p.nx * c->p.ny;
+        const int vx = r0_vx(c->esz, c->r0.lmax);
+        HIPCHK(c, c->esz == 4 ? launch_r0_layout<float>(c->at<float>(c->L.M[c->cur]), (float *)M, c->r0.ncell, nxy, vx, false, c->stream)
+                              : launch_r0_layout<double>(c->at<double>(c->L.M[c->cur]), (double *)M, c->r0.ncell, nxy, vx, false, c->stream),
+               "layout of Mb");
+    } else if (M && n_state(c) > 0) {
         HIPCHK(c, hipMemcpyAsync(M, c->ws + c->L.M[c->cur], (size_t)n_state(c) * c->esz, hipMemcpyDeviceToDevice,
                                  c->stream), "copy of M");
+    }
     return MMK_OK;
 }
 

@@ -1,17 +1,19 @@
 // Anchor-resolved bound motors on the capture ball (Sec. 2; Eqs. (4)-(6); Alg. 2) for gfx950.
 //
-// Layout: M_b[cell][x] with x = (i, j) the filament cell, contiguous, so the 64 lanes of a wave
-// hold 64 consecutive filament cells of one run (a, b, k, lo..lo+len-1) and every load and
-// store of the run moves 64 consecutive values.  The run (at most kR0MaxRun cells) lives in
-// registers through both Runge-Kutta stages: M_b is read and written once per micro-step.
+// Layout: the state is tiled over the filament cells x, M[tile][cell][64 vx]: a lane holds vx
+// consecutive filament cells (one 16-byte load for short runs), a wave 64 vx of them, and the
+// cells of a run (a, b, k, lo..lo+len-1) are consecutive rows of a tile, so one run of one wave
+// is len * 64 vx values in one contiguous piece.  The run lives in registers through both
+// Runge-Kutta stages: M_b is read and written once per micro-step.  The caller's layout
+// Mb[cell][x] is converted at set_state / get_state.
 //
 // The two reductions of the model go in opposite directions: the anchor marginal m0(x, th)
 // sums over the anchors of a filament cell, the coarse density of Eq. (5) over the filament
 // cells of an anchor.  The motor kernel makes the first in a block that owns one orientation
-// and 64 filament cells (its four waves take every fourth run of that orientation, then add
-// their totals through LDS in a fixed order) and writes each run's total q0 = sum M ds.  The
-// coarse kernel makes the second from q0 and psi (a gather of psi from L2), one row of
-// partials per wave, and a last kernel adds the rows in a fixed order and forms the clamp and
+// and one tile (its four waves take every fourth run of that orientation, then add their totals
+// through LDS in a fixed order) and writes each run's total q0 = sum M ds at its anchor.  The
+// coarse kernel makes the second from q0 (read in anchor order) and psi by orientation, one row
+// of partials per wave, and a last kernel adds the rows in a fixed order and forms the clamp and
 // the free pool.  No atomics: every result is the same from run to run.
 #include "device_util.h"
 #include "r0.h"
@@ -71,10 +73,6 @@ R0Plan plan_r0(int nx, int ny, int nth, int ns, double lx, double ly, double L, 
     }
     P.seg_start[nth] = (int32_t)P.seg.size();
     P.nseg = (int)P.seg.size();
-    // enough coarse blocks to cover the chip (about 2048), 4 rows of runs per block
-    const int64_t gx = ((int64_t)nx * ny + 63) / 64;
-    const int64_t want = (2048 + gx - 1) / gx;
-    P.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, 64, (P.nseg + 3) / 4}));
     return P;
 }
 
@@ -100,114 +98,280 @@ __device__ __forceinline__ void run_rhs(const T (&y)[LM], T (&R)[LM], int len, T
     }
 }
 
-template <typename T, int LM, int LIM>
+// Both Runge-Kutta stages of VX runs of exactly N cells held in the first N slots of z.
+template <typename T, int N, int LM, int LIM, int VX>
+__device__ __forceinline__ void rk2_exact(T (&z)[VX][LM], const T (&src)[VX], T nv_ds, T k_off, T half_dt, T dt) {
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        T a[N], R[N], y[N];
+#pragma unroll
+        for (int t = 0; t < N; ++t) a[t] = z[v][t];
+        run_rhs<T, N, LIM>(a, R, N, nv_ds, src[v], k_off);
+#pragma unroll
+        for (int t = 0; t < N; ++t) y[t] = a[t] + half_dt * R[t];
+        run_rhs<T, N, LIM>(y, R, N, nv_ds, src[v], k_off);
+#pragma unroll
+        for (int t = 0; t < N; ++t) z[v][t] = a[t] + dt * R[t];
+    }
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void ldv(const T *p, T (&o)[VX]) {
+    if constexpr (VX == 1) {
+        o[0] = *p;
+    } else {
+        typedef T TV __attribute__((ext_vector_type(VX)));  // one 16-byte load, kept in registers
+        const TV v = *reinterpret_cast<const TV *>(p);
+#pragma unroll
+        for (int i = 0; i < VX; ++i) o[i] = v[i];
+    }
+}
+template <typename T, int VX>
+__device__ __forceinline__ void stv(T *p, const T (&o)[VX]) {
+    if constexpr (VX == 1) {
+        *p = o[0];
+    } else {
+        typedef T TV __attribute__((ext_vector_type(VX)));
+        TV v;
+#pragma unroll
+        for (int i = 0; i < VX; ++i) v[i] = o[i];
+        *reinterpret_cast<TV *>(p) = v;
+    }
+}
+
+// Wrap an index that is at most one period out of [0, n).
+__device__ __forceinline__ int wrap1(int v, int n) {
+    v += v < 0 ? n : 0;
+    return v - (v >= n ? n : 0);
+}
+
+// One block: one orientation k and one x-tile of TT = 64 VX filament cells (lane: VX consecutive
+// cells); its four waves take every fourth run of orientation k.  Tiled layout
+// M[tile][cell][TT]: the cells of a run are consecutive rows of TT values, so a run's load is
+// len * TT * sizeof(T) contiguous bytes.
+template <typename T, int LM, int LIM, int VX>
 __global__ __launch_bounds__(256) void k_r0_motor(const T *__restrict__ Min, T *__restrict__ Mout, T *__restrict__ q0,
                                                   T *__restrict__ m0, T *__restrict__ m1,
                                                   const R0Seg *__restrict__ seg, const int32_t *__restrict__ seg_start,
                                                   const T *__restrict__ scale, const T *__restrict__ pool,
                                                   R0Const<T> c) {
-    __shared__ double red[2][4][64];
+    constexpr int TT = 64 * VX;
+    __shared__ double red[2][4][TT];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int k = blockIdx.y;
-    const int64_t x = (int64_t)blockIdx.x * 64 + lane;
-    const bool act = x < c.nxy;
-    const int i = act ? (int)(x / c.ny) : 0;
-    const int j = act ? (int)(x - (int64_t)i * c.ny) : 0;
-    double a0 = 0.0, a1 = 0.0;
+    const int64_t tile = blockIdx.x;
+    const int64_t x0 = tile * TT + lane * VX;
+    int iv[VX], jv[VX];
+    bool ok[VX];
+    double a0[VX], a1[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        const int64_t x = x0 + v;
+        ok[v] = x < c.nxy;
+        iv[v] = ok[v] ? (int)(x / c.ny) : 0;
+        jv[v] = ok[v] ? (int)(x - (int64_t)iv[v] * c.ny) : 0;
+        a0[v] = a1[v] = 0.0;
+    }
+    const int64_t base = tile * c.ncell * TT + lane * VX;
     const int s_end = seg_start[k + 1];
     for (int s = seg_start[k] + w; s < s_end; s += 4) {
         const R0Seg r = seg[s];
         const int lo = r.pack & 1023, len = (r.pack >> 10) & 1023;
         // the anchor of this run at filament cell x: r0 = x - (a, b), periodic (|a| < nx/2)
-        int ia = i - r.a, ja = j - r.b;
-        ia += ia < 0 ? c.nx : 0;
-        ia -= ia >= c.nx ? c.nx : 0;
-        ja += ja < 0 ? c.ny : 0;
-        ja -= ja >= c.ny ? c.ny : 0;
-        T sc = T(1), src = c.k_on;
-        if (scale != nullptr && act) {
-            const int64_t r0 = (int64_t)ia * c.ny + ja;
-            sc = scale[r0];
-            src = pool[r0];
+        int32_t r0v[VX];  // nx ny < 2^31
+        T sc[VX], src[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            r0v[v] = wrap1(iv[v] - r.a, c.nx) * c.ny + wrap1(jv[v] - r.b, c.ny);
+            sc[v] = T(1);
+            src[v] = c.k_on;
+            if (scale != nullptr) {
+                sc[v] = ok[v] ? scale[r0v[v]] : T(1);
+                src[v] = ok[v] ? pool[r0v[v]] : T(0);
+            }
         }
-        const T *pin = Min + (int64_t)r.off * c.nxy + x;
-        T z[LM];
+        const T *pin = Min + base + (int64_t)r.off * TT;
+        T z[VX][LM];
 #pragma unroll
-        for (int t = 0; t < LM; ++t) z[t] = (t < len && act) ? sc * pin[(int64_t)t * c.nxy] : T(0);
+        for (int t = 0; t < LM; ++t) {
+            T q[VX];
+            if (t < len) {
+                ldv<T, VX>(pin + (int64_t)t * TT, q);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VX; ++v) q[v] = T(0);
+            }
+#pragma unroll
+            for (int v = 0; v < VX; ++v) z[v][t] = sc[v] * q[v];
+        }
         if (c.advance) {
-            T R[LM], y[LM];
-            run_rhs<T, LM, LIM>(z, R, len, c.nv_ds, src, c.k_off);
+            if constexpr (LM == 8) {
+                // the run length is the same on every lane: the step for exactly that length
+                switch (len) {
+                    case 1: rk2_exact<T, 1, LM, LIM, VX>(z, src, c.nv_ds, c.k_off, c.half_dt, c.dt); break;
+                    case 2: rk2_exact<T, 2, LM, LIM, VX>(z, src, c.nv_ds, c.k_off, c.half_dt, c.dt); break;
+                    case 3: rk2_exact<T, 3, LM, LIM, VX>(z, src, c.nv_ds, c.k_off, c.half_dt, c.dt); break;
+                    case 4: rk2_exact<T, 4, LM, LIM, VX>(z, src, c.nv_ds, c.k_off, c.half_dt, c.dt); break;
+                    case 5: rk2_exact<T, 5, LM, LIM, VX>(z, src, c.nv_ds, c.k_off, c.half_dt, c.dt); break;
+                    case 6: rk2_exact<T, 6, LM, LIM, VX>(z, src, c.nv_ds, c.k_off, c.half_dt, c.dt); break;
+                    case 7: rk2_exact<T, 7, LM, LIM, VX>(z, src, c.nv_ds, c.k_off, c.half_dt, c.dt); break;
+                    default: rk2_exact<T, 8, LM, LIM, VX>(z, src, c.nv_ds, c.k_off, c.half_dt, c.dt); break;
+                }
+            } else {
 #pragma unroll
-            for (int t = 0; t < LM; ++t) y[t] = z[t] + c.half_dt * R[t];
-            run_rhs<T, LM, LIM>(y, R, len, c.nv_ds, src, c.k_off);
+                for (int v = 0; v < VX; ++v) {
+                    T R[LM], y[LM];
+                    run_rhs<T, LM, LIM>(z[v], R, len, c.nv_ds, src[v], c.k_off);
 #pragma unroll
-            for (int t = 0; t < LM; ++t) z[t] = z[t] + c.dt * R[t];
-            T *pout = Mout + (int64_t)r.off * c.nxy + x;
+                    for (int t = 0; t < LM; ++t) y[t] = z[v][t] + c.half_dt * R[t];
+                    run_rhs<T, LM, LIM>(y, R, len, c.nv_ds, src[v], c.k_off);
+#pragma unroll
+                    for (int t = 0; t < LM; ++t) z[v][t] = z[v][t] + c.dt * R[t];
+                }
+            }
+            T *pout = Mout + base + (int64_t)r.off * TT;
 #pragma unroll
             for (int t = 0; t < LM; ++t)
-                if (t < len && act) pout[(int64_t)t * c.nxy] = z[t];
-        }
-        double t0 = 0.0, t1 = 0.0;
+                if (t < len) {
+                    T q[VX];
 #pragma unroll
-        for (int t = 0; t < LM; ++t)
-            if (t < len) {
-                t0 += (double)z[t];
-                t1 += ((double)(lo + t) + 0.5 - c.half_ns) * (double)z[t];
-            }
-        if (act) q0[(int64_t)s * c.nxy + x] = (T)(t0 * c.ds);
-        a0 += t0;
-        a1 += t1;
+                    for (int v = 0; v < VX; ++v) q[v] = z[v][t];
+                    stv<T, VX>(pout + (int64_t)t * TT, q);
+                }
+        }
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+            for (int t = 0; t < LM; ++t)
+                if (t < len) {
+                    t0 += (double)z[v][t];
+                    t1 += ((double)(lo + t) + 0.5 - c.half_ns) * (double)z[v][t];
+                }
+            // run totals by anchor: q0[run][r0], read in anchor order by the coarse kernel
+            if (ok[v]) q0[(int64_t)s * c.nxy + r0v[v]] = (T)(t0 * c.ds);
+            a0[v] += t0;
+            a1[v] += t1;
+        }
     }
-    red[0][w][lane] = a0;
-    red[1][w][lane] = a1;
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        red[0][w][lane * VX + v] = a0[v];
+        red[1][w][lane * VX + v] = a1[v];
+    }
     __syncthreads();
-    if (w == 0 && act) {
-        const double s0 = ((red[0][0][lane] + red[0][1][lane]) + red[0][2][lane]) + red[0][3][lane];
-        const double s1 = ((red[1][0][lane] + red[1][1][lane]) + red[1][2][lane]) + red[1][3][lane];
-        m0[x * c.nth + k] = (T)(s0 * c.ds * c.dA);
-        m1[x * c.nth + k] = (T)(s1 * c.ds2 * c.dA);
+    if (w == 0) {
+#pragma unroll
+        for (int v = 0; v < VX; ++v)
+            if (ok[v]) {
+                const int q = lane * VX + v;
+                const double s0 = ((red[0][0][q] + red[0][1][q]) + red[0][2][q]) + red[0][3][q];
+                const double s1 = ((red[1][0][q] + red[1][1][q]) + red[1][2][q]) + red[1][3][q];
+                m0[(x0 + v) * c.nth + k] = (T)(s0 * c.ds * c.dA);
+                m1[(x0 + v) * c.nth + k] = (T)(s1 * c.ds2 * c.dA);
+            }
     }
 }
 
+// psi [x][th] -> psiT [th][x] (the coarse kernel reads psi at the filament cells of 64 consecutive
+// anchors: consecutive x for one orientation).
 template <typename T>
-__global__ __launch_bounds__(256) void k_r0_coarse(const T *__restrict__ q0, const T *__restrict__ psi,
+__global__ __launch_bounds__(256) void k_r0_psiT(const T *__restrict__ psi, T *__restrict__ psiT, int64_t nxy, int nth) {
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= nxy * nth) return;
+    const int64_t k = o / nxy, x = o - k * nxy;
+    psiT[o] = psi[x * nth + k];
+}
+
+// One lane: VX consecutive anchors; one wave: one row of partials over every nrow-th run.
+template <typename T, int VX>
+__global__ __launch_bounds__(256) void k_r0_coarse(const T *__restrict__ q0, const T *__restrict__ psiT,
                                                    const R0Seg *__restrict__ seg, double *__restrict__ part,
                                                    R0Const<T> c, int nseg, int nrow) {
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t r0 = (int64_t)blockIdx.x * 64 + lane;
-    const bool act = r0 < c.nxy;
-    const int i0 = act ? (int)(r0 / c.ny) : 0;
-    const int j0 = act ? (int)(r0 - (int64_t)i0 * c.ny) : 0;
-    double acc = 0.0;
-    for (int s = row; s < nseg; s += nrow) {
-        const R0Seg r = seg[s];
-        const int k = r.pack >> 20;
-        // the filament cell of this run at anchor r0: x = r0 + (a, b), periodic
-        int i = i0 + r.a, j = j0 + r.b;
-        i += i < 0 ? c.nx : 0;
-        i -= i >= c.nx ? c.nx : 0;
-        j += j < 0 ? c.ny : 0;
-        j -= j >= c.ny ? c.ny : 0;
-        const int64_t x = (int64_t)i * c.ny + j;
-        if (act) acc += (double)q0[(int64_t)s * c.nxy + x] * (double)psi[x * c.nth + k];
+    const int64_t r00 = ((int64_t)blockIdx.x * 64 + lane) * VX;
+    int iv[VX], jv[VX];
+    bool ok[VX];
+    double acc[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        const int64_t r0 = r00 + v;
+        ok[v] = r0 < c.nxy;
+        iv[v] = ok[v] ? (int)(r0 / c.ny) : 0;
+        jv[v] = ok[v] ? (int)(r0 - (int64_t)iv[v] * c.ny) : 0;
+        acc[v] = 0.0;
     }
-    if (act) part[(int64_t)row * c.nxy + r0] = acc;
+    // this wave's runs are row, row + nrow, ...: in groups of four, the next group's records and
+    // run totals are fetched while the current group is added; then the rest one by one.  The
+    // terms are added in run order either way.
+    auto add = [&](const R0Seg &r, const T (&q)[VX]) {
+        const int k = r.pack >> 20;
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            // the filament cell of this run at anchor r0: x = r0 + (a, b), periodic
+            const int64_t x = (int64_t)wrap1(iv[v] + r.a, c.nx) * c.ny + wrap1(jv[v] + r.b, c.ny);
+            if (ok[v]) acc[v] += (double)q[v] * (double)psiT[(int64_t)k * c.nxy + x];
+        }
+    };
+    const int nw = row < nseg ? (nseg - row + nrow - 1) / nrow : 0;
+    const int groups = nw / 4;
+    R0Seg r[4];
+    T q[4][VX];
+    auto fetch = [&](int s0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            r[u] = seg[s0 + u * nrow];
+            if (ok[0]) ldv<T, VX>(q0 + (int64_t)(s0 + u * nrow) * c.nxy + r00, q[u]);  // nxy % VX == 0
+        }
+    };
+    if (groups > 0) fetch(row);
+    for (int g = 0; g < groups; ++g) {
+        R0Seg rc[4];
+        T qc[4][VX];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            rc[u] = r[u];
+#pragma unroll
+            for (int v = 0; v < VX; ++v) qc[u][v] = q[u][v];
+        }
+        if (g + 1 < groups) fetch(row + (g + 1) * 4 * nrow);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add(rc[u], qc[u]);
+    }
+    for (int s = row + groups * 4 * nrow; s < nseg; s += nrow) {
+        const R0Seg r = seg[s];
+        T q[VX];
+        if (ok[0]) ldv<T, VX>(q0 + (int64_t)s * c.nxy + r00, q);
+        add(r, q);
+    }
+#pragma unroll
+    for (int v = 0; v < VX; ++v)
+        if (ok[v]) part[(int64_t)row * c.nxy + r00 + v] = acc[v];
 }
 
 // coarse = w sum of the rows (fixed order); Alg. 2 / Eq. (6): where coarse > m_total the
 // anchor's factor is m_total / coarse and the pool 0, else 1 and m_total - coarse (pool 1 and
 // no factor without depletion).
+// One block: 64 anchors; its four waves add a quarter of the rows each, combined in LDS in a
+// fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_r0_pool(const double *__restrict__ part, int nrow, T *__restrict__ scale,
                                                  T *__restrict__ pool, T *__restrict__ coarse_out,
                                                  T *__restrict__ free_out, int64_t nxy, double w, double m_total,
                                                  double k_on) {
-    const int64_t r0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r0 >= nxy) return;
-    double sum = 0.0;
-    for (int r = 0; r < nrow; ++r) sum += part[(int64_t)r * nxy + r0];
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, qw = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * 64 + lane;
+    const int per = (nrow + 3) / 4, rb = qw * per, re = min(nrow, rb + per);
+    double part_sum = 0.0;
+    if (r0 < nxy)
+        for (int r = rb; r < re; ++r) part_sum += part[(int64_t)r * nxy + r0];
+    red[qw][lane] = part_sum;
+    __syncthreads();
+    if (qw != 0 || r0 >= nxy) return;
+    const double sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
     const double B = sum * w;
     double f = 1.0;
     if (m_total > 0) {
@@ -222,15 +386,56 @@ __global__ __launch_bounds__(256) void k_r0_pool(const double *__restrict__ part
     if (free_out != nullptr) free_out[r0] = (T)f;
 }
 
+// Between the caller's layout Mb[cell][x] and the tiled one M[tile][cell][tt] (to_tiled = 1: the
+// padding of the last tile is set to 0).
+template <typename T>
+__global__ __launch_bounds__(256) void k_r0_layout(const T *__restrict__ src, T *__restrict__ dst, int64_t ncell,
+                                                   int64_t nxy, int tt, int64_t n, int to_tiled) {
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < n; d += (int64_t)gridDim.x * 256) {
+        const int64_t per = ncell * tt, tl = d / per, rem = d - tl * per, cell = rem / tt, xi = rem - cell * tt;
+        const int64_t x = tl * tt + xi;
+        if (to_tiled)
+            dst[d] = x < nxy ? src[cell * nxy + x] : T(0);
+        else if (x < nxy)
+            dst[cell * nxy + x] = src[d];
+    }
+}
+
 // ---- launchers --------------------------------------------------------------------------------
-template <typename T, int LM>
+int r0_vx(size_t esz, int lmax) {
+    if (lmax <= 8) return (int)(16 / esz);
+    if (lmax <= 16) return (int)(8 / esz);
+    return 1;
+}
+
+// Anchors per lane of the coarse kernel (16-byte loads of the run totals when the rows allow).
+static int coarse_vx(int64_t nxy, size_t esz) {
+    const int v = (int)(16 / esz);
+    return nxy % v == 0 ? v : 1;
+}
+
+int r0_coarse_split(int64_t nxy, int nseg, size_t esz) {
+    // about 1024 blocks of 4 waves over the chip, 4 rows of partials per block
+    const int64_t gx = (nxy + 64 * coarse_vx(nxy, esz) - 1) / (64 * coarse_vx(nxy, esz));
+    const int64_t want = (1024 + gx - 1) / std::max<int64_t>(gx, 1);
+    return (int)std::max<int64_t>(1, std::min<int64_t>({want, 64, ((int64_t)nseg + 3) / 4}));
+}
+
+int64_t r0_tiled_elems(int64_t ncell, int64_t nxy, int vx) {
+    const int64_t tt = 64 * (int64_t)vx;
+    return ((nxy + tt - 1) / tt) * ncell * tt;
+}
+
+template <typename T, int LM, int VX>
 static hipError_t motor_lm(const T *Min, T *Mout, T *q0, T *m0, T *m1, const R0Seg *seg, const int32_t *ss,
                            const T *scale, const T *pool, const R0Const<T> &c, int limiter, hipStream_t s) {
-    const dim3 grid((unsigned)((c.nxy + 63) / 64), (unsigned)c.nth);
+    const dim3 grid((unsigned)((c.nxy + 64 * VX - 1) / (64 * VX)), (unsigned)c.nth);
     if (limiter == 0)
-        hipLaunchKernelGGL((k_r0_motor<T, LM, 0>), grid, dim3(256), 0, s, Min, Mout, q0, m0, m1, seg, ss, scale, pool, c);
+        hipLaunchKernelGGL((k_r0_motor<T, LM, 0, VX>), grid, dim3(256), 0, s, Min, Mout, q0, m0, m1, seg, ss, scale,
+                           pool, c);
     else
-        hipLaunchKernelGGL((k_r0_motor<T, LM, 1>), grid, dim3(256), 0, s, Min, Mout, q0, m0, m1, seg, ss, scale, pool, c);
+        hipLaunchKernelGGL((k_r0_motor<T, LM, 1, VX>), grid, dim3(256), 0, s, Min, Mout, q0, m0, m1, seg, ss, scale,
+                           pool, c);
     return hipGetLastError();
 }
 
@@ -238,39 +443,55 @@ template <typename T>
 hipError_t launch_r0_motor(const T *M_in, T *M_out, T *q0, T *m0, T *m1, const R0Seg *seg, const int32_t *seg_start,
                            const T *scale, const T *pool, const R0Const<T> &c, int lmax, int limiter, hipStream_t s) {
     if (c.nxy <= 0 || c.nth <= 0) return hipSuccess;
-    if (lmax <= 8) return motor_lm<T, 8>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
-    if (lmax <= 16) return motor_lm<T, 16>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
-    if (lmax <= kR0MaxRun) return motor_lm<T, 32>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
+    constexpr int V16 = 16 / sizeof(T), V8 = 8 / sizeof(T) > 0 ? 8 / sizeof(T) : 1;
+    if (c.vx != r0_vx(sizeof(T), lmax)) return hipErrorInvalidValue;
+    if (lmax <= 8) return motor_lm<T, 8, V16>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
+    if (lmax <= 16) return motor_lm<T, 16, V8>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
+    if (lmax <= kR0MaxRun) return motor_lm<T, 32, 1>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
     return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_r0_coarse(const T *q0, const T *psi, const R0Seg *seg, double *part, T *scale, T *pool,
+hipError_t launch_r0_coarse(const T *q0, const T *psi, T *psiT, const R0Seg *seg, double *part, T *scale, T *pool,
                             T *coarse_out, T *free_out, const R0Const<T> &c, int nseg, int nsplit, double dth,
                             double m_total, double k_on, hipStream_t s) {
     if (c.nxy <= 0) return hipSuccess;
-    const unsigned gx = (unsigned)((c.nxy + 63) / 64);
-    hipLaunchKernelGGL(k_r0_coarse<T>, dim3(gx, (unsigned)nsplit), dim3(256), 0, s, q0, psi, seg, part, c, nseg,
-                       4 * nsplit);
+    const int64_t np = c.nxy * c.nth;
+    hipLaunchKernelGGL(k_r0_psiT<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, psi, psiT, c.nxy, c.nth);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    constexpr int V = 16 / sizeof(T);
+    if (coarse_vx(c.nxy, sizeof(T)) == V)
+        hipLaunchKernelGGL((k_r0_coarse<T, V>), dim3((unsigned)((c.nxy + 64 * V - 1) / (64 * V)), (unsigned)nsplit),
+                           dim3(256), 0, s, q0, psiT, seg, part, c, nseg, 4 * nsplit);
+    else
+        hipLaunchKernelGGL((k_r0_coarse<T, 1>), dim3((unsigned)((c.nxy + 63) / 64), (unsigned)nsplit), dim3(256), 0, s,
+                           q0, psiT, seg, part, c, nseg, 4 * nsplit);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const double w = c.dA * dth;  // dx dy dth (q0 already carries ds)
-    hipLaunchKernelGGL(k_r0_pool<T>, dim3((unsigned)((c.nxy + 255) / 256)), dim3(256), 0, s, part, 4 * nsplit, scale,
+    hipLaunchKernelGGL(k_r0_pool<T>, dim3((unsigned)((c.nxy + 63) / 64)), dim3(256), 0, s, part, 4 * nsplit, scale,
                        pool, coarse_out, free_out, c.nxy, w, m_total, k_on);
     return hipGetLastError();
 }
 
-template hipError_t launch_r0_motor<float>(const float *, float *, float *, float *, float *, const R0Seg *,
-                                           const int32_t *, const float *, const float *, const R0Const<float> &, int,
-                                           int, hipStream_t);
-template hipError_t launch_r0_motor<double>(const double *, double *, double *, double *, double *, const R0Seg *,
-                                            const int32_t *, const double *, const double *, const R0Const<double> &,
-                                            int, int, hipStream_t);
-template hipError_t launch_r0_coarse<float>(const float *, const float *, const R0Seg *, double *, float *, float *,
-                                            float *, float *, const R0Const<float> &, int, int, double, double, double,
-                                            hipStream_t);
-template hipError_t launch_r0_coarse<double>(const double *, const double *, const R0Seg *, double *, double *,
-                                             double *, double *, double *, const R0Const<double> &, int, int, double,
-                                             double, double, hipStream_t);
+template <typename T>
+hipError_t launch_r0_layout(const T *src, T *dst, int64_t ncell, int64_t nxy, int vx, bool to_tiled, hipStream_t s) {
+    const int64_t n = r0_tiled_elems(ncell, nxy, vx);
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_r0_layout<T>, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, ncell, nxy, 64 * vx, n,
+                       to_tiled ? 1 : 0);
+    return hipGetLastError();
+}
+
+#define MMK_R0_INST(T)                                                                                              \
+    template hipError_t launch_r0_motor<T>(const T *, T *, T *, T *, T *, const R0Seg *, const int32_t *, const T *, \
+                                           const T *, const R0Const<T> &, int, int, hipStream_t);                   \
+    template hipError_t launch_r0_coarse<T>(const T *, const T *, T *, const R0Seg *, double *, T *, T *, T *, T *,  \
+                                            const R0Const<T> &, int, int, double, double, double, hipStream_t);     \
+    template hipError_t launch_r0_layout<T>(const T *, T *, int64_t, int64_t, int, bool, hipStream_t);
+MMK_R0_INST(float)
+MMK_R0_INST(double)
 
 }  // namespace mmk
