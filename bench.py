@@ -422,7 +422,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--fp64-steps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=80)
+    ap.add_argument("--cpu-steps", type=int, default=130)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64", "depletion", "force",
                                        "substeps", "r0", "r0_fp32"],
