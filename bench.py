@@ -487,6 +487,14 @@ def main():
     if args.only in ("all", "fp64"):
         res["fp64"] = run_forward(p, mmk.FP64, args.fp64_steps, min(args.warmup, 20), K,
                                   event_every=args.event_every)
+    if args.only == "all":
+        # the same grid with one motor launch per micro-step (HBM-bound): FP32 and FP64
+        os.environ["MMK_MOTOR_BLOCK"] = "0"
+        try:
+            res["fp32_1"] = run_forward(p, mmk.FP32, args.fp64_steps, 20, K, event_every=args.event_every)
+            res["fp64_1"] = run_forward(p, mmk.FP64, args.fp64_steps, 20, K, event_every=args.event_every)
+        finally:
+            del os.environ["MMK_MOTOR_BLOCK"]
 
     def summarise(r, b):
         """Whole-step rate, and the motor kernel's roofline over its timed launches.  A K-step
@@ -586,6 +594,12 @@ def main():
                        "motor_frac": s64["gbs"] / HBM_PEAK_GBS, "motor_avg_us": s64["avg_us"],
                        "steps": res["fp64"]["steps"]}
         out["fp32_over_fp64"] = s["steps_per_s"] / s64["steps_per_s"]
+    if "fp32_1" in res and "fp64_1" in res:
+        a1, b1 = summarise(res["fp32_1"], 4), summarise(res["fp64_1"], 8)
+        out["one_launch_per_step"] = {
+            "fp32_micro_steps_per_s": a1["steps_per_s"], "fp64_micro_steps_per_s": b1["steps_per_s"],
+            "fp32_motor_frac_hbm": a1["gbs"] / HBM_PEAK_GBS, "fp64_motor_frac_hbm": b1["gbs"] / HBM_PEAK_GBS,
+            "fp32_over_fp64": a1["steps_per_s"] / b1["steps_per_s"]}
     if args.only == "all":
         log("[bench] motor force leg")
         out["force_fp32"] = run_force(p, mmk.FP32, 10)

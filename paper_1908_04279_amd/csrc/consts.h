@@ -39,6 +39,7 @@ inline MotorConst<T> motor_const(const mmk_params &p, double dt) {
     c.ds = (T)ds;
     c.ds2 = (T)(ds * ds);
     c.nth = p.ntheta;
+    c.wide = 0;
     c.nth_shift = -1;
     for (int k = 0; k < 31; ++k)
         if ((1 << k) == p.ntheta) c.nth_shift = k;

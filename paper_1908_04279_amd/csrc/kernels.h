@@ -18,6 +18,8 @@ struct MotorConst {
     T ds, ds2;     // m0 = ds * sum M,  m1 = ds^2 * sum (l + 1/2 - ns/2) M
     int nth;       // columns per (x, y) point, and log2 of it when a power of two (else -1)
     int nth_shift;
+    int wide;      // 1: 32 bytes of the column per lane (launches doing several micro-steps or
+                   // sub-steps of arithmetic per load), 0: 16 bytes (one step per load)
 };
 
 // Forward motor step over `ncol` independent columns of `ns` cells, in registers: c.nstep

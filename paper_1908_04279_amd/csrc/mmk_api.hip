@@ -161,6 +161,10 @@ struct mmk_ctx {
     WalkPlan wp{};
     bool walk = false;
     bool block = false;  // temporal blocking of the linear motor step (MMK_MOTOR_BLOCK=0: off)
+    // the motor tiling of every untaped launch of this context: wide (32 bytes a lane) when the
+    // launches carry several micro-steps or sub-steps per load; fixed per context so that
+    // every launch sums the s-moments in the same order
+    bool wide = false;
     bool have_state = false, have_fluid = false, have_out = false;
     std::string err;
     bool prof = false;
@@ -245,8 +249,9 @@ static mmk_status motor_half(mmk_ctx *c, const T *M_in, T *M_out, T *m0, T *m1, 
     int slot;
     HIPCHK(c, prof_begin_on(c, 0, &slot, s), "hipEventRecord");
     const T *Dxy = p.m_total > 0 ? c->at<T>(c->L.Dxy) : nullptr;
-    HIPCHK(c, launch_motor_step<T>(M_in, M_out, m0, m1, n_psi(p), p.ns, p.limiter, motor_const<T>(p, dt), Dxy, s),
-           "motor step launch");
+    MotorConst<T> mc = motor_const<T>(p, dt);
+    mc.wide = c->wide && !c->tape.active;
+    HIPCHK(c, launch_motor_step<T>(M_in, M_out, m0, m1, n_psi(p), p.ns, p.limiter, mc, Dxy, s), "motor step launch");
     HIPCHK(c, prof_end_on(c, 0, slot, s), "hipEventRecord");
     return MMK_OK;
 }
@@ -332,6 +337,7 @@ static mmk_status run_steps_blocked(mmk_ctx *c, int K, double dt) {
         const bool out = done + nb == K;  // the call's last micro-step, with the outputs
         const int a = c->cur, b = 1 - c->cur;
         MotorConst<T> mc = motor_const<T>(p, dt);
+        mc.wide = c->wide;
         mc.nstep = nb;
         mc.m0_steps = m0s;
         int slot;
@@ -592,6 +598,7 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     c->walk = c->wp.ok && (ew ? atoi(ew) != 0 : c->esz == 4);
     const char *eb = getenv("MMK_MOTOR_BLOCK");
     c->block = p->m_total == 0 && p->rc == 0 && (eb ? atoi(eb) != 0 : true);
+    c->wide = c->block || p->motor_cfl > 0;
     *out = c;
     return MMK_OK;
 }

@@ -19,13 +19,13 @@
 
 namespace mmk {
 
-// R(z) on this lane's CPL cells.  g: lane index inside the column group; l0 = g * CPL.
-// With the face value h_l = z_l + sigma_l / 2 (flux v0 h_l; h_{-1} = 0 carries the zero
-// influx, and the zero last slope makes h_{ns-1} = z_{ns-1}, the first-order outflow):
-//   R_l = -(v0/ds) (h_l - h_{l-1}) + (src - k_off z_l),  src = k_on times the free pool.
+// Face differences dh_l = h_l - h_{l-1} on this lane's CPL cells, with the face value
+// h_l = z_l + sigma_l / 2 (flux v0 h_l; h_{-1} = 0 carries the zero influx, and the zero last
+// slope makes h_{ns-1} = z_{ns-1}, the first-order outflow), so that
+//   R_l = -(v0/ds) dh_l + (src - k_off z_l),  src = k_on times the free pool.
+// g: lane index inside the column group; l0 = g * CPL.
 template <typename T, int CPL, int LPC, int LIM, bool RAGGED>
-__device__ __forceinline__ void motor_rhs(const T (&z)[CPL], T (&R)[CPL], const MotorConst<T> &c, T src,
-                                          int g, int l0, int ns) {
+__device__ __forceinline__ void motor_dh(const T (&z)[CPL], T (&R)[CPL], int g, int l0, int ns) {
     const T zl = from_prev0<LPC>(z[CPL - 1], g);             // z_{l0-1}; ghost 0 at s = 0
     const T zr = from_next<LPC>(z[0], z[CPL - 1], g);        // z_{l0+CPL}; ghost at s = L
     T d[CPL + 1];                                             // d[j] = z_{l0+j} - z_{l0+j-1}
@@ -47,24 +47,17 @@ __device__ __forceinline__ void motor_rhs(const T (&z)[CPL], T (&R)[CPL], const 
     }
     const T hl = from_prev0<LPC>(h[CPL - 1], g);             // h_{-1} = 0: no influx
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-        const T left = (j == 0) ? hl : h[j - 1];
-        R[j] = c.nv_ds * (h[j] - left) + (src - c.k_off * z[j]);
-    }
+    for (int j = 0; j < CPL; ++j) R[j] = h[j] - ((j == 0) ? hl : h[j - 1]);
 }
 
-// Column total of the lane partials (every lane of the group; with PAIR, the q0 total in the
-// lower half of the group and the q1 total in the upper half).  FP32: each partial is a Kahan
-// pair (value = s - c) summed in FP64 across the lanes and rounded once by the caller, as
-// accurate as a TwoSum butterfly and about half its instructions; FP64: plain sums.
-template <int LPC, bool PAIR, typename T>
-__device__ __forceinline__ double column_total(T s0, T c0, T s1, T c1, int g) {
-    if constexpr (std::is_same<T, float>::value) {
-        const double v0 = (double)s0 - (double)c0, v1 = (double)s1 - (double)c1;
-        return group_sum_pair<LPC, false, PAIR, double>(v0, 0.0, v1, 0.0, g);
-    } else {
-        return group_sum_pair<LPC, false, PAIR, double>(s0, c0, s1, c1, g);
-    }
+// Column total of the lane partials, in FP64 (every lane of the group; with PAIR, the m0 total in
+// the lower half of the group and the m1 total in the upper half), rounded once by the caller.
+// The lane partials are FP64 sums of the lane's cells: for FP32 cells these few terms add
+// exactly in FP64 (unless their exponents differ by ~29 binades), more accurate than a Kahan
+// pair and fewer instructions (an FP64 add issues at the FP32 rate on this chip).
+template <int LPC, bool PAIR>
+__device__ __forceinline__ double column_total(double v0, double v1, int g) {
+    return group_sum_pair<LPC, false, PAIR, double>(v0, 0.0, v1, 0.0, g);
 }
 
 template <typename T, int CPL, int LPC, int LIM, bool RAGGED, bool WANT_M1, bool NT>
@@ -111,15 +104,19 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
 
     // One micro-step: c.nsub explicit-midpoint steps of c.dt in registers (sub-cycling:
     // the local dt* of Alg. 2); the first is outside the loop so that one step compiles as
-    // straight code.  x: the state before, y: after.
+    // straight code.  x: the state before, y: after.  The half step
+    //   y = x + (dt/2) R(x) = (1 - (dt/2) k_off) x + (dt/2) src + (dt/2)(-v0/ds) dh
+    // takes its constants folded (two multiply-adds per cell); the full step is
+    //   y = x + dt (-(v0/ds) dh + (src - k_off y)).
+    const T fa = T(1) - c.half_dt * c.k_off, fb = c.half_dt * src, fg = c.half_dt * c.nv_ds;
     T R[CPL], y[CPL];
     auto rk2 = [&]() {
-        motor_rhs<T, CPL, LPC, LIM, RAGGED>(x, R, c, src, g, l0, ns);
+        motor_dh<T, CPL, LPC, LIM, RAGGED>(x, R, g, l0, ns);
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) y[j] = x[j] + c.half_dt * R[j];
-        motor_rhs<T, CPL, LPC, LIM, RAGGED>(y, R, c, src, g, l0, ns);
+        for (int j = 0; j < CPL; ++j) y[j] = fg * R[j] + (fa * x[j] + fb);
+        motor_dh<T, CPL, LPC, LIM, RAGGED>(y, R, g, l0, ns);
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) y[j] = x[j] + c.dt * R[j];
+        for (int j = 0; j < CPL; ++j) y[j] = x[j] + c.dt * (c.nv_ds * R[j] + (src - c.k_off * y[j]));
     };
     auto micro = [&]() {
         rk2();
@@ -129,24 +126,18 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
             rk2();
         }
     };
-    constexpr bool COMP = std::is_same<T, float>::value;
     // Temporal blocking (c.nstep > 1): the column stays in registers for nstep micro-steps;
     // each but the last leaves its m0 for the psi step (the same bits as an unblocked step),
     // and only the last is stored.
     for (int t = 0; t + 1 < c.nstep; ++t) {
         micro();
-        T s0 = T(0), e0 = T(0), s1 = T(0), e1 = T(0);
+        double v0 = 0.0;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
             const T v = (!RAGGED || l0 + j < ns) ? y[j] : T(0);
-            if constexpr (COMP) {
-                if (j == 0) s0 = v;
-                else kahan_add(s0, e0, v);
-            } else {
-                s0 += v;
-            }
+            v0 = (j == 0) ? (double)v : v0 + (double)v;
         }
-        const double tot = column_total<LPC, false>(s0, e0, s1, e1, g);
+        const double tot = column_total<LPC, false>(v0, 0.0, g);
         if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = (T)(tot * (double)c.ds);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) x[j] = y[j];
@@ -162,29 +153,19 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     }
 
     // s-moments of the new column: m0 = ds sum M, m1 = ds^2 sum (l + 1/2 - ns/2) M, the
-    // weights being exact half-integers.  FP32: Kahan inside the lane, FP64 across the lanes
+    // weights being exact half-integers, summed in FP64 in the lane and across the lanes
     // (column_total).  On output steps one paired butterfly serves both: lane 0 of the group
     // ends with m0, lane LPC/2 with m1; m0 has the same bits on every step.
     const T wb = T(0.5) * (T)(2 * l0 + 1 - ns);  // weight of this lane's first cell
-    T a0s = T(0), a0c = T(0), a1s = T(0), a1c = T(0);
+    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
         const bool in = !RAGGED || (l0 + j < ns);
         const T v = in ? y[j] : T(0);
-        if constexpr (COMP) {
-            if (j == 0) {
-                a0s = v;
-                if constexpr (WANT_M1) a1s = v * wb;
-            } else {
-                kahan_add(a0s, a0c, v);
-                if constexpr (WANT_M1) kahan_add(a1s, a1c, v * (wb + T(j)));
-            }
-        } else {
-            a0s += v;
-            if constexpr (WANT_M1) a1s += v * (wb + T(j));
-        }
+        a0 = (j == 0) ? (double)v : a0 + (double)v;
+        if constexpr (WANT_M1) a1 = (j == 0) ? (double)v * (double)wb : a1 + (double)v * (double)(wb + T(j));
     }
-    const double tot = column_total<LPC, WANT_M1>(a0s, a0c, a1s, a1c, g);
+    const double tot = column_total<LPC, WANT_M1>(a0, a1, g);
     if (active && g == 0) m0[col] = (T)(tot * (double)c.ds);
     if constexpr (WANT_M1)
         if (active && g == LPC / 2) m1[col] = (T)(tot * (double)c.ds2);
@@ -416,12 +397,16 @@ static hipError_t launch_cfg(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
 
 // Lanes per column for the exact tilings (0: use the masked generic kernel).  Default: 16
 // bytes of the column per lane (4 FP32 or 2 FP64 cells), so every vector load and store of a
-// wave covers one contiguous span.  MMK_MOTOR_LPC overrides (measurements).
-static int lanes_per_column(int ns, int elem) {
+// wave covers one contiguous span.  Wide launches (several micro-steps or sub-steps per load,
+// where the arithmetic bounds the launch) take 32 bytes per lane: fewer neighbour exchanges
+// and a shorter s-reduction per cell (measured at 64 cells: FP32 +11%, FP64 +29%; one step per
+// load is faster with 16).  MMK_MOTOR_LPC overrides (measurements).
+static int lanes_per_column(int ns, int elem, bool wide) {
     const int cpl = 16 / elem;
     if (ns < 2 * cpl || ns % cpl != 0) return 0;
     int lpc = ns / cpl;
     if (lpc > 64 || (lpc & (lpc - 1)) != 0) return 0;
+    if (wide && lpc >= 4) lpc /= 2;
     if (const char *e = getenv("MMK_MOTOR_LPC")) {
         const int want = atoi(e);
         if (want >= 2 && want <= 64 && (want & (want - 1)) == 0 && ns % want == 0) {
@@ -458,18 +443,18 @@ hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
         MMK_CHUNK_CASE(4, 2) MMK_CHUNK_CASE(2, 2)
 #undef MMK_CHUNK_CASE
     }
-    const int lpc = lanes_per_column(ns, (int)sizeof(T));
+    const int lpc = lanes_per_column(ns, (int)sizeof(T), c.wide != 0);
 #define MMK_MOTOR_CASE(NS, LPC)                                                                   \
     if (ns == NS && lpc == LPC)                                                                   \
         return launch_cfg<T, NS / LPC, LPC, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Dxy, s);
     if constexpr (sizeof(T) == 4) {
-        MMK_MOTOR_CASE(8, 2) MMK_MOTOR_CASE(16, 4) MMK_MOTOR_CASE(32, 8) MMK_MOTOR_CASE(64, 16)
-        MMK_MOTOR_CASE(64, 8) MMK_MOTOR_CASE(128, 32) MMK_MOTOR_CASE(128, 16) MMK_MOTOR_CASE(256, 64)
-        MMK_MOTOR_CASE(256, 32)
+        MMK_MOTOR_CASE(8, 2) MMK_MOTOR_CASE(16, 4) MMK_MOTOR_CASE(16, 2) MMK_MOTOR_CASE(32, 8)
+        MMK_MOTOR_CASE(32, 4) MMK_MOTOR_CASE(64, 16) MMK_MOTOR_CASE(64, 8) MMK_MOTOR_CASE(128, 32)
+        MMK_MOTOR_CASE(128, 16) MMK_MOTOR_CASE(256, 64) MMK_MOTOR_CASE(256, 32)
     } else {
-        MMK_MOTOR_CASE(4, 2) MMK_MOTOR_CASE(8, 4) MMK_MOTOR_CASE(16, 8) MMK_MOTOR_CASE(32, 16)
-        MMK_MOTOR_CASE(64, 32) MMK_MOTOR_CASE(64, 16) MMK_MOTOR_CASE(128, 64) MMK_MOTOR_CASE(128, 32)
-        MMK_MOTOR_CASE(256, 64)
+        MMK_MOTOR_CASE(4, 2) MMK_MOTOR_CASE(8, 4) MMK_MOTOR_CASE(8, 2) MMK_MOTOR_CASE(16, 8)
+        MMK_MOTOR_CASE(16, 4) MMK_MOTOR_CASE(32, 16) MMK_MOTOR_CASE(32, 8) MMK_MOTOR_CASE(64, 32)
+        MMK_MOTOR_CASE(64, 16) MMK_MOTOR_CASE(128, 64) MMK_MOTOR_CASE(128, 32) MMK_MOTOR_CASE(256, 64)
     }
 #undef MMK_MOTOR_CASE
     // any other length: 16 lanes per column, masked tail cells, scalar loads

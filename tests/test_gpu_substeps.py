@@ -120,12 +120,18 @@ def test_refusals():
 def test_temporal_blocking_is_bitwise_serial(monkeypatch, shape, precision, calls, nch):
     """A run of several mmk_step calls gives the same bits with the motor field blocked over
     up to 16 micro-steps per launch (default for m_total = 0) and with one launch per
-    micro-step (MMK_MOTOR_BLOCK=0); also with sub-cycling inside the blocks."""
+    micro-step (MMK_MOTOR_BLOCK=0); also with sub-cycling inside the blocks.  Both runs use
+    the blocked runs' column tiling (32 bytes a lane; a one-launch-per-step context would
+    otherwise take 16, which sums the s-moments in another order)."""
     import torch
     from paper_1908_04279_amd import mmk
+    nx, ny, nt, ns = shape
     if nch:
         monkeypatch.setenv("MMK_MOTOR_NCH", nch)
-    nx, ny, nt, ns = shape
+    else:
+        cpl = 32 // (4 if precision else 8)
+        if ns % cpl == 0:
+            monkeypatch.setenv("MMK_MOTOR_LPC", str(ns // cpl))
     for cfl in (0.0, 0.15):
         p = ModelParams(nx=nx, ny=ny, ntheta=nt, ns=ns, motor_cfl=cfl)
         psi0 = gen.make_psi0(nx, ny, nt, p.lx, p.ly, seed=0)
