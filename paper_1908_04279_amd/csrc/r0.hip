@@ -28,13 +28,12 @@ namespace mmk {
 // The motor point of cell (a, b, k, l) relative to its anchor is (a dx, b dy) + t p_k with
 // t = s_l - L/2; the cell is tracked when the squared length is at most rc^2 (evaluated in FP64
 // in this order, without contraction, so that the decision is the one the model's definition
-// gives in FP64).
-static bool tracked(double dx, double dy, double dth, double ds, double L, double rc, int a, int b, int k, int l) {
+// gives in FP64).  co, si: cos and sin of k dth.
+static bool tracked(double dx, double dy, double co, double si, double ds, double L, double rc, int a, int b, int l) {
 #pragma clang fp contract(off)
     const double t = (l + 0.5) * ds - 0.5 * L;
-    const double th = k * dth;
-    const double hx = a * dx + t * std::cos(th);
-    const double hy = b * dy + t * std::sin(th);
+    const double hx = a * dx + t * co;
+    const double hy = b * dy + t * si;
     return hx * hx + hy * hy <= rc * rc;
 }
 
@@ -42,17 +41,28 @@ R0Plan plan_r0(int nx, int ny, int nth, int ns, double lx, double ly, double L, 
     R0Plan P;
     if (!(rc > 0) || !(rc + 0.5 * L < 0.5 * lx) || !(rc + 0.5 * L < 0.5 * ly)) return P;
     const double dx = lx / nx, dy = ly / ny, dth = 6.283185307179586476925286766559 / nth, ds = L / ns;
+    std::vector<double> co(nth), si(nth);
+    for (int k = 0; k < nth; ++k) {
+        co[k] = std::cos(k * dth);
+        si[k] = std::sin(k * dth);
+    }
     // every tracked motor point lies within rc + L/2 of its anchor
-    const int A = (int)std::ceil((rc + 0.5 * L) / dx) + 1;
-    const int B = (int)std::ceil((rc + 0.5 * L) / dy) + 1;
+    const double reach = rc + 0.5 * L;
+    const int A = (int)std::ceil(reach / dx) + 1;
+    const int B = (int)std::ceil(reach / dy) + 1;
     for (int a = -A; a <= A; ++a)
-        for (int b = -B; b <= B; ++b)
+        for (int b = -B; b <= B; ++b) {
+            // offsets whose filament centre is farther than rc + L/2 (with a cell of margin)
+            // from the anchor hold no tracked cell
+            const double ca = std::fabs(a * dx) - dx, cb = std::fabs(b * dy) - dy;
+            if (ca > 0 && cb > 0 && ca * ca + cb * cb > reach * reach) continue;
             for (int k = 0; k < nth; ++k)
                 for (int l = 0; l < ns; ++l)
-                    if (tracked(dx, dy, dth, ds, L, rc, a, b, k, l)) {
+                    if (tracked(dx, dy, co[k], si[k], ds, L, rc, a, b, l)) {
                         P.cells.insert(P.cells.end(), {a, b, k, l});
                         ++P.ncell;
                     }
+        }
     P.ok = true;
     if (cells_only) return P;
     std::vector<std::vector<R0Seg>> byk(nth);
