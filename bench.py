@@ -324,15 +324,22 @@ def run_r0(precision, steps, warmup, K, event_every):
     el = time.perf_counter() - t0
     prof = {name: ctx.profile_read(name) for name in ("r0_motor_step", "r0_coarse", "psi_step")}
     ctx.profile(False)
+    # the motor force of the state (anchor-marginal field + spreading), 10 calls
+    ctx.get_force()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(10):
+        ctx.get_force()
+    ms_f, n_f = ctx.profile_read("motor_force")
+    ctx.profile(False)
     co, _ = ctx.get_anchors()
     clamped = float((co > p.m_total).float().mean())
     mass, _ = ctx.get_sums()
     ctx.close()
     b = 4 if precision == mmk.FP32 else 8
-    # the library's coarse split: about 1024 blocks of 64 lanes, 16 bytes of run totals per lane
-    vc = (16 // b) if (p.nx * p.ny) % (16 // b) == 0 else 1
-    gx = -(-(p.nx * p.ny) // (64 * vc))
-    nsplit = max(1, min(-(-1024 // gx), 64, -(-nrun // 4)))
+    # the library's coarse split: about 4096 blocks of 64 lanes, one anchor per lane
+    gx = -(-(p.nx * p.ny) // 64)
+    nsplit = max(1, min(-(-4096 // gx), 64, -(-nrun // 4)))
     mb = r0_motor_bytes(p, b, ncell, nrun, True)
     cb = r0_coarse_bytes(p, b, nrun, nsplit)
     ms_m, n_m = prof["r0_motor_step"]
@@ -350,7 +357,8 @@ def run_r0(precision, steps, warmup, K, event_every):
             "motor_alu_frac": flops / (us_m * 1e-6) / 1e12 / alu_peak,
             "motor_traffic": r0_counters_traffic() if b == 4 else None,
             "coarse_avg_us": us_c, "coarse_algorithmic_bytes": cb, "coarse_gbs": cb / (us_c * 1e-6) / 1e9,
-            "psi_avg_us": us_p, "clamped_anchor_fraction_start": clamped0, "clamped_anchor_fraction_end": clamped,
+            "psi_avg_us": us_p, "force_avg_us": ms_f / n_f * 1e3,
+            "clamped_anchor_fraction_start": clamped0, "clamped_anchor_fraction_end": clamped,
             "mass": mass, "timed_launches": [n_m, n_c, n_p]}
 
 

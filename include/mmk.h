@@ -99,8 +99,9 @@ typedef struct {
                             * are scaled by m_total / coarse and the pool is 0).  Psi is driven by,
                             * and m0 / m1 / the moments report, the anchor marginals
                             * m0(x, th) = sum over anchors and s of M_b ds dx dy (m1 with the lever
-                            * arm s - L/2).  Runs longer than 32 cells, motor_cfl > 0, the tape and
-                            * mmk_get_force give MMK_ERR_UNSUPPORTED.  Three launches per
+                            * arm s - L/2); mmk_get_force spreads the anchor-marginal field
+                            * sum over anchors of M_b dx dy.  Runs longer than 32 cells,
+                            * motor_cfl > 0 and the tape give MMK_ERR_UNSUPPORTED.  Three launches per
                             * micro-step with m_total > 0 (coarse + pool, motor, psi), two with
                             * m_total = 0. */
 } mmk_params;
@@ -152,6 +153,9 @@ mmk_status mmk_get_moments(mmk_ctx *ctx, void *moments);
 mmk_status mmk_get_motor_moments(mmk_ctx *ctx, void *m0, void *m1);
 /* Motor force density of the current state (Eq. (10)), force [2][nx][ny] = (f_x, f_y): every
  * bound-motor cell l of a filament at (x_i, y_j) with orientation p_k adds F p_k psi M_l ds dth
+ * (with rc > 0, M is the anchor marginal sum over anchors of M_b dx dy, the r0 integral of
+ * Eq. (10), formed first; its kernel needs ns * 65 * sizeof(value) <= 160 KB of LDS, else
+ * MMK_ERR_UNSUPPORTED)
  * at its head (x_i, y_j) + (s_l - L/2) p_k, spread onto the cell centres with the two-point
  * hat (bilinear) in x and y, periodic.  The filament length L is in the units of lx, ly.
  * Same bits on every run (each spreading window is private to one wave and summed in a fixed

@@ -114,6 +114,11 @@ void oracle_r0_motor_step(const oracle_params *p, double dt, const int *cells, l
 void oracle_r0_marginal(const oracle_params *p, const int *cells, long ncell, const double *Mb,
                         double *m0, double *m1);
 
+/* the anchor-marginal bound motors M[x][k][l] = sum over anchors of M_b dx dy (the r0 integral
+ * of Eq. (10)); the motor force of the anchor-resolved state is oracle_motor_force of (psi, M) */
+void oracle_r0_marginal_field(const oracle_params *p, const int *cells, long ncell, const double *Mb,
+                              double *M);
+
 /* nsteps micro-steps of the anchor-resolved model; psi and Mb in place.  Each micro-step: with
  * m_total > 0, the coarse density of the current state, the clamp and the free pool of
  * oracle_depletion per anchor; the motor step; psi driven by the marginal m0.  m0, m1, coarse

@@ -60,6 +60,7 @@ def lib():
         L.oracle_r0_coarse.argtypes = [P, _ip, C.c_long, _dp, _dp, _dp]
         L.oracle_r0_motor_step.argtypes = [P, C.c_double, _ip, C.c_long, _dp, _dp, C.c_void_p, C.c_void_p]
         L.oracle_r0_marginal.argtypes = [P, _ip, C.c_long, _dp, C.c_void_p, C.c_void_p]
+        L.oracle_r0_marginal_field.argtypes = [P, _ip, C.c_long, _dp, _dp]
         L.oracle_r0_run.argtypes = [P, C.c_double, C.c_int, _ip, C.c_long, _dp, _dp, _dp, _dp,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_max_threads.restype = C.c_int
@@ -227,6 +228,18 @@ def r0_marginal(p, cells, Mb):
     m1 = np.empty((p.nx, p.ny, p.ntheta))
     lib().oracle_r0_marginal(C.byref(cparams(p)), cells, len(cells), _f64(Mb), _ptr(m0), _ptr(m1))
     return m0, m1
+
+
+def r0_marginal_field(p, cells, Mb):
+    """Anchor-marginal bound motors M [nx][ny][nth][ns] = sum over anchors of M_b dx dy."""
+    M = np.empty((p.nx, p.ny, p.ntheta, p.ns))
+    lib().oracle_r0_marginal_field(C.byref(cparams(p)), cells, len(cells), _f64(Mb), M)
+    return M
+
+
+def r0_motor_force(p, cells, psi, Mb):
+    """Motor force density [2][nx][ny] of an anchor-resolved state (Eq. (10) with its r0 integral)."""
+    return motor_force(p, psi, r0_marginal_field(p, cells, Mb))
 
 
 class OracleR0:

@@ -126,6 +126,18 @@ void oracle_r0_marginal(const oracle_params *p, const int *cells, long ncell, co
     }
 }
 
+void oracle_r0_marginal_field(const oracle_params *p, const int *cells, long ncell, const double *Mb,
+                              double *M) {
+    const long nx = p->nx, ny = p->ny, nth = p->nth, ns = p->ns, nxy = nx * ny;
+    const double dx = p->lx / nx, dy = p->ly / ny;
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < nxy; ++x) {
+        for (long q = 0; q < nth * ns; ++q) M[x * nth * ns + q] = 0.0;
+        for (long c = 0; c < ncell; ++c)
+            M[(x * nth + cells[4 * c + 2]) * ns + cells[4 * c + 3]] += Mb[c * nxy + x] * dx * dy;
+    }
+}
+
 void oracle_r0_run(const oracle_params *p, double dt, int nsteps, const int *cells, long ncell,
                    double *psi, double *Mb, const double *u, const double *gradu, double *m0_out,
                    double *m1_out, double *coarse_out) {

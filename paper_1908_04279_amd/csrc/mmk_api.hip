@@ -34,7 +34,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t M[2], psi[2], psi_tmp, m0, m0s, m1, Dxy, fpart, fblk, fexy, fcs, u, G, stress, mom, tab, partials, sums;
-    size_t q0, r0part, r0scale, r0pool, r0seg, r0start, psiT;  // anchor-resolved model (rc > 0)
+    size_t q0, r0part, r0scale, r0pool, r0seg, r0start, psiT, Mmarg;  // anchor-resolved model (rc > 0)
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -114,7 +114,7 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     L.psi_tmp = (p.m_total > 0 || r0) ? 0 : take(np * e);
     L.m1 = take(np * e);
     L.Dxy = r0 ? 0 : take(2 * nxy * e);
-    if (!r0) {
+    {
         // motor force: partial windows and the spreading records per (pass, cell)
         const ForcePlan fpl = plan_force(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, e);
         const size_t nblk = (size_t)fpl.npass * ((p.ns + fpl.chunk - 1) / fpl.chunk);
@@ -122,7 +122,10 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
         L.fblk = take(nblk * kForceBlock * sizeof(uint32_t));
         L.fexy = take(2 * (size_t)fpl.npass * sizeof(int));
         L.fcs = take(2 * (size_t)fpl.npass * sizeof(double));
-    } else {
+    }
+    if (r0) {
+        // the anchor-marginal field that the motor force spreads
+        L.Mmarg = take((size_t)n_m(p) * e);
         // run totals, coarse partial rows, per-anchor clamp factor and pool, run table
         L.q0 = take((size_t)rp.nseg * nxy * e);
         L.r0part = take((size_t)4 * r0_coarse_split((int64_t)nxy, rp.nseg, e) * nxy * sizeof(double));
@@ -567,7 +570,7 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     // spreading records of the motor force (needed only by mmk_get_force; anchor-marginal model)
     c->fplan = plan_force(p->nx, p->ny, nth, p->ns, p->lx, p->ly, p->L, c->esz);
     ForceRecords &fr = c->frec;
-    c->frec_ok = p->rc == 0 && force_records(nth, p->ns, p->lx, p->ly, p->L, p->nx, p->ny, c->fplan, &fr);
+    c->frec_ok = force_records(nth, p->ns, p->lx, p->ly, p->L, p->nx, p->ny, c->fplan, &fr);
     if (p->rc > 0) {  // tracked cells and runs of the anchor-resolved model
         c->r0 = r0_plan_of(*p);
         c->r0.nsplit = r0_coarse_split((int64_t)p->nx * p->ny, c->r0.nseg, c->esz);
@@ -745,23 +748,36 @@ mmk_status mmk_get_force(mmk_ctx *c, void *force) {
     if (!c) return MMK_ERR_ARG;
     if (!force) return fail(c, MMK_ERR_ARG, "force is NULL");
     if (!c->have_state) return fail(c, MMK_ERR_STATE, "mmk_get_force before mmk_set_state");
-    if (c->p.rc > 0) return fail(c, MMK_ERR_UNSUPPORTED, "the motor force covers the anchor-marginal model (rc = 0)");
     const mmk_params &p = c->p;
     const ForcePlan &fp = c->fplan;
     if (!c->frec_ok || fp.nt == 0)
         return fail(c, MMK_ERR_UNSUPPORTED, "spreading window of %d x %d cells is too large", fp.wx, fp.wy);
+    if (p.rc > 0 && r0_field_lds(p.ns, c->esz) > 160 * 1024)
+        return fail(c, MMK_ERR_UNSUPPORTED, "ns too large for the anchor-marginal field kernel at this precision");
     int slot;
     HIPCHK(c, prof_begin(c, 5, &slot), "hipEventRecord");
     hipError_t e;
+    // the anchor-resolved model spreads its anchor marginal (the r0 integral of Eq. (10))
+    const size_t Msrc = p.rc > 0 ? c->L.Mmarg : c->L.M[c->cur];
+    if (p.rc > 0) {
+        if (c->esz == 4)
+            e = launch_r0_field<float>(c->at<float>(c->L.M[c->cur]), c->at<float>(c->L.Mmarg), c->at<R0Seg>(c->L.r0seg),
+                                       c->at<int32_t>(c->L.r0start), r0_cst<float>(c, 0.0, 0), p.ns, c->stream);
+        else
+            e = launch_r0_field<double>(c->at<double>(c->L.M[c->cur]), c->at<double>(c->L.Mmarg),
+                                        c->at<R0Seg>(c->L.r0seg), c->at<int32_t>(c->L.r0start),
+                                        r0_cst<double>(c, 0.0, 0), p.ns, c->stream);
+        HIPCHK(c, e, "anchor-marginal field launch");
+    }
     const uint32_t *blk = c->at<uint32_t>(c->L.fblk);
     const int *exy = c->at<int>(c->L.fexy);
     const double *cs = c->at<double>(c->L.fcs);
     if (c->esz == 4)
-        e = launch_motor_force<float>(c->at<float>(c->L.M[c->cur]), c->at<float>(c->L.psi[c->cur]), blk, exy, cs,
+        e = launch_motor_force<float>(c->at<float>(Msrc), c->at<float>(c->L.psi[c->cur]), blk, exy, cs,
                                       c->at<double>(c->L.fpart), (float *)force, p.nx, p.ny, p.ntheta, p.ns, p.F,
                                       p.L, fp, c->stream);
     else
-        e = launch_motor_force<double>(c->at<double>(c->L.M[c->cur]), c->at<double>(c->L.psi[c->cur]), blk, exy, cs,
+        e = launch_motor_force<double>(c->at<double>(Msrc), c->at<double>(c->L.psi[c->cur]), blk, exy, cs,
                                        c->at<double>(c->L.fpart), (double *)force, p.nx, p.ny, p.ntheta, p.ns, p.F,
                                        p.L, fp, c->stream);
     if (e == hipErrorInvalidValue)

@@ -69,6 +69,13 @@ hipError_t launch_r0_coarse(const T *q0, const T *psi, T *psiT, const R0Seg *seg
                             T *coarse_out, T *free_out, const R0Const<T> &c, int nseg, int nsplit, double dth,
                             double m_total, double k_on, hipStream_t s);
 
+// The anchor-marginal field M[nx][ny][nth][ns] = dx dy sum over anchors of M_b (tiled Mb), the
+// input of the motor force; LDS bytes per block r0_field_lds (hipErrorInvalidValue above 160 KB).
+size_t r0_field_lds(int ns, size_t esz);
+template <typename T>
+hipError_t launch_r0_field(const T *Mb, T *M, const R0Seg *seg, const int32_t *seg_start, const R0Const<T> &c, int ns,
+                           hipStream_t s);
+
 // Caller layout Mb[cell][nx][ny] -> tiled (to_tiled), or back.
 template <typename T>
 hipError_t launch_r0_layout(const T *src, T *dst, int64_t ncell, int64_t nxy, int vx, bool to_tiled, hipStream_t s);

@@ -412,6 +412,38 @@ __global__ __launch_bounds__(256) void k_r0_layout(const T *__restrict__ src, T 
     }
 }
 
+// The anchor-marginal field M[x][k][l] = dx dy sum over anchors of M_b (the r0 integral of
+// Eq. (10)), which the motor force spreads.  One wave per block: 64 filament cells and one
+// orientation; each lane adds its runs' cells into its own LDS column acc[l][lane] in run order
+// (deterministic, no atomics), then the wave writes the block's (x, k) rows of ns contiguous
+// values.  acc rows are padded to 65 so that the row-wise reads spread over the banks.
+template <typename T>
+__global__ __launch_bounds__(64) void k_r0_field(const T *__restrict__ Mb, T *__restrict__ M,
+                                                 const R0Seg *__restrict__ seg, const int32_t *__restrict__ seg_start,
+                                                 R0Const<T> c, int ns, int tt) {
+    extern __shared__ unsigned char smem_raw[];
+    T *acc = reinterpret_cast<T *>(smem_raw);  // [ns][65]
+    const int lane = threadIdx.x, k = blockIdx.y;
+    const int64_t x = (int64_t)blockIdx.x * 64 + lane;
+    const bool ok = x < c.nxy;
+    for (int l = 0; l < ns; ++l) acc[l * 65 + lane] = T(0);
+    const int64_t base = ok ? (x / tt) * c.ncell * tt + (x % tt) : 0;
+    const int s_end = seg_start[k + 1];
+    for (int s = seg_start[k]; s < s_end; ++s) {
+        const R0Seg r = seg[s];
+        const int lo = r.pack & 1023, len = (r.pack >> 10) & 1023;
+        if (ok)
+            for (int t = 0; t < len; ++t) acc[(lo + t) * 65 + lane] += Mb[base + (int64_t)(r.off + t) * tt];
+    }
+    __syncthreads();
+    const T dA = (T)c.dA;
+    for (int q = 0; q < 64; ++q) {
+        const int64_t x2 = (int64_t)blockIdx.x * 64 + q;
+        if (x2 >= c.nxy) break;
+        for (int l = lane; l < ns; l += 64) M[(x2 * c.nth + k) * ns + l] = acc[l * 65 + q] * dA;
+    }
+}
+
 // ---- launchers --------------------------------------------------------------------------------
 int r0_vx(size_t esz, int lmax) {
     // runs of at most 8 cells: 2 filament cells a lane (8 bytes in FP32, 16 in FP64; measured
@@ -427,16 +459,25 @@ int r0_vx(size_t esz, int lmax) {
     return v;
 }
 
-// Anchors per lane of the coarse kernel (16-byte loads of the run totals when the rows allow).
+// Anchors per lane of the coarse kernel: one (measured at the benchmark workload: 98.6 us per
+// coarse pass in FP32 against 109 with 16-byte loads of the run totals, 138 against 141 in
+// FP64); MMK_R0_CVX = 16 / sizeof(value) takes the 16-byte loads where the rows allow
+// (measurements).
 static int coarse_vx(int64_t nxy, size_t esz) {
     const int v = (int)(16 / esz);
-    return nxy % v == 0 ? v : 1;
+    if (const char *e = getenv("MMK_R0_CVX"))
+        if (atoi(e) == v && nxy % v == 0) return v;
+    return 1;
 }
 
 int r0_coarse_split(int64_t nxy, int nseg, size_t esz) {
-    // about 1024 blocks of 4 waves over the chip, 4 rows of partials per block
+    // about 4096 blocks of 4 waves over the chip (MMK_R0_CBLOCKS overrides, for measurements),
+    // 4 rows of partials per block
+    int64_t target = 4096;
+    if (const char *e = getenv("MMK_R0_CBLOCKS"))
+        if (atoi(e) >= 64) target = atoi(e);
     const int64_t gx = (nxy + 64 * coarse_vx(nxy, esz) - 1) / (64 * coarse_vx(nxy, esz));
-    const int64_t want = (1024 + gx - 1) / std::max<int64_t>(gx, 1);
+    const int64_t want = (target + gx - 1) / std::max<int64_t>(gx, 1);
     return (int)std::max<int64_t>(1, std::min<int64_t>({want, 64, ((int64_t)nseg + 3) / 4}));
 }
 
@@ -506,12 +547,27 @@ hipError_t launch_r0_layout(const T *src, T *dst, int64_t ncell, int64_t nxy, in
     return hipGetLastError();
 }
 
+size_t r0_field_lds(int ns, size_t esz) { return (size_t)ns * 65 * esz; }
+
+template <typename T>
+hipError_t launch_r0_field(const T *Mb, T *M, const R0Seg *seg, const int32_t *seg_start, const R0Const<T> &c, int ns,
+                           hipStream_t s) {
+    if (c.nxy <= 0 || c.nth <= 0) return hipSuccess;
+    const size_t lds = r0_field_lds(ns, sizeof(T));
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((c.nxy + 63) / 64), (unsigned)c.nth);
+    hipLaunchKernelGGL(k_r0_field<T>, grid, dim3(64), lds, s, Mb, M, seg, seg_start, c, ns, 64 * c.vx);
+    return hipGetLastError();
+}
+
 #define MMK_R0_INST(T)                                                                                              \
     template hipError_t launch_r0_motor<T>(const T *, T *, T *, T *, T *, const R0Seg *, const int32_t *, const T *, \
                                            const T *, const R0Const<T> &, int, int, hipStream_t);                   \
     template hipError_t launch_r0_coarse<T>(const T *, const T *, T *, const R0Seg *, double *, T *, T *, T *, T *,  \
                                             const R0Const<T> &, int, int, double, double, double, hipStream_t);     \
-    template hipError_t launch_r0_layout<T>(const T *, T *, int64_t, int64_t, int, bool, hipStream_t);
+    template hipError_t launch_r0_layout<T>(const T *, T *, int64_t, int64_t, int, bool, hipStream_t);            \
+    template hipError_t launch_r0_field<T>(const T *, T *, const R0Seg *, const int32_t *, const R0Const<T> &, int, \
+                                           hipStream_t);
 MMK_R0_INST(float)
 MMK_R0_INST(double)
 

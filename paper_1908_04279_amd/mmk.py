@@ -228,7 +228,8 @@ class Context:
     def get_force(self):
         """Motor force density F2 [2][nx][ny] = (f_x, f_y) of the current state (Eq. (10)):
         F p psi M ds dth of every bound-motor cell spread from its head, (x_i, y_j) +
-        (s_l - L/2) p, onto the four surrounding cell centres (bilinear hat, periodic)."""
+        (s_l - L/2) p, onto the four surrounding cell centres (bilinear hat, periodic).  With
+        rc > 0, M is the anchor marginal of M_b (the r0 integral of Eq. (10))."""
         f = self.empty((2, self.p.nx, self.p.ny))
         self._check(lib().mmk_get_force(self.h, _ptr(f)))
         return f

@@ -1,8 +1,9 @@
 """Anchor-resolved bound motors on the GPU (capture ball of radius rc; Eqs. (4)-(6); Alg. 2) against
 the FP64 oracle: every run-register size of the motor kernel (8, 16, 32 cells), ragged grids, both
 limiters, linear attachment and depletion with the clamp active, a zero start and an empty tracked
-set, at FP64 1e-12 and FP32 1e-5 (norm-wise relative per field); the per-anchor outputs; the
-refusals; repeatable bits; and a sampled check at the benchmark's size and launch configuration."""
+set, at FP64 1e-12 and FP32 1e-5 (norm-wise relative per field); the per-anchor outputs; the motor
+force of the anchor-resolved state (Eq. (10) with its r0 integral); the refusals; repeatable bits;
+and a sampled check at the benchmark's size and launch configuration."""
 import numpy as np
 import pytest
 
@@ -123,9 +124,6 @@ def test_refusals():
     assert ei.value.status == mmk.MMK_ERR_STATE
     ctx.set_state(torch.as_tensor(gen.make_psi0(8, 8, 4, seed=0)))
     with pytest.raises(mmk.MMKError) as ei:
-        ctx.get_force()
-    assert ei.value.status == mmk.MMK_ERR_UNSUPPORTED
-    with pytest.raises(mmk.MMKError) as ei:
         ctx.tape_begin(2)
     assert ei.value.status == mmk.MMK_ERR_UNSUPPORTED
     ctx.close()
@@ -205,3 +203,33 @@ def test_full_size_sampled():
         want = float(np.sum(Mb1[sel, i, j].astype(np.float64))) * ds * dx * dy
         assert abs(m0[i, j, kk] - want) <= 1e-5 * abs(want)
     assert abs(mass1 - 1.0) <= 1e-5
+
+
+@pytest.mark.parametrize("kw,precision", [
+    (dict(nx=20, ny=18, ntheta=16, ns=16, rc=0.35), 0),
+    (dict(nx=9, ny=7, ntheta=12, ns=10, rc=0.6, lx=5.0, ly=6.0, limiter=1), 0),
+    (dict(nx=32, ny=32, ntheta=32, ns=32, rc=0.3), 1),
+])
+def test_force_against_oracle(kw, precision):
+    """get_force of an anchor-resolved state after a few depleted steps: the force of its anchor
+    marginal (oracle: the marginal field, then the oracle's force), twice with the same bits."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(**kw)
+    cells, psi0, Mb0, fl, dt = r0_case(p, True)
+    if precision:
+        psi0, Mb0 = psi0.astype(np.float32), Mb0.astype(np.float32)
+    ctx = mmk.Context(p, precision=precision)
+    ctx.set_state(torch.as_tensor(psi0), torch.as_tensor(Mb0))
+    ctx.set_fluid(*map(torch.as_tensor, fl[0]))
+    ctx.step(4, dt)
+    psi, Mb = ctx.get_state()
+    f1 = ctx.get_force().double().cpu().numpy()
+    f2 = ctx.get_force().double().cpu().numpy()
+    torch.cuda.synchronize()
+    ctx.close()
+    assert np.array_equal(f1, f2)
+    want = A.r0_motor_force(p, cells, psi.double().cpu().numpy(), Mb.double().cpu().numpy())
+    err = rel_err(f1, want)
+    print(f"force rel err {err:.2e}", flush=True)
+    assert err <= (1e-5 if precision else 1e-12)

@@ -266,3 +266,31 @@ def test_clamp_brings_the_anchor_to_its_total():
     o.step(1, dt)
     g = 1 - p.k_off * dt + 0.5 * (p.k_off * dt) ** 2
     assert np.max(np.abs(o.Mb - clamped * g)) <= 1e-15 * np.max(clamped)
+
+
+def test_marginal_field_by_brute_force():
+    """The anchor-marginal field that the motor force of the anchor-resolved model spreads (the
+    r0 integral of Eq. (10)): M(x, k, l) = sum over all anchors of the torus of M_b dx dy, found
+    by minimum-image offsets; its s-sum is the marginal m0."""
+    p = ModelParams(nx=7, ny=6, ntheta=6, ns=5, rc=0.7)
+    cells = A.r0_cells(p)
+    Mb = gen.make_Mb0_random(len(cells), p.nx, p.ny, seed=3)
+    M = A.r0_marginal_field(p, cells, Mb)
+    index = {tuple(int(v) for v in cl): q for q, cl in enumerate(cells)}
+    dx, dy = p.lx / p.nx, p.ly / p.ny
+    bf = np.zeros((p.nx, p.ny, p.ntheta, p.ns))
+    for i in range(p.nx):
+        for j in range(p.ny):
+            for i0 in range(p.nx):
+                for j0 in range(p.ny):
+                    a, b = (i - i0) % p.nx, (j - j0) % p.ny
+                    a = a if a <= p.nx // 2 else a - p.nx
+                    b = b if b <= p.ny // 2 else b - p.ny
+                    for k in range(p.ntheta):
+                        for l in range(p.ns):
+                            q = index.get((a, b, k, l))
+                            if q is not None:
+                                bf[i, j, k, l] += Mb[q, i, j] * dx * dy
+    assert np.max(np.abs(M - bf)) <= 1e-14 * np.max(bf)
+    m0, _ = A.r0_marginal(p, cells, Mb)
+    assert np.max(np.abs(M.sum(-1) * (p.L / p.ns) - m0)) <= 1e-14 * np.max(m0)
