@@ -157,3 +157,30 @@ def test_temporal_blocking_is_bitwise_serial(monkeypatch, shape, precision, call
             outs.append(r)
         for x, y in zip(*outs):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-14), (1, 1e-6)])
+def test_wide_and_narrow_tilings_agree(monkeypatch, precision, tol):
+    """The default blocked context (32 bytes of the column per lane) against one launch per
+    micro-step (16 bytes per lane): the same scheme, only the association of the s-sums differs."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=12, ny=10, ntheta=64, ns=64)
+    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0)
+    M0 = gen.make_M0_random(p.nx, p.ny, p.ntheta, p.ns, seed=5)
+    fl = gen.fluid_schedule(p.nx, p.ny, 3, p.lx, p.ly)
+    dt = gen.cfl_dt(p, fl)
+    outs = []
+    for block in ("1", "0"):
+        monkeypatch.setenv("MMK_MOTOR_BLOCK", block)
+        ctx = mmk.Context(p, precision=precision)
+        cast = (lambda a: a.astype(np.float32)) if precision else (lambda a: a)
+        ctx.set_state(torch.as_tensor(cast(psi0)), torch.as_tensor(cast(M0)))
+        for e in range(3):
+            ctx.set_fluid(*map(torch.as_tensor, fl[e]))
+            ctx.step(10, dt)
+        psi, M = ctx.get_state()
+        outs.append([x.double().cpu().numpy() for x in (psi, M, ctx.get_stress(), ctx.get_moments())])
+        ctx.close()
+    for a, b in zip(*outs):
+        assert rel_err(a, b) <= tol
