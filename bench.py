@@ -458,13 +458,13 @@ def main():
         copy_calibration(args.copy_calib, 10)
         return
     if args.only == "adjoint":
-        print(json.dumps({"adjoint_fp32": run_adjoint("c5_adjoint_fp32_256x256x64x32", mmk.FP32)}), flush=True)
+        print(json.dumps({"adjoint_fp32": run_adjoint("adjoint_fp32_256x256x64x32", mmk.FP32)}), flush=True)
         return
     if args.only == "adjoint64":
-        print(json.dumps({"adjoint_fp64": run_adjoint("c4_adjoint_fp64_64x64x32x32", mmk.FP64)}), flush=True)
+        print(json.dumps({"adjoint_fp64": run_adjoint("adjoint_fp64_64x64x32x32", mmk.FP64)}), flush=True)
         return
     if args.only == "force":
-        print(json.dumps({"force_fp32": run_force(gen.params_for("c3_fp32_256x256x64x64"), mmk.FP32, 10)}),
+        print(json.dumps({"force_fp32": run_force(gen.params_for("fp32_256x256x64x64"), mmk.FP32, 10)}),
               flush=True)
         return
 
@@ -475,19 +475,19 @@ def main():
         print(json.dumps(r0), flush=True)
         return
 
-    p = gen.params_for("c3_fp32_256x256x64x64")
+    p = gen.params_for("fp32_256x256x64x64")
     K = 10
     res = {}
     if args.only in ("all", "depletion"):
         # the same grid with free-motor depletion and the over-binding clamp
-        pd = gen.params_for("c3_fp32_256x256x64x64", m_total=M_TOTAL_BENCH)
+        pd = gen.params_for("fp32_256x256x64x64", m_total=M_TOTAL_BENCH)
         res["depletion"] = run_forward(pd, mmk.FP32, args.depletion_steps, min(args.warmup, 20), K,
                                        event_every=args.event_every)
     if args.only in ("all", "substeps"):
         # fast motors on the same grid: one motor step per micro-step (dt at the motor limit)
         # against motor sub-cycling (dt at the psi limit, n motor steps per launch)
-        pf = gen.params_for("c3_fp32_256x256x64x64", v0=SUBSTEP_V0)
-        ps = gen.params_for("c3_fp32_256x256x64x64", v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH)
+        pf = gen.params_for("fp32_256x256x64x64", v0=SUBSTEP_V0)
+        ps = gen.params_for("fp32_256x256x64x64", v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH)
         res["fast_plain"] = run_forward(pf, mmk.FP32, args.substep_steps, 20, K, event_every=args.event_every)
         res["fast_sub"] = run_forward(ps, mmk.FP32, args.substep_steps, 20, K, event_every=args.event_every)
     if args.only in ("all", "fp32"):
@@ -622,8 +622,8 @@ def main():
     out["adjoint_over_forward"] = None
     if args.only == "all" and not args.no_adjoint:
         log("[bench] adjoint legs")
-        adj32 = run_adjoint("c5_adjoint_fp32_256x256x64x32", mmk.FP32)
-        adj64 = run_adjoint("c4_adjoint_fp64_64x64x32x32", mmk.FP64)
+        adj32 = run_adjoint("adjoint_fp32_256x256x64x32", mmk.FP32)
+        adj64 = run_adjoint("adjoint_fp64_64x64x32x32", mmk.FP64)
         out["adjoint_over_forward"] = adj32["ratio"]
         out["adjoint"] = {"fp32_256x256x64x32_C25": adj32, "fp64_64x64x32x32_C20": adj64}
     if not args.no_cpu_baseline:

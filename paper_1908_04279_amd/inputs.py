@@ -59,18 +59,18 @@ class ModelParams:
 # The five seeded workloads: plain FP64 small case, paper-like FP64 scale, FP32 at
 # 256^2 x 64 x 64, the adjoint case, and the largest single-GPU forward case.
 CONFIGS = {
-    "c1_fp64_16x16x16x16": dict(nx=16, ny=16, ntheta=16, ns=16, steps=100, K=100,
+    "fp64_16x16x16x16": dict(nx=16, ny=16, ntheta=16, ns=16, steps=100, K=100,
                                 precision="fp64", new_fluid_each_exchange=False),
-    "c2_fp64_128x128x64x32": dict(nx=128, ny=128, ntheta=64, ns=32, steps=1000, K=10,
+    "fp64_128x128x64x32": dict(nx=128, ny=128, ntheta=64, ns=32, steps=1000, K=10,
                                   precision="fp64", new_fluid_each_exchange=True),
-    "c3_fp32_256x256x64x64": dict(nx=256, ny=256, ntheta=64, ns=64, steps=500, K=10,
+    "fp32_256x256x64x64": dict(nx=256, ny=256, ntheta=64, ns=64, steps=500, K=10,
                                   precision="fp32", new_fluid_each_exchange=True),
-    "c4_adjoint_fp64_64x64x32x32": dict(nx=64, ny=64, ntheta=32, ns=32, steps=200, K=200,
+    "adjoint_fp64_64x64x32x32": dict(nx=64, ny=64, ntheta=32, ns=32, steps=200, K=200,
                                         ckpt=20, precision="fp64",
                                         new_fluid_each_exchange=False),
-    "c5_fp32_512x512x128x64": dict(nx=512, ny=512, ntheta=128, ns=64, steps=200, K=10,
+    "fp32_512x512x128x64": dict(nx=512, ny=512, ntheta=128, ns=64, steps=200, K=10,
                                    precision="fp32", new_fluid_each_exchange=True),
-    "c5_adjoint_fp32_256x256x64x32": dict(nx=256, ny=256, ntheta=64, ns=32, steps=200,
+    "adjoint_fp32_256x256x64x32": dict(nx=256, ny=256, ntheta=64, ns=32, steps=200,
                                           K=10, ckpt=25, precision="fp32",
                                           new_fluid_each_exchange=True),
 }

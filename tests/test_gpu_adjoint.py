@@ -150,11 +150,11 @@ def fd_check(config, precision, n_dirs, tol_par, tol_dir):
         assert abs(ad - fd) <= tol_dir * abs(fd) + 1e-12
 
 
-def test_c4_fp64_adjoint_against_oracle_finite_differences():
+def test_fp64_adjoint_64x64x32x32_against_oracle_finite_differences():
     """64^2 x 32 x 32, 200 steps, checkpoints every 20: scalars and 16 psi directions."""
-    fd_check("c4_adjoint_fp64_64x64x32x32", 0, 16, 1e-5, 1e-6)
+    fd_check("adjoint_fp64_64x64x32x32", 0, 16, 1e-5, 1e-6)
 
 
-def test_c5_fp32_adjoint_against_oracle_finite_differences():
+def test_fp32_adjoint_256x256x64x32_against_oracle_finite_differences():
     """256^2 x 64 x 32 FP32, 200 steps, fluid every 10, checkpoints every 25."""
-    fd_check("c5_adjoint_fp32_256x256x64x32", 1, 2, 2e-3, 2e-3)
+    fd_check("adjoint_fp32_256x256x64x32", 1, 2, 2e-3, 2e-3)

@@ -29,7 +29,7 @@ def case(shape, seed=0, **kw):
 
 
 @pytest.mark.parametrize("shape,kw", [
-    ((16, 16, 16, 16), {}),                                 # C1 grid: window 2 rings wider than a tile
+    ((16, 16, 16, 16), {}),                                 # 16^2 grid: window 2 rings wider than a tile
     ((21, 13, 32, 20), {"L": 1.7}),                         # ragged tiles, window wider than the grid
     ((5, 7, 12, 8), {}),                                    # window wraps the box several times
     ((40, 24, 64, 128), {"lx": 3.0, "ly": 2.0, "L": 0.8}),  # two staging passes per row
@@ -57,7 +57,7 @@ def test_fp32_against_fp64_oracle():
     assert err <= 1e-5
 
 
-def test_c3_size_fp32_and_repeatability():
+def test_fp32_256x256x64x64_and_repeatability():
     """256^2 x 64 x 64 FP32 (the benchmark grid) against the oracle, and the same bits twice."""
     p, psi, M = case((256, 256, 64, 64))
     psi32, M32 = psi.astype(np.float32), M.astype(np.float32)

@@ -33,8 +33,8 @@ def test_random_M0_small_grids(ns):
     assert e["psi"] <= TOL and e["M"] <= TOL
 
 
-def test_c1_fp32():
-    p = gen.params_for("c1_fp64_16x16x16x16")
+def test_fp32_16x16x16x16():
+    p = gen.params_for("fp64_16x16x16x16")
     psi0, M0, fl, dt = seeded_case(p)
     g = run_gpu(p, psi0, None, fl, 100, 100, dt, precision=1)
     o = run_oracle(p, psi0, np.zeros((16, 16, 16, 16)), fl, 100, 100, dt)
@@ -42,10 +42,10 @@ def test_c1_fp32():
     assert e["stress"] <= TOL and e["mom"] <= TOL
 
 
-def test_c3_fp32_full_size():
+def test_fp32_256x256x64x64_full_size():
     """256^2 x 64 x 64 FP32, 500 steps, a new fluid field every 10 steps, against the FP64
     oracle (column decomposition: M0 = 0 gives identical columns)."""
-    p = gen.params_for("c3_fp32_256x256x64x64")
+    p = gen.params_for("fp32_256x256x64x64")
     psi0, _, fl, dt = seeded_case(p, n_exchanges=50)
     print("gpu", flush=True)
     g = run_gpu(p, psi0, None, fl, 10, 500, dt, precision=1, want_M=False, keep_ctx=True)

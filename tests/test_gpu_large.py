@@ -26,9 +26,9 @@ def run(p, psi0, fl, K, n, dt):
     return ctx
 
 
-def test_c5_fp32_largest_case():
+def test_fp32_512x512x128x64_largest_case():
     import torch
-    p = gen.params_for("c5_fp32_512x512x128x64")
+    p = gen.params_for("fp32_512x512x128x64")
     assert p.nx * p.ny * p.ntheta * p.ns == 2 ** 31
     psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, seed=0)
     fl = gen.fluid_schedule(p.nx, p.ny, 20)

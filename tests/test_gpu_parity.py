@@ -24,8 +24,8 @@ def compare(g, o, fields=FIELDS, tol=TOL):
         assert v <= tol, (k, v)
 
 
-def test_c1_all_fields():
-    p = gen.params_for("c1_fp64_16x16x16x16")
+def test_fp64_16x16x16x16_all_fields():
+    p = gen.params_for("fp64_16x16x16x16")
     psi0, M0, fl, dt = seeded_case(p)
     g = run_gpu(p, psi0, M0, fl, 100, 100, dt)
     o = run_oracle(p, psi0, np.zeros((16, 16, 16, 16)), fl, 100, 100, dt)
@@ -63,10 +63,10 @@ def test_tile_tails_span_several_tiles():
     compare(g, o)
 
 
-def test_c2_full_size_against_column_decomposition():
+def test_fp64_128x128x64x32_full_size_against_column_decomposition():
     """128^2 x 64 x 32, 1000 steps, a new fluid field every 10 steps, M0 = 0.  Every GPU
     column is checked against the oracle column; psi, stress and moments in full."""
-    p = gen.params_for("c2_fp64_128x128x64x32")
+    p = gen.params_for("fp64_128x128x64x32")
     psi0, _, fl, dt = seeded_case(p, n_exchanges=100)
     print("gpu run", flush=True)
     g = run_gpu(p, psi0, None, fl, 10, 1000, dt)
@@ -114,8 +114,8 @@ def test_repeat_runs_are_bitwise_identical_and_resume_matches():
 def test_gpu_invariants():
     import torch
     from paper_1908_04279_amd import mmk
-    # mass conservation and positivity over 200 steps of the C1 workload with random M0
-    p = gen.params_for("c1_fp64_16x16x16x16")
+    # mass conservation and positivity over 200 steps of the 16x16x16x16 workload with random M0
+    p = gen.params_for("fp64_16x16x16x16")
     psi0, M0, fl, dt = seeded_case(p, n_exchanges=4, M0_kind="random")
     g = run_gpu(p, psi0, M0, fl, 50, 200, dt)
     assert abs(g["mass"] - 1.0) <= 1e-13

@@ -39,7 +39,7 @@ def test_single_mode_speed_is_the_amplitude():
 
 
 def test_cfl_dt_matches_the_stated_limits():
-    p = gen.params_for("c1_fp64_16x16x16x16")
+    p = gen.params_for("fp64_16x16x16x16")
     fl = [gen.make_fluid(16, 16, seed=1)]
     dt = gen.cfl_dt(p, fl)
     ds = p.L / p.ns

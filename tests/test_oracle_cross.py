@@ -30,8 +30,8 @@ def run_a(p, psi0, M0, fluids, K, n, dt):
     return o.psi, o.M, s, m
 
 
-def test_c1_config_agrees():
-    p = gen.params_for("c1_fp64_16x16x16x16")
+def test_fp64_16x16x16x16_config_agrees():
+    p = gen.params_for("fp64_16x16x16x16")
     psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, seed=0)
     fl = [gen.make_fluid(p.nx, p.ny, seed=1)]
     dt = gen.cfl_dt(p, fl)
