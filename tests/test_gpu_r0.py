@@ -233,3 +233,24 @@ def test_force_against_oracle(kw, precision):
     err = rel_err(f1, want)
     print(f"force rel err {err:.2e}", flush=True)
     assert err <= (1e-5 if precision else 1e-12)
+
+
+def test_resume_is_bitwise():
+    """8 steps in one context give the same bits as 4 steps, get_state, a new context and set_state,
+    4 more steps (the state carries everything: set_state rebuilds the run totals and marginals
+    with the same sums the motor launch makes)."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=20, ny=18, ntheta=16, ns=16, rc=0.35)
+    cells, psi0, Mb0, fl, dt = r0_case(p, True)
+    a = run_r0_gpu(p, psi0, Mb0, fl, 4, 8, dt)
+    ctx = mmk.Context(p)
+    ctx.set_state(torch.as_tensor(psi0), torch.as_tensor(Mb0))
+    ctx.set_fluid(*map(torch.as_tensor, fl[0]))
+    ctx.step(4, dt)
+    psi, Mb = ctx.get_state()
+    psi, Mb = psi.cpu().numpy(), Mb.cpu().numpy()
+    ctx.close()
+    b = run_r0_gpu(p, psi, Mb, fl[1:], 4, 4, dt)
+    for f in FIELDS:
+        assert np.array_equal(a[f], b[f]), f
