@@ -19,8 +19,9 @@
  *   - Sec. 2, Eq. (5) and the extra-stress step of Alg. 1: moments of Psi.
  *   - Optional depletion (m_total > 0): Eqs. (5)-(6) and the over-binding clamp of Alg. 2,
  *     applied at the start of each micro-step from the current state.
- *   - Optional motor sub-cycling (motor_cfl > 0, linear attachment): the inner loop of
- *     Alg. 2, n steps of dt/n with n from the motor's stability limit.
+ *   - Optional motor sub-cycling (motor_cfl > 0): the inner loop of Alg. 2, n steps of dt/n
+ *     with n from the motor's stability limit; with depletion the clamp and the free pool are
+ *     taken again before every sub-step.
  * Where the paper leaves the discretisation open, the reading is written next to the code.
  */
 #include "oracle.h"
@@ -438,10 +439,19 @@ void oracle_run(const oracle_params *p, double dt, int nsteps, double *psi, doub
         /* order within a micro-step: [depletion of the current state,] motors, then psi
          * driven by the new m0 */
         if (depl) {
+            /* Alg. 2's inner loop with depletion: before each of the n sub-steps of dt/n, the
+             * coarse density of the current sub-state (psi held at its start-of-step value),
+             * the clamp and the pool (n = 1 without sub-cycling) */
             double *scale = B + nxy, *src = B + 2 * nxy;
-            oracle_coarse_bound(p, pa, m0, B);
-            oracle_depletion(p, B, scale, src);
-            motor_step_depleted(p, dt, Ma, Mb, m0, scale, src);
+            const int nsub = oracle_motor_substeps(p, dt);
+            for (int q = 0; q < nsub; ++q) {
+                oracle_coarse_bound(p, pa, m0, B);
+                oracle_depletion(p, B, scale, src);
+                motor_step_depleted(p, dt / nsub, Ma, Mb, m0, scale, src);
+                if (q + 1 < nsub) {
+                    double *t = Ma; Ma = Mb; Mb = t;
+                }
+            }
         } else if (p->motor_cfl > 0.0) {
             oracle_motor_substepped(p, dt, Ma, Mb, m0, NULL);
         } else {

@@ -55,7 +55,8 @@ void oracle_column_moments(const oracle_params *p, const double *M, double *m0, 
 /* Motor sub-steps of one micro-step of length dt (Alg. 2: the inner step dt* is limited by
  * the motor's walking speed and detachment, a rate v0/ds + k_off that is the same at every
  * point): 1 when motor_cfl <= 0, else the least n >= 1 with dt/n * rate <= motor_cfl, i.e.
- * ceil(dt rate / motor_cfl).  Linear attachment only (m_total = 0). */
+ * ceil(dt rate / motor_cfl).  With depletion (oracle_run) each sub-step starts with the coarse
+ * density, the clamp and the free pool of the current sub-state. */
 int oracle_motor_substeps(const oracle_params *p, double dt);
 
 /* n explicit-midpoint steps of dt/n of every column (n from oracle_motor_substeps), then
@@ -86,7 +87,8 @@ void oracle_motor_force(const oracle_params *p, const double *psi, const double 
 
 /* nsteps micro-steps with one fluid field; psi and M are updated in place.
  * m0/m1 receive the moments of the final M (either may be NULL).  With m_total > 0 each
- * micro-step starts with the depletion of oracle_depletion on the current state. */
+ * micro-step (every motor sub-step, with motor_cfl > 0) starts with the depletion of
+ * oracle_depletion on the current state. */
 void oracle_run(const oracle_params *p, double dt, int nsteps, double *psi, double *M,
                 const double *u, const double *gradu, double *m0, double *m1);
 

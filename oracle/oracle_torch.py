@@ -168,13 +168,16 @@ class Problem:
         return max(1, int(math.ceil(dt * rate / cfl)))
 
     def step(self, psi, M, k_on, k_off, v0, u, G, dt):
+        """Motors (n sub-steps, each starting with the clamp and the pool of the current
+        sub-state when m_total > 0), then psi driven by the new m0."""
         p = self.p
-        if getattr(p, "m_total", 0.0) > 0.0:
-            M, k_on = self.depletion(psi, M, k_on)
         n = self.substeps(v0, k_off, dt)
         M1 = M
         for _ in range(n):
-            M1 = motor_step(M1, k_on, k_off, v0, dt / n, self.ds, p.limiter)
+            src = k_on
+            if getattr(p, "m_total", 0.0) > 0.0:
+                M1, src = self.depletion(psi, M1, k_on)
+            M1 = motor_step(M1, src, k_off, v0, dt / n, self.ds, p.limiter)
         m0, _ = s_moments(M1, p.L)
         psi1 = psi_step(psi, m0, u, G, p.F, dt, p.lx, p.ly)
         return psi1, M1

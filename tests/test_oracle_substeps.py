@@ -3,7 +3,9 @@
 Reading: the inner step is limited by the motor's walking speed and detachment, the rate
 v0/ds + k_off, which is the same at every point of this model; a micro-step of length dt
 takes n = ceil(dt (v0/ds + k_off) / motor_cfl) midpoint steps of dt/n (n = 1 when
-motor_cfl = 0), then the s-moments of the result feed the psi step.
+motor_cfl = 0), then the s-moments of the result feed the psi step.  With depletion, each
+sub-step starts with the coarse density, the clamp and the free pool of the current sub-state
+(Alg. 2 clamps inside its inner loop), psi being held at its value at the start of the step.
 """
 import math
 
@@ -107,4 +109,97 @@ def test_c_and_torch_oracles_agree_with_substeps():
         s_a, mom_a = o.get_stress_moments()
         psi_b, M_b, s_b, mom_b = B.forward(p, psi0, M0, fl, 5, 9, dt)
         for x, y in [(psi_a, psi_b), (M_a, M_b), (s_a, s_b), (mom_a, mom_b)]:
+            assert rel_err(x, y.numpy()) <= 1e-13
+
+
+# ---- sub-cycling with depletion: the clamp and the pool before every sub-step (Alg. 2) ----------
+def depleted_random_case(limiter, n):
+    p = ModelParams(nx=3, ny=4, ntheta=8, ns=8, limiter=limiter, k_on=0.9, k_off=0.6, v0=1.2, F=0.8)
+    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, seed=0)
+    M0 = gen.make_M0_random(p.nx, p.ny, p.ntheta, p.ns, seed=5)
+    Bv = A.coarse_bound(p, psi0, M0.sum(-1) * (p.L / p.ns))
+    p.m_total = float(0.5 * (Bv.min() + Bv.max()))
+    assert (Bv > p.m_total).any() and (Bv < p.m_total).any()
+    fl = gen.fluid_schedule(p.nx, p.ny, 1)
+    dt = gen.cfl_dt(p, fl) * (n - 0.5)
+    p.motor_cfl = dt * (p.v0 / (p.L / p.ns) + p.k_off) / (n - 0.5)
+    assert A.motor_substeps(p, dt) == n
+    return p, psi0, M0, fl, dt
+
+
+def test_depleted_substeps_by_hand():
+    """Two sub-steps of a depleted micro-step assembled from the pinned parts: the coarse density
+    of the current sub-state with psi of the step's start, the clamp rule, the column step with
+    the pool as source; then psi driven by the final m0."""
+    p, psi0, M0, fl, dt = depleted_random_case(0, 2)
+    u, G = fl[0]
+    M = M0.copy()
+    for _ in range(2):
+        Bv = A.coarse_bound(p, psi0, M.sum(-1) * (p.L / p.ns))
+        scale, src = A.depletion(p, Bv)
+        out = np.empty_like(M)
+        for i in range(p.nx):
+            for j in range(p.ny):
+                for k in range(p.ntheta):
+                    out[i, j, k] = A.column_step_src(p, dt / 2, scale[i, j] * M[i, j, k], src[i, j])
+        M = out
+    m0 = np.array([[[A.column_moments(p, M[i, j, k])[0] for k in range(p.ntheta)] for j in range(p.ny)]
+                   for i in range(p.nx)])
+    psi1 = A.psi_step(p, dt, psi0, m0, u, G)
+    o = A.OracleA(p)
+    o.set_state(psi0, M0)
+    o.set_fluid(u, G)
+    o.step(1, dt)
+    assert np.max(np.abs(o.M - M)) <= 1e-15 * np.max(np.abs(M))
+    assert np.max(np.abs(o.psi - psi1)) <= 1e-15 * np.max(np.abs(psi1))
+
+
+def test_depleted_one_substep_is_the_plain_depleted_step():
+    p, psi0, M0, fl, dt = depleted_random_case(0, 2)
+    q = ModelParams(**{**p.as_dict(), "motor_cfl": 100.0})
+    r = ModelParams(**{**p.as_dict(), "motor_cfl": 0.0})
+    assert A.motor_substeps(q, dt) == 1
+    outs = []
+    for pp in (q, r):
+        o = A.OracleA(pp)
+        o.set_state(psi0, M0)
+        o.set_fluid(*fl[0])
+        o.step(5, dt)
+        outs.append((o.psi.copy(), o.M.copy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_depleted_substeps_keep_the_coupled_fixed_point():
+    """Uniform psi, no flow, first-order flux: sub-cycled depleted steps converge to the same
+    coupled fixed point as plain steps (F* = m_total / (1 + 2 pi psi_bar k_on S / k_off))."""
+    ns = 16
+    p = ModelParams(nx=2, ny=3, ntheta=4, ns=ns, lx=1.0, ly=1.0, limiter=1, m_total=0.5, k_on=1.3, k_off=0.7,
+                    v0=0.9)
+    psi = np.full((2, 3, 4), 1.0 / (2.0 * math.pi))
+    ds = p.L / ns
+    rho = p.v0 / (p.v0 + p.k_off * ds)
+    S = ds * sum(1.0 - rho ** (l + 1) for l in range(ns))
+    Fstar = p.m_total / (1.0 + 2.0 * math.pi * psi[0, 0, 0] * p.k_on * S / p.k_off)
+    want = (p.k_on * Fstar / p.k_off) * (1.0 - rho ** (np.arange(ns) + 1.0))
+    dt = 3 * 0.35 / (p.v0 / ds + p.k_off)
+    p.motor_cfl = 0.35
+    assert A.motor_substeps(p, dt) == 3
+    o = A.OracleA(p)
+    o.set_state(psi)
+    o.set_fluid(np.zeros((2, 2, 3)), np.zeros((4, 2, 3)))
+    o.step(2500, dt)
+    for col in o.M.reshape(-1, ns):
+        assert np.max(np.abs(col - want)) <= 1e-12 * np.max(want)
+
+
+def test_c_and_torch_oracles_agree_with_depletion_and_substeps():
+    for limiter in (0, 1):
+        p, psi0, M0, fl, dt = depleted_random_case(limiter, 3)
+        o = A.OracleA(p)
+        o.set_state(psi0, M0)
+        o.set_fluid(*fl[0])
+        o.step(9, dt)
+        s_a, mom_a = o.get_stress_moments()
+        psi_b, M_b, s_b, mom_b = B.forward(p, psi0, M0, fl, 9, 9, dt)
+        for x, y in [(o.psi, psi_b), (o.M, M_b), (s_a, s_b), (mom_a, mom_b)]:
             assert rel_err(x, y.numpy()) <= 1e-13
