@@ -490,6 +490,10 @@ def main():
         ps = gen.params_for("fp32_256x256x64x64", v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH)
         res["fast_plain"] = run_forward(pf, mmk.FP32, args.substep_steps, 20, K, event_every=args.event_every)
         res["fast_sub"] = run_forward(ps, mmk.FP32, args.substep_steps, 20, K, event_every=args.event_every)
+        # the same with depletion: every sub-step its own launch after the clamp of its sub-state
+        pds = gen.params_for("fp32_256x256x64x64", v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH, m_total=M_TOTAL_BENCH)
+        res["fast_depl_sub"] = run_forward(pds, mmk.FP32, min(args.substep_steps, 100), 10, K,
+                                           event_every=args.event_every)
     if args.only in ("all", "fp32"):
         res["fp32"] = run_forward(p, mmk.FP32, args.steps, args.warmup, K, event_every=args.event_every)
     if args.only in ("all", "fp64"):
@@ -555,6 +559,11 @@ def main():
                        "motor_us_per_motor_step": sr["motor_us_per_step"] / n, "psi_avg_us": sr["psi_avg_us"]}
         d["speedup_simulated_time"] = (d["subcycled"]["simulated_time_per_s"]
                                        / d["one_motor_step"]["simulated_time_per_s"])
+        if "fast_depl_sub" in res:
+            r = res["fast_depl_sub"]
+            d["depleted_subcycled"] = {"m_total": M_TOTAL_BENCH, "dt": r["dt"],
+                                       "micro_steps_per_s": r["steps"] / r["elapsed"],
+                                       "simulated_time_per_s": r["dt"] * r["steps"] / r["elapsed"]}
         return d
 
     if args.only == "depletion":

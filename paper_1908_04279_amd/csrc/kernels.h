@@ -97,6 +97,11 @@ hipError_t launch_psi_walk(const T *psi_in, T *psi_out, const T *m0, const T *m1
                            const T *tab, T *stress, T *mom, double *partials, T *Dxy, const PsiConst<T> &c,
                            const WalkPlan &wp, hipStream_t s);
 
+// depletion_of() of B[x][y] = dth sum_th psi[x][y][th] m0[x][y][th] into Dxy[x][y][2] (between
+// the sub-steps of a depleted micro-step).  Compensated sums in FP32.
+template <typename T>
+hipError_t launch_depletion_m0(const T *psi, const T *m0, T *Dxy, int64_t nxy, int nth, T dth, T m_total,
+                               hipStream_t s);
 // depletion_of() of the coarse bound density of a state,
 // B[x][y] = dth ds sum_{th, s} psi[x][y][th] M[x][y][th][s] (M NULL: zero), into Dxy[x][y][2].
 // Compensated sums in FP32.

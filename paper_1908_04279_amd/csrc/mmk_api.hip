@@ -73,8 +73,6 @@ std::string check_params(const mmk_params *p) {
 std::string check_supported(const mmk_params *p) {
     if (p->ntheta > kMaxTheta) return "ntheta > 512 is not supported by the psi kernel";
     if (p->ns > kMaxS) return "ns > 512 is not supported by the motor kernel";
-    if (p->motor_cfl > 0 && p->m_total > 0)
-        return "motor sub-cycling (motor_cfl > 0) covers linear attachment only (m_total = 0)";
     if (plan_psi(p->nx, p->ny, p->ntheta, esize(*p), 2).lds_bytes > 64 * 1024)
         return "ntheta too large for the psi kernel's LDS tile at this precision";
     if (p->rc > 0) {
@@ -286,8 +284,39 @@ template <typename T>
 static mmk_status micro_step(mmk_ctx *c, const T *M_in, T *M_out, const T *psi_in, T *psi_out, T *m0,
                              const T *u, const T *G, double dt, bool out) {
     T *m1 = out ? c->at<T>(c->L.m1) : nullptr;
-    mmk_status st = motor_half<T>(c, M_in, M_out, m0, m1, dt, c->stream);
-    if (st != MMK_OK) return st;
+    const mmk_params &p = c->p;
+    const int nsub = (p.m_total > 0 && p.motor_cfl > 0) ? motor_substeps(p, dt) : 1;
+    if (nsub > 1) {
+        // depletion with sub-cycling (Alg. 2's inner loop): n launches of one sub-step dt/n, each
+        // with the clamp factors and pools of the current sub-state (the first from the psi
+        // step before; then from psi of this step's start and the new m0).  The two M buffers
+        // alternate (this path runs untaped: M_in, the context's own buffer, is not needed
+        // after the step); an even n ends in M_in and is copied over.
+        T *bufs[2] = {const_cast<T *>(M_in), M_out};
+        T *Dxy = c->at<T>(c->L.Dxy);
+        const int64_t np = n_psi(p), nxy = (int64_t)p.nx * p.ny;
+        MotorConst<T> mc = motor_const<T>(p, dt);  // dt / n per launch
+        mc.nsub = 1;
+        mc.wide = 0;
+        for (int q = 0; q < nsub; ++q) {
+            if (q > 0)
+                HIPCHK(c, launch_depletion_m0<T>(psi_in, m0, Dxy, nxy, p.ntheta, (T)(kTwoPi / p.ntheta), (T)p.m_total,
+                                                 c->stream),
+                       "depletion factors launch");
+            int slot;
+            HIPCHK(c, prof_begin(c, 0, &slot), "hipEventRecord");
+            HIPCHK(c, launch_motor_step<T>(bufs[q % 2], bufs[(q + 1) % 2], m0, q + 1 == nsub ? m1 : nullptr, np, p.ns,
+                                           p.limiter, mc, Dxy, c->stream),
+                   "motor step launch");
+            HIPCHK(c, prof_end(c, 0, slot), "hipEventRecord");
+        }
+        if (nsub % 2 == 0)
+            HIPCHK(c, hipMemcpyAsync(M_out, M_in, (size_t)n_m(p) * c->esz, hipMemcpyDeviceToDevice, c->stream),
+                   "copy of M");
+    } else {
+        mmk_status st = motor_half<T>(c, M_in, M_out, m0, m1, dt, c->stream);
+        if (st != MMK_OK) return st;
+    }
     return psi_half<T>(c, psi_in, psi_out, m0, m1, u, G, dt, out, c->stream);
 }
 
@@ -601,7 +630,7 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     c->walk = c->wp.ok && (ew ? atoi(ew) != 0 : c->esz == 4);
     const char *eb = getenv("MMK_MOTOR_BLOCK");
     c->block = p->m_total == 0 && p->rc == 0 && (eb ? atoi(eb) != 0 : true);
-    c->wide = c->block || p->motor_cfl > 0;
+    c->wide = c->block || (p->motor_cfl > 0 && p->m_total == 0);
     *out = c;
     return MMK_OK;
 }

@@ -770,6 +770,43 @@ template hipError_t launch_coarse_bound<float>(const float *, const float *, flo
 template hipError_t launch_coarse_bound<double>(const double *, const double *, double *, int64_t, int, int,
                                                 double, double, double, hipStream_t);
 
+// Depletion factors (clamp factor, free pool) per (x, y) from psi and the s-moment m0 of the
+// current motor state: B = dth sum_th psi m0 (Eq. (5) in the anchor-marginal reading), one wave
+// per point, compensated in FP32.  Used between the sub-steps of a depleted micro-step.
+template <typename T>
+__global__ __launch_bounds__(256) void k_depletion_m0(const T *__restrict__ psi, const T *__restrict__ m0,
+                                                      T *__restrict__ Dxy, int64_t nxy, int nth, T dth, T m_total) {
+    const int lane = threadIdx.x & 63;
+    const int64_t xy = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (xy >= nxy) return;  // the whole wave
+    T s = T(0), cmp = T(0);
+    for (int k = lane; k < nth; k += 64) {
+        const T v = psi[xy * nth + k] * m0[xy * nth + k];
+        if (k == lane) s = v;
+        else kahan_add(s, cmp, v);
+    }
+    const T tot = pencil_total<64>(s, cmp);
+    if (lane == 0) {
+        T sc, pool;
+        depletion_of(tot * dth, m_total, sc, pool);
+        Dxy[2 * xy] = sc;
+        Dxy[2 * xy + 1] = pool;
+    }
+}
+
+template <typename T>
+hipError_t launch_depletion_m0(const T *psi, const T *m0, T *Dxy, int64_t nxy, int nth, T dth, T m_total,
+                               hipStream_t s) {
+    if (nxy <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_depletion_m0<T>, dim3((unsigned)((nxy + 3) / 4)), dim3(256), 0, s, psi, m0, Dxy, nxy, nth,
+                       dth, m_total);
+    return hipGetLastError();
+}
+template hipError_t launch_depletion_m0<float>(const float *, const float *, float *, int64_t, int, float, float,
+                                               hipStream_t);
+template hipError_t launch_depletion_m0<double>(const double *, const double *, double *, int64_t, int, double,
+                                                double, hipStream_t);
+
 template <typename T>
 __global__ void k_zero(T *out, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;

@@ -94,9 +94,6 @@ def test_one_substep_is_the_plain_step():
 def test_refusals():
     import torch
     from paper_1908_04279_amd import mmk
-    with pytest.raises(mmk.MMKError) as ei:  # sizing refuses it (the status of a failed sizing is ARG)
-        mmk.Context(ModelParams(nx=4, ny=4, ntheta=8, ns=8, m_total=0.5, motor_cfl=0.4))
-    assert "linear attachment only" in str(ei.value)
     p = ModelParams(nx=4, ny=4, ntheta=8, ns=8, motor_cfl=0.4)
     ctx = mmk.Context(p, ckpt_every=4, max_tape_steps=8)
     ctx.set_state(torch.as_tensor(gen.make_psi0(4, 4, 8, seed=0)))
@@ -184,3 +181,29 @@ def test_wide_and_narrow_tilings_agree(monkeypatch, precision, tol):
         ctx.close()
     for a, b in zip(*outs):
         assert rel_err(a, b) <= tol
+
+
+@pytest.mark.parametrize("shape,n,precision,walk", [
+    ((6, 5, 16, 64), 2, 0, None),     # even n: the last sub-step lands in the first buffer
+    ((7, 4, 32, 8), 3, 0, None),
+    ((12, 10, 64, 32), 4, 0, "1"),    # walking psi kernel
+    ((12, 10, 64, 32), 3, 0, "0"),    # LDS-tiled psi kernel
+    ((20, 18, 64, 64), 2, 1, None),   # FP32 against the FP64 oracle
+])
+def test_depleted_substeps_against_oracle(monkeypatch, shape, n, precision, walk):
+    """Depletion with sub-cycling: every sub-step takes the clamp and the pool of the current
+    sub-state (Alg. 2), m_total between the smallest and the largest coarse density so both
+    branches occur."""
+    if walk is not None:
+        monkeypatch.setenv("MMK_PSI_WALK", walk)
+    nx, ny, nt, ns = shape
+    p = ModelParams(nx=nx, ny=ny, ntheta=nt, ns=ns, k_on=0.9, k_off=0.6, v0=4.0, F=0.8)
+    psi0, M0, fl, dt = substep_case(p, n)
+    Bv = A.coarse_bound(p, psi0, M0.sum(-1) * (p.L / p.ns))
+    p.m_total = float(0.5 * (Bv.min() + Bv.max()))
+    assert (Bv > p.m_total).any() and (Bv < p.m_total).any()
+    if precision:
+        psi0, M0 = psi0.astype(np.float32), M0.astype(np.float32)
+    g = run_gpu(p, psi0, M0, fl, 4, 8, dt, precision=precision)
+    o = run_oracle(p, psi0.astype(np.float64), M0.astype(np.float64), fl, 4, 8, dt)
+    compare(g, o, 1e-5 if precision else 1e-12)
