@@ -490,10 +490,17 @@ def main():
         ps = gen.params_for("fp32_256x256x64x64", v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH)
         res["fast_plain"] = run_forward(pf, mmk.FP32, args.substep_steps, 20, K, event_every=args.event_every)
         res["fast_sub"] = run_forward(ps, mmk.FP32, args.substep_steps, 20, K, event_every=args.event_every)
-        # the same with depletion: every sub-step its own launch after the clamp of its sub-state
+        # the same with depletion: every sub-step after the clamp of its sub-state, all sub-steps
+        # of a micro-step in one launch (one block per (x, y) point), and one launch per sub-step
         pds = gen.params_for("fp32_256x256x64x64", v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH, m_total=M_TOTAL_BENCH)
         res["fast_depl_sub"] = run_forward(pds, mmk.FP32, min(args.substep_steps, 100), 10, K,
                                            event_every=args.event_every)
+        os.environ["MMK_DEPL_SUB"] = "0"
+        try:
+            res["fast_depl_sub_1"] = run_forward(pds, mmk.FP32, min(args.substep_steps, 100), 10, K,
+                                                 event_every=args.event_every)
+        finally:
+            del os.environ["MMK_DEPL_SUB"]
     if args.only in ("all", "fp32"):
         res["fp32"] = run_forward(p, mmk.FP32, args.steps, args.warmup, K, event_every=args.event_every)
     if args.only in ("all", "fp64"):
@@ -559,11 +566,17 @@ def main():
                        "motor_us_per_motor_step": sr["motor_us_per_step"] / n, "psi_avg_us": sr["psi_avg_us"]}
         d["speedup_simulated_time"] = (d["subcycled"]["simulated_time_per_s"]
                                        / d["one_motor_step"]["simulated_time_per_s"])
-        if "fast_depl_sub" in res:
-            r = res["fast_depl_sub"]
-            d["depleted_subcycled"] = {"m_total": M_TOTAL_BENCH, "dt": r["dt"],
-                                       "micro_steps_per_s": r["steps"] / r["elapsed"],
-                                       "simulated_time_per_s": r["dt"] * r["steps"] / r["elapsed"]}
+        for key, name in (("fast_depl_sub", "depleted_subcycled"),
+                          ("fast_depl_sub_1", "depleted_subcycled_launch_per_substep")):
+            if key in res:
+                r = res[key]
+                ms_m, n_m = r["prof"]["motor_step"]
+                n = max(1, math.ceil(r["dt"] * (SUBSTEP_V0 / (p.L / p.ns) + p.k_off) / MOTOR_CFL_BENCH))
+                launches = 1 if key == "fast_depl_sub" else n  # motor launches per micro-step
+                d[name] = {"m_total": M_TOTAL_BENCH, "dt": r["dt"], "motor_steps_per_micro_step": n,
+                           "micro_steps_per_s": r["steps"] / r["elapsed"],
+                           "simulated_time_per_s": r["dt"] * r["steps"] / r["elapsed"],
+                           "motor_us_per_micro_step": ms_m / n_m * 1e3 * launches}
         return d
 
     if args.only == "depletion":

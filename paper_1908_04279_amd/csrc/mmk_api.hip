@@ -166,6 +166,9 @@ struct mmk_ctx {
     // launches carry several micro-steps or sub-steps per load; fixed per context so that
     // every launch sums the s-moments in the same order
     bool wide = false;
+    // depletion with sub-cycling: every sub-step of a micro-step in one launch, one block per
+    // (x, y) point, where the tiling allows it (MMK_DEPL_SUB=0: one launch per sub-step)
+    bool depl_fused = true;
     bool have_state = false, have_fluid = false, have_out = false;
     std::string err;
     bool prof = false;
@@ -286,7 +289,17 @@ static mmk_status micro_step(mmk_ctx *c, const T *M_in, T *M_out, const T *psi_i
     T *m1 = out ? c->at<T>(c->L.m1) : nullptr;
     const mmk_params &p = c->p;
     const int nsub = (p.m_total > 0 && p.motor_cfl > 0) ? motor_substeps(p, dt) : 1;
-    if (nsub > 1) {
+    if (nsub > 1 && c->depl_fused && depl_sub_supported(c->esz, p.ntheta, p.ns, (int64_t)p.nx * p.ny)) {
+        // depletion with sub-cycling (Alg. 2's inner loop) in one launch: each block re-forms the
+        // clamp factor and the pool of its point before every sub-step, from psi of this step's
+        // start and its columns held in registers
+        int slot;
+        HIPCHK(c, prof_begin(c, 0, &slot), "hipEventRecord");
+        HIPCHK(c, launch_motor_depl_sub<T>(M_in, M_out, m0, m1, psi_in, (int64_t)p.nx * p.ny, p.ntheta, p.ns,
+                                           p.limiter, motor_const<T>(p, dt), kTwoPi / p.ntheta, p.m_total, c->stream),
+               "depleted sub-cycling launch");
+        HIPCHK(c, prof_end(c, 0, slot), "hipEventRecord");
+    } else if (nsub > 1) {
         // depletion with sub-cycling (Alg. 2's inner loop): n launches of one sub-step dt/n, each
         // with the clamp factors and pools of the current sub-state (the first from the psi
         // step before; then from psi of this step's start and the new m0).  The two M buffers
@@ -631,6 +644,8 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     const char *eb = getenv("MMK_MOTOR_BLOCK");
     c->block = p->m_total == 0 && p->rc == 0 && (eb ? atoi(eb) != 0 : true);
     c->wide = c->block || (p->motor_cfl > 0 && p->m_total == 0);
+    const char *ed = getenv("MMK_DEPL_SUB");
+    c->depl_fused = ed ? atoi(ed) != 0 : true;
     *out = c;
     return MMK_OK;
 }

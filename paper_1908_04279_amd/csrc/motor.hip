@@ -429,6 +429,122 @@ static int chunks_per_lane(int ns, int elem) {
     return nch;
 }
 
+// Depleted micro-step with sub-cycling in one launch (Alg. 2's inner loop with the clamp inside
+// it).  One block per (x, y) point holds all nth of its columns, LPC lanes each.  Before each of
+// the c.nsub sub-steps of c.dt the block forms the coarse density B = dth sum_k psi_k m0_k of its
+// current columns (each column's m0 by the FP64 butterfly, the sum over k in LDS in a fixed
+// order), the clamp factor and the free pool (Eq. (6)); every column is scaled and stepped in
+// registers.  M is read and written once per micro-step.
+template <typename T, int CPL, int LPC, int LIM, bool WANT_M1>
+__global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M_in, T *__restrict__ M_out,
+                                                         T *__restrict__ m0, T *__restrict__ m1,
+                                                         const T *__restrict__ psi, int nth, int ns,
+                                                         MotorConst<T> c, double dth, double m_total) {
+    // column terms psi_k m0_k of sub-step q in part[q & 1]: one barrier per sub-step (the
+    // buffer written at q + 2 was read by every wave before it passed the barrier of q + 1)
+    __shared__ double part[2][1024 / LPC];
+    const int g = threadIdx.x % LPC, k = threadIdx.x / LPC;
+    const int lane = threadIdx.x & 63;
+    const int64_t col = (int64_t)blockIdx.x * nth + k;
+    const int l0 = g * CPL;
+    const int64_t base = col * (int64_t)ns + l0;
+    T x[CPL], R[CPL], y[CPL];
+    load_cells<T, CPL, false>(M_in + base, x);
+    const double ps = (double)psi[col];
+    for (int q = 0; q < c.nsub; ++q) {
+        double v0 = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) v0 = (j == 0) ? (double)x[j] : v0 + (double)x[j];
+        const double tot = column_total<LPC, false>(v0, 0.0, g);
+        if (g == 0) part[q & 1][k] = ps * (tot * (double)c.ds);
+        __syncthreads();
+        // every wave forms B itself in the same fixed order: lane i adds columns i, i + 64, ...
+        // in order, then a butterfly over the wave
+        double v = 0.0;
+        for (int kk = lane; kk < nth; kk += 64) v += part[q & 1][kk];
+        const double B = group_sum<64>(v);
+        T sc, pool;
+        depletion_of((T)(B * dth), (T)m_total, sc, pool);
+        const T src = c.k_on * pool;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) x[j] *= sc;
+        // the midpoint step of k_motor_step, half step with folded constants
+        const T fa = T(1) - c.half_dt * c.k_off, fb = c.half_dt * src, fg = c.half_dt * c.nv_ds;
+        motor_dh<T, CPL, LPC, LIM, false>(x, R, g, l0, ns);
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) y[j] = fg * R[j] + (fa * x[j] + fb);
+        motor_dh<T, CPL, LPC, LIM, false>(y, R, g, l0, ns);
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) y[j] = x[j] + c.dt * (c.nv_ds * R[j] + (src - c.k_off * y[j]));
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) x[j] = y[j];
+    }
+    store_cells<T, CPL, false>(M_out + base, x);
+    const T wb = T(0.5) * (T)(2 * l0 + 1 - ns);
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        a0 = (j == 0) ? (double)x[j] : a0 + (double)x[j];
+        if constexpr (WANT_M1) a1 = (j == 0) ? (double)x[j] * (double)wb : a1 + (double)x[j] * (double)(wb + T(j));
+    }
+    const double tot = column_total<LPC, WANT_M1>(a0, a1, g);
+    if (g == 0) m0[col] = (T)(tot * (double)c.ds);
+    if constexpr (WANT_M1)
+        if (g == LPC / 2) m1[col] = (T)(tot * (double)c.ds2);
+}
+
+template <typename T, int CPL, int LPC>
+static hipError_t launch_depl_sub_cfg(const T *M_in, T *M_out, T *m0, T *m1, const T *psi, int64_t nxy, int nth,
+                                      int ns, int limiter, const MotorConst<T> &c, double dth, double m_total,
+                                      hipStream_t s) {
+    const int threads = nth * LPC;
+#define MMK_DS(LIM, M1)                                                                                        \
+    hipLaunchKernelGGL((k_motor_depl_sub<T, CPL, LPC, LIM, M1>), dim3((unsigned)nxy), dim3(threads), 0, s, M_in, \
+                       M_out, m0, m1, psi, nth, ns, c, dth, m_total)
+    if (limiter == 0) {
+        if (m1) MMK_DS(0, true); else MMK_DS(0, false);
+    } else {
+        if (m1) MMK_DS(1, true); else MMK_DS(1, false);
+    }
+#undef MMK_DS
+    return hipGetLastError();
+}
+
+// Lanes per column of the single-launch depleted kernel (32 bytes of the column per lane), 0 where
+// it has no tiling for ns.
+static int depl_sub_lpc(size_t esz, int ns) {
+    if (esz == 4) return ns == 32 ? 4 : ns == 64 ? 8 : ns == 128 ? 16 : 0;
+    return ns == 16 ? 4 : ns == 32 ? 8 : ns == 64 ? 16 : 0;
+}
+
+bool depl_sub_supported(size_t esz, int nth, int ns, int64_t nxy) {
+    const int lpc = depl_sub_lpc(esz, ns);
+    return lpc > 0 && nth >= 1 && (int64_t)nth * lpc <= 1024 && (nth * lpc) % 64 == 0 && nxy <= 0x7fffffff;
+}
+
+template <typename T>
+hipError_t launch_motor_depl_sub(const T *M_in, T *M_out, T *m0, T *m1, const T *psi, int64_t nxy, int nth, int ns,
+                                 int limiter, const MotorConst<T> &c, double dth, double m_total, hipStream_t s) {
+    if (!depl_sub_supported(sizeof(T), nth, ns, nxy)) return hipErrorNotSupported;
+    if (nxy <= 0) return hipSuccess;
+    // 32 bytes of each column per lane (several sub-steps of arithmetic per load)
+    if constexpr (sizeof(T) == 4) {
+        if (ns == 64) return launch_depl_sub_cfg<T, 8, 8>(M_in, M_out, m0, m1, psi, nxy, nth, ns, limiter, c, dth, m_total, s);
+        if (ns == 32) return launch_depl_sub_cfg<T, 8, 4>(M_in, M_out, m0, m1, psi, nxy, nth, ns, limiter, c, dth, m_total, s);
+        if (ns == 128) return launch_depl_sub_cfg<T, 8, 16>(M_in, M_out, m0, m1, psi, nxy, nth, ns, limiter, c, dth, m_total, s);
+    } else {
+        if (ns == 64) return launch_depl_sub_cfg<T, 4, 16>(M_in, M_out, m0, m1, psi, nxy, nth, ns, limiter, c, dth, m_total, s);
+        if (ns == 32) return launch_depl_sub_cfg<T, 4, 8>(M_in, M_out, m0, m1, psi, nxy, nth, ns, limiter, c, dth, m_total, s);
+        if (ns == 16) return launch_depl_sub_cfg<T, 4, 4>(M_in, M_out, m0, m1, psi, nxy, nth, ns, limiter, c, dth, m_total, s);
+    }
+    return hipErrorNotSupported;
+}
+template hipError_t launch_motor_depl_sub<float>(const float *, float *, float *, float *, const float *, int64_t, int,
+                                                 int, int, const MotorConst<float> &, double, double, hipStream_t);
+template hipError_t launch_motor_depl_sub<double>(const double *, double *, double *, double *, const double *,
+                                                  int64_t, int, int, int, const MotorConst<double> &, double, double,
+                                                  hipStream_t);
+
 template <typename T>
 hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                              int limiter, const MotorConst<T> &c, const T *Dxy, hipStream_t s) {

@@ -183,17 +183,25 @@ def test_wide_and_narrow_tilings_agree(monkeypatch, precision, tol):
         assert rel_err(a, b) <= tol
 
 
-@pytest.mark.parametrize("shape,n,precision,walk", [
-    ((6, 5, 16, 64), 2, 0, None),     # even n: the last sub-step lands in the first buffer
-    ((7, 4, 32, 8), 3, 0, None),
-    ((12, 10, 64, 32), 4, 0, "1"),    # walking psi kernel
-    ((12, 10, 64, 32), 3, 0, "0"),    # LDS-tiled psi kernel
-    ((20, 18, 64, 64), 2, 1, None),   # FP32 against the FP64 oracle
+@pytest.mark.parametrize("shape,n,precision,walk,fused", [
+    ((6, 5, 16, 64), 2, 0, None, "0"),     # one launch per sub-step; even n: the last sub-step
+                                           # lands in the first buffer
+    ((6, 5, 16, 64), 2, 0, None, "1"),     # all sub-steps in one launch, 16 lanes per column
+    ((7, 4, 32, 8), 3, 0, None, "1"),      # no single-launch tiling for ns = 8: per sub-step
+    ((10, 7, 10, 32), 3, 0, None, "1"),    # 10 x 8 lanes, not whole waves: per sub-step
+    ((9, 5, 16, 16), 5, 0, None, "1"),     # single launch, 4 lanes per column, one wave a block
+    ((12, 10, 64, 32), 4, 0, "1", "1"),    # walking psi kernel
+    ((12, 10, 64, 32), 3, 0, "0", "0"),    # LDS-tiled psi kernel
+    ((12, 10, 64, 32), 3, 0, "0", "1"),
+    ((20, 18, 64, 64), 2, 1, None, "1"),   # FP32 against the FP64 oracle
+    ((20, 18, 64, 64), 3, 1, None, "0"),
+    ((8, 6, 32, 32), 4, 1, None, "1"),     # FP32, 4 lanes per column
 ])
-def test_depleted_substeps_against_oracle(monkeypatch, shape, n, precision, walk):
+def test_depleted_substeps_against_oracle(monkeypatch, shape, n, precision, walk, fused):
     """Depletion with sub-cycling: every sub-step takes the clamp and the pool of the current
     sub-state (Alg. 2), m_total between the smallest and the largest coarse density so both
-    branches occur."""
+    branches occur; in one launch per micro-step and in one launch per sub-step."""
+    monkeypatch.setenv("MMK_DEPL_SUB", fused)
     if walk is not None:
         monkeypatch.setenv("MMK_PSI_WALK", walk)
     nx, ny, nt, ns = shape
@@ -207,3 +215,29 @@ def test_depleted_substeps_against_oracle(monkeypatch, shape, n, precision, walk
     g = run_gpu(p, psi0, M0, fl, 4, 8, dt, precision=precision)
     o = run_oracle(p, psi0.astype(np.float64), M0.astype(np.float64), fl, 4, 8, dt)
     compare(g, o, 1e-5 if precision else 1e-12)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6)])
+def test_depleted_substeps_one_launch_and_per_substep_agree(monkeypatch, precision, tol):
+    """The single-launch depleted sub-cycling (one block per (x, y) point) against one launch per
+    sub-step: the same scheme; only the association of the coarse-density sum differs."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=16, ny=12, ntheta=64, ns=64, k_on=0.9, k_off=0.6, v0=4.0, F=0.8)
+    psi0, M0, fl, dt = substep_case(p, 3, n_exchanges=3)
+    Bv = A.coarse_bound(p, psi0, M0.sum(-1) * (p.L / p.ns))
+    p.m_total = float(0.5 * (Bv.min() + Bv.max()))
+    outs = []
+    for fused in ("1", "0"):
+        monkeypatch.setenv("MMK_DEPL_SUB", fused)
+        ctx = mmk.Context(p, precision=precision)
+        cast = (lambda a: a.astype(np.float32)) if precision else (lambda a: a)
+        ctx.set_state(torch.as_tensor(cast(psi0)), torch.as_tensor(cast(M0)))
+        for e in range(3):
+            ctx.set_fluid(*map(torch.as_tensor, fl[e]))
+            ctx.step(6, dt)
+        psi, M = ctx.get_state()
+        outs.append([x.double().cpu().numpy() for x in (psi, M, ctx.get_stress(), ctx.get_moments())])
+        ctx.close()
+    for a, b in zip(*outs):
+        assert rel_err(a, b) <= tol
