@@ -79,10 +79,14 @@ typedef struct {
                             * steps of dt / n inside one launch (M is read and written once),
                             * the s-moments taken after the last; n <= 4096.  The stability
                             * limit is the same at every point here, so one n serves all.
-                            * With m_total > 0 each sub-step is its own launch, preceded by the
-                            * clamp and the free pool of the current sub-state (Alg. 2 clamps
-                            * inside its inner loop), psi held at its start-of-step value.
-                            * Not supported by the tape. */
+                            * With m_total > 0 each sub-step is preceded by the clamp and the
+                            * free pool of the current sub-state (Alg. 2 clamps inside its
+                            * inner loop), psi held at its start-of-step value: all sub-steps
+                            * in one launch with one block per (x, y) point where the column
+                            * tiling allows it (FP32 ns = 32, 64, 128; FP64 ns = 16, 32, 64;
+                            * ntheta times the lanes per column a multiple of 64, at most
+                            * 1024), else one launch per sub-step.  Not supported by the
+                            * tape. */
     double rc;             /* >= 0.  0: the anchor-marginal model above.  > 0: anchor-resolved
                             * bound motors M_b(r0, x, th, s) (Sec. 2, Eqs. (4)-(6), Alg. 2) with
                             * capture radius rc; needs rc + L/2 < lx/2 and < ly/2 (else
