@@ -121,9 +121,10 @@ void oracle_r0_marginal(const oracle_params *p, const int *cells, long ncell, co
 void oracle_r0_marginal_field(const oracle_params *p, const int *cells, long ncell, const double *Mb,
                               double *M);
 
-/* nsteps micro-steps of the anchor-resolved model; psi and Mb in place.  Each micro-step: with
- * m_total > 0, the coarse density of the current state, the clamp and the free pool of
- * oracle_depletion per anchor; the motor step; psi driven by the marginal m0.  m0, m1, coarse
+/* nsteps micro-steps of the anchor-resolved model; psi and Mb in place.  Each micro-step: n
+ * motor sub-steps of dt/n (n from oracle_motor_substeps), each preceded, with m_total > 0, by
+ * the coarse density of the current sub-state (psi of the step's start), the clamp and the
+ * free pool of oracle_depletion per anchor; then psi driven by the marginal m0.  m0, m1, coarse
  * (each may be NULL) receive the marginals and the coarse density of the final state. */
 void oracle_r0_run(const oracle_params *p, double dt, int nsteps, const int *cells, long ncell,
                    double *psi, double *Mb, const double *u, const double *gradu, double *m0,

@@ -17,7 +17,9 @@
  *     minus end; inside the run the flux and the RK2 step are those of the full column;
  *   - the attachment indicator of Eq. (4) is 1 on every tracked cell;
  *   - the clamp and the free pool are taken at the start of each micro-step from the current
- *     (psi, M_b), as in the anchor-marginal depletion;
+ *     (psi, M_b), as in the anchor-marginal depletion; with motor sub-cycling (motor_cfl > 0)
+ *     at the start of each motor sub-step, from the current sub-state and psi of the step's
+ *     start (Alg. 2 clamps inside its inner loop);
  *   - psi is driven by the anchor marginal m0 = sum over anchors and s of M_b ds dx dy (the r0
  *     integral of Eq. (10) taken as a sum over the anchor lattice with area dx dy).
  */
@@ -148,16 +150,26 @@ void oracle_r0_run(const oracle_params *p, double dt, int nsteps, const int *cel
     double *m0 = (double *)malloc(sizeof(double) * (size_t)npsi);
     double *B = (double *)malloc(sizeof(double) * (size_t)(3 * nxy));
     double *Ma = Mb, *Mn = M2, *pa = psi, *pb = psi2;
+    /* motor sub-cycling (the local dt* of Alg. 2): nsub steps of dt/nsub, nsub = 1 when
+     * motor_cfl is 0; the rate bound is the same for every anchor, so one count serves all */
+    const int nsub = oracle_motor_substeps(p, dt);
     for (int n = 0; n < nsteps; ++n) {
-        /* order: [clamp and pool from the current state,] motors, psi driven by the new m0 */
-        double *scale = NULL, *src = NULL;
-        if (depl) {
-            scale = B + nxy;
-            src = B + 2 * nxy;
-            oracle_r0_coarse(p, cells, ncell, pa, Ma, B);
-            oracle_depletion(p, B, scale, src);
+        /* order: for each motor sub-step [the clamp and the pool of every anchor from the
+         * current sub-state, psi held at its start-of-step value,] the run step; then psi
+         * driven by the new m0 */
+        for (int q = 0; q < nsub; ++q) {
+            double *scale = NULL, *src = NULL;
+            if (depl) {
+                scale = B + nxy;
+                src = B + 2 * nxy;
+                oracle_r0_coarse(p, cells, ncell, pa, Ma, B);
+                oracle_depletion(p, B, scale, src);
+            }
+            oracle_r0_motor_step(p, dt / nsub, cells, ncell, Ma, Mn, scale, src);
+            if (q + 1 < nsub) {
+                double *t = Ma; Ma = Mn; Mn = t;
+            }
         }
-        oracle_r0_motor_step(p, dt, cells, ncell, Ma, Mn, scale, src);
         oracle_r0_marginal(p, cells, ncell, Mn, m0, NULL);
         oracle_psi_step(p, dt, pa, m0, u, gradu, pb);
         double *t = Ma; Ma = Mn; Mn = t;

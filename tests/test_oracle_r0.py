@@ -294,3 +294,93 @@ def test_marginal_field_by_brute_force():
     assert np.max(np.abs(M - bf)) <= 1e-14 * np.max(bf)
     m0, _ = A.r0_marginal(p, cells, Mb)
     assert np.max(np.abs(M.sum(-1) * (p.L / p.ns) - m0)) <= 1e-14 * np.max(m0)
+
+
+def test_substeps_no_walking_closed_form():
+    """Sub-cycling (motor_cfl > 0) without walking, linear attachment: n midpoint steps of
+    h = dt/n per micro-step map M - c to (M - c) g^n, g = 1 - k_off h + (k_off h)^2 / 2."""
+    p = ModelParams(nx=10, ny=8, ntheta=8, ns=6, rc=0.5, v0=0.0, k_on=0.7, k_off=1.3)
+    dt, K = 0.05, 4
+    p.motor_cfl = 0.025  # rate k_off: n = ceil(0.05 * 1.3 / 0.025) = 3
+    n = A.motor_substeps(p, dt)
+    assert n == 3
+    cells = A.r0_cells(p)
+    Mb0 = gen.make_Mb0_random(len(cells), p.nx, p.ny, p.k_on, p.k_off, seed=2)
+    o = A.OracleR0(p)
+    o.set_state(gen.make_psi0(p.nx, p.ny, p.ntheta, seed=0), Mb0)
+    o.set_fluid(*gen.make_fluid(p.nx, p.ny))
+    o.step(K, dt)
+    h = dt / n
+    g = 1 - p.k_off * h + 0.5 * (p.k_off * h) ** 2
+    c = p.k_on / p.k_off
+    want = c + (Mb0 - c) * g ** (n * K)
+    assert np.max(np.abs(o.Mb - want)) <= 1e-14 * np.max(np.abs(want))
+
+
+def test_one_substep_is_the_plain_step():
+    """motor_cfl so large that n = 1: the same bits as motor_cfl = 0, with depletion."""
+    p = ModelParams(nx=7, ny=6, ntheta=6, ns=7, rc=0.75, v0=1.1, k_on=0.9, k_off=0.6)
+    cells = A.r0_cells(p)
+    psi = gen.make_psi0(p.nx, p.ny, p.ntheta, seed=0)
+    Mb0 = gen.make_Mb0_random(len(cells), p.nx, p.ny, p.k_on, p.k_off, seed=4)
+    p.m_total = float(np.median(A.r0_coarse(p, cells, psi, Mb0)))
+    u, G = gen.make_fluid(p.nx, p.ny)
+    dt = 0.5 * gen.cfl_dt(p, [(u, G)])
+    outs = []
+    for cfl in (0.0, 1e6):
+        p.motor_cfl = cfl
+        o = A.OracleR0(p)
+        o.set_state(psi, Mb0)
+        o.set_fluid(u, G)
+        o.step(3, dt)
+        outs.append(o.get_state())
+    assert A.motor_substeps(p, dt) == 1
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_substeps_by_anchors():
+    """Two micro-steps of 3 motor sub-steps with depletion against the pure-Python step by
+    anchors applied to each sub-step: the clamp and the pool of every anchor are re-formed from
+    the current sub-state before each sub-step, psi held at its start-of-step value (Alg. 2);
+    psi then follows the m0 of the last sub-step."""
+    p = ModelParams(nx=7, ny=6, ntheta=6, ns=7, rc=0.75, v0=1.1, k_on=0.9, k_off=0.6)
+    cells = A.r0_cells(p)
+    psi = gen.make_psi0(p.nx, p.ny, p.ntheta, seed=0)
+    Mb0 = gen.make_Mb0_random(len(cells), p.nx, p.ny, p.k_on, p.k_off, seed=4)
+    p.m_total = float(np.median(A.r0_coarse(p, cells, psi, Mb0)))
+    u, G = gen.make_fluid(p.nx, p.ny)
+    dt = 0.5 * gen.cfl_dt(p, [(u, G)])
+    rate = p.v0 / (p.L / p.ns) + p.k_off
+    p.motor_cfl = dt * rate / 2.5  # n = 3
+    n = A.motor_substeps(p, dt)
+    assert n == 3
+    Mb_of = {}
+    for q, (a, b, k, l) in enumerate(cells):
+        for i in range(p.nx):
+            for j in range(p.ny):
+                Mb_of[((i - a) % p.nx, (j - b) % p.ny, i, j, int(k), int(l))] = Mb0[q, i, j]
+    ps = psi.copy()
+    clamped = []
+    for _ in range(2):
+        for _ in range(n):
+            Mb_of, coarse, m0, m1 = py_r0_step(p, dt / n, ps, Mb_of)
+            clamped.append(np.mean(coarse > p.m_total))
+        ps = A.psi_step(p, dt, ps, m0, u, G)
+    assert 0.2 < clamped[0] < 0.8
+    o = A.OracleR0(p)
+    o.set_state(psi, Mb0)
+    o.set_fluid(u, G)
+    o.step(2, dt)
+    got = np.zeros_like(Mb0)
+    for (i0, j0, i, j, k, l), v in Mb_of.items():
+        a, b = (i - i0) % p.nx, (j - j0) % p.ny
+        a = a if a <= p.nx // 2 else a - p.nx
+        b = b if b <= p.ny // 2 else b - p.ny
+        q = np.nonzero((cells == (a, b, k, l)).all(axis=1))[0]
+        got[q[0], i, j] = v
+    assert np.max(np.abs(o.Mb - got)) <= 1e-13 * np.max(np.abs(got))
+    gm0, gm1 = o.marginals()
+    assert np.max(np.abs(gm0 - m0)) <= 1e-13 * np.max(np.abs(m0))
+    assert np.max(np.abs(gm1 - m1)) <= 1e-13 * np.max(np.abs(m1))
+    assert np.max(np.abs(o.psi - ps)) <= 1e-13 * np.max(np.abs(ps))
