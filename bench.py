@@ -83,6 +83,12 @@ def motor_flops(p, with_m1, nstep=1):
     return cells * (MOTOR_FLOPS_PER_CELL * nstep + (M1_FLOPS_PER_CELL if with_m1 else 0))
 
 
+def motor_substeps(p, dt):
+    """Motor sub-steps per micro-step, by the rule documented for mmk_params.motor_cfl."""
+    cfl = getattr(p, "motor_cfl", 0.0)
+    return max(1, math.ceil(dt * (p.v0 / (p.L / p.ns) + p.k_off) / cfl)) if cfl > 0 else 1
+
+
 def block_plan(p, K):
     """Motor launches per K-step call and micro-steps in each: blocks of up to MAX_BLOCK for
     the linear model (m_total = 0), unless MMK_MOTOR_BLOCK=0; else one per micro-step."""
@@ -281,12 +287,35 @@ def r0_counters_traffic():
     return float(kv["hbm_bytes_per_launch"])
 
 
-def run_r0(precision, steps, warmup, K, event_every):
-    """The anchor-resolved micro-step (coarse + pool, motor, psi) on the R0_BENCH workload."""
+def r0_substeps(args):
+    """Fast motors (v0 = SUBSTEP_V0) on the anchor-resolved workload: one motor step per
+    micro-step (dt at the motor limit) against motor sub-cycling (dt at the psi limit), as
+    simulated time per second; with depletion (every sub-step its own launch after its anchors'
+    clamp) and with linear attachment (the sub-steps in registers)."""
+    from paper_1908_04279_amd import mmk
+    keep = ("micro_steps_per_s", "dt", "simulated_time_per_s", "motor_substeps", "motor_avg_us",
+            "coarse_avg_us", "psi_avg_us")
+    d = {"v0": SUBSTEP_V0, "motor_cfl": MOTOR_CFL_BENCH}
+    for name, over in (("one_motor_step", dict(v0=SUBSTEP_V0)),
+                       ("subcycled", dict(v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH)),
+                       ("one_motor_step_linear", dict(v0=SUBSTEP_V0, m_total=0.0)),
+                       ("subcycled_linear", dict(v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH, m_total=0.0))):
+        r = run_r0(mmk.FP32, args.r0_steps, 20, 10, args.event_every, **over)
+        d[name] = {k: r[k] for k in keep if k in r}
+    d["speedup_simulated_time"] = (d["subcycled"]["simulated_time_per_s"]
+                                   / d["one_motor_step"]["simulated_time_per_s"])
+    d["speedup_simulated_time_linear"] = (d["subcycled_linear"]["simulated_time_per_s"]
+                                          / d["one_motor_step_linear"]["simulated_time_per_s"])
+    return d
+
+
+def run_r0(precision, steps, warmup, K, event_every, **over):
+    """The anchor-resolved micro-step (coarse + pool, motor, psi) on the R0_BENCH workload
+    (parameters in `over` replace the defaults: faster motors, motor sub-cycling)."""
     import torch
     from paper_1908_04279_amd import inputs as gen
     from paper_1908_04279_amd import mmk
-    p = gen.ModelParams(**R0_BENCH, m_total=R0_M_TOTAL)
+    p = gen.ModelParams(**{**R0_BENCH, "m_total": R0_M_TOTAL, **over})
     cells = mmk.r0_cells(p)
     ncell, nrun = len(cells), r0_runs(cells)
     n_ex = (warmup + steps) // K + 2
@@ -345,18 +374,20 @@ def run_r0(precision, steps, warmup, K, event_every):
     ms_m, n_m = prof["r0_motor_step"]
     ms_c, n_c = prof["r0_coarse"]
     ms_p, n_p = prof["psi_step"]
-    us_m, us_c, us_p = ms_m / n_m * 1e3, ms_c / n_c * 1e3, ms_p / n_p * 1e3
+    us_m, us_p = ms_m / n_m * 1e3, ms_p / n_p * 1e3
+    us_c = ms_c / n_c * 1e3 if n_c else None  # no coarse launches without depletion
     flops = ncell * p.nx * p.ny * (MOTOR_FLOPS_PER_CELL + M1_FLOPS_PER_CELL)
     alu_peak = FP32_VECTOR_PEAK_TFLOPS if b == 4 else FP64_VECTOR_PEAK_TFLOPS
     return {"workload": f"{p.nx}x{p.ny} anchors and filament cells, {p.ntheta} orientations, {p.ns} arclength "
                         f"cells, capture radius {p.rc}, m_total {p.m_total}",
             "tracked_cells_per_filament_cell": ncell, "Mb_cells": ncell * p.nx * p.ny, "runs": nrun,
             "steps": steps, "micro_steps_per_s": steps / el, "ms_per_step": el / steps * 1e3,
-            "motor_avg_us": us_m, "motor_algorithmic_bytes": mb, "motor_gbs": mb / (us_m * 1e-6) / 1e9,
+            "dt": dt, "simulated_time_per_s": dt * steps / el,
+            "motor_substeps": motor_substeps(p, dt), "motor_avg_us": us_m, "motor_algorithmic_bytes": mb, "motor_gbs": mb / (us_m * 1e-6) / 1e9,
             "motor_frac": mb / (us_m * 1e-6) / 1e9 / HBM_PEAK_GBS,
             "motor_alu_frac": flops / (us_m * 1e-6) / 1e12 / alu_peak,
             "motor_traffic": r0_counters_traffic() if b == 4 else None,
-            "coarse_avg_us": us_c, "coarse_algorithmic_bytes": cb, "coarse_gbs": cb / (us_c * 1e-6) / 1e9,
+            "coarse_avg_us": us_c, "coarse_algorithmic_bytes": cb, "coarse_gbs": cb / (us_c * 1e-6) / 1e9 if us_c else None,
             "psi_avg_us": us_p, "force_avg_us": ms_f / n_f * 1e3,
             "clamped_anchor_fraction_start": clamped0, "clamped_anchor_fraction_end": clamped,
             "mass": mass, "timed_launches": [n_m, n_c, n_p]}
@@ -472,6 +503,7 @@ def main():
         r0 = {"anchor_resolved_fp32": run_r0(mmk.FP32, args.r0_steps, 20, 10, args.event_every)}
         if args.only == "r0":
             r0["anchor_resolved_fp64"] = run_r0(mmk.FP64, args.r0_steps, 20, 10, args.event_every)
+            r0["anchor_resolved_substeps_fp32"] = r0_substeps(args)
         print(json.dumps(r0), flush=True)
         return
 
@@ -638,6 +670,7 @@ def main():
     if args.only == "all":
         out["anchor_resolved_fp32"] = run_r0(mmk.FP32, args.r0_steps, 20, K, args.event_every)
         out["anchor_resolved_fp64"] = run_r0(mmk.FP64, args.r0_steps, 20, K, args.event_every)
+        out["anchor_resolved_substeps_fp32"] = r0_substeps(args)
     if "depletion" in res:
         out["depletion_fp32"] = depletion_summary()
         out["depletion_fp32"]["relative_to_linear"] = out["depletion_fp32"]["micro_steps_per_s"] / s["steps_per_s"]

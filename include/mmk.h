@@ -106,9 +106,12 @@ typedef struct {
                             * and m0 / m1 / the moments report, the anchor marginals
                             * m0(x, th) = sum over anchors and s of M_b ds dx dy (m1 with the lever
                             * arm s - L/2); mmk_get_force spreads the anchor-marginal field
-                            * sum over anchors of M_b dx dy.  Runs longer than 32 cells,
-                            * motor_cfl > 0 and the tape give MMK_ERR_UNSUPPORTED.  Three launches per
-                            * micro-step with m_total > 0 (coarse + pool, motor, psi), two with
+                            * sum over anchors of M_b dx dy.  With motor_cfl > 0 the runs
+                            * sub-cycle as above, n steps of dt / n, and with m_total > 0 every
+                            * sub-step starts with the clamp and the pool of the current
+                            * sub-state (psi of the step's start).  Runs longer than 32 cells
+                            * and the tape give MMK_ERR_UNSUPPORTED.  Launches per micro-step:
+                            * n (coarse + pool, motor) + 1 (psi) with m_total > 0, n + 1 with
                             * m_total = 0. */
 } mmk_params;
 

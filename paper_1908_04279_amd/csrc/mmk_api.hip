@@ -76,7 +76,6 @@ std::string check_supported(const mmk_params *p) {
     if (plan_psi(p->nx, p->ny, p->ntheta, esize(*p), 2).lds_bytes > 64 * 1024)
         return "ntheta too large for the psi kernel's LDS tile at this precision";
     if (p->rc > 0) {
-        if (p->motor_cfl > 0) return "the anchor-resolved model (rc > 0) has no motor sub-cycling (motor_cfl = 0)";
         const R0Plan rp = r0_plan_of(*p);
         if (rp.lmax > kR0MaxRun) return "runs of tracked cells longer than 32 (rc too large for ns)";
         if (rp.ncell > INT32_MAX || (double)rp.ncell * p->nx * p->ny > 9.0e18) return "too many tracked cells";
@@ -428,6 +427,7 @@ static R0Const<T> r0_const(const mmk_params &p, double dt, int advance) {
     c.ncell = 0;
     c.vx = 1;
     c.advance = advance;
+    c.nsub = 1;
     return c;
 }
 
@@ -439,16 +439,23 @@ static R0Const<T> r0_cst(const mmk_ctx *c, double dt, int advance) {
     return k;
 }
 
-// Motor step of every run (advance = 0: only the run totals and marginals of the current state).
 template <typename T>
-static mmk_status r0_motor(mmk_ctx *c, const T *M_in, T *M_out, double dt, int advance, bool clamp) {
+static R0Const<T> r0_with_nsub(R0Const<T> k, int nsub) {
+    k.nsub = nsub;
+    return k;
+}
+
+// nsub motor steps of dt of every run (advance = 0: only the run totals and marginals of the
+// current state).
+template <typename T>
+static mmk_status r0_motor(mmk_ctx *c, const T *M_in, T *M_out, double dt, int advance, bool clamp, int nsub = 1) {
     const mmk_params &p = c->p;
     int slot;
     HIPCHK(c, prof_begin(c, 6, &slot), "hipEventRecord");
     HIPCHK(c, launch_r0_motor<T>(M_in, M_out, c->at<T>(c->L.q0), c->at<T>(c->L.m0), c->at<T>(c->L.m1),
                                  c->at<R0Seg>(c->L.r0seg), c->at<int32_t>(c->L.r0start),
                                  clamp ? c->at<T>(c->L.r0scale) : nullptr, clamp ? c->at<T>(c->L.r0pool) : nullptr,
-                                 r0_cst<T>(c, dt, advance), c->r0.lmax, p.limiter, c->stream),
+                                 r0_with_nsub(r0_cst<T>(c, dt, advance), nsub), c->r0.lmax, p.limiter, c->stream),
            "anchor-resolved motor launch");
     HIPCHK(c, prof_end(c, 6, slot), "hipEventRecord");
     return MMK_OK;
@@ -472,16 +479,33 @@ static mmk_status r0_anchors(mmk_ctx *c, bool clamp, T *coarse_out, T *free_out)
     return MMK_OK;
 }
 
-// Each micro-step: [coarse density, clamp and pool of the current state (m_total > 0),] the
-// motor step of every run with the anchor marginals, then psi driven by the marginal m0.
+// Each micro-step: n motor sub-steps of dt/n (motor_substeps; n = 1 without sub-cycling), then
+// psi driven by the marginal m0.  With m_total > 0 each sub-step is its own launch after the
+// coarse density, clamp and pool of the current sub-state (psi of the step's start; Alg. 2
+// clamps inside its inner loop), alternating between the two M buffers (an even n ends in the
+// first and is copied over); without, one launch takes all n sub-steps in registers.
 template <typename T>
 static mmk_status run_steps_r0(mmk_ctx *c, int K, double dt) {
     const bool depl = c->p.m_total > 0;
+    const int nsub = motor_substeps(c->p, dt);
+    const double h = dt / nsub;
+    const size_t mbytes = (size_t)n_state_held(c) * sizeof(T);
     for (int n = 0; n < K; ++n) {
         const int a = c->cur, b = 1 - c->cur;
         mmk_status st = MMK_OK;
-        if (depl) st = r0_anchors<T>(c, true, nullptr, nullptr);
-        if (st == MMK_OK) st = r0_motor<T>(c, c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), dt, 1, depl);
+        if (!depl) {
+            st = r0_motor<T>(c, c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), h, 1, false, nsub);
+        } else {
+            for (int q = 0; q < nsub && st == MMK_OK; ++q) {
+                st = r0_anchors<T>(c, true, nullptr, nullptr);
+                if (st == MMK_OK)
+                    st = r0_motor<T>(c, c->at<T>(c->L.M[q % 2 ? b : a]), c->at<T>(c->L.M[q % 2 ? a : b]), h, 1, true);
+            }
+        }
+        if (st == MMK_OK && depl && nsub % 2 == 0 && mbytes > 0)
+            HIPCHK(c, hipMemcpyAsync(c->at<T>(c->L.M[b]), c->at<T>(c->L.M[a]), mbytes, hipMemcpyDeviceToDevice,
+                                     c->stream),
+                   "copy of M_b");
         if (st == MMK_OK)
             st = psi_half<T>(c, c->at<T>(c->L.psi[a]), c->at<T>(c->L.psi[b]), c->at<T>(c->L.m0), c->at<T>(c->L.m1),
                              c->at<T>(c->L.u), c->at<T>(c->L.G), dt, n == K - 1, c->stream);

@@ -41,6 +41,7 @@ struct R0Const {
     int64_t nxy, ncell;
     int vx;       // filament cells per lane (r0_vx); the tile is 64 vx cells
     int advance;  // 0: moments and run totals of the given state only (no update, no store)
+    int nsub;     // midpoint steps of dt per launch (> 1 only without the clamp: scale == nullptr)
 };
 
 // Filament cells per lane of the motor kernel for runs of at most lmax cells: 2 for runs <= 8,
@@ -51,7 +52,7 @@ int r0_coarse_split(int64_t nxy, int nseg, size_t esz);
 // Elements of the tiled state M[tile][cell][64 vx] (the last tile padded).
 int64_t r0_tiled_elems(int64_t ncell, int64_t nxy, int vx);
 
-// One motor step of every run (M_in -> M_out, tiled layout), each run a column with the no-influx
+// c.nsub motor steps of c.dt of every run (M_in -> M_out, tiled layout), each run a column with the no-influx
 // and free-outflow ends; the anchor's clamp factor scale[r0] multiplies the run first and pool[r0]
 // (k_on times the free pool) is its source (scale == nullptr: factor 1, source k_on).  Writes the
 // run totals by anchor, q0[run][r0] = sum M ds, and the anchor marginals m0, m1 [nx][ny][nth] of

@@ -160,7 +160,7 @@ __device__ __forceinline__ int wrap1(int v, int n) {
 // cells); its four waves take every fourth run of orientation k.  Tiled layout
 // M[tile][cell][TT]: the cells of a run are consecutive rows of TT values, so a run's load is
 // len * TT * sizeof(T) contiguous bytes.
-template <typename T, int LM, int LIM, int VX>
+template <typename T, int LM, int LIM, int VX, bool MULTI>
 __global__ __launch_bounds__(256) void k_r0_motor(const T *__restrict__ Min, T *__restrict__ Mout, T *__restrict__ q0,
                                                   T *__restrict__ m0, T *__restrict__ m1,
                                                   const R0Seg *__restrict__ seg, const int32_t *__restrict__ seg_start,
@@ -216,7 +216,10 @@ __global__ __launch_bounds__(256) void k_r0_motor(const T *__restrict__ Min, T *
 #pragma unroll
             for (int v = 0; v < VX; ++v) z[v][t] = sc[v] * q[v];
         }
-        if (c.advance) {
+        // c.nsub midpoint steps of c.dt in registers (sub-cycling without a clamp between them);
+        // the one-step instantiation keeps the registers of a single step
+        const int nsub = MULTI ? c.nsub : 1;
+        for (int sub = 0; c.advance && sub < nsub; ++sub) {
             if constexpr (LM == 8) {
                 // the run length is the same on every lane: the step for exactly that length
                 switch (len) {
@@ -241,6 +244,8 @@ __global__ __launch_bounds__(256) void k_r0_motor(const T *__restrict__ Min, T *
                     for (int t = 0; t < LM; ++t) z[v][t] = z[v][t] + c.dt * R[t];
                 }
             }
+        }
+        if (c.advance) {
             T *pout = Mout + base + (int64_t)r.off * TT;
 #pragma unroll
             for (int t = 0; t < LM; ++t)
@@ -490,12 +495,15 @@ template <typename T, int LM, int VX>
 static hipError_t motor_lm(const T *Min, T *Mout, T *q0, T *m0, T *m1, const R0Seg *seg, const int32_t *ss,
                            const T *scale, const T *pool, const R0Const<T> &c, int limiter, hipStream_t s) {
     const dim3 grid((unsigned)((c.nxy + 64 * VX - 1) / (64 * VX)), (unsigned)c.nth);
-    if (limiter == 0)
-        hipLaunchKernelGGL((k_r0_motor<T, LM, 0, VX>), grid, dim3(256), 0, s, Min, Mout, q0, m0, m1, seg, ss, scale,
-                           pool, c);
-    else
-        hipLaunchKernelGGL((k_r0_motor<T, LM, 1, VX>), grid, dim3(256), 0, s, Min, Mout, q0, m0, m1, seg, ss, scale,
-                           pool, c);
+#define MMK_R0M(LIM, MULTI)                                                                                    \
+    hipLaunchKernelGGL((k_r0_motor<T, LM, LIM, VX, MULTI>), grid, dim3(256), 0, s, Min, Mout, q0, m0, m1, seg, ss, \
+                       scale, pool, c)
+    if (c.nsub > 1) {
+        if (limiter == 0) MMK_R0M(0, true); else MMK_R0M(1, true);
+    } else {
+        if (limiter == 0) MMK_R0M(0, false); else MMK_R0M(1, false);
+    }
+#undef MMK_R0M
     return hipGetLastError();
 }
 
@@ -505,6 +513,7 @@ hipError_t launch_r0_motor(const T *M_in, T *M_out, T *q0, T *m0, T *m1, const R
     if (c.nxy <= 0 || c.nth <= 0) return hipSuccess;
     constexpr int V16 = 16 / sizeof(T), V8 = 8 / sizeof(T) > 0 ? 8 / sizeof(T) : 1;
     if (c.vx != r0_vx(sizeof(T), lmax)) return hipErrorInvalidValue;
+    if (c.nsub < 1 || (c.nsub > 1 && scale != nullptr)) return hipErrorInvalidValue;  // the clamp is per step
     if (lmax <= 8 && c.vx == 1) return motor_lm<T, 8, 1>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
     if (lmax <= 8 && c.vx == 2) return motor_lm<T, 8, 2>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);
     if (lmax <= 8) return motor_lm<T, 8, V16>(M_in, M_out, q0, m0, m1, seg, seg_start, scale, pool, c, limiter, s);

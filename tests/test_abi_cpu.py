@@ -112,7 +112,7 @@ def test_r0_cells_refusals_and_workspace():
     n = mmk.lib().mmk_r0_cells(C.byref(mmk.make_params(p)), None)
     ws = mmk.workspace_bytes(mmk.make_params(p, mmk.FP64))
     assert ws >= 2 * n * 32 * 32 * 8
-    for bad, msg in [(dict(ns=64, rc=0.5), "longer than 32"), (dict(rc=0.3, motor_cfl=0.4), "sub-cycling")]:
+    for bad, msg in [(dict(ns=64, rc=0.5), "longer than 32")]:
         q = params(**bad)
         assert mmk.lib().mmk_workspace_bytes(C.byref(mmk.make_params(q)), 0, 0) == 0
         assert msg in mmk.lib().mmk_last_error(None).decode()

@@ -108,9 +108,6 @@ def test_refusals():
     with pytest.raises(mmk.MMKError) as ei:   # rc + L/2 not below half the box
         mmk.Context(ModelParams(nx=8, ny=8, ntheta=4, ns=4, rc=2.7))
     assert "rc + L/2" in str(ei.value)
-    with pytest.raises(mmk.MMKError) as ei:   # sub-cycling
-        mmk.Context(ModelParams(nx=8, ny=8, ntheta=4, ns=4, rc=0.5, motor_cfl=0.4))
-    assert "sub-cycling" in str(ei.value)
     with pytest.raises(mmk.MMKError) as ei:   # a run of more than 32 cells
         mmk.Context(ModelParams(nx=8, ny=8, ntheta=4, ns=64, rc=0.5))
     assert "longer than 32" in str(ei.value)
@@ -254,3 +251,61 @@ def test_resume_is_bitwise():
     b = run_r0_gpu(p, psi, Mb, fl[1:], 4, 4, dt)
     for f in FIELDS:
         assert np.array_equal(a[f], b[f]), f
+
+
+SUBSTEP_CASES = [
+    # kw, depletion, motor sub-steps per micro-step, (K, n)
+    (dict(nx=16, ny=16, ntheta=8, ns=8, rc=0.45), False, 3, (3, 7)),
+    (dict(nx=20, ny=18, ntheta=16, ns=16, rc=0.35), True, 2, (4, 8)),      # even: ends in the other buffer
+    (dict(nx=9, ny=7, ntheta=12, ns=10, rc=0.6, lx=5.0, ly=6.0, limiter=1), True, 4, (3, 6)),
+    (dict(nx=24, ny=22, ntheta=16, ns=24, rc=0.45, v0=1.7), True, 3, (3, 5)),   # runs <= 16 / 32
+    # linear attachment: all sub-steps in registers, one launch per micro-step
+    (dict(nx=24, ny=22, ntheta=16, ns=24, rc=0.45, v0=1.7), False, 2, (3, 5)),
+    (dict(nx=9, ny=7, ntheta=12, ns=10, rc=0.6, lx=5.0, ly=6.0, limiter=1), False, 5, (3, 6)),
+]
+
+
+def substep_r0_case(p, depletion, nsub):
+    """r0_case at the psi limit (motor_cfl > 0 leaves the motor rate out of it), then motor_cfl
+    chosen so that a micro-step takes nsub motor sub-steps."""
+    p.motor_cfl = 1.0
+    cells, psi0, Mb0, fl, dt = r0_case(p, depletion)
+    rate = p.v0 / (p.L / p.ns) + p.k_off
+    p.motor_cfl = dt * rate / (nsub - 0.5)
+    assert A.motor_substeps(p, dt) == nsub
+    return cells, psi0, Mb0, fl, dt
+
+
+@pytest.mark.parametrize("kw,depletion,nsub,Kn", SUBSTEP_CASES)
+def test_substeps_fp64_against_oracle(kw, depletion, nsub, Kn):
+    """Motor sub-cycling of the runs (Alg. 2's local dt*), with depletion every sub-step after the
+    clamp and the pool of its anchor's current sub-state."""
+    p = ModelParams(**kw)
+    cells, psi0, Mb0, fl, dt = substep_r0_case(p, depletion, nsub)
+    K, n = Kn
+    g = run_r0_gpu(p, psi0, Mb0, fl, K, n, dt)
+    o = run_r0_oracle(p, psi0, Mb0, fl, K, n, dt)
+    compare(g, o, 1e-12)
+
+
+@pytest.mark.parametrize("depletion", [True, False])
+def test_substeps_fp32_against_fp64_oracle(depletion):
+    p = ModelParams(nx=20, ny=18, ntheta=16, ns=16, rc=0.35)
+    cells, psi0, Mb0, fl, dt = substep_r0_case(p, depletion, 3)
+    psi32, Mb32 = psi0.astype(np.float32), Mb0.astype(np.float32)
+    g = run_r0_gpu(p, psi32, Mb32, fl, 4, 8, dt, precision=1)
+    o = run_r0_oracle(p, psi32.astype(np.float64), Mb32.astype(np.float64), fl, 4, 8, dt)
+    compare(g, o, 1e-5)
+
+
+def test_one_substep_is_the_plain_step():
+    """motor_cfl so large that n = 1: the same bits as motor_cfl = 0, with depletion."""
+    p = ModelParams(nx=20, ny=18, ntheta=16, ns=16, rc=0.35)
+    cells, psi0, Mb0, fl, dt = r0_case(p, True)
+    outs = []
+    for cfl in (0.0, 1e6):
+        p.motor_cfl = cfl
+        g = run_r0_gpu(p, psi0, Mb0, fl, 3, 6, dt)
+        outs.append(g)
+    for f in FIELDS:
+        assert np.array_equal(outs[0][f], outs[1][f]), f
