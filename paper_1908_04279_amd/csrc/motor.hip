@@ -50,11 +50,21 @@ __device__ __forceinline__ void motor_dh(const T (&z)[CPL], T (&R)[CPL], int g, 
     for (int j = 0; j < CPL; ++j) R[j] = h[j] - ((j == 0) ? hl : h[j - 1]);
 }
 
+// The lane's part of m0: its CPL cells added in the cell precision, in order, then widened
+// (one half-rate FP64 operation per lane instead of two per cell).  In FP32 the few terms
+// carry a relative error of at most (CPL - 1) units of 2^-24; the lanes then add in FP64.
+template <typename T, int CPL, bool RAGGED>
+__device__ __forceinline__ double lane_m0(const T (&y)[CPL], int l0, int ns) {
+    T v = y[0];
+#pragma unroll
+    for (int j = 1; j < CPL; ++j) v += (!RAGGED || l0 + j < ns) ? y[j] : T(0);
+    return (!RAGGED || l0 < ns) ? (double)v : 0.0;
+}
+
 // Column total of the lane partials, in FP64 (every lane of the group; with PAIR, the m0 total in
 // the lower half of the group and the m1 total in the upper half), rounded once by the caller.
-// The lane partials are FP64 sums of the lane's cells: for FP32 cells these few terms add
-// exactly in FP64 (unless their exponents differ by ~29 binades), more accurate than a Kahan
-// pair and fewer instructions (an FP64 add issues at the FP32 rate on this chip).
+// The m0 lane partials are sums of the lane's few cells in the cell precision (lane_m0); the
+// butterfly over the lanes adds in FP64.
 template <int LPC, bool PAIR>
 __device__ __forceinline__ double column_total(double v0, double v1, int g) {
     return group_sum_pair<LPC, false, PAIR, double>(v0, 0.0, v1, 0.0, g);
@@ -131,13 +141,7 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     // and only the last is stored.
     for (int t = 0; t + 1 < c.nstep; ++t) {
         micro();
-        double v0 = 0.0;
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-            const T v = (!RAGGED || l0 + j < ns) ? y[j] : T(0);
-            v0 = (j == 0) ? (double)v : v0 + (double)v;
-        }
-        const double tot = column_total<LPC, false>(v0, 0.0, g);
+        const double tot = column_total<LPC, false>(lane_m0<T, CPL, RAGGED>(y, l0, ns), 0.0, g);
         if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = (T)(tot * (double)c.ds);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) x[j] = y[j];
@@ -153,19 +157,20 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     }
 
     // s-moments of the new column: m0 = ds sum M, m1 = ds^2 sum (l + 1/2 - ns/2) M, the
-    // weights being exact half-integers, summed in FP64 in the lane and across the lanes
-    // (column_total).  On output steps one paired butterfly serves both: lane 0 of the group
+    // weights being exact half-integers; m0 from the lane sums of lane_m0, m1 summed in FP64 in
+    // the lane; both across the lanes in FP64 (column_total).  On output steps one paired butterfly serves both: lane 0 of the group
     // ends with m0, lane LPC/2 with m1; m0 has the same bits on every step.
     const T wb = T(0.5) * (T)(2 * l0 + 1 - ns);  // weight of this lane's first cell
-    double a0 = 0.0, a1 = 0.0;
+    double a1 = 0.0;
+    if constexpr (WANT_M1) {
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-        const bool in = !RAGGED || (l0 + j < ns);
-        const T v = in ? y[j] : T(0);
-        a0 = (j == 0) ? (double)v : a0 + (double)v;
-        if constexpr (WANT_M1) a1 = (j == 0) ? (double)v * (double)wb : a1 + (double)v * (double)(wb + T(j));
+        for (int j = 0; j < CPL; ++j) {
+            const bool in = !RAGGED || (l0 + j < ns);
+            const T v = in ? y[j] : T(0);
+            a1 = (j == 0) ? (double)v * (double)wb : a1 + (double)v * (double)(wb + T(j));
+        }
     }
-    const double tot = column_total<LPC, WANT_M1>(a0, a1, g);
+    const double tot = column_total<LPC, WANT_M1>(lane_m0<T, CPL, RAGGED>(y, l0, ns), a1, g);
     if (active && g == 0) m0[col] = (T)(tot * (double)c.ds);
     if constexpr (WANT_M1)
         if (active && g == LPC / 2) m1[col] = (T)(tot * (double)c.ds2);
@@ -452,10 +457,7 @@ __global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M
     load_cells<T, CPL, false>(M_in + base, x);
     const double ps = (double)psi[col];
     for (int q = 0; q < c.nsub; ++q) {
-        double v0 = 0.0;
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) v0 = (j == 0) ? (double)x[j] : v0 + (double)x[j];
-        const double tot = column_total<LPC, false>(v0, 0.0, g);
+        const double tot = column_total<LPC, false>(lane_m0<T, CPL, false>(x, l0, ns), 0.0, g);
         if (g == 0) part[q & 1][k] = ps * (tot * (double)c.ds);
         __syncthreads();
         // every wave forms B itself in the same fixed order: lane i adds columns i, i + 64, ...
@@ -481,13 +483,12 @@ __global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M
     }
     store_cells<T, CPL, false>(M_out + base, x);
     const T wb = T(0.5) * (T)(2 * l0 + 1 - ns);
-    double a0 = 0.0, a1 = 0.0;
+    double a1 = 0.0;
+    if constexpr (WANT_M1) {
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-        a0 = (j == 0) ? (double)x[j] : a0 + (double)x[j];
-        if constexpr (WANT_M1) a1 = (j == 0) ? (double)x[j] * (double)wb : a1 + (double)x[j] * (double)(wb + T(j));
+        for (int j = 0; j < CPL; ++j) a1 = (j == 0) ? (double)x[j] * (double)wb : a1 + (double)x[j] * (double)(wb + T(j));
     }
-    const double tot = column_total<LPC, WANT_M1>(a0, a1, g);
+    const double tot = column_total<LPC, WANT_M1>(lane_m0<T, CPL, false>(x, l0, ns), a1, g);
     if (g == 0) m0[col] = (T)(tot * (double)c.ds);
     if constexpr (WANT_M1)
         if (g == LPC / 2) m1[col] = (T)(tot * (double)c.ds2);
