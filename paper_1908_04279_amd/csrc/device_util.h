@@ -283,13 +283,16 @@ __device__ __forceinline__ T superbee(T a, T b) {
     return (a * b > T(0)) ? copysign(m, b) : T(0);
 }
 // FP32: minmod(x, y) = med3(x, y, 0), and superbee = maxmod(minmod(2a, b), minmod(a, 2b)).
-// Both minmods carry the sign of b (or are 0), so their maxmod is med3(p, q, sgn(b) inf).
-// Every operation is exact (doubling, median, sign copy): the value equals the definition.
+// Both minmods lie between 0 and 2b (|p| <= |b|, |q| <= 2|b|, each with the sign of b or 0), so
+// their maxmod is med3(p, q, 2b): the larger for b > 0, the smaller for b < 0, 0 for b = 0.
+// Every operation is exact (doubling, median): the value equals the definition, and 2b is the
+// doubling the neighbouring cell makes of the same difference.
 template <>
 __device__ __forceinline__ float superbee<float>(float a, float b) {
+    const float b2 = b + b;
     const float p = __builtin_amdgcn_fmed3f(a + a, b, 0.0f);
-    const float q = __builtin_amdgcn_fmed3f(a, b + b, 0.0f);
-    return __builtin_amdgcn_fmed3f(p, q, copysignf(__builtin_inff(), b));
+    const float q = __builtin_amdgcn_fmed3f(a, b2, 0.0f);
+    return __builtin_amdgcn_fmed3f(p, q, b2);
 }
 
 }  // namespace mmk
