@@ -405,13 +405,16 @@ static hipError_t launch_cfg(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
 // wave covers one contiguous span.  Wide launches (several micro-steps or sub-steps per load,
 // where the arithmetic bounds the launch) take 32 bytes per lane: fewer neighbour exchanges
 // and a shorter s-reduction per cell (measured at 64 cells: FP32 +11%, FP64 +29%; one step per
-// load is faster with 16).  MMK_MOTOR_LPC overrides (measurements).
+// load is faster with 16); FP32 columns of 64 cells take 64 bytes (16 cells) per lane, another
+// 10% (1302 -> 1168 us per 10-micro-step launch at 256x256x64).  MMK_MOTOR_LPC overrides
+// (measurements).
 static int lanes_per_column(int ns, int elem, bool wide) {
     const int cpl = 16 / elem;
     if (ns < 2 * cpl || ns % cpl != 0) return 0;
     int lpc = ns / cpl;
     if (lpc > 64 || (lpc & (lpc - 1)) != 0) return 0;
-    if (wide && lpc >= 4) lpc /= 2;
+    if (wide && elem == 4 && ns == 64) lpc = 4;
+    else if (wide && lpc >= 4) lpc /= 2;
     if (const char *e = getenv("MMK_MOTOR_LPC")) {
         const int want = atoi(e);
         if (want >= 2 && want <= 64 && (want & (want - 1)) == 0 && ns % want == 0) {
@@ -566,7 +569,7 @@ hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
         return launch_cfg<T, NS / LPC, LPC, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Dxy, s);
     if constexpr (sizeof(T) == 4) {
         MMK_MOTOR_CASE(8, 2) MMK_MOTOR_CASE(16, 4) MMK_MOTOR_CASE(16, 2) MMK_MOTOR_CASE(32, 8)
-        MMK_MOTOR_CASE(32, 4) MMK_MOTOR_CASE(64, 16) MMK_MOTOR_CASE(64, 8) MMK_MOTOR_CASE(128, 32)
+        MMK_MOTOR_CASE(32, 4) MMK_MOTOR_CASE(64, 16) MMK_MOTOR_CASE(64, 8) MMK_MOTOR_CASE(64, 4) MMK_MOTOR_CASE(128, 32)
         MMK_MOTOR_CASE(128, 16) MMK_MOTOR_CASE(256, 64) MMK_MOTOR_CASE(256, 32)
     } else {
         MMK_MOTOR_CASE(4, 2) MMK_MOTOR_CASE(8, 4) MMK_MOTOR_CASE(8, 2) MMK_MOTOR_CASE(16, 8)
