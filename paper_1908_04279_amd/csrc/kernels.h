@@ -100,8 +100,8 @@ hipError_t launch_psi_walk(const T *psi_in, T *psi_out, const T *m0, const T *m1
 // Depleted micro-step with c.nsub sub-steps of c.dt in one launch: one block per (x, y) point
 // holding its nth columns; the clamp and the free pool of the current sub-state before each
 // sub-step.  hipErrorNotSupported where depl_sub_supported() is false: ns of 32 bytes per lane
-// times a power of two up to 16 lanes, nth * lanes a multiple of 64 and at most 1024 (the
-// caller then launches one sub-step at a time).
+// (64 for FP32 ns = 64) times a power of two up to 16 lanes, nth * lanes a multiple of 64 and
+// at most 1024 (the caller then launches one sub-step at a time).
 bool depl_sub_supported(size_t esz, int nth, int ns, int64_t nxy);
 template <typename T>
 hipError_t launch_motor_depl_sub(const T *M_in, T *M_out, T *m0, T *m1, const T *psi, int64_t nxy, int nth, int ns,
