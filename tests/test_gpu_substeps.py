@@ -158,8 +158,9 @@ def test_temporal_blocking_is_bitwise_serial(monkeypatch, shape, precision, call
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-14), (1, 1e-6)])
 def test_wide_and_narrow_tilings_agree(monkeypatch, precision, tol):
-    """The default blocked context (32 bytes of the column per lane) against one launch per
-    micro-step (16 bytes per lane): the same scheme, only the association of the s-sums differs."""
+    """The default blocked context (64 bytes of the column per lane in FP32, 32 in FP64) against
+    one launch per micro-step (16 bytes per lane): the same scheme, only the association of the
+    s-sums differs."""
     import torch
     from paper_1908_04279_amd import mmk
     p = ModelParams(nx=12, ny=10, ntheta=64, ns=64)
