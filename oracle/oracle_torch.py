@@ -153,7 +153,10 @@ class Problem:
         m0, _ = s_moments(M, p.L)
         B = (psi * m0).sum(-1) * dth
         over = B > p.m_total
-        scale = torch.where(over, p.m_total / B, torch.ones_like(B))
+        # the masked branch divides by 1, not by B: where B = 0 a division by B would carry
+        # 0 * inf = NaN into the gradient even though its value is discarded
+        scale = torch.where(over, p.m_total / torch.where(over, B, torch.ones_like(B)),
+                            torch.ones_like(B))
         src = torch.where(over, torch.zeros_like(B), k_on * (p.m_total - B))
         return M * scale[:, :, None, None], src[:, :, None, None]
 

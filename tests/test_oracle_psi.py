@@ -218,3 +218,46 @@ def test_motor_gliding_moves_filaments_against_their_orientation():
     assert np.abs(psi[:, :, 0] - minus_x).max() <= 1e-13
     assert np.abs(psi[:, :, 2] - minus_y).max() <= 1e-13
     assert np.abs(psi[:, :, 4] - plus_x).max() <= 1e-13
+
+
+def test_global_sums_closed_forms():
+    """mass = sum psi dx dy dth and sum_sigma = sum sigma dx dy (the FP64 global sums of the
+    extra-stress step), pinned on states whose integrals are known in closed form.  The box is
+    not square and dx != dy, so a dx/dy swap, a missing dth or a missing dx dy fails.
+      * uniform psi = a: mass = a 2 pi lx ly;
+      * all filaments along th = 0 with c = int psi dth: sum sigma_xx = sigma_f c lx ly / 2,
+        sum sigma_yy = -sigma_f c lx ly / 2, sum sigma_xy = 0, mass = c lx ly;
+      * isotropic psi = a with lever moment m1: the motor dipole stress integrates to
+        F m1 a pi lx ly on the diagonal, the filament part to 0;
+      * one occupied cell: mass = psi dx dy dth exactly."""
+    nth = 16
+    lx, ly = 2.0, 3.5
+    p = ModelParams(nx=4, ny=5, ntheta=nth, ns=4, lx=lx, ly=ly, F=1.3, sigma_f=0.8)
+    dth = TWO_PI / nth
+    zero_stress = np.zeros((3, p.nx, p.ny))
+    a = 0.37
+    mass, _ = A.global_sums(p, np.full((p.nx, p.ny, nth), a), zero_stress)
+    assert mass == pytest.approx(a * TWO_PI * lx * ly, rel=1e-14)
+
+    c = 1.9
+    psi = np.zeros((p.nx, p.ny, nth))
+    psi[..., 0] = c / dth
+    s, _ = A.moments(p, psi, np.full(psi.shape, 0.3), np.zeros(psi.shape))
+    mass, ss = A.global_sums(p, psi, s)
+    assert mass == pytest.approx(c * lx * ly, rel=1e-14)
+    assert ss[0] == pytest.approx(0.5 * p.sigma_f * c * lx * ly, rel=1e-14)
+    assert ss[2] == pytest.approx(-0.5 * p.sigma_f * c * lx * ly, rel=1e-14)
+    assert abs(ss[1]) < 1e-14
+
+    m1 = 0.07
+    psi = np.full((p.nx, p.ny, nth), a)
+    s, _ = A.moments(p, psi, np.full(psi.shape, 0.3), np.full(psi.shape, m1))
+    mass, ss = A.global_sums(p, psi, s)
+    want = p.F * m1 * a * math.pi * lx * ly
+    assert ss[0] == pytest.approx(want, rel=1e-13) and ss[2] == pytest.approx(want, rel=1e-13)
+    assert abs(ss[1]) < 1e-14
+
+    psi = np.zeros((p.nx, p.ny, nth))
+    psi[3, 4, 7] = 2.5
+    mass, _ = A.global_sums(p, psi, zero_stress)
+    assert mass == pytest.approx(2.5 * (lx / p.nx) * (ly / p.ny) * dth, rel=1e-15)
