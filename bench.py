@@ -89,10 +89,11 @@ def motor_substeps(p, dt):
     return max(1, math.ceil(dt * (p.v0 / (p.L / p.ns) + p.k_off) / cfl)) if cfl > 0 else 1
 
 
-def block_plan(p, K):
+def block_plan(p, K, options=None):
     """Motor launches per K-step call and micro-steps in each: blocks of up to MAX_BLOCK for
-    the linear model (m_total = 0), unless MMK_MOTOR_BLOCK=0; else one per micro-step."""
-    if getattr(p, "m_total", 0.0) > 0 or os.environ.get("MMK_MOTOR_BLOCK", "1") == "0":
+    the linear model (m_total = 0), unless the motor_block option is 0; else one per
+    micro-step."""
+    if getattr(p, "m_total", 0.0) > 0 or (options or {}).get("motor_block", 1) == 0:
         return [1] * K
     return [min(MAX_BLOCK, K - d) for d in range(0, K, MAX_BLOCK)]
 
@@ -105,7 +106,7 @@ def psi_bytes(p, b, out):
     return b * (3 * n_psi + 6 * nxy) + (b * (n_psi + 10 * nxy) if out else 0)
 
 
-def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1):
+def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1, options=None):
     import torch
     from paper_1908_04279_amd import inputs as gen
     from paper_1908_04279_amd import mmk
@@ -114,7 +115,7 @@ def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1):
     log(f"[bench] generating {n_ex} fluid fields for {p.nx}x{p.ny}")
     fluids_np = [gen.make_fluid(p.nx, p.ny, p.lx, p.ly, seed=1 + e) for e in range(n_ex)]
     dt = gen.cfl_dt(p, fluids_np)
-    ctx = mmk.Context(p, precision=precision)
+    ctx = mmk.Context(p, precision=precision, options=options)
     fl = [(torch.as_tensor(u).to(ctx.device, ctx.dtype), torch.as_tensor(g).to(ctx.device, ctx.dtype))
           for u, g in fluids_np]
     psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0)
@@ -151,7 +152,7 @@ def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1):
     mass, ss = ctx.get_sums()
     ctx.close()
     return dict(elapsed=elapsed, steps=steps, dt=dt, prof=prof, mass=mass, event_every=event_every,
-                blocks=block_plan(p, K))
+                blocks=block_plan(p, K, options))
 
 
 def run_adjoint(name, precision):
@@ -527,12 +528,8 @@ def main():
         pds = gen.params_for("fp32_256x256x64x64", v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH, m_total=M_TOTAL_BENCH)
         res["fast_depl_sub"] = run_forward(pds, mmk.FP32, min(args.substep_steps, 100), 10, K,
                                            event_every=args.event_every)
-        os.environ["MMK_DEPL_SUB"] = "0"
-        try:
-            res["fast_depl_sub_1"] = run_forward(pds, mmk.FP32, min(args.substep_steps, 100), 10, K,
-                                                 event_every=args.event_every)
-        finally:
-            del os.environ["MMK_DEPL_SUB"]
+        res["fast_depl_sub_1"] = run_forward(pds, mmk.FP32, min(args.substep_steps, 100), 10, K,
+                                             event_every=args.event_every, options={"depl_fused": 0})
     if args.only in ("all", "fp32"):
         res["fp32"] = run_forward(p, mmk.FP32, args.steps, args.warmup, K, event_every=args.event_every)
     if args.only in ("all", "fp64"):
@@ -540,12 +537,10 @@ def main():
                                   event_every=args.event_every)
     if args.only == "all":
         # the same grid with one motor launch per micro-step (HBM-bound): FP32 and FP64
-        os.environ["MMK_MOTOR_BLOCK"] = "0"
-        try:
-            res["fp32_1"] = run_forward(p, mmk.FP32, args.fp64_steps, 20, K, event_every=args.event_every)
-            res["fp64_1"] = run_forward(p, mmk.FP64, args.fp64_steps, 20, K, event_every=args.event_every)
-        finally:
-            del os.environ["MMK_MOTOR_BLOCK"]
+        res["fp32_1"] = run_forward(p, mmk.FP32, args.fp64_steps, 20, K, event_every=args.event_every,
+                                    options={"motor_block": 0})
+        res["fp64_1"] = run_forward(p, mmk.FP64, args.fp64_steps, 20, K, event_every=args.event_every,
+                                    options={"motor_block": 0})
 
     def summarise(r, b):
         """Whole-step rate, and the motor kernel's roofline over its timed launches.  A K-step

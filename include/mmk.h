@@ -195,6 +195,35 @@ mmk_status mmk_tape_backward(mmk_ctx *ctx, const void *g_sigma, const void *g_mo
                              void *g_psi0, double g_params[3]);
 mmk_status mmk_tape_end(mmk_ctx *ctx);
 
+/* Implementation options of a context (project extras, not in the paper).  Each selects
+ * between kernels or launch shapes that compute the same micro-step; the defaults are the
+ * ones measured fastest on MI355X.  Results under any setting agree with the defaults up to the
+ * association of the s-sums (the lane tiling) and are bitwise equal where the tiling is the
+ * same.  An option may be set at any time between calls and applies from the next call on.
+ * MMK_ERR_ARG for an unknown option or a value outside its range.  No device work. */
+typedef enum {
+    MMK_OPT_MOTOR_BLOCK = 0,   /* 1 (default): with m_total = 0, rc = 0 and no tape, one motor
+                                * launch advances M through up to 16 micro-steps of a call (the
+                                * column stays in registers; m0 of every micro-step is kept for
+                                * its psi step); 0: one motor launch per micro-step */
+    MMK_OPT_PSI_KERNEL = 1,    /* 0 (default): the LDS-free walking psi kernel for ntheta = 64
+                                * or 128 in FP32, the LDS-tiled one otherwise; 1: LDS-tiled;
+                                * 2: walking where ntheta allows it, else LDS-tiled */
+    MMK_OPT_DEPL_FUSED = 2,    /* 1 (default): depletion with motor sub-cycling runs all
+                                * sub-steps of a micro-step in one launch where the tiling allows
+                                * it; 0: one launch per sub-step */
+    MMK_OPT_MOTOR_LANES = 3,   /* 0 (default: from ns, the precision and whether a launch takes
+                                * several steps per load); else lanes per motor column, a power
+                                * of two 2 .. 64; a value without a compiled tiling for ns and the
+                                * precision leaves the default */
+    MMK_OPT_MOTOR_CHUNKS = 4,  /* 0 (default): each lane holds consecutive cells; 2 or 4: each
+                                * lane holds that many 16-byte chunks spaced a lane group apart
+                                * (no depletion; a value without a tiling for ns leaves 0) */
+    MMK_OPT_MOTOR_NT = 5       /* -1 (default): nontemporal loads and stores of M in FP32, plain
+                                * in FP64; 0: plain; 1: nontemporal */
+} mmk_option;
+mmk_status mmk_set_option(mmk_ctx *ctx, int32_t option, int32_t value);
+
 /* Kernel timing: with enable = N > 0 every N-th launch of each kernel is bracketed by HIP
  * events on the context's stream (enable = 0 turns timing off, < 0 is MMK_ERR_ARG).
  * mmk_profile_read (synchronizes) sums the elapsed times of the timed launches of `kernel_id`
@@ -203,6 +232,9 @@ mmk_status mmk_tape_end(mmk_ctx *ctx);
  * since profiling was enabled; up to 65536 launches per id are timed. */
 mmk_status mmk_profile(mmk_ctx *ctx, int32_t enable);
 mmk_status mmk_profile_read(mmk_ctx *ctx, int32_t kernel_id, double *total_ms, int64_t *launches);
+/* After mmk_profile: time every `every`-th launch of kernel_id from here on (0: none of them),
+ * restarting its count; the other ids keep theirs.  Synchronizes. */
+mmk_status mmk_profile_every(mmk_ctx *ctx, int32_t kernel_id, int32_t every);
 
 /* Message of the last failure on ctx; with ctx == NULL, of the last failed mmk_create or
  * mmk_workspace_bytes on this thread. */

@@ -40,6 +40,9 @@ inline MotorConst<T> motor_const(const mmk_params &p, double dt) {
     c.ds2 = (T)(ds * ds);
     c.nth = p.ntheta;
     c.wide = 0;
+    c.lanes = 0;
+    c.chunks = 0;
+    c.nt = -1;
     c.nth_shift = -1;
     for (int k = 0; k < 31; ++k)
         if ((1 << k) == p.ntheta) c.nth_shift = k;

@@ -14,7 +14,6 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -155,26 +154,27 @@ struct mmk_ctx {
     Layout L{};
     PsiLaunch pl{}, pl_rev{};
     int cur = 0;    // index of the current M / psi buffers
+    // implementation options (mmk_set_option), and what they select
+    int opt[6] = {1, 0, 1, 0, 0, -1};
     // ntheta = 64, 128: the psi step runs as the LDS-free walking kernel (default in FP32, where
-    // it measured as fast as the LDS-tiled one; in FP64 the LDS-tiled kernel is faster;
-    // MMK_PSI_WALK=0/1 overrides)
+    // it measured as fast as the LDS-tiled one; in FP64 the LDS-tiled kernel is faster)
     WalkPlan wp{};
     bool walk = false;
-    bool block = false;  // temporal blocking of the linear motor step (MMK_MOTOR_BLOCK=0: off)
+    bool block = false;  // temporal blocking of the linear motor step
     // the motor tiling of every untaped launch of this context: wide (32 bytes a lane) when the
     // launches carry several micro-steps or sub-steps per load; fixed per context so that
     // every launch sums the s-moments in the same order
     bool wide = false;
     // depletion with sub-cycling: every sub-step of a micro-step in one launch, one block per
-    // (x, y) point, where the tiling allows it (MMK_DEPL_SUB=0: one launch per sub-step)
+    // (x, y) point, where the tiling allows it
     bool depl_fused = true;
     bool have_state = false, have_fluid = false, have_out = false;
     std::string err;
     bool prof = false;
-    int prof_every = 1;              // time every prof_every-th launch of each kernel id
-    int64_t seen[kProfIds] = {0, 0, 0, 0, 0, 0};
+    int prof_every[kProfIds] = {1, 1, 1, 1, 1, 1, 1, 1};  // time every n-th launch of each kernel id (0: none)
+    int64_t seen[kProfIds] = {0, 0, 0, 0, 0, 0, 0, 0};
     std::vector<hipEvent_t> ev[kProfIds];  // start/stop pairs
-    int nev[kProfIds] = {0, 0, 0, 0, 0, 0};
+    int nev[kProfIds] = {0, 0, 0, 0, 0, 0, 0, 0};
     TapeState tape;
     std::vector<double> host_tab64;  // host copies of the angle tables (outlive the async copy)
     std::vector<float> host_tab32;
@@ -225,8 +225,8 @@ static mmk_status hipfail(mmk_ctx *c, hipError_t e, const char *what) {
 // ---- profiling: event pairs around launches ---------------------------------------------
 static hipError_t prof_begin_on(mmk_ctx *c, int id, int *slot, hipStream_t s) {
     *slot = -1;
-    if (!c->prof || c->nev[id] >= kProfMax) return hipSuccess;
-    if (c->seen[id]++ % c->prof_every != 0) return hipSuccess;
+    if (!c->prof || c->nev[id] >= kProfMax || c->prof_every[id] == 0) return hipSuccess;
+    if (c->seen[id]++ % c->prof_every[id] != 0) return hipSuccess;
     int i = c->nev[id];
     while ((int)c->ev[id].size() < 2 * (i + 1)) {
         hipEvent_t e;
@@ -245,6 +245,27 @@ static hipError_t prof_end_on(mmk_ctx *c, int id, int slot, hipStream_t s) {
 static hipError_t prof_begin(mmk_ctx *c, int id, int *slot) { return prof_begin_on(c, id, slot, c->stream); }
 static hipError_t prof_end(mmk_ctx *c, int id, int slot) { return prof_end_on(c, id, slot, c->stream); }
 
+// What the options select (mmk_set_option); called at create and after every change.
+static void apply_options(mmk_ctx *c) {
+    const mmk_params &p = c->p;
+    const int psik = c->opt[MMK_OPT_PSI_KERNEL];
+    c->walk = c->wp.ok && (psik == 0 ? c->esz == 4 : psik == 2);
+    c->block = p.m_total == 0 && p.rc == 0 && c->opt[MMK_OPT_MOTOR_BLOCK] != 0;
+    c->wide = c->block || (p.motor_cfl > 0 && p.m_total == 0);
+    c->depl_fused = c->opt[MMK_OPT_DEPL_FUSED] != 0;
+}
+
+// Motor constants of one launch with the context's tiling options.
+template <typename T>
+static MotorConst<T> motor_cst(const mmk_ctx *c, double dt, bool wide) {
+    MotorConst<T> mc = motor_const<T>(c->p, dt);
+    mc.wide = wide ? 1 : 0;
+    mc.lanes = c->opt[MMK_OPT_MOTOR_LANES];
+    mc.chunks = c->opt[MMK_OPT_MOTOR_CHUNKS];
+    mc.nt = c->opt[MMK_OPT_MOTOR_NT];
+    return mc;
+}
+
 // ---- typed step ---------------------------------------------------------------------------
 template <typename T>
 static mmk_status motor_half(mmk_ctx *c, const T *M_in, T *M_out, T *m0, T *m1, double dt, hipStream_t s) {
@@ -252,8 +273,7 @@ static mmk_status motor_half(mmk_ctx *c, const T *M_in, T *M_out, T *m0, T *m1, 
     int slot;
     HIPCHK(c, prof_begin_on(c, 0, &slot, s), "hipEventRecord");
     const T *Dxy = p.m_total > 0 ? c->at<T>(c->L.Dxy) : nullptr;
-    MotorConst<T> mc = motor_const<T>(p, dt);
-    mc.wide = c->wide && !c->tape.active;
+    const MotorConst<T> mc = motor_cst<T>(c, dt, c->wide && !c->tape.active);
     HIPCHK(c, launch_motor_step<T>(M_in, M_out, m0, m1, n_psi(p), p.ns, p.limiter, mc, Dxy, s), "motor step launch");
     HIPCHK(c, prof_end_on(c, 0, slot, s), "hipEventRecord");
     return MMK_OK;
@@ -307,9 +327,8 @@ static mmk_status micro_step(mmk_ctx *c, const T *M_in, T *M_out, const T *psi_i
         T *bufs[2] = {const_cast<T *>(M_in), M_out};
         T *Dxy = c->at<T>(c->L.Dxy);
         const int64_t np = n_psi(p), nxy = (int64_t)p.nx * p.ny;
-        MotorConst<T> mc = motor_const<T>(p, dt);  // dt / n per launch
+        MotorConst<T> mc = motor_cst<T>(c, dt, false);  // dt / n per launch
         mc.nsub = 1;
-        mc.wide = 0;
         for (int q = 0; q < nsub; ++q) {
             if (q > 0)
                 HIPCHK(c, launch_depletion_m0<T>(psi_in, m0, Dxy, nxy, p.ntheta, (T)(kTwoPi / p.ntheta), (T)p.m_total,
@@ -380,8 +399,7 @@ static mmk_status run_steps_blocked(mmk_ctx *c, int K, double dt) {
         const int nb = std::min(kMaxBlock, K - done);
         const bool out = done + nb == K;  // the call's last micro-step, with the outputs
         const int a = c->cur, b = 1 - c->cur;
-        MotorConst<T> mc = motor_const<T>(p, dt);
-        mc.wide = c->wide;
+        MotorConst<T> mc = motor_cst<T>(c, dt, c->wide);
         mc.nstep = nb;
         mc.m0_steps = m0s;
         int slot;
@@ -663,13 +681,7 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
     }
     tape_init(&c->tape, ckpt_every, ckpt_every > 0 ? max_tape_steps : 0);
     c->wp = plan_walk(p->nx, p->ny, p->ntheta);
-    const char *ew = getenv("MMK_PSI_WALK");
-    c->walk = c->wp.ok && (ew ? atoi(ew) != 0 : c->esz == 4);
-    const char *eb = getenv("MMK_MOTOR_BLOCK");
-    c->block = p->m_total == 0 && p->rc == 0 && (eb ? atoi(eb) != 0 : true);
-    c->wide = c->block || (p->motor_cfl > 0 && p->m_total == 0);
-    const char *ed = getenv("MMK_DEPL_SUB");
-    c->depl_fused = ed ? atoi(ed) != 0 : true;
+    apply_options(c);
     *out = c;
     return MMK_OK;
 }
@@ -693,6 +705,24 @@ mmk_status mmk_set_params(mmk_ctx *c, double k_on, double k_off, double v0) {
     c->p.k_on = k_on;
     c->p.k_off = k_off;
     c->p.v0 = v0;
+    return MMK_OK;
+}
+
+mmk_status mmk_set_option(mmk_ctx *c, int32_t option, int32_t value) {
+    if (!c) return MMK_ERR_ARG;
+    bool ok;
+    switch (option) {
+        case MMK_OPT_MOTOR_BLOCK:
+        case MMK_OPT_DEPL_FUSED: ok = value == 0 || value == 1; break;
+        case MMK_OPT_PSI_KERNEL: ok = value >= 0 && value <= 2; break;
+        case MMK_OPT_MOTOR_LANES: ok = value == 0 || (value >= 2 && value <= 64 && (value & (value - 1)) == 0); break;
+        case MMK_OPT_MOTOR_CHUNKS: ok = value == 0 || value == 1 || value == 2 || value == 4; break;
+        case MMK_OPT_MOTOR_NT: ok = value >= -1 && value <= 1; break;
+        default: return fail(c, MMK_ERR_ARG, "unknown option %d", option);
+    }
+    if (!ok) return fail(c, MMK_ERR_ARG, "value %d out of range for option %d", value, option);
+    c->opt[option] = value;
+    apply_options(c);
     return MMK_OK;
 }
 
@@ -917,8 +947,18 @@ mmk_status mmk_profile(mmk_ctx *c, int32_t enable) {
     HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (enable < 0) return fail(c, MMK_ERR_ARG, "enable must be >= 0");
     c->prof = enable != 0;
-    c->prof_every = enable > 0 ? enable : 1;
-    for (int i = 0; i < kProfIds; ++i) c->nev[i] = 0, c->seen[i] = 0;
+    for (int i = 0; i < kProfIds; ++i) c->nev[i] = 0, c->seen[i] = 0, c->prof_every[i] = enable > 0 ? enable : 1;
+    return MMK_OK;
+}
+
+mmk_status mmk_profile_every(mmk_ctx *c, int32_t id, int32_t every) {
+    if (!c) return MMK_ERR_ARG;
+    if (id < 0 || id >= kProfIds) return fail(c, MMK_ERR_ARG, "kernel id out of range");
+    if (every < 0) return fail(c, MMK_ERR_ARG, "every must be >= 0");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    c->prof_every[id] = every;
+    c->nev[id] = 0;
+    c->seen[id] = 0;
     return MMK_OK;
 }
 

@@ -14,7 +14,6 @@
 #include "device_util.h"
 #include "kernels.h"
 
-#include <cstdlib>
 #include <type_traits>
 
 namespace mmk {
@@ -371,19 +370,13 @@ static hipError_t launch_nt(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol,
 }
 
 // Streaming (nontemporal) loads/stores of M keep psi and m0 of the next psi step in the
-// caches: measured faster in FP32, slower in FP64 on MI355X.  MMK_MOTOR_NT=0/1 overrides.
-static bool motor_nontemporal(int elem) {
-    static const int env = [] {
-        const char *e = getenv("MMK_MOTOR_NT");
-        return e ? atoi(e) : -1;
-    }();
-    return env >= 0 ? env != 0 : elem == 4;
-}
+// caches: measured faster in FP32, slower in FP64 on MI355X.  opt: -1 that default, 0 or 1.
+static bool motor_nontemporal(int elem, int opt) { return opt >= 0 ? opt != 0 : elem == 4; }
 
 template <typename T, int CPL, int LPC, bool RAGGED, int LIM>
 static hipError_t launch_lim(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                              const MotorConst<T> &c, const T *Dxy, hipStream_t s, unsigned blocks) {
-    if (!RAGGED && motor_nontemporal((int)sizeof(T)))
+    if (!RAGGED && motor_nontemporal((int)sizeof(T), c.nt))
         return launch_nt<T, CPL, LPC, RAGGED, LIM, true>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, blocks);
     return launch_nt<T, CPL, LPC, RAGGED, LIM, false>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, blocks);
 }
@@ -406,35 +399,30 @@ static hipError_t launch_cfg(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
 // where the arithmetic bounds the launch) take 32 bytes per lane: fewer neighbour exchanges
 // and a shorter s-reduction per cell (measured at 64 cells: FP32 +11%, FP64 +29%; one step per
 // load is faster with 16); FP32 columns of 64 cells take 64 bytes (16 cells) per lane, another
-// 10% (1302 -> 1168 us per 10-micro-step launch at 256x256x64).  MMK_MOTOR_LPC overrides
-// (measurements).
-static int lanes_per_column(int ns, int elem, bool wide) {
+// 10% (1302 -> 1168 us per 10-micro-step launch at 256x256x64).  want > 0 (the lanes option)
+// replaces the default when it leaves 16 to 64 bytes per lane.
+static int lanes_per_column(int ns, int elem, bool wide, int want) {
     const int cpl = 16 / elem;
     if (ns < 2 * cpl || ns % cpl != 0) return 0;
     int lpc = ns / cpl;
     if (lpc > 64 || (lpc & (lpc - 1)) != 0) return 0;
     if (wide && elem == 4 && ns == 64) lpc = 4;
     else if (wide && lpc >= 4) lpc /= 2;
-    if (const char *e = getenv("MMK_MOTOR_LPC")) {
-        const int want = atoi(e);
-        if (want >= 2 && want <= 64 && (want & (want - 1)) == 0 && ns % want == 0) {
-            const int c = ns / want;
-            if (c * elem >= 16 && c <= 16) lpc = want;
-        }
+    if (want >= 2 && want <= 64 && (want & (want - 1)) == 0 && ns % want == 0) {
+        const int c = ns / want;
+        if (c * elem >= 16 && c <= 16) lpc = want;
     }
     return lpc;
 }
 
-// Chunks of 16 bytes per lane for the chunked tiling (1: plain tiling).  MMK_MOTOR_NCH
-// overrides the default (measurements).
-static int chunks_per_lane(int ns, int elem) {
-    int nch = 1;
-    if (const char *e = getenv("MMK_MOTOR_NCH")) nch = atoi(e);
+// Chunks of 16 bytes per lane for the chunked tiling (1: plain tiling): `want` (the chunks
+// option) where ns allows it.
+static int chunks_per_lane(int ns, int elem, int want) {
     const int w = 16 / elem;
-    if (nch < 2 || ns % (nch * w) != 0) return 1;
-    const int lpc = ns / (nch * w);
+    if (want < 2 || ns % (want * w) != 0) return 1;
+    const int lpc = ns / (want * w);
     if (lpc < 2 || lpc > 16 || (lpc & (lpc - 1)) != 0) return 1;
-    return nch;
+    return want;
 }
 
 // Depleted micro-step with sub-cycling in one launch (Alg. 2's inner loop with the clamp inside
@@ -554,9 +542,9 @@ template <typename T>
 hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                              int limiter, const MotorConst<T> &c, const T *Dxy, hipStream_t s) {
     // the chunked tiling has no depletion
-    const int nch = Dxy ? 1 : chunks_per_lane(ns, (int)sizeof(T));
+    const int nch = Dxy ? 1 : chunks_per_lane(ns, (int)sizeof(T), c.chunks);
     if (nch > 1) {
-        const bool nt = motor_nontemporal((int)sizeof(T));
+        const bool nt = motor_nontemporal((int)sizeof(T), c.nt);
         const int lpc = ns / (nch * (16 / (int)sizeof(T)));
 #define MMK_CHUNK_CASE(NCH, LPC)                                                              \
         if (nch == NCH && lpc == LPC) return launch_chunked<T, NCH, LPC>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s, nt);
@@ -564,7 +552,7 @@ hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
         MMK_CHUNK_CASE(4, 2) MMK_CHUNK_CASE(2, 2)
 #undef MMK_CHUNK_CASE
     }
-    const int lpc = lanes_per_column(ns, (int)sizeof(T), c.wide != 0);
+    const int lpc = lanes_per_column(ns, (int)sizeof(T), c.wide != 0, c.lanes);
 #define MMK_MOTOR_CASE(NS, LPC)                                                                   \
     if (ns == NS && lpc == LPC)                                                                   \
         return launch_cfg<T, NS / LPC, LPC, false>(M_in, M_out, m0, m1, ncol, ns, limiter, c, Dxy, s);

@@ -16,7 +16,6 @@
 #include "psi_dev.h"
 
 #include <cstdio>
-#include <cstdlib>
 #include <type_traits>
 
 namespace mmk {
@@ -29,7 +28,7 @@ static size_t psi_lds(int ti, int tj, int nth, size_t elem, int nf) {
 // Tile choice: the largest of the candidate tiles whose LDS footprint stays <= 40 KB (so
 // several blocks share a CU), else <= 64 KB, that still gives at least kMinTiles blocks; a grid
 // too small for that takes the fitting compiled tile with the most blocks (latency, not
-// bandwidth, bounds such grids).  MMK_PSI_TILE=TIxTJ overrides (measurements).
+// bandwidth, bounds such grids).
 static constexpr int kMinTiles = 1024;
 PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem, int nf) {
     static const int cand[][2] = {{8, 8}, {4, 8}, {4, 4}, {2, 4}, {2, 2}, {1, 2}, {1, 1}};
@@ -37,15 +36,6 @@ PsiLaunch plan_psi(int nx, int ny, int nth, size_t elem, int nf) {
     PsiLaunch pl{};
     pl.group = nth <= 16 ? 16 : (nth <= 32 ? 32 : 64);
     bool chosen = false;
-    if (const char *e = nf == 2 ? getenv("MMK_PSI_TILE") : nullptr) {
-        int a = 0, b = 0;
-        if (sscanf(e, "%dx%d", &a, &b) == 2 && a > 0 && b > 0 && a <= 16 && b <= 16 &&
-            psi_lds(a, b, nth, elem, nf) <= 64 * 1024) {
-            pl.ti = a;
-            pl.tj = b;
-            chosen = true;
-        }
-    }
     auto ntiles = [&](int ti, int tj) { return (long)((nx + ti - 1) / ti) * ((ny + tj - 1) / tj); };
     for (size_t limit : {(size_t)40 * 1024, (size_t)64 * 1024}) {
         if (chosen) break;

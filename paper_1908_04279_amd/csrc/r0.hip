@@ -20,7 +20,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstdlib>
 
 namespace mmk {
 
@@ -456,32 +455,15 @@ int r0_vx(size_t esz, int lmax) {
     int v = 1;
     if (lmax <= 8) v = 2;
     else if (lmax <= 16) v = (int)(8 / esz);
-    // MMK_R0_VX = 1, 2 or 4 overrides for runs of at most 8 cells (measurements)
-    if (const char *e = getenv("MMK_R0_VX")) {
-        const int want = atoi(e);
-        if (lmax <= 8 && (want == 1 || want == 2 || (want == 4 && esz == 4))) v = want;
-    }
     return v;
 }
 
-// Anchors per lane of the coarse kernel: one (measured at the benchmark workload: 98.6 us per
-// coarse pass in FP32 against 109 with 16-byte loads of the run totals, 138 against 141 in
-// FP64); MMK_R0_CVX = 16 / sizeof(value) takes the 16-byte loads where the rows allow
-// (measurements).
-static int coarse_vx(int64_t nxy, size_t esz) {
-    const int v = (int)(16 / esz);
-    if (const char *e = getenv("MMK_R0_CVX"))
-        if (atoi(e) == v && nxy % v == 0) return v;
-    return 1;
-}
 
 int r0_coarse_split(int64_t nxy, int nseg, size_t esz) {
-    // about 4096 blocks of 4 waves over the chip (MMK_R0_CBLOCKS overrides, for measurements),
-    // 4 rows of partials per block
-    int64_t target = 4096;
-    if (const char *e = getenv("MMK_R0_CBLOCKS"))
-        if (atoi(e) >= 64) target = atoi(e);
-    const int64_t gx = (nxy + 64 * coarse_vx(nxy, esz) - 1) / (64 * coarse_vx(nxy, esz));
+    // about 4096 blocks of 4 waves over the chip, 4 rows of partials per block
+    const int64_t target = 4096;
+    (void)esz;
+    const int64_t gx = (nxy + 63) / 64;
     const int64_t want = (target + gx - 1) / std::max<int64_t>(gx, 1);
     return (int)std::max<int64_t>(1, std::min<int64_t>({want, 64, ((int64_t)nseg + 3) / 4}));
 }
@@ -531,13 +513,10 @@ hipError_t launch_r0_coarse(const T *q0, const T *psi, T *psiT, const R0Seg *seg
     hipLaunchKernelGGL(k_r0_psiT<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, psi, psiT, c.nxy, c.nth);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    constexpr int V = 16 / sizeof(T);
-    if (coarse_vx(c.nxy, sizeof(T)) == V)
-        hipLaunchKernelGGL((k_r0_coarse<T, V>), dim3((unsigned)((c.nxy + 64 * V - 1) / (64 * V)), (unsigned)nsplit),
-                           dim3(256), 0, s, q0, psiT, seg, part, c, nseg, 4 * nsplit);
-    else
-        hipLaunchKernelGGL((k_r0_coarse<T, 1>), dim3((unsigned)((c.nxy + 63) / 64), (unsigned)nsplit), dim3(256), 0, s,
-                           q0, psiT, seg, part, c, nseg, 4 * nsplit);
+    // one anchor per lane (measured at the benchmark workload: 98.6 us per coarse pass in FP32
+    // against 109 with 16-byte loads of the run totals, 138 against 141 in FP64)
+    hipLaunchKernelGGL((k_r0_coarse<T, 1>), dim3((unsigned)((c.nxy + 63) / 64), (unsigned)nsplit), dim3(256), 0, s,
+                       q0, psiT, seg, part, c, nseg, 4 * nsplit);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double w = c.dA * dth;  // dx dy dth (q0 already carries ds)

@@ -20,13 +20,17 @@ LIB_PATH = os.path.join(HERE, "libmmk.so")
 MMK_OK, MMK_ERR_ARG, MMK_ERR_NOMEM, MMK_ERR_HIP, MMK_ERR_STATE, MMK_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 SUPERBEE, UPWIND1 = 0, 1
+# implementation options (mmk_set_option): name -> id
+OPTIONS = {"motor_block": 0, "psi_kernel": 1, "depl_fused": 2, "motor_lanes": 3, "motor_chunks": 4,
+           "motor_nt": 5}
 KERNEL_IDS = {"motor_step": 0, "psi_step": 1, "global_sums": 2, "psi_step_reverse": 3,
               "motor_step_reverse": 4, "motor_force": 5, "r0_motor_step": 6, "r0_coarse": 7}
 
 EXPORTS = ["mmk_workspace_bytes", "mmk_create", "mmk_destroy", "mmk_set_params", "mmk_set_state",
            "mmk_set_fluid", "mmk_step", "mmk_get_state", "mmk_get_stress", "mmk_get_moments",
            "mmk_get_motor_moments", "mmk_get_force", "mmk_get_anchors", "mmk_r0_cells", "mmk_get_sums", "mmk_tape_begin", "mmk_tape_backward",
-           "mmk_tape_end", "mmk_profile", "mmk_profile_read", "mmk_last_error"]
+           "mmk_tape_end", "mmk_profile", "mmk_profile_read", "mmk_profile_every", "mmk_set_option",
+           "mmk_last_error"]
 
 
 class MMKError(RuntimeError):
@@ -77,6 +81,8 @@ def lib():
             "mmk_tape_end": ([vp], C.c_int),
             "mmk_profile": ([vp, i32], C.c_int),
             "mmk_profile_read": ([vp, i32, C.POINTER(d), C.POINTER(i64)], C.c_int),
+            "mmk_profile_every": ([vp, i32, i32], C.c_int),
+            "mmk_set_option": ([vp, i32, i32], C.c_int),
             "mmk_last_error": ([vp], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -132,7 +138,7 @@ class Context:
     """
 
     def __init__(self, p, precision=FP64, ckpt_every=0, max_tape_steps=0, device=None,
-                 stream=None):
+                 stream=None, options=None):
         self.p = p
         self.params = make_params(p, precision)
         self.dtype = torch.float64 if precision == FP64 else torch.float32
@@ -155,6 +161,8 @@ class Context:
             self.shape_M = (self.ncell, nx, ny)
         else:
             self.shape_M = (nx, ny, nt, ns)
+        for name, value in (options or {}).items():
+            self.set_option(name, value)
 
     # -- helpers ------------------------------------------------------------------------
     def _check(self, st):
@@ -184,6 +192,10 @@ class Context:
     # -- C-ABI calls ------------------------------------------------------------------------
     def set_params(self, k_on, k_off, v0):
         self._check(lib().mmk_set_params(self.h, float(k_on), float(k_off), float(v0)))
+
+    def set_option(self, name, value):
+        """mmk_set_option by name (OPTIONS): an implementation choice of the same micro-step."""
+        self._check(lib().mmk_set_option(self.h, OPTIONS[name], int(value)))
 
     def set_state(self, psi, M=None):
         psi_t = self._dev(psi, self.shape_psi)
@@ -264,6 +276,11 @@ class Context:
     def profile(self, enable=True, every=1):
         """Time every `every`-th launch of each kernel with HIP events (enable=False: off)."""
         self._check(lib().mmk_profile(self.h, int(every) if enable else 0))
+
+    def profile_every(self, kernel, every):
+        """After profile(): time every `every`-th launch of one kernel (0: none)."""
+        kid = KERNEL_IDS[kernel] if isinstance(kernel, str) else int(kernel)
+        self._check(lib().mmk_profile_every(self.h, kid, int(every)))
 
     def profile_read(self, kernel):
         kid = KERNEL_IDS[kernel] if isinstance(kernel, str) else int(kernel)

@@ -44,12 +44,11 @@ def compare(g, o, tol):
 @pytest.mark.parametrize("walk", ["0", "1"])
 @pytest.mark.parametrize("shape,limiter", [((5, 7, 12, 16), 0), ((9, 6, 64, 32), 0), ((9, 6, 64, 32), 1),
                                            ((4, 5, 128, 8), 0), ((13, 3, 32, 20), 1)])
-def test_fp64_against_oracle(monkeypatch, shape, limiter, walk):
+def test_fp64_against_oracle(shape, limiter, walk):
     nx, ny, nt, ns = shape
     p = ModelParams(nx=nx, ny=ny, ntheta=nt, ns=ns, limiter=limiter, k_on=0.9, k_off=0.6, v0=1.2, F=0.8)
     psi0, M0, fl, dt = depleted_case(p)
-    monkeypatch.setenv("MMK_PSI_WALK", walk)
-    g = run_gpu(p, psi0, M0, fl, 6, 17, dt)
+    g = run_gpu(p, psi0, M0, fl, 6, 17, dt, options={"psi_kernel": 2 if walk == "1" else 1})
     o = run_oracle(p, psi0, M0, fl, 6, 17, dt)
     compare(g, o, 1e-12)
 

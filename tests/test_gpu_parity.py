@@ -161,7 +161,7 @@ def test_error_codes():
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("shape", [(20, 18, 64, 64), (13, 7, 128, 16), (9, 5, 64, 128), (1, 1, 64, 32),
                                    (17, 3, 128, 64)])
-def test_walking_and_lds_psi_kernels_agree(monkeypatch, precision, shape):
+def test_walking_and_lds_psi_kernels_agree(precision, shape):
     """ntheta = 64, 128: the LDS-free walking psi kernel (8 x 4 pencil tiles, one wave per row)
     against the LDS-tiled one, over several calls and fluid exchanges, on grids that are not
     multiples of either tile; the FP64 result also against the oracle."""
@@ -169,9 +169,8 @@ def test_walking_and_lds_psi_kernels_agree(monkeypatch, precision, shape):
     p = ModelParams(nx=nx, ny=ny, ntheta=nt, ns=ns)
     psi0, M0, fl, dt = seeded_case(p, n_exchanges=4, M0_kind="random")
     runs = {}
-    for name, walk in (("walk", "1"), ("lds", "0")):
-        monkeypatch.setenv("MMK_PSI_WALK", walk)
-        runs[name] = run_gpu(p, psi0, M0, fl, 7, 25, dt, precision=precision)
+    for name, kernel in (("walk", 2), ("lds", 1)):
+        runs[name] = run_gpu(p, psi0, M0, fl, 7, 25, dt, precision=precision, options={"psi_kernel": kernel})
     compare(runs["walk"], runs["lds"], tol=1e-12 if precision == 0 else 1e-5)
     if precision == 0:
         compare(runs["walk"], run_oracle(p, psi0, M0, fl, 7, 25, dt))

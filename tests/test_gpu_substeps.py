@@ -54,13 +54,12 @@ def test_fp64_against_oracle(shape, limiter, n):
     compare(g, o, 1e-12)
 
 
-def test_chunked_blocked_against_oracle(monkeypatch):
+def test_chunked_blocked_against_oracle():
     """The chunked tiling (16 cells a lane) with sub-cycling inside blocks, FP64, against the
     oracle."""
-    monkeypatch.setenv("MMK_MOTOR_NCH", "4")
     p = ModelParams(nx=6, ny=5, ntheta=16, ns=64, k_on=0.9, k_off=0.6, v0=4.0, F=0.8)
     psi0, M0, fl, dt = substep_case(p, 3)
-    g = run_gpu(p, psi0, M0, fl, 9, 18, dt)
+    g = run_gpu(p, psi0, M0, fl, 9, 18, dt, options={"motor_chunks": 4})
     o = run_oracle(p, psi0, M0, fl, 9, 18, dt)
     compare(g, o, 1e-12)
 
@@ -107,28 +106,28 @@ def test_refusals():
     ctx.close()
 
 
-@pytest.mark.parametrize("shape,precision,calls,nch", [
+@pytest.mark.parametrize("shape,precision,calls,tiling", [
     ((8, 6, 16, 32), 0, [1, 7, 16, 17, 33], None),   # blocks of 16 with every remainder kind
     ((9, 5, 12, 20), 0, [10, 3], None),              # masked generic kernel
-    ((12, 10, 64, 64), 1, [10, 10, 25], None),       # FP32, compiled walk psi kernel
-    ((12, 10, 64, 64), 1, [10, 7], "2"),             # FP32, chunked tiling (8 cells a lane)
-    ((8, 6, 16, 64), 0, [12, 5], "2"),               # FP64, chunked tiling
+    ((12, 10, 64, 64), 1, [10, 10, 25], None),       # FP32, the default wide tiling (16 cells a lane)
+    ((12, 10, 64, 32), 1, [10, 6], None),            # FP32, 8 cells a lane
+    ((12, 10, 64, 64), 0, [10, 10, 25], None),       # FP64, 8 cells a lane
+    ((12, 10, 64, 64), 1, [10, 7], {"motor_chunks": 2}),   # FP32, chunked tiling (8 cells a lane)
+    ((8, 6, 16, 64), 0, [12, 5], {"motor_chunks": 2}),     # FP64, chunked tiling
 ])
-def test_temporal_blocking_is_bitwise_serial(monkeypatch, shape, precision, calls, nch):
+def test_temporal_blocking_is_bitwise_serial(shape, precision, calls, tiling):
     """A run of several mmk_step calls gives the same bits with the motor field blocked over
-    up to 16 micro-steps per launch (default for m_total = 0) and with one launch per
-    micro-step (MMK_MOTOR_BLOCK=0); also with sub-cycling inside the blocks.  Both runs use
-    the blocked runs' column tiling (32 bytes a lane; a one-launch-per-step context would
-    otherwise take 16, which sums the s-moments in another order)."""
+    up to 16 micro-steps per launch (the default for m_total = 0) and with one launch per
+    micro-step (motor_block = 0); also with sub-cycling inside the blocks.  The serial run is
+    given the blocked run's column tiling through the motor_lanes option (the blocked default:
+    16 cells a lane for FP32 columns of 64, 32 bytes a lane otherwise; a one-launch-per-step
+    context would otherwise take 16 bytes, which sums the s-moments in another order)."""
     import torch
     from paper_1908_04279_amd import mmk
     nx, ny, nt, ns = shape
-    if nch:
-        monkeypatch.setenv("MMK_MOTOR_NCH", nch)
-    else:
-        cpl = 32 // (4 if precision else 8)
-        if ns % cpl == 0:
-            monkeypatch.setenv("MMK_MOTOR_LPC", str(ns // cpl))
+    if tiling is None:
+        cpl = (16 if ns == 64 else 8) if precision else 4
+        tiling = {"motor_lanes": ns // cpl} if ns % cpl == 0 else {}
     for cfl in (0.0, 0.15):
         p = ModelParams(nx=nx, ny=ny, ntheta=nt, ns=ns, motor_cfl=cfl)
         psi0 = gen.make_psi0(nx, ny, nt, p.lx, p.ly, seed=0)
@@ -136,9 +135,10 @@ def test_temporal_blocking_is_bitwise_serial(monkeypatch, shape, precision, call
         fl = gen.fluid_schedule(nx, ny, len(calls), p.lx, p.ly)
         dt = gen.cfl_dt(p, fl)
         outs = []
-        for block in ("1", "0"):
-            monkeypatch.setenv("MMK_MOTOR_BLOCK", block)
-            ctx = mmk.Context(p, precision=precision)
+        for block in (1, 0):
+            # the blocked run keeps the default tiling; the serial run is given it
+            opts = {"motor_block": block, **(tiling if (block == 0 or "motor_chunks" in tiling) else {})}
+            ctx = mmk.Context(p, precision=precision, options=opts)
             if precision:
                 ctx.set_state(torch.as_tensor(psi0.astype(np.float32)), torch.as_tensor(M0.astype(np.float32)))
             else:
@@ -157,7 +157,7 @@ def test_temporal_blocking_is_bitwise_serial(monkeypatch, shape, precision, call
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-14), (1, 1e-6)])
-def test_wide_and_narrow_tilings_agree(monkeypatch, precision, tol):
+def test_wide_and_narrow_tilings_agree(precision, tol):
     """The default blocked context (64 bytes of the column per lane in FP32, 32 in FP64) against
     one launch per micro-step (16 bytes per lane): the same scheme, only the association of the
     s-sums differs."""
@@ -169,9 +169,8 @@ def test_wide_and_narrow_tilings_agree(monkeypatch, precision, tol):
     fl = gen.fluid_schedule(p.nx, p.ny, 3, p.lx, p.ly)
     dt = gen.cfl_dt(p, fl)
     outs = []
-    for block in ("1", "0"):
-        monkeypatch.setenv("MMK_MOTOR_BLOCK", block)
-        ctx = mmk.Context(p, precision=precision)
+    for block in (1, 0):
+        ctx = mmk.Context(p, precision=precision, options={"motor_block": block})
         cast = (lambda a: a.astype(np.float32)) if precision else (lambda a: a)
         ctx.set_state(torch.as_tensor(cast(psi0)), torch.as_tensor(cast(M0)))
         for e in range(3):
@@ -198,13 +197,13 @@ def test_wide_and_narrow_tilings_agree(monkeypatch, precision, tol):
     ((20, 18, 64, 64), 3, 1, None, "0"),
     ((8, 6, 32, 32), 4, 1, None, "1"),     # FP32, 4 lanes per column
 ])
-def test_depleted_substeps_against_oracle(monkeypatch, shape, n, precision, walk, fused):
+def test_depleted_substeps_against_oracle(shape, n, precision, walk, fused):
     """Depletion with sub-cycling: every sub-step takes the clamp and the pool of the current
     sub-state (Alg. 2), m_total between the smallest and the largest coarse density so both
     branches occur; in one launch per micro-step and in one launch per sub-step."""
-    monkeypatch.setenv("MMK_DEPL_SUB", fused)
+    opts = {"depl_fused": int(fused)}
     if walk is not None:
-        monkeypatch.setenv("MMK_PSI_WALK", walk)
+        opts["psi_kernel"] = 2 if walk == "1" else 1
     nx, ny, nt, ns = shape
     p = ModelParams(nx=nx, ny=ny, ntheta=nt, ns=ns, k_on=0.9, k_off=0.6, v0=4.0, F=0.8)
     psi0, M0, fl, dt = substep_case(p, n)
@@ -213,13 +212,13 @@ def test_depleted_substeps_against_oracle(monkeypatch, shape, n, precision, walk
     assert (Bv > p.m_total).any() and (Bv < p.m_total).any()
     if precision:
         psi0, M0 = psi0.astype(np.float32), M0.astype(np.float32)
-    g = run_gpu(p, psi0, M0, fl, 4, 8, dt, precision=precision)
+    g = run_gpu(p, psi0, M0, fl, 4, 8, dt, precision=precision, options=opts)
     o = run_oracle(p, psi0.astype(np.float64), M0.astype(np.float64), fl, 4, 8, dt)
     compare(g, o, 1e-5 if precision else 1e-12)
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6)])
-def test_depleted_substeps_one_launch_and_per_substep_agree(monkeypatch, precision, tol):
+def test_depleted_substeps_one_launch_and_per_substep_agree(precision, tol):
     """The single-launch depleted sub-cycling (one block per (x, y) point) against one launch per
     sub-step: the same scheme; only the association of the coarse-density sum differs."""
     import torch
@@ -229,9 +228,8 @@ def test_depleted_substeps_one_launch_and_per_substep_agree(monkeypatch, precisi
     Bv = A.coarse_bound(p, psi0, M0.sum(-1) * (p.L / p.ns))
     p.m_total = float(0.5 * (Bv.min() + Bv.max()))
     outs = []
-    for fused in ("1", "0"):
-        monkeypatch.setenv("MMK_DEPL_SUB", fused)
-        ctx = mmk.Context(p, precision=precision)
+    for fused in (1, 0):
+        ctx = mmk.Context(p, precision=precision, options={"depl_fused": fused})
         cast = (lambda a: a.astype(np.float32)) if precision else (lambda a: a)
         ctx.set_state(torch.as_tensor(cast(psi0)), torch.as_tensor(cast(M0)))
         for e in range(3):
