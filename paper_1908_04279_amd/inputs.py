@@ -159,6 +159,34 @@ def make_M0_random(nx, ny, ntheta, ns, k_on=1.0, k_off=0.5, seed=5):
     return np.ascontiguousarray(rng.uniform(0.0, k_on / k_off, (nx, ny, ntheta, ns)))
 
 
+def M0_columns_values(cols, ns, k_on=1.0, k_off=0.5):
+    """Closed-form bound-motor density whose columns differ (no random draw, so any column can
+    be formed on its own): column c (flat index of (x, y, th)) holds
+        (1 + (c mod 97) / 97) * (k_on / k_off) * (l + 1/2) / ns,   l = 0 .. ns-1,
+    in FP64.  97 is prime, so columns 2^k apart (a wrapped 32-bit offset) hold other values.
+    cols: integer array of column indices; returns [len(cols)][ns]."""
+    cols = np.asarray(cols, dtype=np.int64)
+    w = 1.0 + (cols % 97).astype(np.float64) / 97.0
+    ramp = (k_on / k_off) * (np.arange(ns, dtype=np.float64) + 0.5) / ns
+    return w[:, None] * ramp[None, :]
+
+
+def make_M0_columns_device(nx, ny, ntheta, ns, dtype, device, k_on=1.0, k_off=0.5, chunk=1 << 22):
+    """M0_columns_values for every column of the grid, formed on the device in FP64 and rounded
+    once to `dtype` (the same values as the host form), [nx][ny][ntheta][ns]; built in chunks of
+    columns to bound the FP64 temporaries."""
+    import torch
+    ncol = nx * ny * ntheta
+    out = torch.empty((ncol, ns), dtype=dtype, device=device)
+    ramp = (k_on / k_off) * (torch.arange(ns, dtype=torch.float64, device=device) + 0.5) / ns
+    for c0 in range(0, ncol, chunk):
+        c1 = min(ncol, c0 + chunk)
+        cols = torch.arange(c0, c1, dtype=torch.int64, device=device)
+        w = 1.0 + (cols % 97).to(torch.float64) / 97.0
+        out[c0:c1] = (w[:, None] * ramp[None, :]).to(dtype)
+    return out.view(nx, ny, ntheta, ns)
+
+
 def make_Mb0_random(ncell, nx, ny, k_on=1.0, k_off=0.5, seed=6):
     """Random anchor-resolved bound-motor density [ncell][nx][ny], U[0, k_on/k_off]."""
     rng = np.random.default_rng(seed)

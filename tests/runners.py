@@ -116,3 +116,37 @@ def run_r0_gpu(p, psi0, Mb0, fluids, K, n, dt, precision=0, options=None):
     torch.cuda.synchronize()
     ctx.close()
     return out
+
+
+def run_oracle_window(p, psi0, M0_of_cols, fluids, calls, dt, i, j, R):
+    """FP64 oracle at grid point (i, j) after the micro-steps of `calls` (K of each mmk_step
+    call; call e uses fluids[e]), from the (2R+1) x (2R+1) patch of the periodic grid centred
+    there.  The patch runs as a periodic grid of its own with the full grid's cell sizes.  The
+    donor-cell stencil reaches one cell per step and the motor columns of the linear model are
+    independent, so for sum(calls) <= R the patch centre sees only its true neighbours and the
+    result there is the full-grid oracle's, bit for bit (pinned on the CPU).
+    psi0: the full [nx][ny][nth] array; M0_of_cols(cols) -> [len(cols)][ns], the initial motor
+    columns by flat column index (i, j, k) -> (i ny + j) nth + k.
+    Returns the centre's psi [nth], M [nth][ns], m0, m1 [nth], stress [3], moments [7]."""
+    from dataclasses import replace
+    n = int(sum(calls))
+    assert R >= n
+    w = 2 * R + 1
+    if w >= min(p.nx, p.ny):
+        raise ValueError("window as large as the grid: run the full oracle")
+    ii = (i + np.arange(-R, R + 1)) % p.nx
+    jj = (j + np.arange(-R, R + 1)) % p.ny
+    q = replace(p, nx=w, ny=w, lx=p.lx / p.nx * w, ly=p.ly / p.ny * w)
+    psi = np.ascontiguousarray(np.asarray(psi0)[np.ix_(ii, jj)], dtype=np.float64)
+    cols = ((ii[:, None, None] * p.ny + jj[None, :, None]) * p.ntheta
+            + np.arange(p.ntheta)[None, None, :]).reshape(-1)
+    M = np.ascontiguousarray(M0_of_cols(cols), dtype=np.float64).reshape(w, w, p.ntheta, p.ns)
+    o = A.OracleA(q)
+    o.set_state(psi, M)
+    for e, k in enumerate(calls):
+        u, g = fluids[e]
+        o.set_fluid(np.ascontiguousarray(u[:, ii][:, :, jj]), np.ascontiguousarray(g[:, ii][:, :, jj]))
+        o.step(int(k), dt)
+    stress, mom = o.get_stress_moments()
+    return dict(psi=o.psi[R, R].copy(), M=o.M[R, R].copy(), m0=o.m0[R, R].copy(), m1=o.m1[R, R].copy(),
+                stress=stress[:, R, R].copy(), mom=mom[:, R, R].copy())

@@ -83,3 +83,29 @@ def test_uniform_columns_decompose_bitwise():
     assert np.array_equal(np.broadcast_to(col, M_a.shape), M_a)
     s, m = A.moments(p, psi, np.full(psi.shape, m0c), np.full(psi.shape, m1c))
     assert np.array_equal(s, s_a) and np.array_equal(m, m_a)
+
+
+@pytest.mark.parametrize("point", [(0, 0), (7, 5), (13, 10), (2, 9)])
+def test_window_oracle_is_the_full_oracle_at_its_centre(point):
+    """The windowed oracle the full-size parity cases sample with: a (2R+1)^2 patch run as its
+    own periodic grid gives, at its centre, the full oracle's values bit for bit after R
+    micro-steps (columns differ, three calls with their own fluid fields, a grid edge)."""
+    from tests.runners import run_oracle_window
+    p = ModelParams(nx=14, ny=11, ntheta=8, ns=8, F=0.8)
+    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0)
+    fl = gen.fluid_schedule(p.nx, p.ny, 3, p.lx, p.ly)
+    dt = gen.cfl_dt(p, fl)
+    calls = [2, 1, 1]
+    M0 = gen.M0_columns_values(np.arange(p.nx * p.ny * p.ntheta), p.ns).reshape(p.nx, p.ny, p.ntheta, p.ns)
+    o = A.OracleA(p)
+    o.set_state(psi0, M0)
+    for e, k in enumerate(calls):
+        o.set_fluid(*fl[e])
+        o.step(k, dt)
+    s, m = o.get_stress_moments()
+    i, j = point
+    w = run_oracle_window(p, psi0, lambda c: gen.M0_columns_values(c, p.ns), fl, calls, dt, i, j, R=4)
+    assert np.array_equal(w["psi"], o.psi[i, j])
+    assert np.array_equal(w["M"], o.M[i, j])
+    assert np.array_equal(w["m0"], o.m0[i, j]) and np.array_equal(w["m1"], o.m1[i, j])
+    assert np.array_equal(w["stress"], s[:, i, j]) and np.array_equal(w["mom"], m[:, i, j])
