@@ -5,9 +5,16 @@ arclength cells (268M bound-motor cells), FP32 storage and arithmetic, a new see
 field every K = 10 micro-steps, stress/moments/global sums on every exchange.  A "step" is
 one micro-step of the whole path: motor column step, s-moments, psi donor-cell update,
 and (every 10th) theta-moments, stress and FP64 global sums.  Inputs are resident in HBM
-before the timed region.  Also measured: the same grid in FP64, the same grid in FP32 with
-free-motor depletion, the motor force density of the grid, the adjoint/forward time ratios,
-and the oracle (FP64 C, OpenMP) on a bounded sample of the same grid on the host cores.
+before the timed region.  The headline runs the library's default order, in which the motor
+field of the linear model is advanced through the 10 micro-steps of a call in one launch
+(every cell of every micro-step is computed; M is read and written once per call); the
+same grid with one motor launch per micro-step (the HBM-bound form) is reported beside it,
+each with its own roofline.  Also measured: both forms in FP64, 512^2 x 128 x 64 FP32,
+128^2 x 64 x 32 FP64, the launch-bound 16^2 x 16 x 16 FP64 case eager and as a replayed HIP
+graph, free-motor depletion, motor sub-cycling, the motor force density, the anchor-resolved
+model, the adjoint/forward time ratios, the VALU issue rates of the chip, the FP32 error per
+output against the FP64 oracle, and the oracle (FP64 C) on bounded samples on the host
+cores (all threads at 256^2 x 64 x 64, one thread at 16^2 x 16 x 16 and 128^2 x 64 x 32).
 
 Prints one JSON line.  --gpus N > 1 is refused: this path runs on one GPU.
 """
@@ -34,6 +41,9 @@ CSRC = os.path.join(ROOT, "paper_1908_04279_amd", "csrc")
 # counters count only while those sources are unchanged)
 COUNTERS = (os.path.join(ROOT, "profiles", "motor_step_f32_256x256x64x64_counters.txt"),
             ["motor.hip", "device_util.h", "kernels.h"])
+# the same for one motor launch per micro-step (16 bytes of the column per lane)
+COUNTERS_PLAIN = (os.path.join(ROOT, "profiles", "motor_step_plain_f32_256x256x64x64_counters.txt"),
+                  ["motor.hip", "device_util.h", "kernels.h"])
 # kernel launches bracketed by HIP events inside the timed region: every EVENT_EVERY-th launch
 # of each kernel (an event pair on every launch costs ~14 us per micro-step on MI355X, ~4%)
 EVENT_EVERY = 13
@@ -106,20 +116,43 @@ def psi_bytes(p, b, out):
     return b * (3 * n_psi + 6 * nxy) + (b * (n_psi + 10 * nxy) if out else 0)
 
 
-def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1, options=None):
+_INPUTS = {}
+
+
+def fluids_of(p, n):
+    """Seeded fluid fields 1 .. n of the grid (host, FP64), generated once per grid."""
+    key = ("fluid", p.nx, p.ny, p.lx, p.ly)
+    from paper_1908_04279_amd import inputs as gen
+    have = _INPUTS.setdefault(key, [])
+    for e in range(len(have), n):
+        have.append(gen.make_fluid(p.nx, p.ny, p.lx, p.ly, seed=1 + e))
+    return have[:n]
+
+
+def psi0_of(p):
+    """Seeded initial filament density of the grid (host, FP64), generated once per grid."""
+    key = ("psi0", p.nx, p.ny, p.ntheta, p.lx, p.ly)
+    if key not in _INPUTS:
+        from paper_1908_04279_amd import inputs as gen
+        _INPUTS[key] = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0)
+    return _INPUTS[key]
+
+
+def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1, options=None, motor_every=None):
+    """One forward leg: warmup, then `steps` micro-steps in calls of K with a new fluid field
+    each, timed on the host around the whole; every event_every-th launch of each kernel (of
+    the motor kernel every motor_every-th, if given) carries HIP events."""
     import torch
     from paper_1908_04279_amd import inputs as gen
     from paper_1908_04279_amd import mmk
 
     n_ex = (warmup + steps) // K + 2
-    log(f"[bench] generating {n_ex} fluid fields for {p.nx}x{p.ny}")
-    fluids_np = [gen.make_fluid(p.nx, p.ny, p.lx, p.ly, seed=1 + e) for e in range(n_ex)]
+    fluids_np = fluids_of(p, n_ex)
     dt = gen.cfl_dt(p, fluids_np)
     ctx = mmk.Context(p, precision=precision, options=options)
     fl = [(torch.as_tensor(u).to(ctx.device, ctx.dtype), torch.as_tensor(g).to(ctx.device, ctx.dtype))
           for u, g in fluids_np]
-    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0)
-    ctx.set_state(torch.as_tensor(psi0))
+    ctx.set_state(torch.as_tensor(psi0_of(p)))
     torch.cuda.synchronize()
 
     def advance(nsteps, e0):
@@ -132,11 +165,14 @@ def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1, opt
             e += 1
         return e
 
-    log(f"[bench] warmup {warmup} steps")
+    log(f"[bench] {p.nx}x{p.ny}x{p.ntheta}x{p.ns} {'FP32' if precision == mmk.FP32 else 'FP64'} "
+        f"{options or ''}: warmup {warmup} steps, {steps} timed")
     e = advance(warmup, 0)
     torch.cuda.synchronize()
     if profile:
         ctx.profile(True, every=event_every)
+        if motor_every is not None:
+            ctx.profile_every("motor_step", motor_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     advance(steps, e)
@@ -152,7 +188,8 @@ def run_forward(p, precision, steps, warmup, K, profile=True, event_every=1, opt
     mass, ss = ctx.get_sums()
     ctx.close()
     return dict(elapsed=elapsed, steps=steps, dt=dt, prof=prof, mass=mass, event_every=event_every,
-                blocks=block_plan(p, K, options))
+                motor_every=event_every if motor_every is None else motor_every,
+                blocks=block_plan(p, K, options), p=p, K=K, precision=precision)
 
 
 def run_adjoint(name, precision):
@@ -230,7 +267,7 @@ def run_force(p, precision, reps):
     from paper_1908_04279_amd import inputs as gen
     from paper_1908_04279_amd import mmk
     ctx = mmk.Context(p, precision=precision)
-    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0)
+    psi0 = psi0_of(p)
     M0 = torch.rand(p.nx, p.ny, p.ntheta, p.ns, dtype=ctx.dtype, device=ctx.device,
                     generator=torch.Generator(device=ctx.device).manual_seed(5)) * (p.k_on / p.k_off)
     ctx.set_state(torch.as_tensor(psi0), M0)
@@ -320,12 +357,12 @@ def run_r0(precision, steps, warmup, K, event_every, **over):
     cells = mmk.r0_cells(p)
     ncell, nrun = len(cells), r0_runs(cells)
     n_ex = (warmup + steps) // K + 2
-    fluids_np = [gen.make_fluid(p.nx, p.ny, p.lx, p.ly, seed=1 + e) for e in range(n_ex)]
+    fluids_np = fluids_of(p, n_ex)
     dt = gen.cfl_dt(p, fluids_np)
     ctx = mmk.Context(p, precision=precision)
     fl = [(torch.as_tensor(u).to(ctx.device, ctx.dtype), torch.as_tensor(g).to(ctx.device, ctx.dtype))
           for u, g in fluids_np]
-    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0)
+    psi0 = psi0_of(p)
     Mb0 = torch.rand(ncell, p.nx, p.ny, dtype=ctx.dtype, device=ctx.device,
                      generator=torch.Generator(device=ctx.device).manual_seed(6)) * (p.k_on / p.k_off)
     ctx.set_state(torch.as_tensor(psi0), Mb0)
@@ -412,12 +449,12 @@ def sources_sha(files):
     return h.hexdigest()[:16]
 
 
-def counters_traffic(n_plain, n_out, steps_per_launch=1):
+def counters_traffic(n_plain, n_out, steps_per_launch=1, counters=COUNTERS):
     """HBM bytes per motor launch (weighted like `achieved`: n_plain launches without and
-    n_out with the m1 output) from the committed rocprofv3 counter summary, or None when it
+    n_out with the m1 output) from a committed rocprofv3 counter summary, or None when it
     is missing, was taken on different kernel sources or on launches of another number of
     micro-steps."""
-    path, files = COUNTERS
+    path, files = counters
     if not os.path.exists(path):
         return None
     kv = {}
@@ -438,22 +475,153 @@ def counters_traffic(n_plain, n_out, steps_per_launch=1):
 
 
 def cpu_baseline(p, sample_steps):
-    """The FP64 C oracle on the same grid, a few micro-steps, on the host cores."""
+    """The FP64 C oracle on the same grid (M0 = 0, fluid seed 1 held fixed), a few micro-steps,
+    on the host cores.  Returns the record and the oracle (its state is the FP64 reference of
+    the FP32 error report)."""
     from oracle import oracle_a as A
     from paper_1908_04279_amd import inputs as gen
-    u, g = gen.make_fluid(p.nx, p.ny, p.lx, p.ly, seed=1)
+    u, g = fluids_of(p, 1)[0]
     dt = gen.cfl_dt(p, [(u, g)])
     o = A.OracleA(p)
-    o.set_state(gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0))
+    o.set_state(psi0_of(p))
     o.set_fluid(u, g)
     threads = A.max_threads()
     log(f"[bench] cpu baseline: oracle, {sample_steps} steps, {threads} threads")
     t0 = time.perf_counter()
     o.step(sample_steps, dt)
     el = time.perf_counter() - t0
-    return dict(value=sample_steps / el, unit="micro-steps/s", cores=threads, kind="oracle",
-                sample=f"{sample_steps} FP64 micro-steps of the full {p.nx}x{p.ny}x{p.ntheta}x{p.ns} grid "
-                       f"(C oracle, OpenMP over x rows), {el:.1f} s")
+    rec = dict(value=sample_steps / el, unit="micro-steps/s", cores=threads, kind="oracle",
+               sample=f"{sample_steps} FP64 micro-steps of the full {p.nx}x{p.ny}x{p.ntheta}x{p.ns} grid "
+                      f"(C oracle, OpenMP over x rows), {el:.1f} s")
+    return rec, o, dt
+
+
+def cpu_oracle_one_thread(name, steps):
+    """The FP64 C oracle on one host thread (the analogue of a single-threaded code) on a
+    bounded sample of a seeded workload: `steps` micro-steps from its initial state."""
+    from oracle import oracle_a as A
+    from paper_1908_04279_amd import inputs as gen
+    p = gen.params_for(name)
+    u, g = fluids_of(p, 1)[0]
+    dt = gen.cfl_dt(p, [(u, g)])
+    o = A.OracleA(p)
+    o.set_state(psi0_of(p))
+    o.set_fluid(u, g)
+    before = A.max_threads()
+    A.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o.step(steps, dt)
+        el = time.perf_counter() - t0
+    finally:
+        A.set_threads(before)
+    return {"value": steps / el, "unit": "micro-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} FP64 micro-steps of {p.nx}x{p.ny}x{p.ntheta}x{p.ns} on one thread, {el:.2f} s"}
+
+
+def fp32_errors(p, o, dt, steps):
+    """The FP32 path against the FP64 oracle state of the CPU baseline (same inputs, dt and
+    steps; one call): norm-wise relative error max|x - ref| / max|ref| per output."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    from oracle import oracle_a as A
+    ctx = mmk.Context(p, precision=mmk.FP32)
+    ctx.set_state(torch.as_tensor(psi0_of(p)))
+    ctx.set_fluid(*map(torch.as_tensor, fluids_of(p, 1)[0]))
+    ctx.step(steps, dt)
+    psi, M = ctx.get_state()
+    m0, m1 = ctx.get_motor_moments()
+    stress, mom = ctx.get_stress(), ctx.get_moments()
+    mass, ss = ctx.get_sums()
+    s_ref, mom_ref = o.get_stress_moments()
+    mass_ref, ss_ref = A.global_sums(p, o.psi, s_ref)
+
+    def rel(x, ref):
+        x = x.double().cpu().numpy() if hasattr(x, "cpu") else np.asarray(x, dtype=np.float64)
+        return float(np.abs(x - ref).max() / np.abs(ref).max())
+    names = ["c", "n_x", "n_y", "D_xx", "D_xy", "D_yy", "B"]
+    out = {"steps": steps, "grid": f"{p.nx}x{p.ny}x{p.ntheta}x{p.ns}",
+           "stress_xx": rel(stress[0], s_ref[0]), "stress_xy": rel(stress[1], s_ref[1]),
+           "stress_yy": rel(stress[2], s_ref[2]), "stress": rel(stress, s_ref)}
+    for i, n in enumerate(names):
+        out[f"moment_{n}"] = rel(mom[i], mom_ref[i])
+    # M columns stay equal (M0 = 0): every column against the oracle's
+    out.update(psi=rel(psi, o.psi), M=rel(M[0, 0], o.M[0, 0]) if M.numel() else None,
+               M_columns_spread=float((M.amax(dim=(0, 1)) - M.amin(dim=(0, 1))).abs().max()),
+               m0=rel(m0, o.m0), m1=rel(m1, o.m1), mass=abs(mass - mass_ref) / abs(mass_ref),
+               sum_sigma=float(np.abs(np.array(ss) - ss_ref).max() / np.abs(ss_ref).max()))
+    ctx.close()
+    return out
+
+
+def run_launch_bound(reps):
+    """The 16^2 x 16 x 16 FP64 workload (100 micro-steps per call, fixed fluid): host-timed
+    micro-steps/s of repeated calls, eager (mmk_step) and as a replayed HIP graph
+    (mmk_step_graph), after two untimed calls each."""
+    import torch
+    from paper_1908_04279_amd import inputs as gen
+    from paper_1908_04279_amd import mmk
+    p = gen.params_for("fp64_16x16x16x16")
+    K = gen.CONFIGS["fp64_16x16x16x16"]["K"]
+    fl = fluids_of(p, 1)
+    dt = gen.cfl_dt(p, fl)
+    out = {"workload": "16x16 grid, 16 orientations, 16 arclength cells, FP64, 100 micro-steps per call",
+           "calls": reps}
+    for mode in ("eager", "graph"):
+        ctx = mmk.Context(p)
+        ctx.set_state(torch.as_tensor(psi0_of(p)))
+        ctx.set_fluid(*map(torch.as_tensor, fl[0]))
+        run = ctx.step if mode == "eager" else ctx.step_graph
+        for _ in range(2):
+            run(K, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run(K, dt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx.close()
+        out[f"{mode}_micro_steps_per_s"] = reps * K / el
+        out[f"{mode}_us_per_micro_step"] = el / (reps * K) * 1e6
+    out["graph_over_eager"] = out["graph_micro_steps_per_s"] / out["eager_micro_steps_per_s"]
+    return out
+
+
+CALIB_KINDS = {"fma_f32": (0, 2), "add_f32": (1, 1), "max_f32": (2, 1), "med3_f32": (3, 1),
+               "fma_f64": (4, 2), "mov_dpp": (5, 0), "cmp_cndmask": (6, 0)}
+
+
+def valu_calibration():
+    """Issue rate of single VALU instruction kinds on the whole chip (libmmk_calib): 8192 waves
+    (8 per SIMD) of 8 independent chains; wave64 instructions per second, lane operations per
+    second and, for the arithmetic kinds, FLOP/s (an FMA counted as 2)."""
+    import ctypes as C
+    import torch
+    path = os.path.join(ROOT, "paper_1908_04279_amd", "libmmk_calib.so")
+    if not os.path.exists(path):
+        return None
+    L = C.CDLL(path)
+    f = L.mmk_calib_valu
+    f.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
+    f.restype = C.c_int
+    blocks, iters = 2048, 4096
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {"waves": blocks * 4, "instructions_per_lane": 64 * iters}
+    for name, (kind, flops) in CALIB_KINDS.items():
+        ms = C.c_double()
+        for rep in range(2):   # the second launch is the measurement
+            st = f(kind, blocks, iters, C.c_void_p(out.data_ptr()), stream, C.byref(ms))
+            if st != 0:
+                return {"error": f"calibration kind {name}: hip error {st}"}
+        per_count = 2 if name == "cmp_cndmask" else 1
+        wave_insts = blocks * 4 * 64 * iters * per_count
+        rate = wave_insts / (ms.value * 1e-3)
+        res[name] = {"ms": ms.value, "wave_instructions_per_s": rate, "lane_ops_per_s": rate * 64,
+                     "cycles_per_wave_instruction_per_simd": 256 * 4 * 2.4e9 / rate}
+        if flops:
+            res[name]["tflops"] = rate * 64 * flops / 1e12
+    return res
 
 
 def main():
@@ -464,16 +632,18 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=130)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "fp32", "fp64", "adjoint", "adjoint64", "depletion", "force",
-                                       "substeps", "r0", "r0_fp32"],
+    ap.add_argument("--only", choices=["all", "fp32", "fp64", "fp32_1", "adjoint", "adjoint64", "depletion", "force",
+                                       "substeps", "r0", "r0_fp32", "large", "c2", "launch_bound", "calib"],
                     default="all",
                     help="restrict to one leg (used for profiler runs)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--depletion-steps", type=int, default=200)
     ap.add_argument("--substep-steps", type=int, default=200)
     ap.add_argument("--r0-steps", type=int, default=200)
+    ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--event-every", type=int, default=EVENT_EVERY,
-                    help="bracket every N-th launch of each kernel with HIP events")
+                    help="bracket every N-th launch of each kernel with HIP events (the headline leg's "
+                         "motor launches: every one)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -499,6 +669,12 @@ def main():
         print(json.dumps({"force_fp32": run_force(gen.params_for("fp32_256x256x64x64"), mmk.FP32, 10)}),
               flush=True)
         return
+    if args.only == "calib":
+        print(json.dumps({"valu_calibration": valu_calibration()}), flush=True)
+        return
+    if args.only == "launch_bound":
+        print(json.dumps({"launch_bound_fp64_16x16x16x16": run_launch_bound(50)}), flush=True)
+        return
 
     if args.only in ("r0", "r0_fp32"):
         r0 = {"anchor_resolved_fp32": run_r0(mmk.FP32, args.r0_steps, 20, 10, args.event_every)}
@@ -511,6 +687,10 @@ def main():
     p = gen.params_for("fp32_256x256x64x64")
     K = 10
     res = {}
+    calib = None
+    if args.only == "all":
+        log("[bench] VALU calibration")
+        calib = valu_calibration()
     if args.only in ("all", "depletion"):
         # the same grid with free-motor depletion and the over-binding clamp
         pd = gen.params_for("fp32_256x256x64x64", m_total=M_TOTAL_BENCH)
@@ -530,48 +710,77 @@ def main():
                                            event_every=args.event_every)
         res["fast_depl_sub_1"] = run_forward(pds, mmk.FP32, min(args.substep_steps, 100), 10, K,
                                              event_every=args.event_every, options={"depl_fused": 0})
-    if args.only in ("all", "fp32"):
-        res["fp32"] = run_forward(p, mmk.FP32, args.steps, args.warmup, K, event_every=args.event_every)
     if args.only in ("all", "fp64"):
         res["fp64"] = run_forward(p, mmk.FP64, args.fp64_steps, min(args.warmup, 20), K,
                                   event_every=args.event_every)
-    if args.only == "all":
+    if args.only in ("all", "fp32"):
+        # the headline: runs right after the FP64 leg (the chip at its working clock), every
+        # motor launch of the timed region bracketed by HIP events
+        res["fp32"] = run_forward(p, mmk.FP32, args.steps, args.warmup, K, event_every=args.event_every,
+                                  motor_every=1)
+    if args.only in ("all", "fp32_1"):
         # the same grid with one motor launch per micro-step (HBM-bound): FP32 and FP64
         res["fp32_1"] = run_forward(p, mmk.FP32, args.fp64_steps, 20, K, event_every=args.event_every,
                                     options={"motor_block": 0})
+    if args.only == "all":
         res["fp64_1"] = run_forward(p, mmk.FP64, args.fp64_steps, 20, K, event_every=args.event_every,
                                     options={"motor_block": 0})
+    large = {}
+    if args.only in ("all", "large"):
+        # the largest single-GPU case, 512^2 x 128 x 64 FP32 (2^31 motor cells), both orders
+        pl = gen.params_for("fp32_512x512x128x64")
+        torch.cuda.reset_peak_memory_stats()
+        large["blocked"] = run_forward(pl, mmk.FP32, args.large_steps, 10, K, event_every=args.event_every,
+                                       motor_every=1)
+        large["peak_device_gb"] = torch.cuda.max_memory_allocated() / 1e9
+        large["one_launch"] = run_forward(pl, mmk.FP32, args.large_steps, 10, K, event_every=args.event_every,
+                                          options={"motor_block": 0}, motor_every=1)
+    c2 = None
+    if args.only in ("all", "c2"):
+        # paper-like scale in FP64: 128^2 x 64 x 32, 1000 micro-steps, a new fluid every 10
+        c2 = run_forward(gen.params_for("fp64_128x128x64x32"), mmk.FP64, 1000, 20, K, event_every=args.event_every)
 
-    def summarise(r, b):
+    def summarise(r):
         """Whole-step rate, and the motor kernel's roofline over its timed launches.  A K-step
         call runs the motor launches of r["blocks"] (micro-steps each); the last one of a call
         carries the outputs (m1, stress, moments), as does the psi launch of the call's last
         micro-step.  Launches j = 0, E, 2E, ... of each kernel in the timed region carry HIP
-        events."""
-        calls = r["steps"] // K
+        events (E = r["motor_every"] for the motor kernel, r["event_every"] for psi)."""
+        q, Kr = r["p"], r["K"]
+        b = 4 if r["precision"] == mmk.FP32 else 8
+        calls = r["steps"] // Kr
         blocks = r["blocks"]
         sps = r["steps"] / r["elapsed"]
         launches = [(nb, i == len(blocks) - 1) for _ in range(calls) for i, nb in enumerate(blocks)]
-        total = sum(motor_bytes(p, b, out, nb) for nb, out in launches) \
-            + (r["steps"] - calls) * psi_bytes(p, b, False) + calls * psi_bytes(p, b, True)
-        timed_m = launches[::r["event_every"]]
+        total = sum(motor_bytes(q, b, out, nb) for nb, out in launches) \
+            + (r["steps"] - calls) * psi_bytes(q, b, False) + calls * psi_bytes(q, b, True)
+        timed_m = launches[::r["motor_every"]]
         timed_p = list(range(0, r["steps"], r["event_every"]))
         ms_m, n_m = r["prof"]["motor_step"]
         ms_p, n_p = r["prof"]["psi_step"]
         assert n_m == len(timed_m) and n_p == len(timed_p), (n_m, n_p, len(timed_m), len(timed_p))
         n_out = sum(1 for _, out in timed_m if out)
-        kb = sum(motor_bytes(p, b, out, nb) for nb, out in timed_m) / n_m
-        kf = sum(motor_flops(p, out, nb) for nb, out in timed_m) / n_m
+        kb = sum(motor_bytes(q, b, out, nb) for nb, out in timed_m) / n_m
+        kf = sum(motor_flops(q, out, nb) for nb, out in timed_m) / n_m
         steps_per_launch = sum(nb for nb, _ in timed_m) / n_m
         return dict(steps_per_s=sps, step_gbs=total / r["elapsed"] / 1e9, avg_us=ms_m / n_m * 1e3,
                     gbs=kb / (ms_m / n_m / 1e3) / 1e9, bytes_per_launch=kb, n_plain=n_m - n_out,
                     tflops=kf / (ms_m / n_m / 1e3) / 1e12, flops_per_launch=kf,
                     n_out=n_out, psi_avg_us=ms_p / n_p * 1e3, timed_launches=n_m, mass=r["mass"],
                     steps_per_launch=steps_per_launch,
-                    motor_us_per_step=ms_m / n_m * 1e3 / steps_per_launch)
+                    motor_us_per_step=ms_m / n_m * 1e3 / steps_per_launch, b=b)
+
+    def hbm_roofline(sm, counters=None):
+        traffic = counters_traffic(sm["n_plain"], sm["n_out"], sm["steps_per_launch"], counters) \
+            if counters and sm["b"] == 4 else None
+        return {"bound": "hbm", "achieved": sm["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": sm["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "motor column step, one launch per micro-step",
+                "avg_launch_us": sm["avg_us"], "algorithmic_bytes_per_launch": sm["bytes_per_launch"],
+                "timed_launches": sm["timed_launches"], "output_launches_timed": sm["n_out"]}
 
     def depletion_summary():
-        sd = summarise(res["depletion"], 4)
+        sd = summarise(res["depletion"])
         d = {"m_total": M_TOTAL_BENCH, "micro_steps_per_s": sd["steps_per_s"],
              "ms_per_step": 1e3 / sd["steps_per_s"], "motor_avg_us": sd["avg_us"], "motor_gbs": sd["gbs"],
              "motor_frac": sd["gbs"] / HBM_PEAK_GBS, "psi_avg_us": sd["psi_avg_us"],
@@ -584,7 +793,7 @@ def main():
         d = {"v0": SUBSTEP_V0, "motor_cfl": MOTOR_CFL_BENCH}
         for key, name in (("fast_plain", "one_motor_step"), ("fast_sub", "subcycled")):
             r = res[key]
-            sr = summarise(r, 4)
+            sr = summarise(r)
             rate = SUBSTEP_V0 / (p.L / p.ns) + p.k_off
             n = max(1, math.ceil(r["dt"] * rate / MOTOR_CFL_BENCH)) if key == "fast_sub" else 1
             d[name] = {"dt": r["dt"], "motor_steps_per_micro_step": n, "micro_steps_per_s": sr["steps_per_s"],
@@ -612,52 +821,90 @@ def main():
     if args.only == "substeps":
         print(json.dumps({"substeps_fp32": substep_summary()}), flush=True)
         return
+    if args.only in ("large", "c2"):
+        d = {}
+        if large:
+            d["fp32_512x512x128x64"] = {k: (summarise(v) if isinstance(v, dict) else v) for k, v in large.items()}
+        if c2:
+            d["fp64_128x128x64x32"] = summarise(c2)
+        print(json.dumps(d), flush=True)
+        return
 
     out = {"metric": METRIC, "unit": "micro-steps/s", "n_gpus": 1, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
-    main_leg = "fp32" if "fp32" in res else "fp64"
-    b_main = 4 if main_leg == "fp32" else 8
-    s = summarise(res[main_leg], b_main)
+    main_leg = "fp32" if "fp32" in res else ("fp32_1" if "fp32_1" in res else "fp64")
+    s = summarise(res[main_leg])
+    blocked = max(res[main_leg]["blocks"]) > 1
     out.update(value=s["steps_per_s"], steps=res[main_leg]["steps"], warmup=args.warmup,
-               ms_per_step=1e3 / s["steps_per_s"], dtype="f32" if main_leg == "fp32" else "f64",
+               ms_per_step=1e3 / s["steps_per_s"], dtype="f32" if s["b"] == 4 else "f64",
                config={"workload": "256x256 grid, 64 orientations, 64 arclength cells, "
-                                   f"{'FP32' if main_leg == 'fp32' else 'FP64'}, fluid exchange every 10 steps",
+                                   f"{'FP32' if s['b'] == 4 else 'FP64'}, fluid exchange every 10 steps, "
+                                   + ("motor field blocked over the 10 micro-steps of a call"
+                                      if blocked else "one motor launch per micro-step"),
                        "nx": p.nx, "ny": p.ny, "ntheta": p.ntheta, "ns": p.ns,
                        "motor_cells": p.nx * p.ny * p.ntheta * p.ns, "K": K})
-    traffic = counters_traffic(s["n_plain"], s["n_out"], s["steps_per_launch"]) if main_leg == "fp32" else None
-    # the motor launch against the roof it is closest to: HBM for one micro-step per launch,
-    # the FP32 vector ALU when the field is blocked over several micro-steps
-    alu_peak = FP32_VECTOR_PEAK_TFLOPS if main_leg == "fp32" else FP64_VECTOR_PEAK_TFLOPS
-    hbm_frac, alu_frac = s["gbs"] / HBM_PEAK_GBS, s["tflops"] / alu_peak
-    if alu_frac > hbm_frac:
-        roof = {"bound": "alu", "achieved": s["tflops"], "peak": alu_peak, "unit": "TFLOP/s", "frac": alu_frac}
+    if blocked:
+        # the blocked launch does 10 micro-steps of arithmetic per read and write of M: the
+        # vector ALU bounds it; the roof is the published FP32 (FP64) vector peak, with the
+        # chip's measured issue rates beside it
+        alu_peak = FP32_VECTOR_PEAK_TFLOPS if s["b"] == 4 else FP64_VECTOR_PEAK_TFLOPS
+        traffic = counters_traffic(s["n_plain"], s["n_out"], s["steps_per_launch"]) if s["b"] == 4 else None
+        roof = {"bound": "alu", "achieved": s["tflops"], "peak": alu_peak, "unit": "TFLOP/s",
+                "frac": s["tflops"] / alu_peak, "traffic": traffic,
+                "kernel": "motor column step, 10 micro-steps per launch (temporally blocked)"}
+        if calib and "fma_f32" in calib:
+            meas = calib["fma_f32" if s["b"] == 4 else "fma_f64"]["tflops"]
+            roof.update(measured_fma_peak_tflops=meas, frac_of_measured_fma_peak=s["tflops"] / meas)
     else:
-        roof = {"bound": "hbm", "achieved": s["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_frac}
-    roof.update({"traffic": traffic, "kernel": "motor column step", "avg_launch_us": s["avg_us"],
-                 "micro_steps_per_launch": s["steps_per_launch"],
+        roof = hbm_roofline(s, COUNTERS_PLAIN)
+        roof["achieved"] = s["gbs"]
+    roof.update({"avg_launch_us": s["avg_us"], "micro_steps_per_launch": s["steps_per_launch"],
                  "motor_us_per_micro_step": s["motor_us_per_step"],
                  "algorithmic_bytes_per_launch": s["bytes_per_launch"], "hbm_gbs": s["gbs"],
-                 "hbm_frac": hbm_frac, "algorithmic_flops_per_launch": s["flops_per_launch"],
-                 "alu_tflops": s["tflops"], "alu_frac": alu_frac,
-                 "timed_launches": s["timed_launches"], "output_launches_timed": s["n_out"]})
+                 "hbm_frac": s["gbs"] / HBM_PEAK_GBS, "algorithmic_flops_per_launch": s["flops_per_launch"],
+                 "alu_tflops": s["tflops"], "timed_launches": s["timed_launches"],
+                 "output_launches_timed": s["n_out"]})
     out["roofline"] = roof
     out["step_hbm_gbs"] = s["step_gbs"]
     out["step_hbm_frac"] = s["step_gbs"] / HBM_PEAK_GBS
     out["psi_step_avg_us"] = s["psi_avg_us"]
     if "fp32" in res and "fp64" in res:
-        s64 = summarise(res["fp64"], 8)
+        s64 = summarise(res["fp64"])
         out["fp64"] = {"micro_steps_per_s": s64["steps_per_s"], "ms_per_step": 1e3 / s64["steps_per_s"],
                        "step_hbm_gbs": s64["step_gbs"], "motor_gbs": s64["gbs"],
-                       "motor_frac": s64["gbs"] / HBM_PEAK_GBS, "motor_avg_us": s64["avg_us"],
+                       "motor_tflops": s64["tflops"], "motor_alu_frac": s64["tflops"] / FP64_VECTOR_PEAK_TFLOPS,
+                       "motor_avg_us": s64["avg_us"], "psi_avg_us": s64["psi_avg_us"],
                        "steps": res["fp64"]["steps"]}
         out["fp32_over_fp64"] = s["steps_per_s"] / s64["steps_per_s"]
     if "fp32_1" in res and "fp64_1" in res:
-        a1, b1 = summarise(res["fp32_1"], 4), summarise(res["fp64_1"], 8)
+        a1, b1 = summarise(res["fp32_1"]), summarise(res["fp64_1"])
         out["one_launch_per_step"] = {
             "fp32_micro_steps_per_s": a1["steps_per_s"], "fp64_micro_steps_per_s": b1["steps_per_s"],
-            "fp32_motor_frac_hbm": a1["gbs"] / HBM_PEAK_GBS, "fp64_motor_frac_hbm": b1["gbs"] / HBM_PEAK_GBS,
-            "fp32_over_fp64": a1["steps_per_s"] / b1["steps_per_s"]}
+            "fp32_ms_per_step": 1e3 / a1["steps_per_s"], "fp32_step_hbm_gbs": a1["step_gbs"],
+            "fp32_step_hbm_frac": a1["step_gbs"] / HBM_PEAK_GBS, "fp64_step_hbm_gbs": b1["step_gbs"],
+            "fp64_step_hbm_frac": b1["step_gbs"] / HBM_PEAK_GBS,
+            "fp32_psi_avg_us": a1["psi_avg_us"], "fp64_psi_avg_us": b1["psi_avg_us"],
+            "fp32_over_fp64": a1["steps_per_s"] / b1["steps_per_s"],
+            "roofline": hbm_roofline(a1, COUNTERS_PLAIN), "roofline_fp64": hbm_roofline(b1)}
+    if large:
+        lb, l1 = summarise(large["blocked"]), summarise(large["one_launch"])
+        pl = large["blocked"]["p"]
+        out["fp32_512x512x128x64"] = {
+            "motor_cells": pl.nx * pl.ny * pl.ntheta * pl.ns, "steps": large["blocked"]["steps"],
+            "micro_steps_per_s": lb["steps_per_s"], "step_hbm_gbs": lb["step_gbs"], "motor_avg_us": lb["avg_us"],
+            "motor_tflops": lb["tflops"], "psi_avg_us": lb["psi_avg_us"],
+            "one_launch_micro_steps_per_s": l1["steps_per_s"], "one_launch_step_hbm_gbs": l1["step_gbs"],
+            "one_launch_step_hbm_frac": l1["step_gbs"] / HBM_PEAK_GBS, "one_launch_motor_gbs": l1["gbs"],
+            "one_launch_motor_frac": l1["gbs"] / HBM_PEAK_GBS, "one_launch_psi_avg_us": l1["psi_avg_us"],
+            "peak_device_gb": large["peak_device_gb"]}
+    if c2:
+        sc = summarise(c2)
+        out["fp64_128x128x64x32"] = {"steps": c2["steps"], "micro_steps_per_s": sc["steps_per_s"],
+                                     "ms_per_step": 1e3 / sc["steps_per_s"], "step_hbm_gbs": sc["step_gbs"],
+                                     "motor_avg_us": sc["avg_us"], "psi_avg_us": sc["psi_avg_us"]}
     if args.only == "all":
+        log("[bench] launch-bound leg")
+        out["launch_bound_fp64_16x16x16x16"] = run_launch_bound(50)
         log("[bench] motor force leg")
         out["force_fp32"] = run_force(p, mmk.FP32, 10)
     if "fast_sub" in res:
@@ -676,8 +923,19 @@ def main():
         adj64 = run_adjoint("adjoint_fp64_64x64x32x32", mmk.FP64)
         out["adjoint_over_forward"] = adj32["ratio"]
         out["adjoint"] = {"fp32_256x256x64x32_C25": adj32, "fp64_64x64x32x32_C20": adj64}
+    if calib:
+        out["valu_calibration"] = calib
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+        rec, o, dt0 = cpu_baseline(p, args.cpu_steps)
+        out["cpu_baseline"] = rec
+        log("[bench] FP32 error per output against the oracle")
+        out["fp32_error_vs_fp64_oracle"] = fp32_errors(p, o, dt0, args.cpu_steps)
+        del o
+        if args.only == "all":
+            log("[bench] oracle on one thread")
+            out["cpu_oracle_one_thread"] = {
+                "fp64_16x16x16x16": cpu_oracle_one_thread("fp64_16x16x16x16", 100),
+                "fp64_128x128x64x32": cpu_oracle_one_thread("fp64_128x128x64x32", 20)}
     print(json.dumps(out), flush=True)
 
 

@@ -123,42 +123,81 @@ typedef struct {
  * invalid params or an unusable rc (<= 0, or rc + L/2 not below lx/2 and ly/2). */
 int64_t mmk_r0_cells(const mmk_params *p, int32_t *cells);
 
-/* Bytes of device workspace a context needs.  ckpt_every > 0 reserves the adjoint tape:
+/* Bytes of device workspace a context needs (the fields of one micro-step, Sec. 3.1: the whole
+ * state stays resident on the device between steps).  ckpt_every > 0 reserves the adjoint tape:
  * checkpoints of (Psi, M) every ckpt_every steps for up to max_tape_steps taped steps, a
  * ckpt_every-step recompute buffer, adjoint fields and one fluid slot per taped step.
  * ckpt_every = 0 (max_tape_steps ignored) gives the forward-only size.  Returns 0 on
  * invalid params. */
 size_t mmk_workspace_bytes(const mmk_params *p, int32_t ckpt_every, int32_t max_tape_steps);
 
-/* Creates a context on the current HIP device.  workspace: device pointer, 256-byte
- * aligned, ws_bytes >= mmk_workspace_bytes(p, ckpt_every, max_tape_steps).  hip_stream:
- * a hipStream_t (NULL = the null stream).  *out receives the context (host memory owned by
- * the library, freed by mmk_destroy).  Fills the trig tables in the workspace (async). */
+/* Creates a context on the current HIP device: the grid and model of Sec. 2 (Eqs. (1)-(6))
+ * with the discretisation of its Sec. 3.1 (uniform theta and s, superbee, two-stage RK).
+ * workspace: device pointer, 256-byte aligned, ws_bytes >= mmk_workspace_bytes(p, ckpt_every,
+ * max_tape_steps); the caller keeps it alive until mmk_destroy.  hip_stream: a hipStream_t
+ * (NULL = the null stream).  *out receives the context (host memory owned by the library,
+ * freed by mmk_destroy).  Fills the angle tables in the workspace and synchronizes once.
+ * MMK_ERR_ARG: invalid params, NULL or misaligned workspace; MMK_ERR_NOMEM: ws_bytes too small;
+ * MMK_ERR_UNSUPPORTED: sizes beyond the kernels (message says which). */
 mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, void *hip_stream,
                       int32_t ckpt_every, int32_t max_tape_steps, mmk_ctx **out);
 mmk_status mmk_destroy(mmk_ctx *ctx);
 
-/* Replaces k_on, k_off, v0 (host values) for the following steps. */
+/* Replaces the rates of Eq. (4), k_on, k_off, and the walking speed v0 (host values) for the
+ * following steps (for finite-difference and gradient runs).  MMK_ERR_ARG: non-finite values or
+ * v0 < 0; MMK_ERR_STATE: inside a taped run that has steps. */
 mmk_status mmk_set_params(mmk_ctx *ctx, double k_on, double k_off, double v0);
 
-/* Copies the state in: psi [nx][ny][ntheta]; M [nx][ny][ntheta][ns], or NULL for M = 0. */
+/* Copies the state in (device to device, stream-ordered; the sources may be freed once the
+ * stream has passed the call): the filament density psi [nx][ny][ntheta] of Eq. (1) and the
+ * bound-motor density M [nx][ny][ntheta][ns] of Eq. (4), or NULL for M = 0.  Drops the outputs
+ * of earlier steps.  MMK_ERR_ARG: psi NULL; MMK_ERR_STATE: during a taped run. */
 mmk_status mmk_set_state(mmk_ctx *ctx, const void *psi, const void *M);
 
-/* Copies the fluid velocity u [2][nx][ny] and its gradient gradu [4][nx][ny] in; they act
- * on every following micro-step until replaced (the macro exchange). */
+/* Copies the fluid velocity u [2][nx][ny] and its gradient gradu [4][nx][ny] in (device to
+ * device, stream-ordered); they act on every following micro-step until replaced.  This is the
+ * exchange with the macroscale Stokes solve of Eqs. (7)-(9) in Alg. 1: the velocity enters the
+ * translational velocity of Eq. (2), its gradient the rotation rate of Eq. (3).  Recorded by an
+ * active tape.  MMK_ERR_ARG: NULL pointer. */
 mmk_status mmk_set_fluid(mmk_ctx *ctx, const void *u, const void *gradu);
 
-/* Runs K >= 0 micro-steps of size dt (finite, > 0), motors first then Psi driven by the new
- * m0.  The last step also computes stress, moments and the FP64 global sums.  No host sync.
- * Two kernel launches per micro-step (motor, then psi). */
+/* Runs K >= 0 micro-steps of size dt (finite, > 0), each the bound-motor update of Eq. (4)
+ * (Alg. 2: two-stage RK per column, with the clamp and the free pool of Eqs. (5)-(6) under
+ * m_total > 0, sub-cycled under motor_cfl > 0) followed by the conservative update of psi,
+ * Eq. (1), with the velocities of Eqs. (2)-(3) driven by the new m0.  The last micro-step also
+ * forms the theta-moments and the extra stress (the stress step of Alg. 1) and the FP64 global
+ * sums.  No host sync.  Launches: for the linear model one motor launch per up to 16 micro-steps
+ * (MMK_OPT_MOTOR_BLOCK) and one psi launch per micro-step; see mmk_params for the others.
+ * MMK_ERR_ARG: K < 0, dt not finite or <= 0, more than 4096 motor sub-steps, or a taped run past
+ * max_tape_steps; MMK_ERR_STATE: no state or no fluid set. */
 mmk_status mmk_step(mmk_ctx *ctx, int32_t K, double dt);
 
-/* Copies the current state out (either pointer may be NULL). */
+/* The same K micro-steps as mmk_step, replayed as one HIP graph launch on the context's stream
+ * (for launch-bound small grids, where the host's launch overhead exceeds the kernels' time;
+ * Sec. 3.1 puts the micro-step loop on the GPU with no host work between steps).  The first call
+ * for a (K, dt) from a given state buffer captures the launches mmk_step(K, dt) would enqueue
+ * into a graph held by the context (on a capture stream of the library's own; nothing runs
+ * during the capture), later calls replay it: the same kernels with the same arguments, so the
+ * results are bitwise those of mmk_step.  Fields are read and written in place, so set_state and
+ * set_fluid between calls take effect.  mmk_set_params and mmk_set_option drop the captured
+ * graphs; at most 8 are held.  Launches are not timed by mmk_profile.  MMK_ERR_STATE during a
+ * taped run (use mmk_step); otherwise errors as mmk_step.  No host sync. */
+mmk_status mmk_step_graph(mmk_ctx *ctx, int32_t K, double dt);
+
+/* Copies the current state (psi, M as in mmk_set_state) out, device to device, stream-ordered
+ * (either pointer may be NULL).  MMK_ERR_STATE: no state set. */
 mmk_status mmk_get_state(mmk_ctx *ctx, void *psi, void *M);
-/* Stress / moments of the state after the last mmk_step with K > 0. */
+/* Outputs of the last micro-step of the last mmk_step with K > 0 (the extra-stress step of
+ * Alg. 1, from Psi of Eq. (1) and the s-moments of Eq. (5)): sigma [3][nx][ny] =
+ * sigma_f (D - c I/2) + F sum_th psi m1 p p dth, and moments [7][nx][ny] = (c, n_x, n_y, D_xx,
+ * D_xy, D_yy, B) with c = sum psi dth, n = sum psi p dth, D = sum psi p p dth and the coarse
+ * bound density B = sum psi m0 dth (Eq. (5) reduced to one filament).  Device to device,
+ * stream-ordered.  MMK_ERR_ARG: NULL pointer; MMK_ERR_STATE: no step has produced outputs. */
 mmk_status mmk_get_stress(mmk_ctx *ctx, void *sigma);
 mmk_status mmk_get_moments(mmk_ctx *ctx, void *moments);
-/* s-moments of the current M: m0 always, m1 as of the last step that produced outputs. */
+/* s-moments of the current M (Eq. (5) per filament, and the lever-arm moment that enters the
+ * stress): m0 = sum M ds always, m1 = sum (s - L/2) M ds as of the last step that produced
+ * outputs; [nx][ny][ntheta] each, either pointer may be NULL.  MMK_ERR_STATE: no outputs yet. */
 mmk_status mmk_get_motor_moments(mmk_ctx *ctx, void *m0, void *m1);
 /* Motor force density of the current state (Eq. (10)), force [2][nx][ny] = (f_x, f_y): every
  * bound-motor cell l of a filament at (x_i, y_j) with orientation p_k adds F p_k psi M_l ds dth
@@ -178,11 +217,14 @@ mmk_status mmk_get_force(mmk_ctx *ctx, void *force);
  * Eq. (6) before the next step's clamp, m_total - min(coarse, m_total) (1 with m_total = 0).
  * Either pointer may be NULL.  Needs state.  No host sync. */
 mmk_status mmk_get_anchors(mmk_ctx *ctx, void *coarse, void *free_pool);
-/* host outputs, synchronizes: mass = sum Psi dx dy dth and sum_sigma[c] = sum sigma_c dx dy,
- * both accumulated in FP64 in a fixed order (bitwise reproducible). */
+/* Global sums of the last outputs (the total filament count that Eq. (1) conserves, and the
+ * domain integral of the extra stress of Alg. 1), host outputs, synchronizes: mass =
+ * sum Psi dx dy dth and sum_sigma[c] = sum sigma_c dx dy, accumulated in FP64 (compensated) in a
+ * fixed order (bitwise reproducible).  Either pointer may be NULL.  MMK_ERR_STATE: no outputs. */
 mmk_status mmk_get_sums(mmk_ctx *ctx, double *mass, double sum_sigma[3]);
 
-/* Adjoint tape.  mmk_tape_begin records the current state as checkpoint 0 and the current
+/* Adjoint tape (a project extra: the paper has no adjoint; it differentiates the micro-step of
+ * mmk_step).  mmk_tape_begin records the current state as checkpoint 0 and the current
  * fluid; later set_fluid/step calls are recorded (at most max_tape_steps steps).
  * mmk_tape_backward (synchronizes) returns the gradient of
  *     L = <g_sigma, sigma(T)> + <g_moments, moments(T)>
@@ -224,7 +266,8 @@ typedef enum {
 } mmk_option;
 mmk_status mmk_set_option(mmk_ctx *ctx, int32_t option, int32_t value);
 
-/* Kernel timing: with enable = N > 0 every N-th launch of each kernel is bracketed by HIP
+/* Kernel timing (a measurement extra, in the spirit of the profiler-driven analysis of
+ * Sec. 3.2): with enable = N > 0 every N-th launch of each kernel is bracketed by HIP
  * events on the context's stream (enable = 0 turns timing off, < 0 is MMK_ERR_ARG).
  * mmk_profile_read (synchronizes) sums the elapsed times of the timed launches of `kernel_id`
  * (0 motor step, 1 psi step, 2 global sums, 3 reverse psi step, 4 reverse motor step, 5 motor

@@ -1,4 +1,5 @@
-"""Builds libmmk.so (HIP, gfx950) in-tree from csrc/*.hip with hipcc.
+"""Builds libmmk.so (HIP, gfx950) in-tree from csrc/*.hip with hipcc, and the benchmark's
+VALU calibration helper libmmk_calib.so from csrc/calib/valu_rate.hip.
 
 Run as `python -m paper_1908_04279_amd.build` (or through __graft_entry__.build()).
 Packed FP32 instructions are disabled for all device code.
@@ -13,6 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmmk.so")
+# measurement helper of the benchmark (VALU issue-rate calibration), not part of the library
+CALIB_SRC = os.path.join(CSRC, "calib", "valu_rate.hip")
+CALIB_LIB = os.path.join(HERE, "libmmk_calib.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -49,6 +53,13 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    cmd = [HIPCC, *CFLAGS, "-shared", "-o", CALIB_LIB + ".tmp", CALIB_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {CALIB_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(CALIB_LIB + ".tmp", CALIB_LIB)
     return LIB
 
 

@@ -176,6 +176,14 @@ struct mmk_ctx {
     std::vector<hipEvent_t> ev[kProfIds];  // start/stop pairs
     int nev[kProfIds] = {0, 0, 0, 0, 0, 0, 0, 0};
     TapeState tape;
+    // mmk_step_graph: captured K-step sequences by (K, dt, starting buffer), replayed on stream
+    struct Graph {
+        int K = 0, cur_in = 0, cur_out = 0;
+        double dt = 0;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t capture_stream = nullptr;
     std::vector<double> host_tab64;  // host copies of the angle tables (outlive the async copy)
     std::vector<float> host_tab32;
     R0Plan r0;          // anchor-resolved model: tracked cells and runs (rc > 0)
@@ -244,6 +252,14 @@ static hipError_t prof_end_on(mmk_ctx *c, int id, int slot, hipStream_t s) {
 }
 static hipError_t prof_begin(mmk_ctx *c, int id, int *slot) { return prof_begin_on(c, id, slot, c->stream); }
 static hipError_t prof_end(mmk_ctx *c, int id, int slot) { return prof_end_on(c, id, slot, c->stream); }
+
+// Drops the captured step graphs (their launches carry the options and buffers of the time
+// they were captured).
+static void drop_graphs(mmk_ctx *c) {
+    for (auto &g : c->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
 
 // What the options select (mmk_set_option); called at create and after every change.
 static void apply_options(mmk_ctx *c) {
@@ -689,6 +705,8 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
 mmk_status mmk_destroy(mmk_ctx *c) {
     if (!c) return MMK_ERR_ARG;
     (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (int i = 0; i < kProfIds; ++i)
         for (hipEvent_t e : c->ev[i]) (void)hipEventDestroy(e);
     delete c;
@@ -705,6 +723,7 @@ mmk_status mmk_set_params(mmk_ctx *c, double k_on, double k_off, double v0) {
     c->p.k_on = k_on;
     c->p.k_off = k_off;
     c->p.v0 = v0;
+    drop_graphs(c);
     return MMK_OK;
 }
 
@@ -723,6 +742,7 @@ mmk_status mmk_set_option(mmk_ctx *c, int32_t option, int32_t value) {
     if (!ok) return fail(c, MMK_ERR_ARG, "value %d out of range for option %d", value, option);
     c->opt[option] = value;
     apply_options(c);
+    drop_graphs(c);
     return MMK_OK;
 }
 
@@ -793,6 +813,61 @@ mmk_status mmk_step(mmk_ctx *c, int32_t K, double dt) {
     if (c->tape.active && c->tape.steps + K > c->tape.max_steps)
         return fail(c, MMK_ERR_ARG, "taped run would exceed max_tape_steps (%d)", c->tape.max_steps);
     return c->esz == 4 ? run_steps<float>(c, K, dt) : run_steps<double>(c, K, dt);
+}
+
+mmk_status mmk_step_graph(mmk_ctx *c, int32_t K, double dt) {
+    if (!c) return MMK_ERR_ARG;
+    if (K < 0) return fail(c, MMK_ERR_ARG, "K must be >= 0");
+    if (!std::isfinite(dt) || dt <= 0) return fail(c, MMK_ERR_ARG, "dt must be finite and > 0");
+    if (!c->have_state) return fail(c, MMK_ERR_STATE, "mmk_step_graph before mmk_set_state");
+    if (!c->have_fluid) return fail(c, MMK_ERR_STATE, "mmk_step_graph before mmk_set_fluid");
+    if (c->tape.active) return fail(c, MMK_ERR_STATE, "mmk_step_graph during a taped run (use mmk_step)");
+    if (K == 0) return MMK_OK;
+    if (motor_substeps(c->p, dt) < 1)
+        return fail(c, MMK_ERR_ARG, "dt (v0/ds + k_off) / motor_cfl needs more than %d motor sub-steps",
+                    kMaxSubsteps);
+    mmk_ctx::Graph *g = nullptr;
+    for (auto &x : c->graphs)
+        if (x.K == K && x.dt == dt && x.cur_in == c->cur) g = &x;
+    if (!g) {
+        if (c->graphs.size() >= 8) drop_graphs(c);
+        if (!c->capture_stream)
+            HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+        // record the launches of mmk_step(K, dt) from this buffer into a graph: the same code
+        // path enqueues them on a capturing stream of the library's own (nothing runs)
+        mmk_ctx::Graph ng;
+        ng.K = K;
+        ng.dt = dt;
+        ng.cur_in = c->cur;
+        hipStream_t user = c->stream;
+        const bool prof = c->prof;
+        c->prof = false;
+        c->stream = c->capture_stream;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        mmk_status st = MMK_OK;
+        if (e == hipSuccess) st = c->esz == 4 ? run_steps<float>(c, K, dt) : run_steps<double>(c, K, dt);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(c->stream, &graph) : e;
+        c->stream = user;
+        c->prof = prof;
+        ng.cur_out = c->cur;
+        c->cur = ng.cur_in;  // nothing has run yet
+        if (e != hipSuccess) return hipfail(c, e, "hipStreamBeginCapture");
+        if (st != MMK_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e2 != hipSuccess) return hipfail(c, e2, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&ng.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hipfail(c, e, "hipGraphInstantiate");
+        c->graphs.push_back(ng);
+        g = &c->graphs.back();
+    }
+    HIPCHK(c, hipGraphLaunch(g->exec, c->stream), "hipGraphLaunch");
+    c->cur = g->cur_out;
+    c->have_out = true;
+    return MMK_OK;
 }
 
 mmk_status mmk_get_state(mmk_ctx *c, void *psi, void *M) {
@@ -978,6 +1053,13 @@ mmk_status mmk_profile_read(mmk_ctx *c, int32_t id, double *total_ms, int64_t *l
     return MMK_OK;
 }
 
+}  // extern "C"
+
+namespace mmk {
+void set_create_error(const char *msg) { g_create_error = msg; }
+}  // namespace mmk
+
+extern "C" {
 const char *mmk_last_error(const mmk_ctx *c) {
     return c ? c->err.c_str() : g_create_error.c_str();
 }

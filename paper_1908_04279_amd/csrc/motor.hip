@@ -49,24 +49,53 @@ __device__ __forceinline__ void motor_dh(const T (&z)[CPL], T (&R)[CPL], int g, 
     for (int j = 0; j < CPL; ++j) R[j] = h[j] - ((j == 0) ? hl : h[j - 1]);
 }
 
-// The lane's part of m0: its CPL cells added in the cell precision, in order, then widened
-// (one half-rate FP64 operation per lane instead of two per cell).  In FP32 the few terms
-// carry a relative error of at most (CPL - 1) units of 2^-24; the lanes then add in FP64.
+// The lane's part of m0 = ds sum M as a Kahan pair (value = s - c).  FP64: the CPL cells added
+// in order (c = 0).  FP32: the cells added plainly in runs of four consecutive cells (at most
+// three roundings each), the runs' sums then added with Kahan's compensation; with the
+// compensated butterfly of column_total this keeps the FP32 column total within a few units of
+// 2^-24 of the sum of its cells, and costs about one extra operation per cell over a plain sum.
 template <typename T, int CPL, bool RAGGED>
-__device__ __forceinline__ double lane_m0(const T (&y)[CPL], int l0, int ns) {
-    T v = y[0];
+__device__ __forceinline__ void lane_m0(const T (&y)[CPL], int l0, int ns, T &s, T &c) {
+    auto cell = [&](int j) { return (!RAGGED || l0 + j < ns) ? y[j] : T(0); };
+    c = T(0);
+    if constexpr (std::is_same<T, double>::value || CPL < 8) {
+        s = cell(0);
 #pragma unroll
-    for (int j = 1; j < CPL; ++j) v += (!RAGGED || l0 + j < ns) ? y[j] : T(0);
-    return (!RAGGED || l0 < ns) ? (double)v : 0.0;
+        for (int j = 1; j < CPL; ++j) s += cell(j);
+    } else {
+        constexpr int RUN = 4;
+#pragma unroll
+        for (int q = 0; q < CPL / RUN; ++q) {
+            T r = cell(q * RUN);
+#pragma unroll
+            for (int j = 1; j < RUN; ++j) r += cell(q * RUN + j);
+            if (q == 0) s = r;
+            else kahan_add(s, c, r);
+        }
+    }
 }
 
-// Column total of the lane partials, in FP64 (every lane of the group; with PAIR, the m0 total in
-// the lower half of the group and the m1 total in the upper half), rounded once by the caller.
-// The m0 lane partials are sums of the lane's few cells in the cell precision (lane_m0); the
-// butterfly over the lanes adds in FP64.
-template <int LPC, bool PAIR>
-__device__ __forceinline__ double column_total(double v0, double v1, int g) {
-    return group_sum_pair<LPC, false, PAIR, double>(v0, 0.0, v1, 0.0, g);
+// The lane's part of m1 = ds^2 sum (l + 1/2 - ns/2) M (the weights are exact half-integers; wb
+// is the weight of the lane's first cell) as a Kahan pair: FP64 in order, FP32 with Kahan's
+// compensation on every term (output steps only).
+template <typename T, int CPL, bool RAGGED>
+__device__ __forceinline__ void lane_m1(const T (&y)[CPL], int l0, int ns, T wb, T &s, T &c) {
+    c = T(0);
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const T v = (!RAGGED || l0 + j < ns) ? y[j] * (wb + T(j)) : T(0);
+        if (j == 0) s = v;
+        else if constexpr (std::is_same<T, double>::value) s += v;
+        else kahan_add(s, c, v);
+    }
+}
+
+// Column total of the lane partials (every lane of the group; with PAIR, the m0 total in the
+// lower half of the group and the m1 total in the upper half), in the cell precision: FP64 a
+// plain butterfly, FP32 a TwoSum butterfly carrying the Kahan compensations along.
+template <typename T, int LPC, bool PAIR>
+__device__ __forceinline__ T column_total(T s0, T c0, T s1, T c1, int g) {
+    return group_sum_pair<LPC, std::is_same<T, float>::value, PAIR, T>(s0, c0, s1, c1, g);
 }
 
 template <typename T, int CPL, int LPC, int LIM, bool RAGGED, bool WANT_M1, bool NT>
@@ -140,8 +169,10 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     // and only the last is stored.
     for (int t = 0; t + 1 < c.nstep; ++t) {
         micro();
-        const double tot = column_total<LPC, false>(lane_m0<T, CPL, RAGGED>(y, l0, ns), 0.0, g);
-        if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = (T)(tot * (double)c.ds);
+        T s0, c0;
+        lane_m0<T, CPL, RAGGED>(y, l0, ns, s0, c0);
+        const T tot = column_total<T, LPC, false>(s0, c0, T(0), T(0), g);
+        if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = tot * c.ds;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) x[j] = y[j];
     }
@@ -156,23 +187,16 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     }
 
     // s-moments of the new column: m0 = ds sum M, m1 = ds^2 sum (l + 1/2 - ns/2) M, the
-    // weights being exact half-integers; m0 from the lane sums of lane_m0, m1 summed in FP64 in
-    // the lane; both across the lanes in FP64 (column_total).  On output steps one paired butterfly serves both: lane 0 of the group
-    // ends with m0, lane LPC/2 with m1; m0 has the same bits on every step.
-    const T wb = T(0.5) * (T)(2 * l0 + 1 - ns);  // weight of this lane's first cell
-    double a1 = 0.0;
-    if constexpr (WANT_M1) {
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-            const bool in = !RAGGED || (l0 + j < ns);
-            const T v = in ? y[j] : T(0);
-            a1 = (j == 0) ? (double)v * (double)wb : a1 + (double)v * (double)(wb + T(j));
-        }
-    }
-    const double tot = column_total<LPC, WANT_M1>(lane_m0<T, CPL, RAGGED>(y, l0, ns), a1, g);
-    if (active && g == 0) m0[col] = (T)(tot * (double)c.ds);
+    // weights being exact half-integers; lane partials (lane_m0, lane_m1), then the column
+    // total (column_total).  On output steps one paired butterfly serves both: lane 0 of the
+    // group ends with m0, lane LPC/2 with m1; m0 has the same bits on every step.
+    T s0, c0, s1 = T(0), c1 = T(0);
+    lane_m0<T, CPL, RAGGED>(y, l0, ns, s0, c0);
+    if constexpr (WANT_M1) lane_m1<T, CPL, RAGGED>(y, l0, ns, T(0.5) * (T)(2 * l0 + 1 - ns), s1, c1);
+    const T tot = column_total<T, LPC, WANT_M1>(s0, c0, s1, c1, g);
+    if (active && g == 0) m0[col] = tot * c.ds;
     if constexpr (WANT_M1)
-        if (active && g == LPC / 2) m1[col] = (T)(tot * (double)c.ds2);
+        if (active && g == LPC / 2) m1[col] = tot * c.ds2;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -428,9 +452,9 @@ static int chunks_per_lane(int ns, int elem, int want) {
 // Depleted micro-step with sub-cycling in one launch (Alg. 2's inner loop with the clamp inside
 // it).  One block per (x, y) point holds all nth of its columns, LPC lanes each.  Before each of
 // the c.nsub sub-steps of c.dt the block forms the coarse density B = dth sum_k psi_k m0_k of its
-// current columns (each column's m0 by the FP64 butterfly, the sum over k in LDS in a fixed
-// order), the clamp factor and the free pool (Eq. (6)); every column is scaled and stepped in
-// registers.  M is read and written once per micro-step.
+// current columns (each column's m0 as in k_motor_step, the sum over k in LDS in a fixed order,
+// compensated in FP32), the clamp factor and the free pool (Eq. (6)); every column is scaled
+// and stepped in registers.  M is read and written once per micro-step.
 template <typename T, int CPL, int LPC, int LIM, bool WANT_M1>
 __global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M_in, T *__restrict__ M_out,
                                                          T *__restrict__ m0, T *__restrict__ m1,
@@ -438,7 +462,7 @@ __global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M
                                                          MotorConst<T> c, double dth, double m_total) {
     // column terms psi_k m0_k of sub-step q in part[q & 1]: one barrier per sub-step (the
     // buffer written at q + 2 was read by every wave before it passed the barrier of q + 1)
-    __shared__ double part[2][1024 / LPC];
+    __shared__ T part[2][1024 / LPC];
     const int g = threadIdx.x % LPC, k = threadIdx.x / LPC;
     const int lane = threadIdx.x & 63;
     const int64_t col = (int64_t)blockIdx.x * nth + k;
@@ -446,18 +470,23 @@ __global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M
     const int64_t base = col * (int64_t)ns + l0;
     T x[CPL], R[CPL], y[CPL];
     load_cells<T, CPL, false>(M_in + base, x);
-    const double ps = (double)psi[col];
+    const T ps = psi[col];
     for (int q = 0; q < c.nsub; ++q) {
-        const double tot = column_total<LPC, false>(lane_m0<T, CPL, false>(x, l0, ns), 0.0, g);
-        if (g == 0) part[q & 1][k] = ps * (tot * (double)c.ds);
+        T s0, c0;
+        lane_m0<T, CPL, false>(x, l0, ns, s0, c0);
+        const T tot = column_total<T, LPC, false>(s0, c0, T(0), T(0), g);
+        if (g == 0) part[q & 1][k] = ps * (tot * c.ds);
         __syncthreads();
         // every wave forms B itself in the same fixed order: lane i adds columns i, i + 64, ...
-        // in order, then a butterfly over the wave
-        double v = 0.0;
-        for (int kk = lane; kk < nth; kk += 64) v += part[q & 1][kk];
-        const double B = group_sum<64>(v);
+        // in order (Kahan in FP32), then a butterfly over the wave (compensated in FP32)
+        T v = T(0), vc = T(0);
+        for (int kk = lane; kk < nth; kk += 64) {
+            if constexpr (std::is_same<T, float>::value) kahan_add(v, vc, part[q & 1][kk]);
+            else v += part[q & 1][kk];
+        }
+        const T B = column_total<T, 64, false>(v, vc, T(0), T(0), 0);
         T sc, pool;
-        depletion_of((T)(B * dth), (T)m_total, sc, pool);
+        depletion_of(B * (T)dth, (T)m_total, sc, pool);
         const T src = c.k_on * pool;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) x[j] *= sc;
@@ -473,16 +502,13 @@ __global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M
         for (int j = 0; j < CPL; ++j) x[j] = y[j];
     }
     store_cells<T, CPL, false>(M_out + base, x);
-    const T wb = T(0.5) * (T)(2 * l0 + 1 - ns);
-    double a1 = 0.0;
-    if constexpr (WANT_M1) {
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) a1 = (j == 0) ? (double)x[j] * (double)wb : a1 + (double)x[j] * (double)(wb + T(j));
-    }
-    const double tot = column_total<LPC, WANT_M1>(lane_m0<T, CPL, false>(x, l0, ns), a1, g);
-    if (g == 0) m0[col] = (T)(tot * (double)c.ds);
+    T s0, c0, s1 = T(0), c1 = T(0);
+    lane_m0<T, CPL, false>(x, l0, ns, s0, c0);
+    if constexpr (WANT_M1) lane_m1<T, CPL, false>(x, l0, ns, T(0.5) * (T)(2 * l0 + 1 - ns), s1, c1);
+    const T tot = column_total<T, LPC, WANT_M1>(s0, c0, s1, c1, g);
+    if (g == 0) m0[col] = tot * c.ds;
     if constexpr (WANT_M1)
-        if (g == LPC / 2) m1[col] = (T)(tot * (double)c.ds2);
+        if (g == LPC / 2) m1[col] = tot * c.ds2;
 }
 
 template <typename T, int CPL, int LPC>

@@ -30,6 +30,7 @@ EXPORTS = ["mmk_workspace_bytes", "mmk_create", "mmk_destroy", "mmk_set_params",
            "mmk_set_fluid", "mmk_step", "mmk_get_state", "mmk_get_stress", "mmk_get_moments",
            "mmk_get_motor_moments", "mmk_get_force", "mmk_get_anchors", "mmk_r0_cells", "mmk_get_sums", "mmk_tape_begin", "mmk_tape_backward",
            "mmk_tape_end", "mmk_profile", "mmk_profile_read", "mmk_profile_every", "mmk_set_option",
+           "mmk_step_graph",
            "mmk_last_error"]
 
 
@@ -68,6 +69,7 @@ def lib():
             "mmk_set_state": ([vp, vp, vp], C.c_int),
             "mmk_set_fluid": ([vp, vp, vp], C.c_int),
             "mmk_step": ([vp, i32, d], C.c_int),
+            "mmk_step_graph": ([vp, i32, d], C.c_int),
             "mmk_get_state": ([vp, vp, vp], C.c_int),
             "mmk_get_stress": ([vp, vp], C.c_int),
             "mmk_get_moments": ([vp, vp], C.c_int),
@@ -211,6 +213,10 @@ class Context:
 
     def step(self, K, dt):
         self._check(lib().mmk_step(self.h, int(K), float(dt)))
+
+    def step_graph(self, K, dt):
+        """mmk_step_graph: the K micro-steps of step(K, dt) as one replayed HIP graph."""
+        self._check(lib().mmk_step_graph(self.h, int(K), float(dt)))
 
     def get_state(self):
         psi, M = self.empty(self.shape_psi), self.empty(self.shape_M)

@@ -60,3 +60,43 @@ def test_fp32_256x256x64x64_full_size():
     print(f"M (all columns vs the oracle column): {m_err:.2e}; mass drift {abs(g['mass'] - 1.0):.2e}", flush=True)
     assert e["stress"] <= TOL and e["mom"] <= TOL
     assert m_err <= TOL and e["psi"] <= TOL
+
+
+@pytest.mark.parametrize("block", [1, 0])
+def test_fp32_s_moments_are_compensated(block):
+    """The FP32 s-reductions (cells summed in runs of four, the runs with Kahan's compensation,
+    a TwoSum butterfly over the lanes): m0 and m1 of columns whose cells span nine decades lie
+    within 8 units of 2^-24 of the exactly rounded sums of the same FP32 cells, relative to the
+    sums of magnitudes; both the blocked launch (16 cells a lane) and one launch per step
+    (4 cells a lane)."""
+    import math
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=6, ny=5, ntheta=16, ns=64)
+    rng = np.random.default_rng(11)
+    M0 = (10.0 ** rng.uniform(-6, 3, (p.nx, p.ny, p.ntheta, p.ns))).astype(np.float32)
+    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0).astype(np.float32)
+    fl = gen.fluid_schedule(p.nx, p.ny, 1, p.lx, p.ly)
+    ctx = mmk.Context(p, precision=mmk.FP32, options={"motor_block": block})
+    ctx.set_state(torch.as_tensor(psi0), torch.as_tensor(M0))
+    ctx.set_fluid(*map(torch.as_tensor, fl[0]))
+    ctx.step(3, 1e-4)
+    _, M = ctx.get_state()
+    m0, m1 = ctx.get_motor_moments()
+    M = M.double().cpu().numpy().reshape(-1, p.ns)
+    m0 = m0.double().cpu().numpy().ravel()
+    m1 = m1.double().cpu().numpy().ravel()
+    ctx.close()
+    ds = float(np.float32(p.L / p.ns))
+    ds2 = float(np.float32((p.L / p.ns) ** 2))
+    w = (np.arange(p.ns) + 0.5 - p.ns / 2).astype(np.float64)
+    u = 2.0 ** -24
+    worst0 = worst1 = 0.0
+    for c in range(M.shape[0]):
+        ex0 = math.fsum(M[c]) * ds
+        t1 = (M[c].astype(np.float32) * w.astype(np.float32)).astype(np.float64)  # FP32 products
+        ex1 = math.fsum(t1) * ds2
+        worst0 = max(worst0, abs(m0[c] - ex0) / (np.abs(M[c]).sum() * ds))
+        worst1 = max(worst1, abs(m1[c] - ex1) / (np.abs(t1).sum() * ds2))
+    print(f"m0: {worst0 / u:.2f} u, m1: {worst1 / u:.2f} u", flush=True)
+    assert worst0 <= 8 * u and worst1 <= 8 * u
