@@ -279,8 +279,25 @@ mmk_status mmk_profile_read(mmk_ctx *ctx, int32_t kernel_id, double *total_ms, i
  * restarting its count; the other ids keep theirs.  Synchronizes. */
 mmk_status mmk_profile_every(mmk_ctx *ctx, int32_t kernel_id, int32_t every);
 
-/* Message of the last failure on ctx; with ctx == NULL, of the last failed mmk_create or
- * mmk_workspace_bytes on this thread. */
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the global sums of mmk_get_sums computed without a
+ * context or a workspace, from caller-given device arrays psi [nx][ny][ntheta] and sigma
+ * [3][nx][ny] in the precision p->precision (only nx, ny, ntheta, lx, ly and precision of *p are
+ * read): mass = sum psi dx dy dth and sum_sigma[c] = sum sigma_c dx dy (host outputs),
+ * accumulated in FP64 (compensated) in a fixed order, bitwise reproducible.  Its block partials
+ * live in a static device array of the library (4096 rows of 4 doubles and the 4 totals,
+ * 131104 bytes; one copy per device, held until the process ends); nothing is allocated, and
+ * every row it reads is written first in the same call.  Calls that overlap on one device race
+ * for that array: serialise them (one stream, or host synchronisation).  Work is ordered on
+ * hip_stream (NULL = the null stream) and the call synchronizes it.  MMK_ERR_ARG: NULL pointers,
+ * sizes < 1, bad precision or box; MMK_ERR_UNSUPPORTED: more than 2^36 psi cells (the scratch
+ * holds 4096 partial rows of at most 2^24 cells) or a device index beyond 63; MMK_ERR_HIP: a
+ * HIP call failed.  The message is given by mmk_last_error(NULL). */
+mmk_status mmk_sums_static(const mmk_params *p, const void *psi, const void *sigma, void *hip_stream,
+                           double *mass, double sum_sigma[3]);
+
+/* Message of the last failure on ctx; with ctx == NULL, of the last failed mmk_create,
+ * mmk_workspace_bytes or mmk_sums_static on this thread. */
 const char *mmk_last_error(const mmk_ctx *ctx);
 
 #ifdef __cplusplus

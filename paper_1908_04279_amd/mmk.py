@@ -30,7 +30,7 @@ EXPORTS = ["mmk_workspace_bytes", "mmk_create", "mmk_destroy", "mmk_set_params",
            "mmk_set_fluid", "mmk_step", "mmk_get_state", "mmk_get_stress", "mmk_get_moments",
            "mmk_get_motor_moments", "mmk_get_force", "mmk_get_anchors", "mmk_r0_cells", "mmk_get_sums", "mmk_tape_begin", "mmk_tape_backward",
            "mmk_tape_end", "mmk_profile", "mmk_profile_read", "mmk_profile_every", "mmk_set_option",
-           "mmk_step_graph",
+           "mmk_step_graph", "mmk_sums_static",
            "mmk_last_error"]
 
 
@@ -85,6 +85,7 @@ def lib():
             "mmk_profile_read": ([vp, i32, C.POINTER(d), C.POINTER(i64)], C.c_int),
             "mmk_profile_every": ([vp, i32, i32], C.c_int),
             "mmk_set_option": ([vp, i32, i32], C.c_int),
+            "mmk_sums_static": ([P, vp, vp, vp, C.POINTER(d), C.POINTER(d)], C.c_int),
             "mmk_last_error": ([vp], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -122,6 +123,20 @@ def r0_cells(p):
     if n > 0:
         lib().mmk_r0_cells(C.byref(params), C.c_void_p(cells.ctypes.data))
     return cells
+
+
+def sums_static(p, precision, psi, sigma, stream=None):
+    """mmk_sums_static: (mass, sum_sigma[3]) of device tensors psi [nx][ny][ntheta] and sigma
+    [3][nx][ny] without a context (the library's static scratch; nothing is allocated)."""
+    params = make_params(p, precision)
+    mass = C.c_double()
+    ss = (C.c_double * 3)()
+    s = stream if stream is not None else torch.cuda.current_stream(psi.device)
+    st = lib().mmk_sums_static(C.byref(params), _ptr(psi), _ptr(sigma), C.c_void_p(s.cuda_stream),
+                               C.byref(mass), ss)
+    if st != MMK_OK:
+        raise MMKError(st, lib().mmk_last_error(None).decode())
+    return mass.value, [ss[0], ss[1], ss[2]]
 
 
 def _ptr(t):
