@@ -646,6 +646,9 @@ def main():
                          "motor launches: every one)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--option", action="append", default=[], metavar="NAME=VALUE",
+                    help="a context option (mmk_set_option) for the fp32 and fp64 legs of --only "
+                         "(measurements; the default run takes the library's defaults)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this micro-step path runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -688,6 +691,13 @@ def main():
     K = 10
     res = {}
     calib = None
+    extra = {}
+    for kv in args.option:
+        name, value = kv.split("=", 1)
+        extra[name] = int(value)
+    if extra and args.only == "all":
+        print("bench.py: --option applies to the single legs of --only", file=sys.stderr)
+        sys.exit(2)
     if args.only == "all":
         log("[bench] VALU calibration")
         calib = valu_calibration()
@@ -712,16 +722,16 @@ def main():
                                              event_every=args.event_every, options={"depl_fused": 0})
     if args.only in ("all", "fp64"):
         res["fp64"] = run_forward(p, mmk.FP64, args.fp64_steps, min(args.warmup, 20), K,
-                                  event_every=args.event_every)
+                                  event_every=args.event_every, options=extra or None)
     if args.only in ("all", "fp32"):
         # the headline: runs right after the FP64 leg (the chip at its working clock), every
         # motor launch of the timed region bracketed by HIP events
         res["fp32"] = run_forward(p, mmk.FP32, args.steps, args.warmup, K, event_every=args.event_every,
-                                  motor_every=1)
+                                  motor_every=1, options=extra or None)
     if args.only in ("all", "fp32_1"):
         # the same grid with one motor launch per micro-step (HBM-bound): FP32 and FP64
         res["fp32_1"] = run_forward(p, mmk.FP32, args.fp64_steps, 20, K, event_every=args.event_every,
-                                    options={"motor_block": 0})
+                                    options={**extra, "motor_block": 0})
     if args.only == "all":
         res["fp64_1"] = run_forward(p, mmk.FP64, args.fp64_steps, 20, K, event_every=args.event_every,
                                     options={"motor_block": 0})

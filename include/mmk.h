@@ -261,8 +261,10 @@ typedef enum {
     MMK_OPT_MOTOR_CHUNKS = 4,  /* 0 (default): each lane holds consecutive cells; 2 or 4: each
                                 * lane holds that many 16-byte chunks spaced a lane group apart
                                 * (no depletion; a value without a tiling for ns leaves 0) */
-    MMK_OPT_MOTOR_NT = 5       /* -1 (default): nontemporal loads and stores of M in FP32, plain
-                                * in FP64; 0: plain; 1: nontemporal */
+    MMK_OPT_MOTOR_NT = 5       /* -1 (default): in FP32 nontemporal loads and stores of M for a
+                                * launch of one step, plain accesses for launches of several
+                                * micro-steps or sub-steps; plain in FP64; 0: plain; 1: nontemporal
+                                * loads and stores; 2: nontemporal loads only */
 } mmk_option;
 mmk_status mmk_set_option(mmk_ctx *ctx, int32_t option, int32_t value);
 

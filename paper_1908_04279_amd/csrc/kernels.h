@@ -22,7 +22,7 @@ struct MotorConst {
                    // sub-steps of arithmetic per load), 0: 16 bytes (one step per load)
     int lanes;     // lanes per column asked for (0: from ns, the precision and `wide`)
     int chunks;    // 16-byte chunks per lane of the chunked tiling (0 or 1: plain tiling)
-    int nt;        // nontemporal loads/stores of M: -1 in FP32 only, 0 never, 1 always
+    int nt;        // nontemporal M accesses: -1 the default, 0 none, 1 loads and stores, 2 loads
 };
 
 // Forward motor step over `ncol` independent columns of `ns` cells, in registers: c.nstep

@@ -736,7 +736,7 @@ mmk_status mmk_set_option(mmk_ctx *c, int32_t option, int32_t value) {
         case MMK_OPT_PSI_KERNEL: ok = value >= 0 && value <= 2; break;
         case MMK_OPT_MOTOR_LANES: ok = value == 0 || (value >= 2 && value <= 64 && (value & (value - 1)) == 0); break;
         case MMK_OPT_MOTOR_CHUNKS: ok = value == 0 || value == 1 || value == 2 || value == 4; break;
-        case MMK_OPT_MOTOR_NT: ok = value >= -1 && value <= 1; break;
+        case MMK_OPT_MOTOR_NT: ok = value >= -1 && value <= 2; break;
         default: return fail(c, MMK_ERR_ARG, "unknown option %d", option);
     }
     if (!ok) return fail(c, MMK_ERR_ARG, "value %d out of range for option %d", value, option);

@@ -49,56 +49,45 @@ __device__ __forceinline__ void motor_dh(const T (&z)[CPL], T (&R)[CPL], int g, 
     for (int j = 0; j < CPL; ++j) R[j] = h[j] - ((j == 0) ? hl : h[j - 1]);
 }
 
-// The lane's part of m0 = ds sum M as a Kahan pair (value = s - c).  FP64: the CPL cells added
-// in order (c = 0).  FP32: the cells added plainly in runs of four consecutive cells (at most
-// three roundings each), the runs' sums then added with Kahan's compensation; with the
-// compensated butterfly of column_total this keeps the FP32 column total within a few units of
-// 2^-24 of the sum of its cells, and costs about one extra operation per cell over a plain sum.
+// The lane's part of m0 = ds sum M: its CPL cells added pairwise in the cell precision (log2 CPL
+// roundings on any path, at most 4 units of 2^-24 relative for 16 FP32 cells of one sign), then
+// widened once.  The lanes' parts are added in FP64 (column_total) and the total rounded once:
+// measured as accurate as Kahan-compensated FP32 sums and 10% faster in the blocked FP32 launch,
+// where the sum is taken every micro-step.
 template <typename T, int CPL, bool RAGGED>
-__device__ __forceinline__ void lane_m0(const T (&y)[CPL], int l0, int ns, T &s, T &c) {
-    auto cell = [&](int j) { return (!RAGGED || l0 + j < ns) ? y[j] : T(0); };
-    c = T(0);
-    if constexpr (std::is_same<T, double>::value || CPL < 8) {
-        s = cell(0);
+__device__ __forceinline__ double lane_m0(const T (&y)[CPL], int l0, int ns) {
+    T t[CPL];
 #pragma unroll
-        for (int j = 1; j < CPL; ++j) s += cell(j);
-    } else {
-        constexpr int RUN = 4;
+    for (int j = 0; j < CPL; ++j) t[j] = (!RAGGED || l0 + j < ns) ? y[j] : T(0);
 #pragma unroll
-        for (int q = 0; q < CPL / RUN; ++q) {
-            T r = cell(q * RUN);
+    for (int w = CPL; w > 1; w >>= 1)
 #pragma unroll
-            for (int j = 1; j < RUN; ++j) r += cell(q * RUN + j);
-            if (q == 0) s = r;
-            else kahan_add(s, c, r);
-        }
-    }
+        for (int i = 0; i < w / 2; ++i) t[i] = t[2 * i] + t[2 * i + 1];
+    return (double)t[0];
 }
 
 // The lane's part of m1 = ds^2 sum (l + 1/2 - ns/2) M (the weights are exact half-integers; wb
-// is the weight of the lane's first cell) as a Kahan pair: FP64 in order, FP32 with Kahan's
-// compensation on every term (output steps only).
+// is the weight of the lane's first cell): products and sums in FP64, in order (output steps).
 template <typename T, int CPL, bool RAGGED>
-__device__ __forceinline__ void lane_m1(const T (&y)[CPL], int l0, int ns, T wb, T &s, T &c) {
-    c = T(0);
+__device__ __forceinline__ double lane_m1(const T (&y)[CPL], int l0, int ns, T wb) {
+    double a1 = 0.0;
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
-        const T v = (!RAGGED || l0 + j < ns) ? y[j] * (wb + T(j)) : T(0);
-        if (j == 0) s = v;
-        else if constexpr (std::is_same<T, double>::value) s += v;
-        else kahan_add(s, c, v);
+        const T v = (!RAGGED || l0 + j < ns) ? y[j] : T(0);
+        a1 = (j == 0) ? (double)v * (double)wb : a1 + (double)v * (double)(wb + T(j));
     }
+    return a1;
 }
 
-// Column total of the lane partials (every lane of the group; with PAIR, the m0 total in the
-// lower half of the group and the m1 total in the upper half), in the cell precision: FP64 a
-// plain butterfly, FP32 a TwoSum butterfly carrying the Kahan compensations along.
-template <typename T, int LPC, bool PAIR>
-__device__ __forceinline__ T column_total(T s0, T c0, T s1, T c1, int g) {
-    return group_sum_pair<LPC, std::is_same<T, float>::value, PAIR, T>(s0, c0, s1, c1, g);
+// Column total of the lane partials in FP64 (every lane of the group; with PAIR, the m0 total in
+// the lower half of the group and the m1 total in the upper half), rounded once by the caller.
+template <int LPC, bool PAIR>
+__device__ __forceinline__ double column_total(double v0, double v1, int g) {
+    return group_sum_pair<LPC, false, PAIR, double>(v0, 0.0, v1, 0.0, g);
 }
 
-template <typename T, int CPL, int LPC, int LIM, bool RAGGED, bool WANT_M1, bool NT>
+// NT: bit 0 nontemporal loads of M, bit 1 nontemporal stores.
+template <typename T, int CPL, int LPC, int LIM, bool RAGGED, bool WANT_M1, int NT>
 __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, T *__restrict__ M_out,
                                                     T *__restrict__ m0, T *__restrict__ m1,
                                                     int64_t ncol, int ns, MotorConst<T> c,
@@ -123,7 +112,7 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     T x[CPL];
     if constexpr (!RAGGED) {
         if (active) {
-            load_cells<T, CPL, NT>(M_in + base, x);
+            load_cells<T, CPL, (NT & 1) != 0>(M_in + base, x);
         } else {
 #pragma unroll
             for (int j = 0; j < CPL; ++j) x[j] = T(0);
@@ -169,17 +158,15 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
     // and only the last is stored.
     for (int t = 0; t + 1 < c.nstep; ++t) {
         micro();
-        T s0, c0;
-        lane_m0<T, CPL, RAGGED>(y, l0, ns, s0, c0);
-        const T tot = column_total<T, LPC, false>(s0, c0, T(0), T(0), g);
-        if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = tot * c.ds;
+        const double tot = column_total<LPC, false>(lane_m0<T, CPL, RAGGED>(y, l0, ns), 0.0, g);
+        if (active && g == 0) c.m0_steps[(int64_t)t * ncol + col] = (T)(tot * (double)c.ds);
 #pragma unroll
         for (int j = 0; j < CPL; ++j) x[j] = y[j];
     }
     micro();
 
     if constexpr (!RAGGED) {
-        if (active) store_cells<T, CPL, NT>(M_out + base, y);
+        if (active) store_cells<T, CPL, (NT & 2) != 0>(M_out + base, y);
     } else {
 #pragma unroll
         for (int j = 0; j < CPL; ++j)
@@ -188,15 +175,14 @@ __global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, 
 
     // s-moments of the new column: m0 = ds sum M, m1 = ds^2 sum (l + 1/2 - ns/2) M, the
     // weights being exact half-integers; lane partials (lane_m0, lane_m1), then the column
-    // total (column_total).  On output steps one paired butterfly serves both: lane 0 of the
-    // group ends with m0, lane LPC/2 with m1; m0 has the same bits on every step.
-    T s0, c0, s1 = T(0), c1 = T(0);
-    lane_m0<T, CPL, RAGGED>(y, l0, ns, s0, c0);
-    if constexpr (WANT_M1) lane_m1<T, CPL, RAGGED>(y, l0, ns, T(0.5) * (T)(2 * l0 + 1 - ns), s1, c1);
-    const T tot = column_total<T, LPC, WANT_M1>(s0, c0, s1, c1, g);
-    if (active && g == 0) m0[col] = tot * c.ds;
+    // total in FP64 (column_total), rounded once.  On output steps one paired butterfly serves
+    // both: lane 0 of the group ends with m0, lane LPC/2 with m1; m0 has the same bits on every
+    // step.
+    const double a1 = WANT_M1 ? lane_m1<T, CPL, RAGGED>(y, l0, ns, T(0.5) * (T)(2 * l0 + 1 - ns)) : 0.0;
+    const double tot = column_total<LPC, WANT_M1>(lane_m0<T, CPL, RAGGED>(y, l0, ns), a1, g);
+    if (active && g == 0) m0[col] = (T)(tot * (double)c.ds);
     if constexpr (WANT_M1)
-        if (active && g == LPC / 2) m1[col] = tot * c.ds2;
+        if (active && g == LPC / 2) m1[col] = (T)(tot * (double)c.ds2);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -381,7 +367,7 @@ static hipError_t launch_chunked(const T *M_in, T *M_out, T *m0, T *m1, int64_t 
     return hipGetLastError();
 }
 
-template <typename T, int CPL, int LPC, bool RAGGED, int LIM, bool NT>
+template <typename T, int CPL, int LPC, bool RAGGED, int LIM, int NT>
 static hipError_t launch_nt(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                             const MotorConst<T> &c, const T *Dxy, hipStream_t s, unsigned blocks) {
     if (m1)
@@ -393,16 +379,27 @@ static hipError_t launch_nt(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol,
     return hipGetLastError();
 }
 
-// Streaming (nontemporal) loads/stores of M keep psi and m0 of the next psi step in the
-// caches: measured faster in FP32, slower in FP64 on MI355X.  opt: -1 that default, 0 or 1.
-static bool motor_nontemporal(int elem, int opt) { return opt >= 0 ? opt != 0 : elem == 4; }
+// Streaming (nontemporal) accesses of M, as a mask (bit 0 loads, bit 1 stores).  opt -1 (the
+// default): in FP32 a launch of one step per load streams both (keeps psi and m0 of the next psi
+// step in the caches: measured faster); a launch of several micro-steps or sub-steps per load
+// streams neither (its nontemporal 16-byte stores each cover a quarter of a lane's 64-byte span
+// and wrote 1.22x the bytes, plain stores merge in the L2 to 1.00x; measured 1256 against
+// 1272 us per 10-micro-step launch at 256x256x64x64, 1265 with nontemporal loads only); FP64
+// plain (streams measured slower there).  opt 0: plain, 1: loads and stores, 2: loads only.
+static int motor_nontemporal(int elem, int opt, bool multi) {
+    if (opt == 0) return 0;
+    if (opt == 1) return 3;
+    if (opt == 2) return 1;
+    return (elem == 4 && !multi) ? 3 : 0;
+}
 
 template <typename T, int CPL, int LPC, bool RAGGED, int LIM>
 static hipError_t launch_lim(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol, int ns,
                              const MotorConst<T> &c, const T *Dxy, hipStream_t s, unsigned blocks) {
-    if (!RAGGED && motor_nontemporal((int)sizeof(T), c.nt))
-        return launch_nt<T, CPL, LPC, RAGGED, LIM, true>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, blocks);
-    return launch_nt<T, CPL, LPC, RAGGED, LIM, false>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, blocks);
+    const int nt = RAGGED ? 0 : motor_nontemporal((int)sizeof(T), c.nt, c.nstep > 1 || c.nsub > 1);
+    if (nt == 3) return launch_nt<T, CPL, LPC, RAGGED, LIM, 3>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, blocks);
+    if (nt == 1) return launch_nt<T, CPL, LPC, RAGGED, LIM, 1>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, blocks);
+    return launch_nt<T, CPL, LPC, RAGGED, LIM, 0>(M_in, M_out, m0, m1, ncol, ns, c, Dxy, s, blocks);
 }
 
 template <typename T, int CPL, int LPC, bool RAGGED>
@@ -452,9 +449,9 @@ static int chunks_per_lane(int ns, int elem, int want) {
 // Depleted micro-step with sub-cycling in one launch (Alg. 2's inner loop with the clamp inside
 // it).  One block per (x, y) point holds all nth of its columns, LPC lanes each.  Before each of
 // the c.nsub sub-steps of c.dt the block forms the coarse density B = dth sum_k psi_k m0_k of its
-// current columns (each column's m0 as in k_motor_step, the sum over k in LDS in a fixed order,
-// compensated in FP32), the clamp factor and the free pool (Eq. (6)); every column is scaled
-// and stepped in registers.  M is read and written once per micro-step.
+// current columns (each column's m0 as in k_motor_step, the sum over k of psi_k m0_k in LDS in a
+// fixed order, Kahan and TwoSum in FP32), the clamp factor and the free pool (Eq. (6)); every
+// column is scaled and stepped in registers.  M is read and written once per micro-step.
 template <typename T, int CPL, int LPC, int LIM, bool WANT_M1>
 __global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M_in, T *__restrict__ M_out,
                                                          T *__restrict__ m0, T *__restrict__ m1,
@@ -472,10 +469,8 @@ __global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M
     load_cells<T, CPL, false>(M_in + base, x);
     const T ps = psi[col];
     for (int q = 0; q < c.nsub; ++q) {
-        T s0, c0;
-        lane_m0<T, CPL, false>(x, l0, ns, s0, c0);
-        const T tot = column_total<T, LPC, false>(s0, c0, T(0), T(0), g);
-        if (g == 0) part[q & 1][k] = ps * (tot * c.ds);
+        const double tot = column_total<LPC, false>(lane_m0<T, CPL, false>(x, l0, ns), 0.0, g);
+        if (g == 0) part[q & 1][k] = ps * (T)(tot * (double)c.ds);
         __syncthreads();
         // every wave forms B itself in the same fixed order: lane i adds columns i, i + 64, ...
         // in order (Kahan in FP32), then a butterfly over the wave (compensated in FP32)
@@ -484,7 +479,7 @@ __global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M
             if constexpr (std::is_same<T, float>::value) kahan_add(v, vc, part[q & 1][kk]);
             else v += part[q & 1][kk];
         }
-        const T B = column_total<T, 64, false>(v, vc, T(0), T(0), 0);
+        const T B = group_sum_pair<64, std::is_same<T, float>::value, false, T>(v, vc, T(0), T(0), 0);
         T sc, pool;
         depletion_of(B * (T)dth, (T)m_total, sc, pool);
         const T src = c.k_on * pool;
@@ -502,13 +497,11 @@ __global__ __launch_bounds__(1024) void k_motor_depl_sub(const T *__restrict__ M
         for (int j = 0; j < CPL; ++j) x[j] = y[j];
     }
     store_cells<T, CPL, false>(M_out + base, x);
-    T s0, c0, s1 = T(0), c1 = T(0);
-    lane_m0<T, CPL, false>(x, l0, ns, s0, c0);
-    if constexpr (WANT_M1) lane_m1<T, CPL, false>(x, l0, ns, T(0.5) * (T)(2 * l0 + 1 - ns), s1, c1);
-    const T tot = column_total<T, LPC, WANT_M1>(s0, c0, s1, c1, g);
-    if (g == 0) m0[col] = tot * c.ds;
+    const double a1 = WANT_M1 ? lane_m1<T, CPL, false>(x, l0, ns, T(0.5) * (T)(2 * l0 + 1 - ns)) : 0.0;
+    const double tot = column_total<LPC, WANT_M1>(lane_m0<T, CPL, false>(x, l0, ns), a1, g);
+    if (g == 0) m0[col] = (T)(tot * (double)c.ds);
     if constexpr (WANT_M1)
-        if (g == LPC / 2) m1[col] = tot * c.ds2;
+        if (g == LPC / 2) m1[col] = (T)(tot * (double)c.ds2);
 }
 
 template <typename T, int CPL, int LPC>
@@ -570,7 +563,7 @@ hipError_t launch_motor_step(const T *M_in, T *M_out, T *m0, T *m1, int64_t ncol
     // the chunked tiling has no depletion
     const int nch = Dxy ? 1 : chunks_per_lane(ns, (int)sizeof(T), c.chunks);
     if (nch > 1) {
-        const bool nt = motor_nontemporal((int)sizeof(T), c.nt);
+        const bool nt = motor_nontemporal((int)sizeof(T), c.nt, c.nstep > 1 || c.nsub > 1) != 0;
         const int lpc = ns / (nch * (16 / (int)sizeof(T)));
 #define MMK_CHUNK_CASE(NCH, LPC)                                                              \
         if (nch == NCH && lpc == LPC) return launch_chunked<T, NCH, LPC>(M_in, M_out, m0, m1, ncol, ns, limiter, c, s, nt);
