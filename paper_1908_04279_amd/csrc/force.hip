@@ -269,9 +269,8 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
             for (int j = 0; j < CH; ++j) {
                 {
                     // Corners the head has moved past are spread before the move: tt on any
-                    // move, tl on a step along x, lt on a step along y (a spread of 0 on the
-                    // current corner when there is none: adding +0 changes no sum), lt and ll
-                    // as well on the rare diagonal step or jump.  Branch-free but for those.
+                    // move, tl on a step along x, lt on a step along y, lt and ll as well on
+                    // the rare diagonal step or jump.
                     // record j: wave-uniform, read out of the lanes that hold it
                     const int d = j * RS;
                     const int rc = (int)__builtin_amdgcn_readlane(rv[d >> 6], d & 63);
@@ -290,11 +289,15 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
                     }
                     const int code = rc & 7;
                     const bool sx = code & 1, sy = code & 2;
-                    spread(code ? att : T(0), pc);
-                    spread(sx ? atl : sy ? alt : T(0), sx ? pc + ey : pc + ex);
-                    if (sx && sy) {
-                        spread(alt, pc + ex);
-                        if (code == 7) spread(all, pc + ex + ey);
+                    // the move code is wave-uniform: heads that stay in their corner cell (code
+                    // 0, about a third of the cells) spread nothing, with no divergence
+                    if (code) {
+                        spread(att, pc);
+                        spread(sx ? atl : alt, sx ? pc + ey : pc + ex);
+                        if (sx && sy) {
+                            spread(alt, pc + ex);
+                            if (code == 7) spread(all, pc + ex + ey);
+                        }
                     }
                     // the survivors move to their new roles, the rest restart from 0 (selects)
                     const bool jump = code == 7;

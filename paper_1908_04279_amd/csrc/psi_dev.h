@@ -186,27 +186,51 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
                 fxc[s] = donor(Axm, Pm, Pc[s]);
             }
         }
-#pragma unroll 1
-        for (int t = 0; t < TI; ++t) {
-            const int i = i0 + t;
-            if (i >= nx) break;
+        // Two sets of neighbour registers: the loads of pencil t + 1 go into one set before the
+        // arithmetic of pencil t reads the other (software pipelining without register copies,
+        // so each wait counts only the older set's loads).  The wave-uniform u and grad u go
+        // through the vector memory path too (an offset the compiler cannot prove uniform): all
+        // loads then retire in order, and no wait on the scalar cache holds the pipeline.
+        const int64_t vz = (int64_t)__builtin_amdgcn_mbcnt_lo(0u, 0u);  // 0 on every lane
+        struct Nb {
+            T Pxp[KPL], Mxp[KPL], Pym[KPL], Mym[KPL], Pyp[KPL], Myp[KPL];
+            T ux_p, uy_c, uy_m, uy_p, Gxx, Gxy, Gyx, Gyy;
+        };
+        Nb A, B;
+        auto fetch = [&](Nb &X, int i) {
             const int ip = (i + 1 == nx) ? 0 : i + 1;
             const int64_t pc = (int64_t)i * ny + j, pxp = (int64_t)ip * ny + j;
             const int64_t pym = (int64_t)i * ny + jm, pyp = (int64_t)i * ny + jp;
-            T Pxp[KPL], Mxp[KPL], Pym[KPL], Mym[KPL], Pyp[KPL], Myp[KPL];
 #pragma unroll
             for (int s = 0; s < KPL; ++s) {
                 const int k = lane + 64 * s;
-                Pxp[s] = psi_in[pxp * NTH + k];
-                Mxp[s] = m0[pxp * NTH + k];
-                Pym[s] = psi_in[pym * NTH + k];
-                Mym[s] = m0[pym * NTH + k];
-                Pyp[s] = psi_in[pyp * NTH + k];
-                Myp[s] = m0[pyp * NTH + k];
+                X.Pxp[s] = psi_in[pxp * NTH + k];
+                X.Mxp[s] = m0[pxp * NTH + k];
+                X.Pym[s] = psi_in[pym * NTH + k];
+                X.Mym[s] = m0[pym * NTH + k];
+                X.Pyp[s] = psi_in[pyp * NTH + k];
+                X.Myp[s] = m0[pyp * NTH + k];
             }
-            const T ux_p = u[pxp];
-            const T uy_c = u[nxy + pc], uy_m = u[nxy + pym], uy_p = u[nxy + pyp];
-            const T Gxx = Gr[pc], Gxy = Gr[nxy + pc], Gyx = Gr[2 * nxy + pc], Gyy = Gr[3 * nxy + pc];
+            X.ux_p = u[pxp + vz];
+            X.uy_c = u[nxy + pc + vz];
+            X.uy_m = u[nxy + pym + vz];
+            X.uy_p = u[nxy + pyp + vz];
+            X.Gxx = Gr[pc + vz];
+            X.Gxy = Gr[nxy + pc + vz];
+            X.Gyx = Gr[2 * nxy + pc + vz];
+            X.Gyy = Gr[3 * nxy + pc + vz];
+        };
+        auto pencil = [&](const Nb &X, int i) {
+            const int64_t pc = (int64_t)i * ny + j;
+            const T(&Pxp)[KPL] = X.Pxp;
+            const T(&Mxp)[KPL] = X.Mxp;
+            const T(&Pym)[KPL] = X.Pym;
+            const T(&Mym)[KPL] = X.Mym;
+            const T(&Pyp)[KPL] = X.Pyp;
+            const T(&Myp)[KPL] = X.Myp;
+            const T ux_p = X.ux_p;
+            const T uy_c = X.uy_c, uy_m = X.uy_m, uy_p = X.uy_p;
+            const T Gxx = X.Gxx, Gxy = X.Gxy, Gyx = X.Gyx, Gyy = X.Gyy;
             // psi at orientation k+1: lane k+1, or lane 0 of the next slot for lane 63
             T rp[KPL];
 #pragma unroll
@@ -298,6 +322,20 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
                 Mc[s] = Mxp[s];
             }
             ux_c = ux_p;
+        };
+        // every fetch is issued (the last ones reload a pencil already in range), so that each
+        // path leaves the same loads in flight and the waits stay exact
+        fetch(A, i0);
+#pragma unroll 1
+        for (int t = 0; t < TI; t += 2) {
+            const int i = i0 + t;
+            if (i >= nx) break;
+            const bool more = t + 1 < TI && i + 1 < nx;
+            fetch(B, more ? i + 1 : i);
+            pencil(A, i);
+            if (!more) break;
+            fetch(A, (t + 2 < TI && i + 2 < nx) ? i + 2 : i + 1);
+            pencil(B, i + 1);
         }
     }
     if constexpr (OUT) {

@@ -106,3 +106,37 @@ def test_graph_refusals():
     assert ei.value.status == mmk.MMK_ERR_ARG
     ctx.step_graph(2, 0.01)
     ctx.close()
+
+
+@pytest.mark.parametrize("over", [
+    dict(rc=0.45, m_total=0.01),                            # coarse pass and motor launch per step
+    dict(rc=0.45, m_total=0.01, motor_cfl=0.25, v0=4.0),    # per sub-step (6: an even count, a copy)
+    dict(rc=0.45, motor_cfl=0.2, v0=4.0),                   # sub-steps in registers
+])
+def test_graph_anchor_resolved_matches_eager_bitwise(over):
+    """The anchor-resolved model through mmk_step_graph against mmk_step, bit for bit after every
+    call (state, marginals, outputs, per-anchor coarse density and pool)."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=12, ny=12, ntheta=8, ns=8, **over)
+    ncell = len(mmk.r0_cells(p))
+    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, p.lx, p.ly, seed=0)
+    Mb0 = gen.make_Mb0_random(ncell, p.nx, p.ny, seed=4)
+    fl = gen.fluid_schedule(p.nx, p.ny, 3, p.lx, p.ly)
+    dt = gen.cfl_dt(p, fl)
+    ctxs = [mmk.Context(p) for _ in range(2)]
+    for c in ctxs:
+        c.set_state(torch.as_tensor(psi0), torch.as_tensor(Mb0))
+    for e, k in enumerate([3, 2, 3]):
+        for c in ctxs:
+            c.set_fluid(*map(torch.as_tensor, fl[e]))
+        ctxs[0].step(k, dt)
+        ctxs[1].step_graph(k, dt)
+        torch.cuda.synchronize()
+        a, b = outputs(ctxs[0]), outputs(ctxs[1])
+        a += [x.cpu().numpy() for x in ctxs[0].get_anchors()]
+        b += [x.cpu().numpy() for x in ctxs[1].get_anchors()]
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), (e, k)
+    for c in ctxs:
+        c.close()
