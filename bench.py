@@ -647,7 +647,7 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--option", action="append", default=[], metavar="NAME=VALUE",
-                    help="a context option (mmk_set_option) for the fp32 and fp64 legs of --only "
+                    help="a context option (mmk_set_option) for the fp32, fp64 and large legs of --only "
                          "(measurements; the default run takes the library's defaults)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -741,10 +741,10 @@ def main():
         pl = gen.params_for("fp32_512x512x128x64")
         torch.cuda.reset_peak_memory_stats()
         large["blocked"] = run_forward(pl, mmk.FP32, args.large_steps, 10, K, event_every=args.event_every,
-                                       motor_every=1)
+                                       motor_every=1, options=extra or None)
         large["peak_device_gb"] = torch.cuda.max_memory_allocated() / 1e9
         large["one_launch"] = run_forward(pl, mmk.FP32, args.large_steps, 10, K, event_every=args.event_every,
-                                          options={"motor_block": 0}, motor_every=1)
+                                          options={**extra, "motor_block": 0}, motor_every=1)
     c2 = None
     if args.only in ("all", "c2"):
         # paper-like scale in FP64: 128^2 x 64 x 32, 1000 micro-steps, a new fluid every 10

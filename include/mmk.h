@@ -249,8 +249,10 @@ typedef enum {
                                 * column stays in registers; m0 of every micro-step is kept for
                                 * its psi step); 0: one motor launch per micro-step */
     MMK_OPT_PSI_KERNEL = 1,    /* 0 (default): the LDS-free walking psi kernel for ntheta = 64
-                                * or 128 in FP32, the LDS-tiled one otherwise; 1: LDS-tiled;
-                                * 2: walking where ntheta allows it, else LDS-tiled */
+                                * or 128 in FP32, and in FP64 where nx is a multiple of 8 (the
+                                * walk with a ring of register sets), the LDS-tiled one
+                                * otherwise; 1: LDS-tiled; 2: walking where ntheta allows it,
+                                * else LDS-tiled */
     MMK_OPT_DEPL_FUSED = 2,    /* 1 (default): depletion with motor sub-cycling runs all
                                 * sub-steps of a micro-step in one launch where the tiling allows
                                 * it; 0: one launch per sub-step */
@@ -261,10 +263,15 @@ typedef enum {
     MMK_OPT_MOTOR_CHUNKS = 4,  /* 0 (default): each lane holds consecutive cells; 2 or 4: each
                                 * lane holds that many 16-byte chunks spaced a lane group apart
                                 * (no depletion; a value without a tiling for ns leaves 0) */
-    MMK_OPT_MOTOR_NT = 5       /* -1 (default): in FP32 nontemporal loads and stores of M for a
+    MMK_OPT_MOTOR_NT = 5,      /* -1 (default): in FP32 nontemporal loads and stores of M for a
                                 * launch of one step, plain accesses for launches of several
                                 * micro-steps or sub-steps; plain in FP64; 0: plain; 1: nontemporal
                                 * loads and stores; 2: nontemporal loads only */
+    MMK_OPT_PSI_DEPTH = 6      /* walking psi kernel: pencils of a walk of 8 whose loads are in
+                                * flight together, where nx is a multiple of 8 (else always two
+                                * alternating register sets); 0 (default): 8 at ntheta = 64, 4
+                                * at 128; 2: two alternating sets; 4, 8: a ring of that many
+                                * sets (4 at ntheta = 128) */
 } mmk_option;
 mmk_status mmk_set_option(mmk_ctx *ctx, int32_t option, int32_t value);
 

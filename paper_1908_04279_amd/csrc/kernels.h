@@ -91,6 +91,7 @@ struct WalkPlan {
     int ok;              // 0: ntheta not supported by the walking kernel
     int kpl;             // orientations per lane (ntheta / 64)
     int ti, tiles_i, tiles_j, per, blocks;
+    int depth;           // 0: two alternating register sets; 4, 8: a ring of that many (nx % ti == 0)
 };
 WalkPlan plan_walk(int nx, int ny, int nth);
 

@@ -155,7 +155,7 @@ struct mmk_ctx {
     PsiLaunch pl{}, pl_rev{};
     int cur = 0;    // index of the current M / psi buffers
     // implementation options (mmk_set_option), and what they select
-    int opt[6] = {1, 0, 1, 0, 0, -1};
+    int opt[7] = {1, 0, 1, 0, 0, -1, 0};
     // ntheta = 64, 128: the psi step runs as the LDS-free walking kernel (default in FP32, where
     // it measured as fast as the LDS-tiled one; in FP64 the LDS-tiled kernel is faster)
     WalkPlan wp{};
@@ -265,7 +265,14 @@ static void drop_graphs(mmk_ctx *c) {
 static void apply_options(mmk_ctx *c) {
     const mmk_params &p = c->p;
     const int psik = c->opt[MMK_OPT_PSI_KERNEL];
-    c->walk = c->wp.ok && (psik == 0 ? c->esz == 4 : psik == 2);
+    // ring of register sets in the walk: 8 pencils at ntheta = 64, 4 at 128 (register space),
+    // where the x extent is a multiple of the walk length
+    const int depth = c->opt[MMK_OPT_PSI_DEPTH];
+    const bool ring_ok = c->wp.ok && p.nx % c->wp.ti == 0;
+    c->wp.depth = !ring_ok || depth == 2 ? 0 : depth == 0 ? (c->wp.kpl == 1 ? 8 : 4) : depth;
+    // the walking kernel by default in FP32, and in FP64 where the ring applies (with two sets
+    // the FP64 walk is slower than the LDS-tiled kernel)
+    c->walk = c->wp.ok && (psik == 0 ? (c->esz == 4 || c->wp.depth > 0) : psik == 2);
     c->block = p.m_total == 0 && p.rc == 0 && c->opt[MMK_OPT_MOTOR_BLOCK] != 0;
     c->wide = c->block || (p.motor_cfl > 0 && p.m_total == 0);
     c->depl_fused = c->opt[MMK_OPT_DEPL_FUSED] != 0;
@@ -737,6 +744,7 @@ mmk_status mmk_set_option(mmk_ctx *c, int32_t option, int32_t value) {
         case MMK_OPT_MOTOR_LANES: ok = value == 0 || (value >= 2 && value <= 64 && (value & (value - 1)) == 0); break;
         case MMK_OPT_MOTOR_CHUNKS: ok = value == 0 || value == 1 || value == 2 || value == 4; break;
         case MMK_OPT_MOTOR_NT: ok = value >= -1 && value <= 2; break;
+        case MMK_OPT_PSI_DEPTH: ok = value == 0 || value == 2 || value == 4 || value == 8; break;
         default: return fail(c, MMK_ERR_ARG, "unknown option %d", option);
     }
     if (!ok) return fail(c, MMK_ERR_ARG, "value %d out of range for option %d", value, option);

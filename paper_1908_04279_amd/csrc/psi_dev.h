@@ -122,6 +122,18 @@ __device__ __forceinline__ int wrap(int i, int n) {
 }
 
 
+// value of lane l (wave-uniform l) on every lane
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int l) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    } else {
+        const long long b = __builtin_bit_cast(long long, v);
+        const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+        return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned int)lo);
+    }
+}
+
 // ---- LDS-free psi step: one wave walks a row of pencils along x ----------------------------
 // For ntheta = 64 KPL a pencil is one wave (lane k holds orientations k, k + 64, ...).  A block
 // of four waves owns a tile of TI x 4 pencils; wave w walks the pencils (i0 .. i0+TI-1, j0+w)
@@ -135,7 +147,7 @@ __device__ __forceinline__ int wrap(int i, int n) {
 // Same flux and update expressions as the LDS-tiled kernel; OUT adds the theta-moments, the
 // stress and the FP64 block partials (mass, sum sigma) of the new state; DEPL adds the
 // depletion factors of the new state (Dxy).
-template <typename T, int KPL, int TI, bool OUT, bool DEPL>
+template <typename T, int KPL, int TI, bool OUT, bool DEPL, int D>
 __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *__restrict__ psi_out,
                                               const T *__restrict__ m0, const T *__restrict__ m1,
                                               const T *__restrict__ u, const T *__restrict__ Gr,
@@ -166,40 +178,35 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
             chp[s] = tab[TAB_CH * NTH + k];
             shp[s] = tab[TAB_SH * NTH + k];
         }
-        // centre cells of the first pencil and the flux through its lower x-face
-        T Pc[KPL], Mc[KPL], fxc[KPL];
-        const int64_t pc0 = (int64_t)i0 * ny + j;
-        T ux_c = u[pc0];
-        {
-            const int im = (i0 == 0) ? nx - 1 : i0 - 1;
-            const int64_t pm = (int64_t)im * ny + j;
-            const T ux_m = u[pm];
+        // output steps: the theta tables of the moments and stress
+        T tcc[KPL], tcs[KPL], tss[KPL], th1[KPL], th2[KPL];
+        if constexpr (OUT) {
 #pragma unroll
             for (int s = 0; s < KPL; ++s) {
                 const int k = lane + 64 * s;
-                const T Pm = psi_in[pm * NTH + k], Mm = m0[pm * NTH + k];
-                Pc[s] = psi_in[pc0 * NTH + k];
-                Mc[s] = m0[pc0 * NTH + k];
-                const T ax_m = ux_m - c.F * Mm * co[s];
-                const T ax_c = ux_c - c.F * Mc[s] * co[s];
-                const T Axm = T(0.5) * (ax_m + ax_c);
-                fxc[s] = donor(Axm, Pm, Pc[s]);
+                tcc[s] = tab[TAB_CC * NTH + k];
+                tcs[s] = tab[TAB_CS * NTH + k];
+                tss[s] = tab[TAB_SS * NTH + k];
+                th1[s] = tab[TAB_H1 * NTH + k];
+                th2[s] = tab[TAB_H2 * NTH + k];
             }
         }
-        // Two sets of neighbour registers: the loads of pencil t + 1 go into one set before the
-        // arithmetic of pencil t reads the other (software pipelining without register copies,
-        // so each wait counts only the older set's loads).  The wave-uniform u and grad u go
-        // through the vector memory path too (an offset the compiler cannot prove uniform): all
-        // loads then retire in order, and no wait on the scalar cache holds the pipeline.
+        // The wave-uniform u and grad u go through the vector memory path (an offset the compiler
+        // cannot prove uniform): all loads then retire in order, and no wait on the scalar cache
+        // holds a pipeline of loads.
         const int64_t vz = (int64_t)__builtin_amdgcn_mbcnt_lo(0u, 0u);  // 0 on every lane
-        struct Nb {
+        // the neighbour cells of one pencil (per lane) and its face velocities and velocity
+        // gradient (wave-uniform)
+        struct Nv {
             T Pxp[KPL], Mxp[KPL], Pym[KPL], Mym[KPL], Pyp[KPL], Myp[KPL];
+            T M1[OUT ? KPL : 1];  // output steps: m1 of the pencil itself
+        };
+        struct Nu {
             T ux_p, uy_c, uy_m, uy_p, Gxx, Gxy, Gyx, Gyy;
         };
-        Nb A, B;
-        auto fetch = [&](Nb &X, int i) {
+        auto fetch_v = [&](Nv &X, int i) {
             const int ip = (i + 1 == nx) ? 0 : i + 1;
-            const int64_t pc = (int64_t)i * ny + j, pxp = (int64_t)ip * ny + j;
+            const int64_t pxp = (int64_t)ip * ny + j;
             const int64_t pym = (int64_t)i * ny + jm, pyp = (int64_t)i * ny + jp;
 #pragma unroll
             for (int s = 0; s < KPL; ++s) {
@@ -210,17 +217,59 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
                 X.Mym[s] = m0[pym * NTH + k];
                 X.Pyp[s] = psi_in[pyp * NTH + k];
                 X.Myp[s] = m0[pyp * NTH + k];
+                if constexpr (OUT) X.M1[s] = m1[((int64_t)i * ny + j) * NTH + k];
             }
-            X.ux_p = u[pxp + vz];
-            X.uy_c = u[nxy + pc + vz];
-            X.uy_m = u[nxy + pym + vz];
-            X.uy_p = u[nxy + pyp + vz];
-            X.Gxx = Gr[pc + vz];
-            X.Gxy = Gr[nxy + pc + vz];
-            X.Gyx = Gr[2 * nxy + pc + vz];
-            X.Gyy = Gr[3 * nxy + pc + vz];
         };
-        auto pencil = [&](const Nb &X, int i) {
+        // field f of Nu for pencil i: its address in u (f < 4) or grad u (f >= 4)
+        auto u_offset = [&](int i, int f) -> int64_t {
+            const int ip = (i + 1 == nx) ? 0 : i + 1;
+            const int64_t pc = (int64_t)i * ny + j;
+            switch (f) {
+                case 0: return (int64_t)ip * ny + j;
+                case 1: return nxy + pc;
+                case 2: return nxy + (int64_t)i * ny + jm;
+                case 3: return nxy + (int64_t)i * ny + jp;
+                default: return (int64_t)(f - 4) * nxy + pc;
+            }
+        };
+        auto fetch_u = [&](Nu &X, int i) {
+            X.ux_p = u[u_offset(i, 0) + vz];
+            X.uy_c = u[u_offset(i, 1) + vz];
+            X.uy_m = u[u_offset(i, 2) + vz];
+            X.uy_p = u[u_offset(i, 3) + vz];
+            X.Gxx = Gr[u_offset(i, 4) + vz];
+            X.Gxy = Gr[u_offset(i, 5) + vz];
+            X.Gyx = Gr[u_offset(i, 6) + vz];
+            X.Gyy = Gr[u_offset(i, 7) + vz];
+        };
+        // centre cells of the first pencil and the flux through its lower x-face: loads, then
+        // the flux
+        T Pc[KPL], Mc[KPL], fxc[KPL], Pm[KPL], Mm[KPL];
+        const int64_t pc0 = (int64_t)i0 * ny + j;
+        const int im0 = (i0 == 0) ? nx - 1 : i0 - 1;
+        const int64_t pm0 = (int64_t)im0 * ny + j;
+        const int64_t uz = D > 0 ? vz : 0;
+        T ux_c = u[pc0 + uz];
+        const T ux_m = u[pm0 + uz];
+#pragma unroll
+        for (int s = 0; s < KPL; ++s) {
+            const int k = lane + 64 * s;
+            Pm[s] = psi_in[pm0 * NTH + k];
+            Mm[s] = m0[pm0 * NTH + k];
+            Pc[s] = psi_in[pc0 * NTH + k];
+            Mc[s] = m0[pc0 * NTH + k];
+        }
+        if constexpr (D > 0) __builtin_amdgcn_sched_barrier(0);
+        auto first_flux = [&]() {
+#pragma unroll
+            for (int s = 0; s < KPL; ++s) {
+                const T ax_m = ux_m - c.F * Mm[s] * co[s];
+                const T ax_c = ux_c - c.F * Mc[s] * co[s];
+                const T Axm = T(0.5) * (ax_m + ax_c);
+                fxc[s] = donor(Axm, Pm[s], Pc[s]);
+            }
+        };
+        auto pencil = [&](const Nv &X, const Nu &U, int i) {
             const int64_t pc = (int64_t)i * ny + j;
             const T(&Pxp)[KPL] = X.Pxp;
             const T(&Mxp)[KPL] = X.Mxp;
@@ -228,9 +277,9 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
             const T(&Mym)[KPL] = X.Mym;
             const T(&Pyp)[KPL] = X.Pyp;
             const T(&Myp)[KPL] = X.Myp;
-            const T ux_p = X.ux_p;
-            const T uy_c = X.uy_c, uy_m = X.uy_m, uy_p = X.uy_p;
-            const T Gxx = X.Gxx, Gxy = X.Gxy, Gyx = X.Gyx, Gyy = X.Gyy;
+            const T ux_p = U.ux_p;
+            const T uy_c = U.uy_c, uy_m = U.uy_m, uy_p = U.uy_p;
+            const T Gxx = U.Gxx, Gxy = U.Gxy, Gyx = U.Gyx, Gyy = U.Gyy;
             // psi at orientation k+1: lane k+1, or lane 0 of the next slot for lane 63
             T rp[KPL];
 #pragma unroll
@@ -275,9 +324,8 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
                     else kahan_add(bs, bc, pn * Mc[s]);
                 }
                 if constexpr (OUT) {
-                    const T fm = c.F * m1[pc * NTH + k];
-                    const T cc = tab[TAB_CC * NTH + k], cs = tab[TAB_CS * NTH + k], ss = tab[TAB_SS * NTH + k];
-                    const T h1 = tab[TAB_H1 * NTH + k], h2 = tab[TAB_H2 * NTH + k];
+                    const T fm = c.F * X.M1[s];
+                    const T cc = tcc[s], cs = tcs[s], ss = tss[s], h1 = th1[s], h2 = th2[s];
                     const T terms[NMOM] = {pn,
                                            pn * co[s],
                                            pn * si[s],
@@ -323,19 +371,61 @@ __device__ __forceinline__ void psi_walk_tile(const T *__restrict__ psi_in, T *_
             }
             ux_c = ux_p;
         };
-        // every fetch is issued (the last ones reload a pencil already in range), so that each
-        // path leaves the same loads in flight and the waits stay exact
-        fetch(A, i0);
+        if constexpr (D == 0) {
+            // Two sets of neighbour registers: the loads of pencil t + 1 go into one set before
+            // the arithmetic of pencil t reads the other (software pipelining without register
+            // copies, so each wait counts only the older set's loads).  Every fetch is issued
+            // (the last ones reload a pencil already in range), so that each path leaves the
+            // same loads in flight and the waits stay exact.  Any x extent.
+            first_flux();
+            Nv A, B;
+            Nu UA, UB;
+            fetch_v(A, i0);
+            fetch_u(UA, i0);
 #pragma unroll 1
-        for (int t = 0; t < TI; t += 2) {
-            const int i = i0 + t;
-            if (i >= nx) break;
-            const bool more = t + 1 < TI && i + 1 < nx;
-            fetch(B, more ? i + 1 : i);
-            pencil(A, i);
-            if (!more) break;
-            fetch(A, (t + 2 < TI && i + 2 < nx) ? i + 2 : i + 1);
-            pencil(B, i + 1);
+            for (int t = 0; t < TI; t += 2) {
+                const int i = i0 + t;
+                if (i >= nx) break;
+                const bool more = t + 1 < TI && i + 1 < nx;
+                fetch_v(B, more ? i + 1 : i);
+                fetch_u(UB, more ? i + 1 : i);
+                pencil(A, UA, i);
+                if (!more) break;
+                const int in = (t + 2 < TI && i + 2 < nx) ? i + 2 : i + 1;
+                fetch_v(A, in);
+                fetch_u(UA, in);
+                pencil(B, UB, i + 1);
+            }
+        } else {
+            // A ring of D register sets (x extent a multiple of TI, no ragged walk): the first D
+            // pencils' cells are loaded at once, and pencil t + D's into the set that pencil t
+            // has just used; the schedule barriers keep that order, so D pencils are in flight.
+            // The uniform values of all TI pencils come in one load, field f of pencil t in lane
+            // 8 t + f, and are broadcast from there (lane_value).
+            static_assert(TI * 8 <= 64, "one lane per uniform value of the walk");
+            const int lt = lane >> 3, lf = lane & 7;
+            const int64_t lo = u_offset(i0 + (lt < TI ? lt : 0), lf);
+            const T uvec = lf < 4 ? u[lo] : Gr[lo];
+            Nv S[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) fetch_v(S[t], i0 + t);
+            __builtin_amdgcn_sched_barrier(0);
+            first_flux();
+#pragma unroll
+            for (int t = 0; t < TI; ++t) {
+                Nu U;
+                U.ux_p = lane_value(uvec, 8 * t + 0);
+                U.uy_c = lane_value(uvec, 8 * t + 1);
+                U.uy_m = lane_value(uvec, 8 * t + 2);
+                U.uy_p = lane_value(uvec, 8 * t + 3);
+                U.Gxx = lane_value(uvec, 8 * t + 4);
+                U.Gxy = lane_value(uvec, 8 * t + 5);
+                U.Gyx = lane_value(uvec, 8 * t + 6);
+                U.Gyy = lane_value(uvec, 8 * t + 7);
+                pencil(S[t % D], U, i0 + t);
+                if (t + D < TI) fetch_v(S[t % D], i0 + t + D);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     }
     if constexpr (OUT) {

@@ -17,7 +17,7 @@ WalkPlan plan_walk(int nx, int ny, int nth) {
     return w;
 }
 
-template <typename T, int KPL, int TI, bool OUT, bool DEPL>
+template <typename T, int KPL, int TI, bool OUT, bool DEPL, int D>
 __global__ __launch_bounds__(256) void k_psi_walk(const T *__restrict__ psi_in, T *__restrict__ psi_out,
                                                   const T *__restrict__ m0, const T *__restrict__ m1,
                                                   const T *__restrict__ u, const T *__restrict__ G,
@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_psi_walk(const T *__restrict__ psi_in, 
                                                   T *__restrict__ mom, double *__restrict__ partials,
                                                   T *__restrict__ Dxy, PsiConst<T> c, int tiles_i, int tiles_j,
                                                   int per) {
-    psi_walk_tile<T, KPL, TI, OUT, DEPL>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, Dxy, c, tiles_i,
+    psi_walk_tile<T, KPL, TI, OUT, DEPL, D>(psi_in, psi_out, m0, m1, u, G, tab, stress, mom, partials, Dxy, c, tiles_i,
                                    tiles_j, per, (int)blockIdx.x);
 }
 
@@ -35,18 +35,25 @@ hipError_t launch_psi_walk(const T *psi_in, T *psi_out, const T *m0, const T *m1
                            const WalkPlan &wp, hipStream_t s) {
     if (!wp.ok || wp.ti != 8) return hipErrorInvalidValue;
     const bool out = stress != nullptr;
-#define MMK_WALK(KPL, OUT, DEPL)                                                                           \
-    hipLaunchKernelGGL((k_psi_walk<T, KPL, 8, OUT, DEPL>), dim3(wp.blocks), dim3(256), 0, s, psi_in, psi_out, m0, \
-                       m1, u, G, tab, stress, mom, partials, Dxy, c, wp.tiles_i, wp.tiles_j, wp.per)
-#define MMK_WALK_D(KPL, OUT)                 \
-    if (Dxy) MMK_WALK(KPL, OUT, true);       \
-    else MMK_WALK(KPL, OUT, false);
-    if (wp.kpl == 1) {
-        if (out) { MMK_WALK_D(1, true) } else { MMK_WALK_D(1, false) }
-    } else {
-        if (out) { MMK_WALK_D(2, true) } else { MMK_WALK_D(2, false) }
+#define MMK_WALK(KPL, OUT, DEPL, D)                                                                        \
+    hipLaunchKernelGGL((k_psi_walk<T, KPL, 8, OUT, DEPL, D>), dim3(wp.blocks), dim3(256), 0, s, psi_in, psi_out,   \
+                       m0, m1, u, G, tab, stress, mom, partials, Dxy, c, wp.tiles_i, wp.tiles_j, wp.per)
+#define MMK_WALK_O(KPL, D)                                                    \
+    if (out) {                                                                \
+        if (Dxy) MMK_WALK(KPL, true, true, D); else MMK_WALK(KPL, true, false, D);   \
+    } else {                                                                  \
+        if (Dxy) MMK_WALK(KPL, false, true, D); else MMK_WALK(KPL, false, false, D); \
     }
-#undef MMK_WALK_D
+    const int d = (c.nx % wp.ti == 0) ? wp.depth : 0;
+    if (wp.kpl == 1) {
+        if (d == 8) { MMK_WALK_O(1, 8) }
+        else if (d == 4) { MMK_WALK_O(1, 4) }
+        else { MMK_WALK_O(1, 0) }
+    } else {
+        if (d == 4 || d == 8) { MMK_WALK_O(2, 4) }
+        else { MMK_WALK_O(2, 0) }
+    }
+#undef MMK_WALK_O
 #undef MMK_WALK
     return hipGetLastError();
 }

@@ -174,3 +174,22 @@ def test_walking_and_lds_psi_kernels_agree(precision, shape):
     compare(runs["walk"], runs["lds"], tol=1e-12 if precision == 0 else 1e-5)
     if precision == 0:
         compare(runs["walk"], run_oracle(p, psi0, M0, fl, 7, 25, dt))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("shape", [(16, 18, 64, 64), (8, 7, 64, 32), (24, 5, 128, 16), (40, 3, 128, 32),
+                                   (20, 6, 64, 16)])
+def test_walking_psi_ring_depths_agree(precision, shape):
+    """The walking psi kernel with a ring of 4 and 8 register sets (x extent a multiple of the
+    walk length 8; 20 is not, and runs the two-set form) against the two-set form, over several
+    calls and fluid exchanges; FP64 also against the oracle; with depletion factors (DEPL) too."""
+    nx, ny, nt, ns = shape
+    for m_total in (0.0, 0.05):
+        p = ModelParams(nx=nx, ny=ny, ntheta=nt, ns=ns, m_total=m_total)
+        psi0, M0, fl, dt = seeded_case(p, n_exchanges=4, M0_kind="random")
+        runs = {d: run_gpu(p, psi0, M0, fl, 7, 25, dt, precision=precision,
+                           options={"psi_kernel": 2, "psi_depth": d}) for d in (2, 4, 8)}
+        for d in (4, 8):
+            compare(runs[d], runs[2], tol=1e-14 if precision == 0 else 1e-6)
+        if precision == 0:
+            compare(runs[8], run_oracle(p, psi0, M0, fl, 7, 25, dt))
