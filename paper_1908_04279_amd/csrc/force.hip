@@ -218,8 +218,11 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
             const int q = r * PPL + lq;
             const int pi = min(ti * 8 + (q >> 3), nx - 1), pj = min(tj * 8 + (q & 7), ny - 1);
             const int64_t po = ((int64_t)pi * ny + pj) * pstride;
-            rows[0][r] = *reinterpret_cast<const R *>(Ma + po);
-            rows[1][r] = *reinterpret_cast<const R *>(Mb + po);
+            // M is streamed once: nontemporal, so that it does not push the pass's psi
+            // lines and the records out of L2 (with plain loads they were fetched again on
+            // most passes, 1.27x the algorithmic bytes)
+            rows[0][r] = __builtin_nontemporal_load(reinterpret_cast<const R *>(Ma + po));
+            rows[1][r] = __builtin_nontemporal_load(reinterpret_cast<const R *>(Mb + po));
         }
         const uint32_t *b = blk + ((size_t)k * nchunk + ch) * kForceBlock + lane;
 #pragma unroll
