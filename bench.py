@@ -592,7 +592,8 @@ CALIB_KINDS = {"fma_f32": (0, 2), "add_f32": (1, 1), "max_f32": (2, 1), "med3_f3
                "mul_f32": (8, 1), "sub_f32": (9, 1), "cndmask_sgpr_mask": (10, 0), "mov_b32": (11, 0),
                "min3_f32": (12, 0), "add_f32_dpp": (13, 1), "add_med3_alternating": (14, 0),
                "add_f64": (15, 1), "med3_f32_const0": (16, 0), "fma_f32_const": (17, 2),
-               "fma_f32_sgpr": (18, 2), "max_f32_abs": (19, 0)}
+               "fma_f32_sgpr": (18, 2), "max_f32_abs": (19, 0), "add_med3_each_other": (20, 0),
+               "motor_mix": (21, 0)}
 
 
 def valu_calibration():

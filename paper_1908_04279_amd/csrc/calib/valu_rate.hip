@@ -24,6 +24,8 @@ enum Kind {
     FMA_K = 17,        // fma with the inline constant 0.5 as one source
     FMA_SGPR = 18,     // fma with an SGPR source
     MAX_ABS = 19,      // VOP3 max with an absolute-value modifier
+    ADD_MED3_ALT = 20, // add and med3 alternating instruction by instruction
+    MOTOR_MIX = 21,    // the motor step's mix: of every 9, 3 med3, 2 sub, 1 add, 2 fma, 1 fmac
 };
 
 template <int KIND>
@@ -52,6 +54,19 @@ __device__ __forceinline__ void op32(float &a, float b, float c, uint64_t m, int
     if constexpr (KIND == FMA_K) asm volatile("v_fma_f32 %0, %1, 0.5, %0" : "+v"(a) : "v"(b));
     if constexpr (KIND == FMA_SGPR) asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(a) : "s"(b), "v"(c));
     if constexpr (KIND == MAX_ABS) asm volatile("v_max_f32_e64 %0, |%0|, %1" : "+v"(a) : "v"(b));
+    if constexpr (KIND == ADD_MED3_ALT) {
+        if (u & 1) asm volatile("v_med3_f32 %0, %0, %1, %2" : "+v"(a) : "v"(b), "v"(c));
+        else asm volatile("v_add_f32 %0, %0, %1" : "+v"(a) : "v"(b));
+    }
+    if constexpr (KIND == MOTOR_MIX) {
+        switch (u % 9) {
+            case 0: case 1: case 2: asm volatile("v_med3_f32 %0, %0, %1, %2" : "+v"(a) : "v"(b), "v"(c)); break;
+            case 3: case 4: asm volatile("v_sub_f32 %0, %1, %0" : "+v"(a) : "v"(b)); break;
+            case 5: asm volatile("v_add_f32 %0, %0, %1" : "+v"(a) : "v"(b)); break;
+            case 6: case 7: asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(a) : "v"(b), "v"(c)); break;
+            default: asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(a) : "v"(b), "v"(c)); break;
+        }
+    }
 }
 
 template <int KIND>
@@ -64,7 +79,7 @@ __global__ __launch_bounds__(256) void k_valu32(float *out, int iters, float b, 
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) op32<KIND>(a[j], b, c, m, u);
+            for (int j = 0; j < 8; ++j) op32<KIND>(a[j], b, c, m, KIND == ADD_MED3 ? u : 8 * u + j);
     }
     float s = 0;
 #pragma unroll
@@ -127,6 +142,8 @@ extern "C" int mmk_calib_valu(int kind, int blocks, int iters, float *out, void 
         case FMA_K: hipLaunchKernelGGL(k_valu32<FMA_K>, g, t, 0, s, out, iters, 1e-7f, 0.f); break;
         case FMA_SGPR: hipLaunchKernelGGL(k_valu32<FMA_SGPR>, g, t, 0, s, out, iters, 1.0000001f, 1e-7f); break;
         case MAX_ABS: hipLaunchKernelGGL(k_valu32<MAX_ABS>, g, t, 0, s, out, iters, 0.5f, 0.f); break;
+        case ADD_MED3_ALT: hipLaunchKernelGGL(k_valu32<ADD_MED3_ALT>, g, t, 0, s, out, iters, 1e-7f, 2.f); break;
+        case MOTOR_MIX: hipLaunchKernelGGL(k_valu32<MOTOR_MIX>, g, t, 0, s, out, iters, 1e-7f, 1.0000001f); break;
         case MOV_DPP: hipLaunchKernelGGL(k_valu32<MOV_DPP>, g, t, 0, s, out, iters, 0.f, 0.f); break;
         case CNDMASK: hipLaunchKernelGGL(k_valu32<CNDMASK>, g, t, 0, s, out, iters, 0.5f, 0.25f); break;
         default: return (int)hipErrorInvalidValue;

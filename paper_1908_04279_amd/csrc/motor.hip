@@ -86,9 +86,19 @@ __device__ __forceinline__ double column_total(double v0, double v1, int g) {
     return group_sum_pair<LPC, false, PAIR, double>(v0, 0.0, v1, 0.0, g);
 }
 
+// Occupancy target of k_motor_step: FP32 columns of 16 cells a lane (the blocked launch) are
+// held to 64 VGPRs, 8 waves per SIMD (measured 4% faster than the compiler's choice of 78 VGPRs
+// and 6 waves: the extra waves cover the dependent limiter and reduction chains); the other
+// tilings keep the compiler's allocation (forced down, the larger ones spill).
+template <typename T, int CPL, bool RAGGED>
+constexpr int motor_waves_per_eu() {
+    return (sizeof(T) == 4 && CPL == 16 && !RAGGED) ? 8 : 1;
+}
+
 // NT: bit 0 nontemporal loads of M, bit 1 nontemporal stores.
 template <typename T, int CPL, int LPC, int LIM, bool RAGGED, bool WANT_M1, int NT>
-__global__ __launch_bounds__(256) void k_motor_step(const T *__restrict__ M_in, T *__restrict__ M_out,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(motor_waves_per_eu<T, CPL, RAGGED>())))
+void k_motor_step(const T *__restrict__ M_in, T *__restrict__ M_out,
                                                     T *__restrict__ m0, T *__restrict__ m1,
                                                     int64_t ncol, int ns, MotorConst<T> c,
                                                     const T *__restrict__ Dxy) {
