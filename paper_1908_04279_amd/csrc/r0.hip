@@ -299,71 +299,57 @@ __global__ __launch_bounds__(256) void k_r0_psiT(const T *__restrict__ psi, T *_
     psiT[o] = psi[x * nth + k];
 }
 
-// One lane: VX consecutive anchors; one wave: one row of partials over every nrow-th run.
-template <typename T, int VX>
+// One lane: one anchor; one wave: one row of partials over every nrow-th run, added in run order.
+// The wave's run records come 64 at a time, one per lane (no scalar loads to wait for), and are
+// broadcast from there; the run totals and the psi values of four runs are loaded into one of
+// two register sets while the other set's four runs are added, so eight runs' loads are in
+// flight with no copy of a loaded register (a copy would wait for every load).
+template <typename T>
 __global__ __launch_bounds__(256) void k_r0_coarse(const T *__restrict__ q0, const T *__restrict__ psiT,
                                                    const R0Seg *__restrict__ seg, double *__restrict__ part,
                                                    R0Const<T> c, int nseg, int nrow) {
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t r00 = ((int64_t)blockIdx.x * 64 + lane) * VX;
-    int iv[VX], jv[VX];
-    bool ok[VX];
-    double acc[VX];
-#pragma unroll
-    for (int v = 0; v < VX; ++v) {
-        const int64_t r0 = r00 + v;
-        ok[v] = r0 < c.nxy;
-        iv[v] = ok[v] ? (int)(r0 / c.ny) : 0;
-        jv[v] = ok[v] ? (int)(r0 - (int64_t)iv[v] * c.ny) : 0;
-        acc[v] = 0.0;
-    }
-    // this wave's runs are row, row + nrow, ...: in groups of four, the next group's records and
-    // run totals are fetched while the current group is added; then the rest one by one.  The
-    // terms are added in run order either way.
-    auto add = [&](const R0Seg &r, const T (&q)[VX]) {
-        const int k = r.pack >> 20;
-#pragma unroll
-        for (int v = 0; v < VX; ++v) {
-            // the filament cell of this run at anchor r0: x = r0 + (a, b), periodic
-            const int64_t x = (int64_t)wrap1(iv[v] + r.a, c.nx) * c.ny + wrap1(jv[v] + r.b, c.ny);
-            if (ok[v]) acc[v] += (double)q[v] * (double)psiT[(int64_t)k * c.nxy + x];
-        }
-    };
+    const int64_t r0 = (int64_t)blockIdx.x * 64 + lane;
+    const bool ok = r0 < c.nxy;
+    const int64_t rz = ok ? r0 : 0;  // lanes past the last anchor load anchor 0 and add nothing
+    const int iv = (int)(rz / c.ny), jv = (int)(rz - (int64_t)iv * c.ny);
+    double acc = 0.0;
     const int nw = row < nseg ? (nseg - row + nrow - 1) / nrow : 0;
-    const int groups = nw / 4;
-    R0Seg r[4];
-    T q[4][VX];
-    auto fetch = [&](int s0) {
+    for (int base = 0; base < nw; base += 64) {
+        const int cnt = min(64, nw - base);
+        // record of run row + (base + l) nrow in lane l (the last one again past cnt)
+        const R0Seg rec = seg[row + (int64_t)(base + min(lane, cnt - 1)) * nrow];
+        T qa[4], pa[4], qb[4], pb[4];
+        // runs n0 .. n0 + 3 of this batch (clamped to the last, whose repeats are not added)
+        auto fetch = [&](T (&q)[4], T (&pv)[4], int n0) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            r[u] = seg[s0 + u * nrow];
-            if (ok[0]) ldv<T, VX>(q0 + (int64_t)(s0 + u * nrow) * c.nxy + r00, q[u]);  // nxy % VX == 0
+            for (int u = 0; u < 4; ++u) {
+                const int n = min(n0 + u, cnt - 1);
+                const int ra = __builtin_amdgcn_readlane(rec.a, n), rb = __builtin_amdgcn_readlane(rec.b, n);
+                const int k = __builtin_amdgcn_readlane(rec.pack, n) >> 20;
+                const int64_t srun = row + (int64_t)(base + n) * nrow;
+                q[u] = q0[srun * c.nxy + rz];
+                // the filament cell of this run at anchor r0: x = r0 + (a, b), periodic
+                const int64_t x = (int64_t)wrap1(iv + ra, c.nx) * c.ny + wrap1(jv + rb, c.ny);
+                pv[u] = psiT[(int64_t)k * c.nxy + x];
+            }
+        };
+        auto add = [&](const T (&q)[4], const T (&pv)[4], int n0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (ok && n0 + u < cnt) acc += (double)q[u] * (double)pv[u];
+        };
+        fetch(qa, pa, 0);
+        for (int n0 = 0; n0 < cnt; n0 += 8) {
+            fetch(qb, pb, n0 + 4);
+            add(qa, pa, n0);
+            if (n0 + 4 >= cnt) break;
+            fetch(qa, pa, n0 + 8);
+            add(qb, pb, n0 + 4);
         }
-    };
-    if (groups > 0) fetch(row);
-    for (int g = 0; g < groups; ++g) {
-        R0Seg rc[4];
-        T qc[4][VX];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            rc[u] = r[u];
-#pragma unroll
-            for (int v = 0; v < VX; ++v) qc[u][v] = q[u][v];
-        }
-        if (g + 1 < groups) fetch(row + (g + 1) * 4 * nrow);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) add(rc[u], qc[u]);
     }
-    for (int s = row + groups * 4 * nrow; s < nseg; s += nrow) {
-        const R0Seg r = seg[s];
-        T q[VX];
-        if (ok[0]) ldv<T, VX>(q0 + (int64_t)s * c.nxy + r00, q);
-        add(r, q);
-    }
-#pragma unroll
-    for (int v = 0; v < VX; ++v)
-        if (ok[v]) part[(int64_t)row * c.nxy + r00 + v] = acc[v];
+    if (ok) part[(int64_t)row * c.nxy + r0] = acc;
 }
 
 // coarse = w sum of the rows (fixed order); Alg. 2 / Eq. (6): where coarse > m_total the
@@ -513,9 +499,9 @@ hipError_t launch_r0_coarse(const T *q0, const T *psi, T *psiT, const R0Seg *seg
     hipLaunchKernelGGL(k_r0_psiT<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, psi, psiT, c.nxy, c.nth);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // one anchor per lane (measured at the benchmark workload: 98.6 us per coarse pass in FP32
-    // against 109 with 16-byte loads of the run totals, 138 against 141 in FP64)
-    hipLaunchKernelGGL((k_r0_coarse<T, 1>), dim3((unsigned)((c.nxy + 63) / 64), (unsigned)nsplit), dim3(256), 0, s,
+    // one anchor per lane (measured at the benchmark workload with the earlier form of the
+    // kernel: 98.6 us per coarse pass in FP32 against 109 with 16-byte loads of the run totals)
+    hipLaunchKernelGGL((k_r0_coarse<T>), dim3((unsigned)((c.nxy + 63) / 64), (unsigned)nsplit), dim3(256), 0, s,
                        q0, psiT, seg, part, c, nseg, 4 * nsplit);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
