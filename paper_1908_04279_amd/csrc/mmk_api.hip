@@ -156,8 +156,8 @@ struct mmk_ctx {
     int cur = 0;    // index of the current M / psi buffers
     // implementation options (mmk_set_option), and what they select
     int opt[7] = {1, 0, 1, 0, 0, -1, 0};
-    // ntheta = 64, 128: the psi step runs as the LDS-free walking kernel (default in FP32, where
-    // it measured as fast as the LDS-tiled one; in FP64 the LDS-tiled kernel is faster)
+    // ntheta = 64, 128: the psi step runs as the LDS-free walking kernel (by default in FP32,
+    // and in FP64 where nx allows the ring of register sets; apply_options decides)
     WalkPlan wp{};
     bool walk = false;
     bool block = false;  // temporal blocking of the linear motor step
