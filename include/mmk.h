@@ -240,8 +240,8 @@ mmk_status mmk_tape_end(mmk_ctx *ctx);
 /* Implementation options of a context (project extras, not in the paper).  Each selects
  * between kernels or launch shapes that compute the same micro-step; the defaults are the
  * ones measured fastest on MI355X.  Results under any setting agree with the defaults up to the
- * association of the s-sums (the lane tiling) and are bitwise equal where the tiling is the
- * same.  An option may be set at any time between calls and applies from the next call on.
+ * association of the s- and theta-sums (the lane tiling, the psi kernel) and are bitwise equal
+ * where those are the same.  An option may be set at any time between calls and applies from the next call on.
  * MMK_ERR_ARG for an unknown option or a value outside its range.  No device work. */
 typedef enum {
     MMK_OPT_MOTOR_BLOCK = 0,   /* 1 (default): with m_total = 0, rc = 0 and no tape, one motor
