@@ -229,10 +229,18 @@ __global__ __launch_bounds__(64) void k_motor_force(const T *__restrict__ M, con
         for (int j = 0; j < 4; ++j) rnext[j] = b[64 * j];
     };
     load_rows(0, 0);
+    // psi of this lane's point at the pass's two orientations, loaded one pass ahead (used at
+    // once, its load would cost a memory round trip per pass)
+    const T *psi_p = psi + ((int64_t)min(gi, nx - 1) * ny + min(gj, ny - 1)) * nth;
+    T pa_next = psi_p[0], pb_next = psi_p[fp.paired ? nth / 2 : 0];
     for (int k = 0; k < fp.npass; ++k) {
-        const int k2 = fp.paired ? k + nth / 2 : k;
-        const T ca = mine ? cF * psi[((int64_t)gi * ny + gj) * nth + k] : T(0);
-        const T cb = mine && fp.paired ? cF * psi[((int64_t)gi * ny + gj) * nth + k2] : T(0);
+        const T pa = pa_next, pb = pb_next;
+        if (k + 1 < fp.npass) {
+            pa_next = psi_p[k + 1];
+            pb_next = psi_p[fp.paired ? k + 1 + nth / 2 : k + 1];
+        }
+        const T ca = mine ? cF * pa : T(0);
+        const T cb = mine && fp.paired ? cF * pb : T(0);
         const int ex = exy[2 * k], ey = exy[2 * k + 1];
         T att = T(0), alt = T(0), atl = T(0), all = T(0);  // corners of the current head
         int pc = 0;
