@@ -220,7 +220,9 @@ mmk_status mmk_get_anchors(mmk_ctx *ctx, void *coarse, void *free_pool);
 /* Global sums of the last outputs (the total filament count that Eq. (1) conserves, and the
  * domain integral of the extra stress of Alg. 1), host outputs, synchronizes: mass =
  * sum Psi dx dy dth and sum_sigma[c] = sum sigma_c dx dy, accumulated in FP64 (compensated) in a
- * fixed order (bitwise reproducible).  Either pointer may be NULL.  MMK_ERR_STATE: no outputs. */
+ * fixed order (bitwise reproducible).  The output psi step of each mmk_step call leaves FP64
+ * block partials; their reduction runs here, on the context's stream, the first time the sums
+ * of those outputs are asked for.  Either pointer may be NULL.  MMK_ERR_STATE: no outputs. */
 mmk_status mmk_get_sums(mmk_ctx *ctx, double *mass, double sum_sigma[3]);
 
 /* Adjoint tape (a project extra: the paper has no adjoint; it differentiates the micro-step of

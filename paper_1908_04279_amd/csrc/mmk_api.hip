@@ -169,6 +169,11 @@ struct mmk_ctx {
     // (x, y) point, where the tiling allows it
     bool depl_fused = true;
     bool have_state = false, have_fluid = false, have_out = false;
+    // The global sums (mass, sum sigma) reduce the FP64 block partials that the output psi launch
+    // of the last call wrote; they are reduced when mmk_get_sums asks for them (sums_pending),
+    // over sums_blocks rows (the psi kernel of that launch).
+    bool sums_pending = false;
+    int sums_blocks = 0;
     std::string err;
     bool prof = false;
     int prof_every[kProfIds] = {1, 1, 1, 1, 1, 1, 1, 1};  // time every n-th launch of each kernel id (0: none)
@@ -179,6 +184,7 @@ struct mmk_ctx {
     // mmk_step_graph: captured K-step sequences by (K, dt, starting buffer), replayed on stream
     struct Graph {
         int K = 0, cur_in = 0, cur_out = 0;
+        int sums_blocks = 0;  // partial rows the graph's output psi launch writes
         double dt = 0;
         hipGraphExec_t exec = nullptr;
     };
@@ -380,7 +386,7 @@ static mmk_status global_sums(mmk_ctx *c) {
     const double dx = p.lx / p.nx, dy = p.ly / p.ny, dth = kTwoPi / p.ntheta;
     int slot;
     HIPCHK(c, prof_begin(c, 2, &slot), "hipEventRecord");
-    HIPCHK(c, launch_reduce_partials(c->at<double>(c->L.partials), c->walk ? c->wp.blocks : c->pl.blocks,
+    HIPCHK(c, launch_reduce_partials(c->at<double>(c->L.partials), c->sums_blocks,
                                      c->at<double>(c->L.sums),
                                      dx * dy * dth, dx * dy, c->stream),
            "global sums launch");
@@ -565,7 +571,8 @@ static mmk_status run_steps(mmk_ctx *c, int K, double dt) {
     if (st != MMK_OK) return st;
     if (K > 0) {
         c->have_out = true;
-        return global_sums<T>(c);
+        c->sums_pending = true;
+        c->sums_blocks = c->walk ? c->wp.blocks : c->pl.blocks;
     }
     return MMK_OK;
 }
@@ -848,7 +855,8 @@ mmk_status mmk_step_graph(mmk_ctx *c, int32_t K, double dt) {
         ng.dt = dt;
         ng.cur_in = c->cur;
         hipStream_t user = c->stream;
-        const bool prof = c->prof;
+        const bool prof = c->prof, pending = c->sums_pending;
+        const int blocks = c->sums_blocks;
         c->prof = false;
         c->stream = c->capture_stream;
         hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
@@ -859,7 +867,10 @@ mmk_status mmk_step_graph(mmk_ctx *c, int32_t K, double dt) {
         c->stream = user;
         c->prof = prof;
         ng.cur_out = c->cur;
+        ng.sums_blocks = c->sums_blocks;
         c->cur = ng.cur_in;  // nothing has run yet
+        c->sums_pending = pending;
+        c->sums_blocks = blocks;
         if (e != hipSuccess) return hipfail(c, e, "hipStreamBeginCapture");
         if (st != MMK_OK) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -875,6 +886,8 @@ mmk_status mmk_step_graph(mmk_ctx *c, int32_t K, double dt) {
     HIPCHK(c, hipGraphLaunch(g->exec, c->stream), "hipGraphLaunch");
     c->cur = g->cur_out;
     c->have_out = true;
+    c->sums_pending = true;
+    c->sums_blocks = g->sums_blocks;
     return MMK_OK;
 }
 
@@ -988,6 +1001,11 @@ int64_t mmk_r0_cells(const mmk_params *p, int32_t *cells) {
 mmk_status mmk_get_sums(mmk_ctx *c, double *mass, double sum_sigma[3]) {
     if (!c) return MMK_ERR_ARG;
     if (!c->have_out) return fail(c, MMK_ERR_STATE, "no outputs: run mmk_step with K > 0 first");
+    if (c->sums_pending) {
+        const mmk_status st = c->esz == 4 ? global_sums<float>(c) : global_sums<double>(c);
+        if (st != MMK_OK) return st;
+        c->sums_pending = false;
+    }
     double h[4];
     HIPCHK(c, hipMemcpyAsync(h, c->ws + c->L.sums, sizeof h, hipMemcpyDeviceToHost, c->stream), "copy of sums");
     HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
