@@ -193,3 +193,30 @@ def test_walking_psi_ring_depths_agree(precision, shape):
             compare(runs[d], runs[2], tol=1e-14 if precision == 0 else 1e-6)
         if precision == 0:
             compare(runs[8], run_oracle(p, psi0, M0, fl, 7, 25, dt))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sums_follow_the_outputs_they_belong_to(precision):
+    """mmk_get_sums reduces the block partials of the last outputs when first asked: after the
+    psi kernel is switched (other block rows) and after a second call, the sums still match a
+    context that ran the same steps straight through, and asking twice gives the same bits."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=24, ny=20, ntheta=64, ns=16)
+    psi0, M0, fl, dt = seeded_case(p, n_exchanges=2, M0_kind="random")
+    ref = run_gpu(p, psi0, M0, fl, 6, 12, dt, precision=precision)
+    ctx = mmk.Context(p, precision=precision, options={"psi_kernel": 2})
+    ctx.set_state(torch.as_tensor(psi0), torch.as_tensor(M0))
+    ctx.set_fluid(*map(torch.as_tensor, fl[0]))
+    ctx.step(6, dt)
+    ctx.set_option("psi_kernel", 1)       # the sums pending are still those of the walking kernel
+    first = ctx.get_sums()
+    assert first == ctx.get_sums()
+    ctx.set_fluid(*map(torch.as_tensor, fl[1]))
+    ctx.step(6, dt)                       # LDS-tiled psi kernel: other partial rows
+    mass, ss = ctx.get_sums()
+    ctx.close()
+    tol = 1e-12 if precision == 0 else 1e-5
+    assert abs(mass - ref["mass"]) <= tol * abs(ref["mass"])
+    assert np.max(np.abs(np.array(ss) - np.array(ref["sum_sigma"]))) <= tol * np.max(np.abs(ref["sum_sigma"]))
+    assert first[0] == pytest.approx(ref["mass"], rel=1e-6)
