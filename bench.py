@@ -306,6 +306,19 @@ def r0_motor_bytes(p, b, ncell, nrun, depl):
     return b * (2 * ncell * nxy + nrun * nxy + 2 * nxy * p.ntheta + (2 * nxy if depl else 0))
 
 
+def r0_anchor_bytes(p, b, ncell, nrun):
+    """Algorithmic HBM bytes of one launch with one anchor per block (all sub-steps of a depleted
+    micro-step): read and write M_b, read psi, write the run totals q0 and q1 by anchor."""
+    nxy = p.nx * p.ny
+    return b * (2 * ncell * nxy + nxy * p.ntheta + 2 * nrun * nxy)
+
+
+def r0_marg_bytes(p, b, nrun):
+    """The anchor marginals from the run totals: read q0 and q1, write m0 and m1."""
+    nxy = p.nx * p.ny
+    return b * (2 * nrun * nxy + 2 * nxy * p.ntheta)
+
+
 def r0_coarse_bytes(p, b, nrun, nsplit):
     """Coarse density, clamp and pool: read the run totals and psi, write and read the FP64
     partial rows, write the clamp factor and pool."""
@@ -332,24 +345,29 @@ def r0_substeps(args):
     clamp) and with linear attachment (the sub-steps in registers)."""
     from paper_1908_04279_amd import mmk
     keep = ("micro_steps_per_s", "dt", "simulated_time_per_s", "motor_substeps", "motor_avg_us",
-            "coarse_avg_us", "psi_avg_us")
+            "coarse_avg_us", "psi_avg_us", "onepass")
     d = {"v0": SUBSTEP_V0, "motor_cfl": MOTOR_CFL_BENCH}
     for name, over in (("one_motor_step", dict(v0=SUBSTEP_V0)),
                        ("subcycled", dict(v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH)),
+                       ("subcycled_launch_per_substep", dict(v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH,
+                                                             options={"r0_onepass": 0})),
                        ("one_motor_step_linear", dict(v0=SUBSTEP_V0, m_total=0.0)),
                        ("subcycled_linear", dict(v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH, m_total=0.0))):
         r = run_r0(mmk.FP32, args.r0_steps, 20, 10, args.event_every, **over)
         d[name] = {k: r[k] for k in keep if k in r}
     d["speedup_simulated_time"] = (d["subcycled"]["simulated_time_per_s"]
                                    / d["one_motor_step"]["simulated_time_per_s"])
+    d["speedup_simulated_time_launch_per_substep"] = (d["subcycled_launch_per_substep"]["simulated_time_per_s"]
+                                                      / d["one_motor_step"]["simulated_time_per_s"])
     d["speedup_simulated_time_linear"] = (d["subcycled_linear"]["simulated_time_per_s"]
                                           / d["one_motor_step_linear"]["simulated_time_per_s"])
     return d
 
 
-def run_r0(precision, steps, warmup, K, event_every, **over):
+def run_r0(precision, steps, warmup, K, event_every, options=None, **over):
     """The anchor-resolved micro-step (coarse + pool, motor, psi) on the R0_BENCH workload
-    (parameters in `over` replace the defaults: faster motors, motor sub-cycling)."""
+    (parameters in `over` replace the defaults: faster motors, motor sub-cycling; `options`:
+    library options by name)."""
     import torch
     from paper_1908_04279_amd import inputs as gen
     from paper_1908_04279_amd import mmk
@@ -359,7 +377,7 @@ def run_r0(precision, steps, warmup, K, event_every, **over):
     n_ex = (warmup + steps) // K + 2
     fluids_np = fluids_of(p, n_ex)
     dt = gen.cfl_dt(p, fluids_np)
-    ctx = mmk.Context(p, precision=precision)
+    ctx = mmk.Context(p, precision=precision, options=options)
     fl = [(torch.as_tensor(u).to(ctx.device, ctx.dtype), torch.as_tensor(g).to(ctx.device, ctx.dtype))
           for u, g in fluids_np]
     psi0 = psi0_of(p)
@@ -389,7 +407,8 @@ def run_r0(precision, steps, warmup, K, event_every, **over):
     advance(steps, e)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    prof = {name: ctx.profile_read(name) for name in ("r0_motor_step", "r0_coarse", "psi_step")}
+    prof = {name: ctx.profile_read(name)
+            for name in ("r0_motor_step", "r0_coarse", "psi_step", "r0_anchor_step", "r0_marginals")}
     ctx.profile(False)
     # the motor force of the state (anchor-marginal field + spreading), 10 calls
     ctx.get_force()
@@ -412,18 +431,36 @@ def run_r0(precision, steps, warmup, K, event_every, **over):
     ms_m, n_m = prof["r0_motor_step"]
     ms_c, n_c = prof["r0_coarse"]
     ms_p, n_p = prof["psi_step"]
-    us_m, us_p = ms_m / n_m * 1e3, ms_p / n_p * 1e3
+    ms_a, n_a = prof["r0_anchor_step"]
+    ms_g, n_g = prof["r0_marginals"]
+    us_p = ms_p / n_p * 1e3
+    us_m = ms_m / n_m * 1e3 if n_m else None  # none when each micro-step is one launch per anchor
     us_c = ms_c / n_c * 1e3 if n_c else None  # no coarse launches without depletion
     flops = ncell * p.nx * p.ny * (MOTOR_FLOPS_PER_CELL + M1_FLOPS_PER_CELL)
     alu_peak = FP32_VECTOR_PEAK_TFLOPS if b == 4 else FP64_VECTOR_PEAK_TFLOPS
+    onepass = None
+    if n_a:
+        # one launch per micro-step: nsub sub-steps of every cell, each with its clamp's sum
+        # (one multiply-add a cell) and its scaling (one multiply)
+        us_a, us_g = ms_a / n_a * 1e3, ms_g / n_g * 1e3
+        ab, gb = r0_anchor_bytes(p, b, ncell, nrun), r0_marg_bytes(p, b, nrun)
+        nsub = motor_substeps(p, dt)
+        aflops = ncell * p.nx * p.ny * (nsub * (MOTOR_FLOPS_PER_CELL + 3) + M1_FLOPS_PER_CELL)
+        onepass = {"anchor_avg_us": us_a, "anchor_algorithmic_bytes": ab, "anchor_gbs": ab / (us_a * 1e-6) / 1e9,
+                   "anchor_frac": ab / (us_a * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                   "anchor_alu_frac": aflops / (us_a * 1e-6) / 1e12 / alu_peak,
+                   "marginals_avg_us": us_g, "marginals_algorithmic_bytes": gb,
+                   "marginals_gbs": gb / (us_g * 1e-6) / 1e9, "timed_launches": [n_a, n_g]}
     return {"workload": f"{p.nx}x{p.ny} anchors and filament cells, {p.ntheta} orientations, {p.ns} arclength "
                         f"cells, capture radius {p.rc}, m_total {p.m_total}",
             "tracked_cells_per_filament_cell": ncell, "Mb_cells": ncell * p.nx * p.ny, "runs": nrun,
             "steps": steps, "micro_steps_per_s": steps / el, "ms_per_step": el / steps * 1e3,
             "dt": dt, "simulated_time_per_s": dt * steps / el,
-            "motor_substeps": motor_substeps(p, dt), "motor_avg_us": us_m, "motor_algorithmic_bytes": mb, "motor_gbs": mb / (us_m * 1e-6) / 1e9,
-            "motor_frac": mb / (us_m * 1e-6) / 1e9 / HBM_PEAK_GBS,
-            "motor_alu_frac": flops / (us_m * 1e-6) / 1e12 / alu_peak,
+            "motor_substeps": motor_substeps(p, dt), "motor_avg_us": us_m, "motor_algorithmic_bytes": mb,
+            "motor_gbs": mb / (us_m * 1e-6) / 1e9 if us_m else None,
+            "motor_frac": mb / (us_m * 1e-6) / 1e9 / HBM_PEAK_GBS if us_m else None,
+            "motor_alu_frac": flops / (us_m * 1e-6) / 1e12 / alu_peak if us_m else None,
+            "onepass": onepass,
             "motor_traffic": r0_counters_traffic() if b == 4 else None,
             "coarse_avg_us": us_c, "coarse_algorithmic_bytes": cb, "coarse_gbs": cb / (us_c * 1e-6) / 1e9 if us_c else None,
             "psi_avg_us": us_p, "force_avg_us": ms_f / n_f * 1e3,

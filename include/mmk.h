@@ -269,11 +269,18 @@ typedef enum {
                                 * launch of one step, plain accesses for launches of several
                                 * micro-steps or sub-steps; plain in FP64; 0: plain; 1: nontemporal
                                 * loads and stores; 2: nontemporal loads only */
-    MMK_OPT_PSI_DEPTH = 6      /* walking psi kernel: pencils of a walk of 8 whose loads are in
+    MMK_OPT_PSI_DEPTH = 6,     /* walking psi kernel: pencils of a walk of 8 whose loads are in
                                 * flight together, where nx is a multiple of 8 (else always two
                                 * alternating register sets); 0 (default): 8 at ntheta = 64, 4
                                 * at 128; 2: two alternating sets; 4, 8: a ring of that many
                                 * sets (4 at ntheta = 128) */
+    MMK_OPT_R0_ONEPASS = 7     /* anchor-resolved model with depletion and motor sub-cycling:
+                                * 1 (default): where one anchor's tracked cells fit one block
+                                * (1024 threads of 24 register slots in FP32, 16 in FP64), one
+                                * launch per micro-step holds each anchor's cells and runs all
+                                * its sub-steps, re-forming the clamp before each (the state
+                                * is then kept in an anchor-major layout, converted back where
+                                * needed); 0: one coarse pass and one motor launch per sub-step */
 } mmk_option;
 mmk_status mmk_set_option(mmk_ctx *ctx, int32_t option, int32_t value);
 
@@ -282,7 +289,9 @@ mmk_status mmk_set_option(mmk_ctx *ctx, int32_t option, int32_t value);
  * events on the context's stream (enable = 0 turns timing off, < 0 is MMK_ERR_ARG).
  * mmk_profile_read (synchronizes) sums the elapsed times of the timed launches of `kernel_id`
  * (0 motor step, 1 psi step, 2 global sums, 3 reverse psi step, 4 reverse motor step, 5 motor
- * force: spreading and merge, 6 anchor-resolved motor step, 7 anchor coarse density and pool)
+ * force: spreading and merge, 6 anchor-resolved motor step, 7 anchor coarse density and pool,
+ * 8 anchor-resolved sub-steps of a micro-step with one anchor per block, 9 anchor marginals
+ * from its run totals)
  * since profiling was enabled; up to 65536 launches per id are timed. */
 mmk_status mmk_profile(mmk_ctx *ctx, int32_t enable);
 mmk_status mmk_profile_read(mmk_ctx *ctx, int32_t kernel_id, double *total_ms, int64_t *launches);

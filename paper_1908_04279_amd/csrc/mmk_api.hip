@@ -25,7 +25,7 @@ namespace {
 thread_local std::string g_create_error;
 constexpr int kMaxTheta = 512;
 constexpr int kMaxS = 512;
-constexpr int kProfIds = 8;
+constexpr int kProfIds = 10;
 constexpr int kMaxBlock = 16;  // micro-steps per temporally blocked motor launch
 constexpr int kProfMax = 65536;
 
@@ -34,6 +34,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t M[2], psi[2], psi_tmp, m0, m0s, m1, Dxy, fpart, fblk, fexy, fcs, u, G, stress, mom, tab, partials, sums;
     size_t q0, r0part, r0scale, r0pool, r0seg, r0start, psiT, Mmarg;  // anchor-resolved model (rc > 0)
+    size_t q01, r0slot, r0cpos;  // one anchor per block: run total pairs, slot and cell tables
     TapeLayout tape;
     size_t total;
     int psi_blocks;
@@ -43,6 +44,14 @@ int64_t n_psi(const mmk_params &p) { return (int64_t)p.nx * p.ny * p.ntheta; }
 int64_t n_m(const mmk_params &p) { return n_psi(p) * p.ns; }
 R0Plan r0_plan_of(const mmk_params &p, bool cells_only = false) {
     return plan_r0(p.nx, p.ny, p.ntheta, p.ns, p.lx, p.ly, p.L, p.rc, cells_only);
+}
+size_t esize(const mmk_params &p);
+// Slots of the one-pass depleted sub-cycling (one anchor per block), for the parameters that can
+// use it: depletion and motor sub-cycling.
+R0Slots r0_slots_of(const mmk_params &p, const R0Plan &rp) {
+    if (!(p.rc > 0 && p.m_total > 0 && p.motor_cfl > 0)) return R0Slots{};
+    if ((int64_t)p.nx * p.ny * p.ntheta >= ((int64_t)1 << 31)) return R0Slots{};  // 32-bit psi offsets
+    return plan_r0_slots(rp, esize(p));
 }
 size_t esize(const mmk_params &p) { return p.precision == MMK_FP32 ? 4 : 8; }
 
@@ -88,8 +97,11 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     const bool r0 = p.rc > 0;
     const R0Plan rp = r0 ? r0_plan_of(p) : R0Plan{};
     const size_t np = (size_t)n_psi(p), nxy = (size_t)p.nx * p.ny;
-    // M, or the tiled anchor-resolved state (M[tile][cell][64 vx])
-    const size_t nm = r0 ? (size_t)r0_tiled_elems(rp.ncell, (int64_t)nxy, r0_vx(e, rp.lmax)) : (size_t)n_m(p);
+    // M, or the tiled anchor-resolved state (M[tile][cell][64 vx]) or its anchor layout
+    // (M[r0][C][nthr]), whichever is larger
+    const R0Slots rs = r0 ? r0_slots_of(p, rp) : R0Slots{};
+    size_t nm = r0 ? (size_t)r0_tiled_elems(rp.ncell, (int64_t)nxy, r0_vx(e, rp.lmax)) : (size_t)n_m(p);
+    if (rs.ok) nm = std::max(nm, (size_t)rs.per_anchor() * nxy);
     const PsiLaunch pl = plan_psi(p.nx, p.ny, p.ntheta, e, 2);
     const WalkPlan wp = plan_walk(p.nx, p.ny, p.ntheta);
     L.psi_blocks = wp.ok && wp.blocks > pl.blocks ? wp.blocks : pl.blocks;
@@ -130,6 +142,11 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
         L.r0seg = take((size_t)rp.nseg * sizeof(R0Seg));
         L.r0start = take(((size_t)p.ntheta + 1) * sizeof(int32_t));
         L.psiT = take(np * e);
+        if (rs.ok) {
+            L.q01 = take((size_t)2 * rp.nseg * nxy * e);
+            L.r0slot = take(rs.slot_tab.size() * sizeof(int32_t));
+            L.r0cpos = take(rs.cell_pos.size() * sizeof(int32_t));
+        }
     }
     L.u = take(2 * nxy * e);
     L.G = take(4 * nxy * e);
@@ -155,7 +172,7 @@ struct mmk_ctx {
     PsiLaunch pl{}, pl_rev{};
     int cur = 0;    // index of the current M / psi buffers
     // implementation options (mmk_set_option), and what they select
-    int opt[7] = {1, 0, 1, 0, 0, -1, 0};
+    int opt[8] = {1, 0, 1, 0, 0, -1, 0, 1};
     // ntheta = 64, 128: the psi step runs as the LDS-free walking kernel (by default in FP32,
     // and in FP64 where nx allows the ring of register sets; apply_options decides)
     WalkPlan wp{};
@@ -176,14 +193,16 @@ struct mmk_ctx {
     int sums_blocks = 0;
     std::string err;
     bool prof = false;
-    int prof_every[kProfIds] = {1, 1, 1, 1, 1, 1, 1, 1};  // time every n-th launch of each kernel id (0: none)
-    int64_t seen[kProfIds] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int prof_every[kProfIds] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1};  // time every n-th launch of each id (0: none)
+    int64_t seen[kProfIds] = {};
     std::vector<hipEvent_t> ev[kProfIds];  // start/stop pairs
-    int nev[kProfIds] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int nev[kProfIds] = {};
     TapeState tape;
     // mmk_step_graph: captured K-step sequences by (K, dt, starting buffer), replayed on stream
     struct Graph {
         int K = 0, cur_in = 0, cur_out = 0;
+        bool anch_in = false, anch_out = false;  // layout of the anchor-resolved state before and after
+        bool q_pairs_in = false, q_pairs_out = false;  // which run totals are current before and after
         int sums_blocks = 0;  // partial rows the graph's output psi launch writes
         double dt = 0;
         hipGraphExec_t exec = nullptr;
@@ -193,6 +212,12 @@ struct mmk_ctx {
     std::vector<double> host_tab64;  // host copies of the angle tables (outlive the async copy)
     std::vector<float> host_tab32;
     R0Plan r0;          // anchor-resolved model: tracked cells and runs (rc > 0)
+    // One anchor per block (depleted sub-cycling in one pass): its slots, and whether the current
+    // M buffer holds the anchor layout (set by those steps; the tiled layout is restored, into the
+    // current buffer, by whatever needs it: the other steps, get_force).
+    R0Slots r0s;
+    bool r0_anch = false;
+    bool q_pairs = false;  // the current run totals are the one-pass kernel's (q0, q1) pairs
     ForcePlan fplan;    // motor-force spreading geometry
     ForceRecords frec;  // host copy of the force spreading records
     std::vector<uint32_t> host_fblk;
@@ -505,6 +530,7 @@ static mmk_status r0_motor(mmk_ctx *c, const T *M_in, T *M_out, double dt, int a
                                  r0_with_nsub(r0_cst<T>(c, dt, advance), nsub), c->r0.lmax, p.limiter, c->stream),
            "anchor-resolved motor launch");
     HIPCHK(c, prof_end(c, 6, slot), "hipEventRecord");
+    c->q_pairs = false;
     return MMK_OK;
 }
 
@@ -515,7 +541,8 @@ static mmk_status r0_anchors(mmk_ctx *c, bool clamp, T *coarse_out, T *free_out)
     const mmk_params &p = c->p;
     int slot;
     HIPCHK(c, prof_begin(c, 7, &slot), "hipEventRecord");
-    HIPCHK(c, launch_r0_coarse<T>(c->at<T>(c->L.q0), c->at<T>(c->L.psi[c->cur]), c->at<T>(c->L.psiT),
+    HIPCHK(c, launch_r0_coarse<T>(c->q_pairs ? c->at<T>(c->L.q01) : c->at<T>(c->L.q0), c->q_pairs,
+                                  c->at<T>(c->L.psi[c->cur]), c->at<T>(c->L.psiT),
                                   c->at<R0Seg>(c->L.r0seg),
                                   c->at<double>(c->L.r0part), clamp ? c->at<T>(c->L.r0scale) : nullptr,
                                   clamp ? c->at<T>(c->L.r0pool) : nullptr, coarse_out, free_out,
@@ -526,21 +553,80 @@ static mmk_status r0_anchors(mmk_ctx *c, bool clamp, T *coarse_out, T *free_out)
     return MMK_OK;
 }
 
+// The anchor-resolved state back in the tiled layout, in the current buffer (through the other
+// one), if the one-pass steps left it in the anchor layout.
+template <typename T>
+static mmk_status r0_tiled(mmk_ctx *c) {
+    if (!c->r0_anch) return MMK_OK;
+    const int a = c->cur, b = 1 - c->cur;
+    const int vx = r0_vx(sizeof(T), c->r0.lmax);
+    HIPCHK(c, launch_r0_anchor_layout<T>(c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), c->at<int32_t>(c->L.r0cpos),
+                                         r0_cst<T>(c, 0.0, 0), vx, c->r0s.per_anchor(), c->r0s.nthr, false, c->stream),
+           "anchor -> tiled layout of Mb");
+    HIPCHK(c, hipMemcpyAsync(c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), (size_t)n_state_held(c) * sizeof(T),
+                             hipMemcpyDeviceToDevice, c->stream),
+           "copy of Mb");
+    c->r0_anch = false;
+    return MMK_OK;
+}
+
+// One micro-step's nsub motor sub-steps of dt with the clamp re-formed before each, one anchor per
+// block (anchor layout, M_in -> M_out, in place allowed), then m0, m1 from the run totals.
+template <typename T>
+static mmk_status r0_onepass(mmk_ctx *c, const T *M_in, T *M_out, double dt, int nsub) {
+    const mmk_params &p = c->p;
+    int slot;
+    HIPCHK(c, prof_begin(c, 8, &slot), "hipEventRecord");
+    HIPCHK(c, launch_r0_anchor<T>(M_in, M_out, c->at<T>(c->L.q01), c->at<int32_t>(c->L.r0slot),
+                                  c->at<T>(c->L.psi[c->cur]), r0_cst<T>(c, dt, 1), c->r0.nseg,
+                                  c->r0s.C, c->r0s.nthr, nsub, p.m_total, p.k_on, kTwoPi / p.ntheta, p.limiter,
+                                  c->stream),
+           "anchor-owned motor launch");
+    HIPCHK(c, prof_end(c, 8, slot), "hipEventRecord");
+    HIPCHK(c, prof_begin(c, 9, &slot), "hipEventRecord");
+    HIPCHK(c, launch_r0_marg<T>(c->at<T>(c->L.q01), c->r0.nseg, c->at<R0Seg>(c->L.r0seg),
+                                c->at<int32_t>(c->L.r0start), c->at<T>(c->L.m0), c->at<T>(c->L.m1),
+                                r0_cst<T>(c, 0.0, 0), c->stream),
+           "anchor marginals launch");
+    HIPCHK(c, prof_end(c, 9, slot), "hipEventRecord");
+    c->q_pairs = true;
+    return MMK_OK;
+}
+
 // Each micro-step: n motor sub-steps of dt/n (motor_substeps; n = 1 without sub-cycling), then
-// psi driven by the marginal m0.  With m_total > 0 each sub-step is its own launch after the
-// coarse density, clamp and pool of the current sub-state (psi of the step's start; Alg. 2
-// clamps inside its inner loop), alternating between the two M buffers (an even n ends in the
-// first and is copied over); without, one launch takes all n sub-steps in registers.
+// psi driven by the marginal m0.  With m_total > 0 the clamp is re-formed before every sub-step
+// (psi of the step's start; Alg. 2 clamps inside its inner loop): where the tracked set fits one
+// block (MMK_OPT_R0_ONEPASS), one launch holds each anchor's cells and runs all n sub-steps
+// (anchor layout, converted to on the first such step); otherwise each sub-step is its own
+// launch after the coarse density, clamp and pool of the current sub-state, alternating between
+// the two M buffers (an even n ends in the first and is copied over).  Without depletion one
+// launch takes all n sub-steps in registers.
 template <typename T>
 static mmk_status run_steps_r0(mmk_ctx *c, int K, double dt) {
     const bool depl = c->p.m_total > 0;
     const int nsub = motor_substeps(c->p, dt);
     const double h = dt / nsub;
+    const bool onepass = depl && nsub > 1 && c->r0s.ok && c->opt[MMK_OPT_R0_ONEPASS] != 0;
+    if (!onepass) {
+        const mmk_status st = r0_tiled<T>(c);
+        if (st != MMK_OK) return st;
+    }
     const size_t mbytes = (size_t)n_state_held(c) * sizeof(T);
     for (int n = 0; n < K; ++n) {
         const int a = c->cur, b = 1 - c->cur;
         mmk_status st = MMK_OK;
-        if (!depl) {
+        if (onepass) {
+            const T *in = c->at<T>(c->L.M[a]);
+            if (!c->r0_anch) {  // tiled -> anchor layout, into the other buffer; the step runs in place
+                HIPCHK(c, launch_r0_anchor_layout<T>(in, c->at<T>(c->L.M[b]), c->at<int32_t>(c->L.r0cpos),
+                                                     r0_cst<T>(c, 0.0, 0), r0_vx(sizeof(T), c->r0.lmax),
+                                                     c->r0s.per_anchor(), c->r0s.nthr, true, c->stream),
+                       "tiled -> anchor layout of Mb");
+                in = c->at<T>(c->L.M[b]);
+                c->r0_anch = true;
+            }
+            st = r0_onepass<T>(c, in, c->at<T>(c->L.M[b]), h, nsub);
+        } else if (!depl) {
             st = r0_motor<T>(c, c->at<T>(c->L.M[a]), c->at<T>(c->L.M[b]), h, 1, false, nsub);
         } else {
             for (int q = 0; q < nsub && st == MMK_OK; ++q) {
@@ -548,11 +634,11 @@ static mmk_status run_steps_r0(mmk_ctx *c, int K, double dt) {
                 if (st == MMK_OK)
                     st = r0_motor<T>(c, c->at<T>(c->L.M[q % 2 ? b : a]), c->at<T>(c->L.M[q % 2 ? a : b]), h, 1, true);
             }
+            if (st == MMK_OK && nsub % 2 == 0 && mbytes > 0)
+                HIPCHK(c, hipMemcpyAsync(c->at<T>(c->L.M[b]), c->at<T>(c->L.M[a]), mbytes, hipMemcpyDeviceToDevice,
+                                         c->stream),
+                       "copy of M_b");
         }
-        if (st == MMK_OK && depl && nsub % 2 == 0 && mbytes > 0)
-            HIPCHK(c, hipMemcpyAsync(c->at<T>(c->L.M[b]), c->at<T>(c->L.M[a]), mbytes, hipMemcpyDeviceToDevice,
-                                     c->stream),
-                   "copy of M_b");
         if (st == MMK_OK)
             st = psi_half<T>(c, c->at<T>(c->L.psi[a]), c->at<T>(c->L.psi[b]), c->at<T>(c->L.m0), c->at<T>(c->L.m1),
                              c->at<T>(c->L.u), c->at<T>(c->L.G), dt, n == K - 1, c->stream);
@@ -694,6 +780,13 @@ mmk_status mmk_create(const mmk_params *p, void *workspace, size_t ws_bytes, voi
         if (e == hipSuccess)
             e = hipMemcpyAsync(c->ws + L.r0start, c->r0.seg_start.data(), c->r0.seg_start.size() * sizeof(int32_t),
                                hipMemcpyHostToDevice, c->stream);
+        c->r0s = r0_slots_of(*p, c->r0);
+        if (e == hipSuccess && c->r0s.ok)
+            e = hipMemcpyAsync(c->ws + L.r0slot, c->r0s.slot_tab.data(), c->r0s.slot_tab.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && c->r0s.ok)
+            e = hipMemcpyAsync(c->ws + L.r0cpos, c->r0s.cell_pos.data(), c->r0s.cell_pos.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, c->stream);
     }
     if (c->frec_ok) {
         auto up = [&](size_t off, const void *src, size_t bytes) {
@@ -746,7 +839,8 @@ mmk_status mmk_set_option(mmk_ctx *c, int32_t option, int32_t value) {
     bool ok;
     switch (option) {
         case MMK_OPT_MOTOR_BLOCK:
-        case MMK_OPT_DEPL_FUSED: ok = value == 0 || value == 1; break;
+        case MMK_OPT_DEPL_FUSED:
+        case MMK_OPT_R0_ONEPASS: ok = value == 0 || value == 1; break;
         case MMK_OPT_PSI_KERNEL: ok = value >= 0 && value <= 2; break;
         case MMK_OPT_MOTOR_LANES: ok = value == 0 || (value >= 2 && value <= 64 && (value & (value - 1)) == 0); break;
         case MMK_OPT_MOTOR_CHUNKS: ok = value == 0 || value == 1 || value == 2 || value == 4; break;
@@ -771,6 +865,7 @@ mmk_status mmk_set_state(mmk_ctx *c, const void *psi, const void *M) {
     const int vx = r0_vx(c->esz, c->r0.lmax);
     HIPCHK(c, hipMemcpyAsync(c->ws + c->L.psi[c->cur], psi, np, hipMemcpyDeviceToDevice, c->stream),
            "copy of psi");
+    c->r0_anch = false;
     if (M && nm > 0 && c->p.rc > 0) {  // caller layout -> tiled
         HIPCHK(c, c->esz == 4 ? launch_r0_layout<float>((const float *)M, c->at<float>(c->L.M[c->cur]), c->r0.ncell, nxy, vx, true, c->stream)
                               : launch_r0_layout<double>((const double *)M, c->at<double>(c->L.M[c->cur]), c->r0.ncell, nxy, vx, true, c->stream),
@@ -843,7 +938,8 @@ mmk_status mmk_step_graph(mmk_ctx *c, int32_t K, double dt) {
                     kMaxSubsteps);
     mmk_ctx::Graph *g = nullptr;
     for (auto &x : c->graphs)
-        if (x.K == K && x.dt == dt && x.cur_in == c->cur) g = &x;
+        if (x.K == K && x.dt == dt && x.cur_in == c->cur && x.anch_in == c->r0_anch && x.q_pairs_in == c->q_pairs)
+            g = &x;
     if (!g) {
         if (c->graphs.size() >= 8) drop_graphs(c);
         if (!c->capture_stream)
@@ -854,6 +950,9 @@ mmk_status mmk_step_graph(mmk_ctx *c, int32_t K, double dt) {
         ng.K = K;
         ng.dt = dt;
         ng.cur_in = c->cur;
+        ng.anch_in = c->r0_anch;
+        const bool qp = c->q_pairs;
+        ng.q_pairs_in = qp;
         hipStream_t user = c->stream;
         const bool prof = c->prof, pending = c->sums_pending;
         const int blocks = c->sums_blocks;
@@ -867,8 +966,12 @@ mmk_status mmk_step_graph(mmk_ctx *c, int32_t K, double dt) {
         c->stream = user;
         c->prof = prof;
         ng.cur_out = c->cur;
+        ng.anch_out = c->r0_anch;
+        ng.q_pairs_out = c->q_pairs;
+        c->q_pairs = qp;
         ng.sums_blocks = c->sums_blocks;
         c->cur = ng.cur_in;  // nothing has run yet
+        c->r0_anch = ng.anch_in;
         c->sums_pending = pending;
         c->sums_blocks = blocks;
         if (e != hipSuccess) return hipfail(c, e, "hipStreamBeginCapture");
@@ -885,6 +988,8 @@ mmk_status mmk_step_graph(mmk_ctx *c, int32_t K, double dt) {
     }
     HIPCHK(c, hipGraphLaunch(g->exec, c->stream), "hipGraphLaunch");
     c->cur = g->cur_out;
+    c->r0_anch = g->anch_out;
+    c->q_pairs = g->q_pairs_out;
     c->have_out = true;
     c->sums_pending = true;
     c->sums_blocks = g->sums_blocks;
@@ -897,7 +1002,16 @@ mmk_status mmk_get_state(mmk_ctx *c, void *psi, void *M) {
     if (psi)
         HIPCHK(c, hipMemcpyAsync(psi, c->ws + c->L.psi[c->cur], (size_t)n_psi(c->p) * c->esz,
                                  hipMemcpyDeviceToDevice, c->stream), "copy of psi");
-    if (M && n_state(c) > 0 && c->p.rc > 0) {  // tiled -> caller layout
+    if (M && n_state(c) > 0 && c->p.rc > 0 && c->r0_anch) {  // anchor -> caller layout
+        HIPCHK(c, c->esz == 4 ? launch_r0_anchor_layout<float>(c->at<float>(c->L.M[c->cur]), (float *)M,
+                                                               c->at<int32_t>(c->L.r0cpos), r0_cst<float>(c, 0.0, 0),
+                                                               0, c->r0s.per_anchor(), c->r0s.nthr, false, c->stream)
+                              : launch_r0_anchor_layout<double>(c->at<double>(c->L.M[c->cur]), (double *)M,
+                                                                c->at<int32_t>(c->L.r0cpos),
+                                                                r0_cst<double>(c, 0.0, 0), 0, c->r0s.per_anchor(),
+                                                                c->r0s.nthr, false, c->stream),
+               "layout of Mb");
+    } else if (M && n_state(c) > 0 && c->p.rc > 0) {  // tiled -> caller layout
         const int64_t nxy = (int64_t)c->p.nx * c->p.ny;
         const int vx = r0_vx(c->esz, c->r0.lmax);
         HIPCHK(c, c->esz == 4 ? launch_r0_layout<float>(c->at<float>(c->L.M[c->cur]), (float *)M, c->r0.ncell, nxy, vx, false, c->stream)
@@ -948,6 +1062,10 @@ mmk_status mmk_get_force(mmk_ctx *c, void *force) {
         return fail(c, MMK_ERR_UNSUPPORTED, "spreading window of %d x %d cells is too large", fp.wx, fp.wy);
     if (p.rc > 0 && r0_field_lds(p.ns, c->esz) > 160 * 1024)
         return fail(c, MMK_ERR_UNSUPPORTED, "ns too large for the anchor-marginal field kernel at this precision");
+    if (p.rc > 0) {  // the field kernel reads the tiled layout
+        const mmk_status st = c->esz == 4 ? r0_tiled<float>(c) : r0_tiled<double>(c);
+        if (st != MMK_OK) return st;
+    }
     int slot;
     HIPCHK(c, prof_begin(c, 5, &slot), "hipEventRecord");
     hipError_t e;

@@ -65,10 +65,12 @@ hipError_t launch_r0_motor(const T *M_in, T *M_out, T *q0, T *m0, T *m1, const R
 // scratch for psi by orientation): coarse = dx dy dth sum over runs of q0 psi(x, th_k), then the
 // clamp factor and the source of Alg. 2 / Eq. (6) (m_total > 0), and optionally coarse and the
 // free pool in the field precision.
+// (q0: the motor kernel's run totals q0[run][r0], or with pairs the one-pass kernel's
+// q01[r0][run][2])
 template <typename T>
-hipError_t launch_r0_coarse(const T *q0, const T *psi, T *psiT, const R0Seg *seg, double *part, T *scale, T *pool,
-                            T *coarse_out, T *free_out, const R0Const<T> &c, int nseg, int nsplit, double dth,
-                            double m_total, double k_on, hipStream_t s);
+hipError_t launch_r0_coarse(const T *q0, bool pairs, const T *psi, T *psiT, const R0Seg *seg, double *part, T *scale,
+                            T *pool, T *coarse_out, T *free_out, const R0Const<T> &c, int nseg, int nsplit,
+                            double dth, double m_total, double k_on, hipStream_t s);
 
 // The anchor-marginal field M[nx][ny][nth][ns] = dx dy sum over anchors of M_b (tiled Mb), the
 // input of the motor force; LDS bytes per block r0_field_lds (hipErrorInvalidValue above 160 KB).
@@ -76,6 +78,53 @@ size_t r0_field_lds(int ns, size_t esz);
 template <typename T>
 hipError_t launch_r0_field(const T *Mb, T *M, const R0Seg *seg, const int32_t *seg_start, const R0Const<T> &c, int ns,
                            hipStream_t s);
+
+// ---- one anchor per block: depleted sub-cycling in one pass (Alg. 2's inner loop) ----------
+// With the clamp, every sub-step needs the coarse density of each anchor over all its tracked
+// cells.  In the anchor layout a block holds one anchor's tracked cells in registers (nthr
+// threads of C slots, whole runs per thread, the rest padding) and runs the n sub-steps there,
+// re-forming the clamp by a block-wide sum before each: M_b is read and written once per
+// micro-step.  The state is M[r0][C/4][nthr][4]: slot j of thread t (slot id j nthr + t) at
+// ((j / 4) nthr + t) 4 + j % 4, so that a thread's slots come in 16-byte groups.
+struct R0Slots {
+    bool ok = false;
+    int C = 0, nthr = 0;               // slots per thread, threads per anchor
+    std::vector<int32_t> slot_run;     // [C][nthr]: run of the slot, -1 for padding
+    // [C][nthr][2]: the slot's run and its first arclength cell, run | lo << 20 (-1 for padding),
+    // and the run's offset and orientation, (a + 1024) | (b + 1024) << 11 | k << 22
+    std::vector<int32_t> slot_tab;
+    std::vector<int32_t> cell_pos;     // [ncell][3]: slot (j nthr + t), a, b of every tracked cell
+    int64_t per_anchor() const { return (int64_t)C * nthr; }
+};
+// Dynamic LDS of the one-pass kernel: its decoded slot table, 8 C nthr bytes (at most 160 KB).
+size_t r0_anchor_lds(int C, int nthr);
+// Packs the runs of P into threads (best fit by decreasing length); ok = false when the tracked
+// set does not fit 1024 threads of the largest slot count compiled for the precision (24 in FP32,
+// 16 in FP64), a run is longer than it, or the slot table's fields overflow (2^20 runs, offsets
+// beyond 1023 cells).
+R0Slots plan_r0_slots(const R0Plan &P, size_t esz);
+
+// nsub steps of dt of one micro-step with the clamp re-formed before each (Alg. 2; Eqs. (5)-(6)):
+// coarse = w sum over the anchor's cells of psi(x, th_k) M (w = dx dy dth ds; psi of the step's
+// start), the factor m_total / coarse and pool 0 where coarse > m_total, else 1 and
+// k_on (m_total - coarse).  Anchor layout in and out (in place allowed).  Writes the run totals
+// of the final state anchor-major and side by side, q01[r0][run] = (sum M ds, sum (l + 1/2 -
+// ns/2) M ds^2), which k_r0_marg turns into m0, m1 (and the coarse kernel reads as pairs).
+template <typename T>
+hipError_t launch_r0_anchor(const T *M_in, T *M_out, T *q01, const int32_t *slot_tab, const T *psi,
+                            const R0Const<T> &c, int nrun, int C, int nthr, int nsub, double m_total, double k_on,
+                            double dth, int limiter, hipStream_t s);
+// m0 = dA sum over the runs of orientation th of q0[x - (a, b)][run], m1 likewise from q1, in
+// run order (FP64 sums).
+template <typename T>
+hipError_t launch_r0_marg(const T *q01, int nrun, const R0Seg *seg, const int32_t *seg_start, T *m0, T *m1,
+                          const R0Const<T> &c, hipStream_t s);
+// Between the anchor layout and the tiled one (vx > 0: M[tile][cell][64 vx]) or the caller's
+// (vx = 0: Mb[cell][x]); to_anchor = 1 writes the anchor layout (its padding slots untouched,
+// never read), else the other one (the tiled padding set to 0).
+template <typename T>
+hipError_t launch_r0_anchor_layout(const T *src, T *dst, const int32_t *cell_pos, const R0Const<T> &c, int vx,
+                                   int64_t per_anchor, int nthr, bool to_anchor, hipStream_t s);
 
 // Caller layout Mb[cell][nx][ny] -> tiled (to_tiled), or back.
 template <typename T>

@@ -86,6 +86,77 @@ R0Plan plan_r0(int nx, int ny, int nth, int ns, double lx, double ly, double L, 
     return P;
 }
 
+// Runs into threads for the one-pass kernel: for each compiled slot count C (at least the longest
+// run), the fewest threads (a multiple of 64, at most 1024) into which best fit by decreasing
+// length packs every run; each thread's runs take consecutive slots.
+static constexpr int kR0SlotC[] = {4, 8, 16, 24};
+R0Slots plan_r0_slots(const R0Plan &P, size_t esz) {
+    R0Slots S;
+    if (!P.ok || P.ncell == 0 || P.nseg == 0) return S;
+    std::vector<int> order(P.nseg);
+    for (int i = 0; i < P.nseg; ++i) order[i] = i;
+    auto len_of = [&](int r) { return (P.seg[r].pack >> 10) & 1023; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return len_of(x) > len_of(y); });
+    for (int C : kR0SlotC) {
+        // 24 slots of FP64 do not fit the 128 registers of a 1024-thread block
+        if (C < P.lmax || (esz == 8 && C > 16)) continue;
+        const int64_t tmax = std::min<int64_t>(1024, (160 * 1024 - 512) / (8 * C) / 64 * 64);  // decoded table in LDS
+        const int64_t t0 = 64 * ((P.ncell + 64 * C - 1) / (64 * C));
+        for (int64_t T = t0; T <= tmax; T += 64) {
+            // bins by free capacity; a run goes to a bin with the least free room that holds it
+            std::vector<std::vector<int>> byfree(C + 1);
+            for (int t = (int)T - 1; t >= 0; --t) byfree[C].push_back(t);
+            std::vector<int> fill(T, 0);
+            std::vector<int32_t> slot_run((size_t)C * T, -1);
+            bool ok = true;
+            for (int r : order) {
+                const int len = len_of(r);
+                int f = len;
+                while (f <= C && byfree[f].empty()) ++f;
+                if (f > C) {
+                    ok = false;
+                    break;
+                }
+                const int t = byfree[f].back();
+                byfree[f].pop_back();
+                for (int q = 0; q < len; ++q) slot_run[(size_t)(fill[t] + q) * T + t] = r;
+                fill[t] += len;
+                byfree[f - len].push_back(t);
+            }
+            if (!ok) continue;
+            S.ok = true;
+            S.C = C;
+            S.nthr = (int)T;
+            S.slot_run = std::move(slot_run);
+            S.slot_tab.assign((size_t)2 * C * T, -1);
+            for (size_t q = 0; q < S.slot_run.size(); ++q) {
+                const int r = S.slot_run[q];
+                if (r < 0) continue;
+                const R0Seg &g = P.seg[r];
+                const int lo = g.pack & 1023, k = g.pack >> 20;
+                if (r >= (1 << 20) || std::abs(g.a) > 1023 || std::abs(g.b) > 1023 || k >= 512) return R0Slots{};
+                S.slot_tab[2 * q] = r | lo << 20;
+                S.slot_tab[2 * q + 1] = (g.a + 1024) | (g.b + 1024) << 11 | k << 22;
+            }
+            S.cell_pos.assign((size_t)3 * P.ncell, 0);
+            for (int t = 0; t < T; ++t)
+                for (int j = 0; j < C; ++j) {
+                    const int r = S.slot_run[(size_t)j * T + t];
+                    if (r < 0) continue;
+                    // position in its run: slots of the run above this one in the thread
+                    int q = 0;
+                    while (j - q - 1 >= 0 && S.slot_run[(size_t)(j - q - 1) * T + t] == r) ++q;
+                    const int64_t cell = P.seg[r].off + q;
+                    S.cell_pos[3 * cell] = j * (int)T + t;
+                    S.cell_pos[3 * cell + 1] = P.seg[r].a;
+                    S.cell_pos[3 * cell + 2] = P.seg[r].b;
+                }
+            return S;
+        }
+    }
+    return S;
+}
+
 // ---- device: one run ------------------------------------------------------------------------
 // R(y) of a run of len cells (len <= LM, uniform across the wave): with the face value
 // h_t = y_t + sigma_t / 2 and h_{-1} = 0 (no influx at the run's first cell; the ghost
@@ -289,6 +360,254 @@ __global__ __launch_bounds__(256) void k_r0_motor(const T *__restrict__ Min, T *
     }
 }
 
+// ---- device: one anchor per block (depleted sub-cycling in one pass) -------------------------
+// The slots of a thread in registers: y (the state) and wg (psi of the slot's run at the anchor);
+// bit j of cont is set where slot j continues the run of slot j - 1 (clear at a run's first slot
+// and at slot 0).  The run's ends are bit masks (an AND with 0 or all ones, exact): the left
+// difference y_j - [cont_j] y_{j-1} is y_j at a run's first cell (no influx), the right one
+// [cont_{j+1}] (y_{j+1} - y_j) is 0 at its last (zero slope, first-order outflow), and the face
+// value to the left [cont_j] h_{j-1} is 0 at its first; the rest is run_rhs.  The padding slots
+// (after a thread's runs) form a run of their own that no sum reads and no store writes.
+template <typename T>
+__device__ __forceinline__ T keep_if(T v, int mk) {  // mk: 0 (-> +0) or -1 (-> v)
+    if constexpr (sizeof(T) == 4)
+        return __int_as_float(__float_as_int(v) & mk);
+    else
+        return __longlong_as_double(__double_as_longlong(v) & (long long)mk);
+}
+__device__ __forceinline__ int cont_mask(uint32_t cont, int j) {  // bit j as 0 or -1
+    return (int)__builtin_amdgcn_sbfe(cont, j, 1);
+}
+
+template <typename T, int LIM>
+__device__ __forceinline__ T anchor_rate(T yl, T yc, T yr, int ml, int mr, T &hprev, T nv_ds, T src, T k_off) {
+    const T sig = (LIM == 0) ? superbee(yc - keep_if(yl, ml), keep_if(yr - yc, mr)) : T(0);
+    const T h = yc + T(0.5) * sig;
+    const T R = nv_ds * (h - keep_if(hprev, ml)) + (src - k_off * yc);
+    hprev = h;
+    return R;
+}
+
+// One midpoint step of all slots: y1 = y + dt/2 R(y), y <- y + dt R(y1), the two stages
+// interleaved slot by slot (stage 2 at slot j needs stage 1 at j + 1), so that only three stage-1
+// values are live.
+template <typename T, int C, int LIM>
+__device__ __forceinline__ void anchor_rk2(T (&y)[C], uint32_t cont, T half_dt, T dt, T nv_ds, T src, T k_off) {
+    T h1 = T(0), h2 = T(0);
+    T y1l = T(0), y1c, y1r = T(0);
+    {
+        const int m1 = C > 1 ? cont_mask(cont, 1) : 0;
+        y1c = y[0] + half_dt * anchor_rate<T, LIM>(T(0), y[0], y[C > 1 ? 1 : 0], 0, m1, h1, nv_ds, src, k_off);
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        const int mc = j > 0 ? cont_mask(cont, j) : 0;
+        const int mr = j + 1 < C ? cont_mask(cont, j + 1 < C ? j + 1 : j) : 0;
+        if (j + 1 < C) {
+            const int n = j + 1 < C ? j + 1 : j;
+            const int mrr = n + 1 < C ? cont_mask(cont, n + 1 < C ? n + 1 : n) : 0;
+            y1r = y[n] + half_dt * anchor_rate<T, LIM>(y[j], y[n], y[n + 1 < C ? n + 1 : n], mr, mrr, h1, nv_ds, src,
+                                                       k_off);
+        }
+        y[j] = y[j] + dt * anchor_rate<T, LIM>(y1l, y1c, y1r, mc, mr, h2, nv_ds, src, k_off);
+        y1l = y1c;
+        y1c = y1r;
+    }
+}
+
+// One anchor at a time per block: all its tracked cells, nthr threads of C slots
+// (M[r0][C/4][nthr][4]).  The blocks are persistent: the slot table is the same for every anchor,
+// so each thread decodes its part once (the run boundaries and the padding into two registers;
+// the run, first cell, offset and orientation of each run's first slot into LDS, where each
+// thread reads back only its own entries), so that per anchor there is one round of loads (the
+// state and the psi gathers, all issued before any is used).  The blocks on one XCD
+// (the dispatcher deals blocks to the 8 XCDs in turn) take the anchors of one contiguous range in
+// turn.  Per sub-step: the anchor's coarse density (a wave butterfly,
+// then the waves' sums in a fixed order: the same bits on every thread), its clamp factor and
+// pool, then both RK2 stages in registers.  (Issuing the next anchor's loads before the current
+// anchor's steps, with barriers that fence LDS only, measured no faster at the benchmark workload:
+// 1053 against 1031 us per launch; nor did two blocks per CU: 1167.)
+template <typename T, int C, int LIM>
+__global__ __launch_bounds__(1024) void k_r0_anchor(const T *__restrict__ Min, T *__restrict__ Mout,
+                                                    T *__restrict__ q01, const int2 *__restrict__ tab,
+                                                    const T *__restrict__ psi, R0Const<T> c, int nrun, int nsub,
+                                                    double w, double m_total, double k_on) {
+    static_assert(C % 4 == 0, "slots come in groups of 4");
+    typedef T TV4 __attribute__((ext_vector_type(4)));
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    __shared__ double red[2][16];
+    extern __shared__ int lds_tab[];  // [2][C][nthr]: run | lo << 20, packed (a, b, k) (-1: none)
+    const int nthr = blockDim.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = nthr >> 6;
+    int *exl = lds_tab, *eyl = lds_tab + C * nthr;
+    uint32_t cont = 0;  // bit j: slot j continues the run of slot j - 1
+    int nfill = 0;      // slots before the padding
+    {
+        int2 e[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) e[j] = tab[j * nthr + t];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const bool first = j == 0 || e[j].x != e[j > 0 ? j - 1 : 0].x;
+            cont |= first ? 0u : 1u << j;
+            nfill += e[j].x >= 0;
+            exl[j * nthr + t] = e[j].x;
+            eyl[j * nthr + t] = first && e[j].x >= 0 ? e[j].y : -1;
+        }
+    }
+    const int xcd = blockIdx.x & 7, bx = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+    const int64_t per = (c.nxy + 7) / 8, r_end = min(c.nxy, (int64_t)(xcd + 1) * per);
+    // loads of anchor r: the state (nontemporal: M_b is streamed once and must not push the run
+    // totals out of L2; a thread's 4 slots of a group are one 16-byte (FP64: 32-byte) load,
+    // padding included) and psi(x, th_k) of each run at the anchor, x = r + (a, b), gathered at
+    // its first slot (32-bit offsets: nx ny nth < 2^31 for this kernel)
+    TV4 v[C / 4];
+    T g[C];
+    auto issue = [&](int64_t r) {
+        const TV4 *src = reinterpret_cast<const TV4 *>(Min + r * (int64_t)(C * nthr));
+#pragma unroll
+        for (int q = 0; q < C / 4; ++q) v[q] = __builtin_nontemporal_load(src + q * nthr + t);
+        const int i0 = (int)(r / c.ny), j0 = (int)(r - (int64_t)i0 * c.ny);
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int f = eyl[j * nthr + t];
+            g[j] = T(0);
+            if (f >= 0) {
+                const int a = (f & 2047) - 1024, b = ((f >> 11) & 2047) - 1024, k = f >> 22;
+                g[j] = psi[(wrap1(i0 + a, c.nx) * c.ny + wrap1(j0 + b, c.ny)) * c.nth + k];
+            }
+        }
+    };
+    int ph = 0;  // sub-steps so far: which half of red
+    for (int64_t r0 = (int64_t)xcd * per + bx; r0 < r_end; r0 += nbx) {
+        issue(r0);
+        T y[C], wg[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            y[j] = j < nfill ? v[j >> 2][j & 3] : T(0);
+            wg[j] = ((cont >> j) & 1u) ? wg[j > 0 ? j - 1 : 0] : g[j];
+        }
+        for (int sub = 0; sub < nsub; ++sub, ++ph) {
+            // the thread's part of the coarse density in the field precision (at most 24 terms),
+            // the threads' parts in FP64
+            T pt = T(0);
+#pragma unroll
+            for (int j = 0; j < C; ++j) pt += wg[j] * y[j];
+            const double part = group_sum<64>((double)pt);
+            if (lane == 0) red[ph & 1][wv] = part;
+            __syncthreads();  // (the other half's reads of the sub-step before were done before it)
+            double tot = 0.0;
+            for (int q = 0; q < nw; ++q) tot += red[ph & 1][q];
+            const double B = tot * w;
+            const bool over = B > m_total;
+            const T sc = (T)(over ? m_total / B : 1.0);
+            const T src = (T)(k_on * (over ? 0.0 : m_total - B));
+#pragma unroll
+            for (int j = 0; j < C; ++j) y[j] = sc * y[j];
+            // the run-end masks are taken from cont inside the step (made opaque here, so that
+            // the compiler does not hoist one mask register per slot out of the loop)
+            uint32_t cs = cont;
+            asm volatile("" : "+v"(cs));
+            anchor_rk2<T, C, LIM>(y, cs, c.half_dt, c.dt, c.nv_ds, src, c.k_off);
+        }
+        TV4 *dst = reinterpret_cast<TV4 *>(Mout + r0 * (int64_t)(C * nthr));
+#pragma unroll
+        for (int q = 0; q < C / 4; ++q) {  // (padding slots are stored too: never read)
+            TV4 o;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) o[u] = y[4 * q + u];
+            __builtin_nontemporal_store(o, dst + q * nthr + t);
+        }
+        // run totals of the final state by anchor
+        double t0 = 0.0, t1 = 0.0, lw = 0.0;
+        int run = 0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            if (!((cont >> j) & 1u)) {
+                const int ex = exl[j * nthr + t];
+                run = ex & 0xFFFFF;
+                t0 = t1 = 0.0;
+                lw = (double)(ex >> 20) + 0.5 - c.half_ns;
+            }
+            t0 += (double)y[j];
+            t1 += lw * (double)y[j];
+            lw += 1.0;
+            if (j < nfill && (j + 1 == nfill || !((cont >> (j + 1 < C ? j + 1 : j)) & 1u))) {
+                // (q0, q1) side by side, anchor-major: the block writes one contiguous row of
+                // pairs (stored by run, the pairs of one anchor were scattered over every run's
+                // row: partial lines, and a TLB entry for every few runs)
+                T2 q;
+                q.x = (T)(t0 * c.ds);
+                q.y = (T)(t1 * c.ds2);
+                *reinterpret_cast<T2 *>(q01 + 2 * (r0 * nrun + run)) = q;
+            }
+        }
+    }
+}
+
+// m0(x, th) = dA sum over the runs s of orientation th of q0[x - (a_s, b_s)][s] (and m1 from
+// q1; the pairs (q0, q1) side by side, anchor-major), in run order.  A wave: 64 consecutive
+// filament cells; a load touches 64 anchors' rows, and the other runs of each line loaded (the
+// neighbouring runs, mostly of the same orientation) serve the wave's later loads.
+template <typename T>
+__global__ __launch_bounds__(256) void k_r0_marg(const T *__restrict__ q01, int nrun,
+                                                 const R0Seg *__restrict__ seg, const int32_t *__restrict__ seg_start,
+                                                 T *__restrict__ m0, T *__restrict__ m1, R0Const<T> c) {
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y;
+    const bool okx = x < c.nxy;
+    const int64_t xz = okx ? x : 0;
+    const int iv = (int)(xz / c.ny), jv = (int)(xz - (int64_t)iv * c.ny);
+    double s0 = 0.0, s1 = 0.0;
+    const int s_end = seg_start[k + 1];
+#pragma unroll 4
+    for (int s = seg_start[k]; s < s_end; ++s) {
+        const R0Seg r = seg[s];
+        const int64_t a = ((int64_t)wrap1(iv - r.a, c.nx) * c.ny + wrap1(jv - r.b, c.ny)) * nrun + s;
+        const T2 q = *reinterpret_cast<const T2 *>(q01 + 2 * a);
+        s0 += (double)q.x;
+        s1 += (double)q.y;
+    }
+    if (okx) {
+        m0[x * c.nth + k] = (T)(s0 * c.dA);
+        m1[x * c.nth + k] = (T)(s1 * c.dA);
+    }
+}
+
+// Anchor layout <-> tiled (tt = 64 vx > 0) or caller (tt = 0) layout, over the other layout's
+// elements in order (its side coalesced).
+template <typename T>
+__global__ __launch_bounds__(256) void k_r0_anchor_layout(const T *__restrict__ src, T *__restrict__ dst,
+                                                          const int32_t *__restrict__ cell_pos, R0Const<T> c,
+                                                          int tt, int64_t per_anchor, int nthr, int64_t n,
+                                                          int to_anchor) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        int64_t cell, x;
+        if (tt > 0) {
+            const int64_t pt = c.ncell * tt, tl = e / pt, rem = e - tl * pt;
+            cell = rem / tt;
+            x = tl * tt + (rem - cell * tt);
+            if (x >= c.nxy) {
+                if (!to_anchor) dst[e] = T(0);
+                continue;
+            }
+        } else {
+            cell = e / c.nxy;
+            x = e - cell * c.nxy;
+        }
+        const int i = (int)(x / c.ny), j = (int)(x - (int64_t)i * c.ny);
+        const int64_t r0 = (int64_t)wrap1(i - cell_pos[3 * cell + 1], c.nx) * c.ny + wrap1(j - cell_pos[3 * cell + 2], c.ny);
+        // slot j of thread t (slot id j nthr + t) sits at ((j / 4) nthr + t) 4 + j % 4
+        const int sl = cell_pos[3 * cell], sj = sl / nthr, st = sl - sj * nthr;
+        const int64_t q = r0 * per_anchor + ((int64_t)(sj >> 2) * nthr + st) * 4 + (sj & 3);
+        if (to_anchor)
+            dst[q] = src[e];
+        else
+            dst[e] = src[q];
+    }
+}
+
 // psi [x][th] -> psiT [th][x] (the coarse kernel reads psi at the filament cells of 64 consecutive
 // anchors: consecutive x for one orientation).
 template <typename T>
@@ -307,7 +626,8 @@ __global__ __launch_bounds__(256) void k_r0_psiT(const T *__restrict__ psi, T *_
 template <typename T>
 __global__ __launch_bounds__(256) void k_r0_coarse(const T *__restrict__ q0, const T *__restrict__ psiT,
                                                    const R0Seg *__restrict__ seg, double *__restrict__ part,
-                                                   R0Const<T> c, int nseg, int nrow) {
+                                                   R0Const<T> c, int nseg, int nrow, int64_t qs_run,
+                                                   int64_t qs_anchor) {
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t r0 = (int64_t)blockIdx.x * 64 + lane;
@@ -329,7 +649,7 @@ __global__ __launch_bounds__(256) void k_r0_coarse(const T *__restrict__ q0, con
                 const int ra = __builtin_amdgcn_readlane(rec.a, n), rb = __builtin_amdgcn_readlane(rec.b, n);
                 const int k = __builtin_amdgcn_readlane(rec.pack, n) >> 20;
                 const int64_t srun = row + (int64_t)(base + n) * nrow;
-                q[u] = q0[srun * c.nxy + rz];
+                q[u] = q0[srun * qs_run + rz * qs_anchor];
                 // the filament cell of this run at anchor r0: x = r0 + (a, b), periodic
                 const int64_t x = (int64_t)wrap1(iv + ra, c.nx) * c.ny + wrap1(jv + rb, c.ny);
                 pv[u] = psiT[(int64_t)k * c.nxy + x];
@@ -491,9 +811,9 @@ hipError_t launch_r0_motor(const T *M_in, T *M_out, T *q0, T *m0, T *m1, const R
 }
 
 template <typename T>
-hipError_t launch_r0_coarse(const T *q0, const T *psi, T *psiT, const R0Seg *seg, double *part, T *scale, T *pool,
-                            T *coarse_out, T *free_out, const R0Const<T> &c, int nseg, int nsplit, double dth,
-                            double m_total, double k_on, hipStream_t s) {
+hipError_t launch_r0_coarse(const T *q0, bool pairs, const T *psi, T *psiT, const R0Seg *seg, double *part, T *scale,
+                            T *pool, T *coarse_out, T *free_out, const R0Const<T> &c, int nseg, int nsplit,
+                            double dth, double m_total, double k_on, hipStream_t s) {
     if (c.nxy <= 0) return hipSuccess;
     const int64_t np = c.nxy * c.nth;
     hipLaunchKernelGGL(k_r0_psiT<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, psi, psiT, c.nxy, c.nth);
@@ -502,7 +822,8 @@ hipError_t launch_r0_coarse(const T *q0, const T *psi, T *psiT, const R0Seg *seg
     // one anchor per lane (measured at the benchmark workload with the earlier form of the
     // kernel: 98.6 us per coarse pass in FP32 against 109 with 16-byte loads of the run totals)
     hipLaunchKernelGGL((k_r0_coarse<T>), dim3((unsigned)((c.nxy + 63) / 64), (unsigned)nsplit), dim3(256), 0, s,
-                       q0, psiT, seg, part, c, nseg, 4 * nsplit);
+                       q0, psiT, seg, part, c, nseg, 4 * nsplit, pairs ? (int64_t)2 : c.nxy,
+                       pairs ? (int64_t)2 * nseg : (int64_t)1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double w = c.dA * dth;  // dx dy dth (q0 already carries ds)
@@ -521,6 +842,70 @@ hipError_t launch_r0_layout(const T *src, T *dst, int64_t ncell, int64_t nxy, in
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_r0_anchor(const T *M_in, T *M_out, T *q01, const int32_t *slot_tab, const T *psi,
+                            const R0Const<T> &c, int nrun, int C, int nthr, int nsub, double m_total, double k_on,
+                            double dth, int limiter, hipStream_t s) {
+    if (c.nxy <= 0) return hipSuccess;
+    if (nthr < 64 || nthr > 1024 || nthr % 64 != 0 || nsub < 1) return hipErrorInvalidValue;
+    // persistent blocks: as many as fit the device at once (a multiple of 8, one share per XCD),
+    // at most one per anchor
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int per_cu = 1;  // registers and LDS: one block per CU
+    const int64_t per = (c.nxy + 7) / 8;
+    const int64_t nbx = std::max<int64_t>(1, std::min<int64_t>(per, (int64_t)ncu * per_cu / 8));
+    const dim3 grid((unsigned)(8 * nbx)), block((unsigned)nthr);
+    const size_t lds = r0_anchor_lds(C, nthr);
+    const double w = c.dA * dth * c.ds;  // dx dy dth ds
+    const int2 *tab = reinterpret_cast<const int2 *>(slot_tab);
+    // (24 slots are FP32 only: the FP64 case instantiates nothing new)
+    constexpr int C24 = sizeof(T) == 4 ? 24 : 16;
+#define MMK_R0A(C_, CT_)                                                                                          \
+    case C_:                                                                                                     \
+        if (limiter == 0)                                                                                        \
+            hipLaunchKernelGGL((k_r0_anchor<T, CT_, 0>), grid, block, lds, s, M_in, M_out, q01, tab, psi,            \
+                               c, nrun, nsub, w, m_total, k_on);                                                 \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_r0_anchor<T, CT_, 1>), grid, block, lds, s, M_in, M_out, q01, tab, psi,            \
+                               c, nrun, nsub, w, m_total, k_on);                                                 \
+        break;
+    if (sizeof(T) == 8 && C > 16) return hipErrorInvalidValue;
+    switch (C) {
+        MMK_R0A(4, 4)
+        MMK_R0A(8, 8)
+        MMK_R0A(16, 16)
+        MMK_R0A(24, C24)
+        default: return hipErrorInvalidValue;
+    }
+#undef MMK_R0A
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_r0_marg(const T *q01, int nrun, const R0Seg *seg, const int32_t *seg_start, T *m0, T *m1,
+                          const R0Const<T> &c, hipStream_t s) {
+    if (c.nxy <= 0 || c.nth <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((c.nxy + 255) / 256), (unsigned)c.nth);
+    hipLaunchKernelGGL(k_r0_marg<T>, grid, dim3(256), 0, s, q01, nrun, seg, seg_start, m0, m1, c);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_r0_anchor_layout(const T *src, T *dst, const int32_t *cell_pos, const R0Const<T> &c, int vx,
+                                   int64_t per_anchor, int nthr, bool to_anchor, hipStream_t s) {
+    const int64_t n = vx > 0 ? r0_tiled_elems(c.ncell, c.nxy, vx) : c.ncell * c.nxy;
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_r0_anchor_layout<T>, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, cell_pos, c,
+                       64 * vx, per_anchor, nthr, n, to_anchor ? 1 : 0);
+    return hipGetLastError();
+}
+
+size_t r0_anchor_lds(int C, int nthr) { return (size_t)2 * C * nthr * sizeof(int); }
+
 size_t r0_field_lds(int ns, size_t esz) { return (size_t)ns * 65 * esz; }
 
 template <typename T>
@@ -537,9 +922,15 @@ hipError_t launch_r0_field(const T *Mb, T *M, const R0Seg *seg, const int32_t *s
 #define MMK_R0_INST(T)                                                                                              \
     template hipError_t launch_r0_motor<T>(const T *, T *, T *, T *, T *, const R0Seg *, const int32_t *, const T *, \
                                            const T *, const R0Const<T> &, int, int, hipStream_t);                   \
-    template hipError_t launch_r0_coarse<T>(const T *, const T *, T *, const R0Seg *, double *, T *, T *, T *, T *,  \
-                                            const R0Const<T> &, int, int, double, double, double, hipStream_t);     \
+    template hipError_t launch_r0_coarse<T>(const T *, bool, const T *, T *, const R0Seg *, double *, T *, T *, T *, \
+                                            T *, const R0Const<T> &, int, int, double, double, double, hipStream_t); \
     template hipError_t launch_r0_layout<T>(const T *, T *, int64_t, int64_t, int, bool, hipStream_t);            \
+    template hipError_t launch_r0_anchor<T>(const T *, T *, T *, const int32_t *, const T *, const R0Const<T> &,     \
+                                            int, int, int, int, double, double, double, int, hipStream_t);         \
+    template hipError_t launch_r0_marg<T>(const T *, int, const R0Seg *, const int32_t *, T *, T *,                  \
+                                          const R0Const<T> &, hipStream_t);                                        \
+    template hipError_t launch_r0_anchor_layout<T>(const T *, T *, const int32_t *, const R0Const<T> &, int, int64_t, \
+                                                   int, bool, hipStream_t);                                         \
     template hipError_t launch_r0_field<T>(const T *, T *, const R0Seg *, const int32_t *, const R0Const<T> &, int, \
                                            hipStream_t);
 MMK_R0_INST(float)

@@ -22,9 +22,10 @@ FP64, FP32 = 0, 1
 SUPERBEE, UPWIND1 = 0, 1
 # implementation options (mmk_set_option): name -> id
 OPTIONS = {"motor_block": 0, "psi_kernel": 1, "depl_fused": 2, "motor_lanes": 3, "motor_chunks": 4,
-           "motor_nt": 5, "psi_depth": 6}
+           "motor_nt": 5, "psi_depth": 6, "r0_onepass": 7}
 KERNEL_IDS = {"motor_step": 0, "psi_step": 1, "global_sums": 2, "psi_step_reverse": 3,
-              "motor_step_reverse": 4, "motor_force": 5, "r0_motor_step": 6, "r0_coarse": 7}
+              "motor_step_reverse": 4, "motor_force": 5, "r0_motor_step": 6, "r0_coarse": 7,
+              "r0_anchor_step": 8, "r0_marginals": 9}
 
 EXPORTS = ["mmk_workspace_bytes", "mmk_create", "mmk_destroy", "mmk_set_params", "mmk_set_state",
            "mmk_set_fluid", "mmk_step", "mmk_get_state", "mmk_get_stress", "mmk_get_moments",

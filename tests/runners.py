@@ -42,10 +42,12 @@ def run_oracle_uniform_columns(p, psi0, fluids, K, n, dt, col0=None):
     return dict(psi=psi, col=col, m0=m0, m1=m1, stress=stress, mom=mom, mass=mass, sum_sigma=ss)
 
 
-def run_gpu(p, psi0, M0, fluids, K, n, dt, precision=0, keep_ctx=False, want_M=True, options=None):
+def run_gpu(p, psi0, M0, fluids, K, n, dt, precision=0, keep_ctx=False, want_M=True, options=None, profile=False):
     import torch
     from paper_1908_04279_amd import mmk
     ctx = mmk.Context(p, precision=precision, options=options)
+    if profile:
+        ctx.profile(True)
     ctx.set_state(torch.as_tensor(psi0), None if M0 is None else torch.as_tensor(M0))
     done, e = 0, 0
     while done < n:
@@ -106,10 +108,12 @@ def run_r0_oracle(p, psi0, Mb0, fluids, K, n, dt):
 
 
 def run_r0_gpu(p, psi0, Mb0, fluids, K, n, dt, precision=0, options=None):
-    """The HIP library on the anchor-resolved model, with the per-anchor outputs."""
+    """The HIP library on the anchor-resolved model, with the per-anchor outputs and the number of
+    motor launches of each kind (launches: one anchor per block, one per sub-step or step)."""
     import torch
-    out = run_gpu(p, psi0, Mb0, fluids, K, n, dt, precision=precision, keep_ctx=True, options=options)
+    out = run_gpu(p, psi0, Mb0, fluids, K, n, dt, precision=precision, keep_ctx=True, options=options, profile=True)
     ctx = out.pop("ctx")
+    out["launches"] = {k: ctx.profile_read(k)[1] for k in ("r0_anchor_step", "r0_motor_step")}
     coarse, free = ctx.get_anchors()
     out["coarse"] = coarse.double().cpu().numpy()
     out["free"] = free.double().cpu().numpy()

@@ -31,6 +31,17 @@ def r0_case(p, depletion, zero_start=False, n_exchanges=2, seed=4):
     return cells, psi0, Mb0, fl, dt
 
 
+def run_length_max(cells):
+    brk = np.nonzero((np.diff(cells[:, 3]) != 1) | np.any(np.diff(cells[:, :3], axis=0) != 0, axis=1))[0]
+    return int(np.max(np.diff(np.concatenate([[0], brk + 1, [len(cells)]]))))
+
+
+def onepass_expected(cells, depletion, nsub, precision, onepass=1):
+    """Whether the library takes the one-anchor-per-block launch: depletion with sub-cycling, the
+    option on, and the runs within the slots of a thread (16 in FP64, 24 in FP32)."""
+    return bool(onepass and depletion and nsub > 1 and run_length_max(cells) <= (24 if precision else 16))
+
+
 def compare(g, o, tol, fields=FIELDS):
     errs = {f: rel_err(g[f], o[f]) for f in fields}
     errs["mass"] = abs(g["mass"] - o["mass"]) / abs(o["mass"])
@@ -202,6 +213,75 @@ def test_full_size_sampled():
     assert abs(mass1 - 1.0) <= 1e-5
 
 
+def test_full_size_sampled_onepass():
+    """The sub-cycled benchmark workload (128^2 anchors, 32 orientations, 32 arclength cells,
+    rc = 0.1, fast motors v0 = 8 with motor_cfl = 0.4: 3 sub-steps, FP32, depletion with about half
+    of the anchors clamped at the first sub-step) in its launch configuration (one anchor per block),
+    one micro-step: at sampled anchors the oracle's sub-steps of every run of the anchor, each after
+    the clamp and pool of the anchor's current sub-state (psi of the step's start); the coarse
+    density after the step from the GPU's own new state and psi; the marginal m0 at sampled
+    filament cells against the sum of the GPU's own new state."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=128, ny=128, ntheta=32, ns=32, rc=0.1, v0=8.0, motor_cfl=0.4)
+    cells = A.r0_cells(p)
+    nc = len(cells)
+    rng = np.random.default_rng(12)
+    psi0 = gen.make_psi0(p.nx, p.ny, p.ntheta, seed=0).astype(np.float32)
+    Mb0 = rng.uniform(0.0, 2.0, (nc, p.nx, p.ny)).astype(np.float32)
+    u, G = gen.make_fluid(p.nx, p.ny)
+    dt = gen.cfl_dt(p, [(u, G)])
+    nsub = A.motor_substeps(p, dt)
+    assert nsub == 3
+    h = dt / nsub
+    ds, dx, dy, dth = p.L / p.ns, p.lx / p.nx, p.ly / p.ny, 2 * np.pi / p.ntheta
+    a, b, k = cells[:, 0], cells[:, 1], cells[:, 2]
+
+    def at(field, i0, j0):  # the anchor's cells of a [ncell][nx][ny] field
+        return field[np.arange(nc), (i0 + a) % p.nx, (j0 + b) % p.ny]
+
+    def coarse(y, psi, i0, j0):
+        return float(np.sum(y * psi[(i0 + a) % p.nx, (j0 + b) % p.ny, k].astype(np.float64)) * ds * dx * dy * dth)
+
+    anchors = [(int(rng.integers(p.nx)), int(rng.integers(p.ny))) for _ in range(6)]
+    p.m_total = float(np.median([coarse(at(Mb0, *r).astype(np.float64), psi0, *r) for r in anchors]))
+    ctx = mmk.Context(p, precision=mmk.FP32)
+    ctx.profile(True)
+    ctx.set_state(torch.as_tensor(psi0), torch.as_tensor(Mb0))
+    ctx.set_fluid(torch.as_tensor(u), torch.as_tensor(G))
+    ctx.step(1, dt)
+    psi1, Mb1 = ctx.get_state()
+    m0, _ = ctx.get_motor_moments()
+    co1, _ = ctx.get_anchors()
+    assert onepass_launches(ctx)[0] == 1
+    psi1, Mb1, m0, co1 = psi1.cpu().numpy(), Mb1.cpu().numpy(), m0.cpu().numpy(), co1.cpu().numpy()
+    torch.cuda.synchronize()
+    ctx.close()
+    brk = np.nonzero((np.diff(cells[:, 3]) != 1) | np.any(np.diff(cells[:, :3], axis=0) != 0, axis=1))[0]
+    edges = np.concatenate([[0], brk + 1, [nc]])
+    clamped = 0
+    for (i0, j0) in anchors:
+        y = at(Mb0, i0, j0).astype(np.float64)
+        for q in range(nsub):
+            co = coarse(y, psi0, i0, j0)
+            over = co > p.m_total
+            clamped += over and q == 0
+            scale, src = (p.m_total / co, 0.0) if over else (1.0, p.k_on * (p.m_total - co))
+            for r in range(len(edges) - 1):
+                c0, c1 = edges[r], edges[r + 1]
+                y[c0:c1] = A.run_step(p, h, scale * y[c0:c1], src)
+        got = at(Mb1, i0, j0).astype(np.float64)
+        assert np.max(np.abs(got - y)) <= 1e-5 * 2.0, (i0, j0)
+        want_co = coarse(got, psi1, i0, j0)
+        assert abs(co1[i0, j0] - want_co) <= 1e-5 * want_co, (i0, j0)
+    assert 0 < clamped < len(anchors)
+    for _ in range(8):
+        i, j, kk = int(rng.integers(p.nx)), int(rng.integers(p.ny)), int(rng.integers(p.ntheta))
+        sel = k == kk
+        want = float(np.sum(Mb1[sel, i, j].astype(np.float64))) * ds * dx * dy
+        assert abs(m0[i, j, kk] - want) <= 1e-5 * abs(want)
+
+
 @pytest.mark.parametrize("kw,precision", [
     (dict(nx=20, ny=18, ntheta=16, ns=16, rc=0.35), 0),
     (dict(nx=9, ny=7, ntheta=12, ns=10, rc=0.6, lx=5.0, ly=6.0, limiter=1), 0),
@@ -232,15 +312,18 @@ def test_force_against_oracle(kw, precision):
     assert err <= (1e-5 if precision else 1e-12)
 
 
-def test_resume_is_bitwise():
+@pytest.mark.parametrize("nsub", [1, 3])
+def test_resume_is_bitwise(nsub):
     """8 steps in one context give the same bits as 4 steps, get_state, a new context and set_state,
     4 more steps (the state carries everything: set_state rebuilds the run totals and marginals
-    with the same sums the motor launch makes)."""
+    with the same sums the motor launch makes; with 3 sub-steps the state leaves the first context
+    from the anchor layout and enters the second one tiled)."""
     import torch
     from paper_1908_04279_amd import mmk
     p = ModelParams(nx=20, ny=18, ntheta=16, ns=16, rc=0.35)
-    cells, psi0, Mb0, fl, dt = r0_case(p, True)
+    cells, psi0, Mb0, fl, dt = r0_case(p, True) if nsub == 1 else substep_r0_case(p, True, nsub)
     a = run_r0_gpu(p, psi0, Mb0, fl, 4, 8, dt)
+    assert (a["launches"]["r0_anchor_step"] > 0) == (nsub > 1)
     ctx = mmk.Context(p)
     ctx.set_state(torch.as_tensor(psi0), torch.as_tensor(Mb0))
     ctx.set_fluid(*map(torch.as_tensor, fl[0]))
@@ -276,24 +359,150 @@ def substep_r0_case(p, depletion, nsub):
     return cells, psi0, Mb0, fl, dt
 
 
+@pytest.mark.parametrize("onepass", [1, 0])
 @pytest.mark.parametrize("kw,depletion,nsub,Kn", SUBSTEP_CASES)
-def test_substeps_fp64_against_oracle(kw, depletion, nsub, Kn):
+def test_substeps_fp64_against_oracle(kw, depletion, nsub, Kn, onepass):
     """Motor sub-cycling of the runs (Alg. 2's local dt*), with depletion every sub-step after the
-    clamp and the pool of its anchor's current sub-state."""
+    clamp and the pool of its anchor's current sub-state: one anchor per block (all sub-steps of a
+    micro-step in one launch), and one coarse pass and motor launch per sub-step."""
+    if not depletion and not onepass:
+        pytest.skip("the option selects between the depleted paths only")
     p = ModelParams(**kw)
     cells, psi0, Mb0, fl, dt = substep_r0_case(p, depletion, nsub)
     K, n = Kn
-    g = run_r0_gpu(p, psi0, Mb0, fl, K, n, dt)
+    g = run_r0_gpu(p, psi0, Mb0, fl, K, n, dt, options={"r0_onepass": onepass})
+    print(g["launches"], flush=True)
+    assert (g["launches"]["r0_anchor_step"] == n) == onepass_expected(cells, depletion, nsub, 0, onepass)
     o = run_r0_oracle(p, psi0, Mb0, fl, K, n, dt)
     compare(g, o, 1e-12)
 
 
-@pytest.mark.parametrize("depletion", [True, False])
-def test_substeps_fp32_against_fp64_oracle(depletion):
+def onepass_launches(ctx):
+    return ctx.profile_read("r0_anchor_step")[1], ctx.profile_read("r0_motor_step")[1]
+
+
+@pytest.mark.parametrize("kw,precision", [
+    (dict(nx=20, ny=18, ntheta=16, ns=16, rc=0.35), 0),           # 16 slots a thread
+    (dict(nx=24, ny=22, ntheta=16, ns=24, rc=0.45, v0=1.7), 1),  # runs of 22 cells: 24 slots (FP32)
+])
+def test_onepass_and_per_substep_paths_agree(kw, precision):
+    """The two depleted sub-cycling paths on the same inputs (they differ only in the association of
+    the coarse sums and where the run totals are rounded), and which launches each made."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(**kw)
+    cells, psi0, Mb0, fl, dt = substep_r0_case(p, True, 3)
+    assert onepass_expected(cells, True, 3, precision)
+    if precision:
+        psi0, Mb0 = psi0.astype(np.float32), Mb0.astype(np.float32)
+    outs = []
+    for onepass in (1, 0):
+        ctx = mmk.Context(p, precision=precision, options={"r0_onepass": onepass})
+        ctx.profile(True)
+        ctx.set_state(torch.as_tensor(psi0), torch.as_tensor(Mb0))
+        ctx.set_fluid(*map(torch.as_tensor, fl[0]))
+        ctx.step(3, dt)
+        ctx.set_fluid(*map(torch.as_tensor, fl[1]))
+        ctx.step(2, dt)
+        psi, Mb = ctx.get_state()
+        m0, m1 = ctx.get_motor_moments()
+        co, fr = ctx.get_anchors()
+        n8, n6 = onepass_launches(ctx)
+        # set_state makes one anchor-resolved motor launch (the totals of the new state)
+        assert (n8, n6) == ((5, 1) if onepass else (0, 1 + 5 * 3)), (n8, n6)
+        outs.append({k: v.double().cpu().numpy() for k, v in
+                     dict(psi=psi, M=Mb, m0=m0, m1=m1, stress=ctx.get_stress(), mom=ctx.get_moments(),
+                          coarse=co, free=fr).items()})
+        torch.cuda.synchronize()
+        ctx.close()
+    tol = 2e-6 if precision else 1e-13
+    for f in outs[0]:
+        err = rel_err(outs[0][f], outs[1][f])
+        print(f, f"{err:.2e}", flush=True)
+        assert err <= tol, (f, err)
+
+
+def test_onepass_layout_round_trips():
+    """One context through every change of the state's layout, against the oracle stepped alongside:
+    one-pass steps (anchor layout), get_state, get_anchors and get_force from it, steps of the other
+    path (tiled again), one-pass steps once more, a get_state/set_state round trip; FP64 1e-12."""
+    import torch
+    from paper_1908_04279_amd import mmk
     p = ModelParams(nx=20, ny=18, ntheta=16, ns=16, rc=0.35)
+    cells, psi0, Mb0, fl, dt = substep_r0_case(p, True, 3)
+    ctx = mmk.Context(p)
+    o = A.OracleR0(p)
+    ctx.set_state(torch.as_tensor(psi0), torch.as_tensor(Mb0))
+    o.set_state(psi0, Mb0)
+
+    def check(tag, force=False):
+        psi, Mb = ctx.get_state()
+        psi, Mb = psi.double().cpu().numpy(), Mb.double().cpu().numpy()
+        co, _ = ctx.get_anchors()
+        errs = dict(psi=rel_err(psi, o.psi), M=rel_err(Mb, o.Mb), coarse=rel_err(co.double().cpu().numpy(), o.coarse()))
+        m0, m1 = ctx.get_motor_moments()
+        om0, om1 = o.marginals()
+        errs.update(m0=rel_err(m0.double().cpu().numpy(), om0), m1=rel_err(m1.double().cpu().numpy(), om1))
+        if force:
+            errs["force"] = rel_err(ctx.get_force().double().cpu().numpy(), A.r0_motor_force(p, cells, o.psi, o.Mb))
+        print(tag, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+        for k, v in errs.items():
+            assert v <= 1e-12, (tag, k, v)
+
+    for e, (onepass, K) in enumerate([(1, 2), (1, 1), (0, 2), (1, 2)]):
+        ctx.set_option("r0_onepass", onepass)
+        ctx.set_fluid(*map(torch.as_tensor, fl[e % 2]))
+        o.set_fluid(*fl[e % 2])
+        ctx.step(K, dt)
+        o.step(K, dt)
+        check(f"call {e} onepass {onepass}", force=e in (0, 3))
+    psi, Mb = ctx.get_state()
+    ctx.set_state(psi, Mb)
+    ctx.step(1, dt)
+    o.step(1, dt)
+    check("after set_state")
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def test_onepass_graph_replays_are_bitwise():
+    """mmk_step_graph on the one-pass path: the first graph includes the change to the anchor
+    layout, later ones start from it; a get_force in between (back to tiled) makes the next call
+    use the first graph again.  Every replay has the bits of mmk_step in a twin context."""
+    import torch
+    from paper_1908_04279_amd import mmk
+    p = ModelParams(nx=20, ny=18, ntheta=16, ns=16, rc=0.35)
+    cells, psi0, Mb0, fl, dt = substep_r0_case(p, True, 2)
+    ctxs = [mmk.Context(p), mmk.Context(p)]
+    for c in ctxs:
+        c.set_state(torch.as_tensor(psi0), torch.as_tensor(Mb0))
+        c.set_fluid(*map(torch.as_tensor, fl[0]))
+    for r in range(5):
+        ctxs[0].step_graph(2, dt)
+        ctxs[1].step(2, dt)
+        if r == 2:
+            fa, fb = (c.get_force().double().cpu().numpy() for c in ctxs)
+            assert np.array_equal(fa, fb)
+        torch.cuda.synchronize()  # eager work and synchronisation between the replays
+        (pa, Ma), (pb, Mbb) = (c.get_state() for c in ctxs)
+        assert torch.equal(pa, pb) and torch.equal(Ma, Mbb), r
+        assert torch.equal(ctxs[0].get_stress(), ctxs[1].get_stress()), r
+        assert torch.equal(ctxs[0].get_motor_moments()[0], ctxs[1].get_motor_moments()[0]), r
+    for c in ctxs:
+        c.close()
+
+
+@pytest.mark.parametrize("kw,depletion", [
+    (dict(nx=20, ny=18, ntheta=16, ns=16, rc=0.35), True),
+    (dict(nx=20, ny=18, ntheta=16, ns=16, rc=0.35), False),
+    (dict(nx=24, ny=22, ntheta=16, ns=24, rc=0.45, v0=1.7), True),  # one anchor per block, 24 slots
+])
+def test_substeps_fp32_against_fp64_oracle(kw, depletion):
+    p = ModelParams(**kw)
     cells, psi0, Mb0, fl, dt = substep_r0_case(p, depletion, 3)
     psi32, Mb32 = psi0.astype(np.float32), Mb0.astype(np.float32)
     g = run_r0_gpu(p, psi32, Mb32, fl, 4, 8, dt, precision=1)
+    assert (g["launches"]["r0_anchor_step"] == 8) == onepass_expected(cells, depletion, 3, 1)
     o = run_r0_oracle(p, psi32.astype(np.float64), Mb32.astype(np.float64), fl, 4, 8, dt)
     compare(g, o, 1e-5)
 
