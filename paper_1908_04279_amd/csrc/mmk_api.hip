@@ -143,7 +143,7 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
         L.r0start = take(((size_t)p.ntheta + 1) * sizeof(int32_t));
         L.psiT = take(np * e);
         if (rs.ok) {
-            L.q01 = take((size_t)2 * rp.nseg * nxy * e);
+            L.q01 = take((size_t)2 * rp.nseg * ((nxy + 15) / 16 * 16) * e);  // tiles of 16 anchors
             L.r0slot = take(rs.slot_tab.size() * sizeof(int32_t));
             L.r0cpos = take(rs.cell_pos.size() * sizeof(int32_t));
         }

@@ -66,7 +66,7 @@ hipError_t launch_r0_motor(const T *M_in, T *M_out, T *q0, T *m0, T *m1, const R
 // clamp factor and the source of Alg. 2 / Eq. (6) (m_total > 0), and optionally coarse and the
 // free pool in the field precision.
 // (q0: the motor kernel's run totals q0[run][r0], or with pairs the one-pass kernel's
-// q01[r0][run][2])
+// q01[r0 / 16][run][r0 % 16][2])
 template <typename T>
 hipError_t launch_r0_coarse(const T *q0, bool pairs, const T *psi, T *psiT, const R0Seg *seg, double *part, T *scale,
                             T *pool, T *coarse_out, T *free_out, const R0Const<T> &c, int nseg, int nsplit,
@@ -108,14 +108,15 @@ R0Slots plan_r0_slots(const R0Plan &P, size_t esz);
 // coarse = w sum over the anchor's cells of psi(x, th_k) M (w = dx dy dth ds; psi of the step's
 // start), the factor m_total / coarse and pool 0 where coarse > m_total, else 1 and
 // k_on (m_total - coarse).  Anchor layout in and out (in place allowed).  Writes the run totals
-// of the final state anchor-major and side by side, q01[r0][run] = (sum M ds, sum (l + 1/2 -
-// ns/2) M ds^2), which k_r0_marg turns into m0, m1 (and the coarse kernel reads as pairs).
+// of the final state side by side in tiles of 16 anchors, q01[r0 / 16][run][r0 % 16] = (sum M
+// ds, sum (l + 1/2 - ns/2) M ds^2), which k_r0_marg turns into m0, m1 (and the coarse kernel
+// reads as pairs).
 template <typename T>
 hipError_t launch_r0_anchor(const T *M_in, T *M_out, T *q01, const int32_t *slot_tab, const T *psi,
                             const R0Const<T> &c, int nrun, int C, int nthr, int nsub, double m_total, double k_on,
                             double dth, int limiter, hipStream_t s);
-// m0 = dA sum over the runs of orientation th of q0[x - (a, b)][run], m1 likewise from q1, in
-// run order (FP64 sums).
+// m0 = dA sum over the runs of orientation th of q0 of the run at anchor x - (a, b), m1 likewise
+// from q1, in run order (FP64 sums).
 template <typename T>
 hipError_t launch_r0_marg(const T *q01, int nrun, const R0Seg *seg, const int32_t *seg_start, T *m0, T *m1,
                           const R0Const<T> &c, hipStream_t s);

@@ -361,6 +361,12 @@ __global__ __launch_bounds__(256) void k_r0_motor(const T *__restrict__ Min, T *
 }
 
 // ---- device: one anchor per block (depleted sub-cycling in one pass) -------------------------
+// Pair (q0, q1) of run s at anchor r in the one-pass kernel's run totals: tiles of 16 anchors,
+// q01[r / 16][s][r % 16] (times 2 values).
+__host__ __device__ __forceinline__ int64_t r0_pair_index(int64_t r, int64_t s, int64_t nrun) {
+    return ((r >> 4) * nrun + s) * 16 + (r & 15);
+}
+
 // The slots of a thread in registers: y (the state) and wg (psi of the slot's run at the anchor);
 // bit j of cont is set where slot j continues the run of slot j - 1 (clear at a run's first slot
 // and at slot 0).  The run's ends are bit masks (an AND with 0 or all ones, exact): the left
@@ -533,22 +539,21 @@ __global__ __launch_bounds__(1024) void k_r0_anchor(const T *__restrict__ Min, T
             t1 += lw * (double)y[j];
             lw += 1.0;
             if (j < nfill && (j + 1 == nfill || !((cont >> (j + 1 < C ? j + 1 : j)) & 1u))) {
-                // (q0, q1) side by side, anchor-major: the block writes one contiguous row of
-                // pairs (stored by run, the pairs of one anchor were scattered over every run's
-                // row: partial lines, and a TLB entry for every few runs)
+                // (q0, q1) side by side, in tiles of 16 anchors: q01[r0 / 16][run][r0 % 16].
+                // The tile's 16 anchors are in flight at the same time on one XCD, so each line
+                // of 16 pairs forms whole in its L2, and a block's stores stay inside one tile
                 T2 q;
                 q.x = (T)(t0 * c.ds);
                 q.y = (T)(t1 * c.ds2);
-                *reinterpret_cast<T2 *>(q01 + 2 * (r0 * nrun + run)) = q;
+                *reinterpret_cast<T2 *>(q01 + 2 * r0_pair_index(r0, run, nrun)) = q;
             }
         }
     }
 }
 
-// m0(x, th) = dA sum over the runs s of orientation th of q0[x - (a_s, b_s)][s] (and m1 from
-// q1; the pairs (q0, q1) side by side, anchor-major), in run order.  A wave: 64 consecutive
-// filament cells; a load touches 64 anchors' rows, and the other runs of each line loaded (the
-// neighbouring runs, mostly of the same orientation) serve the wave's later loads.
+// m0(x, th) = dA sum over the runs s of orientation th of q0 of run s at anchor x - (a_s, b_s)
+// (and m1 from q1; the pairs (q0, q1) side by side in tiles of 16 anchors), in run order.  A
+// wave: 64 consecutive filament cells, so a run's loads are 64 consecutive anchors: 4 or 5 lines.
 template <typename T>
 __global__ __launch_bounds__(256) void k_r0_marg(const T *__restrict__ q01, int nrun,
                                                  const R0Seg *__restrict__ seg, const int32_t *__restrict__ seg_start,
@@ -564,7 +569,7 @@ __global__ __launch_bounds__(256) void k_r0_marg(const T *__restrict__ q01, int 
 #pragma unroll 4
     for (int s = seg_start[k]; s < s_end; ++s) {
         const R0Seg r = seg[s];
-        const int64_t a = ((int64_t)wrap1(iv - r.a, c.nx) * c.ny + wrap1(jv - r.b, c.ny)) * nrun + s;
+        const int64_t a = r0_pair_index((int64_t)wrap1(iv - r.a, c.nx) * c.ny + wrap1(jv - r.b, c.ny), s, nrun);
         const T2 q = *reinterpret_cast<const T2 *>(q01 + 2 * a);
         s0 += (double)q.x;
         s1 += (double)q.y;
@@ -626,8 +631,7 @@ __global__ __launch_bounds__(256) void k_r0_psiT(const T *__restrict__ psi, T *_
 template <typename T>
 __global__ __launch_bounds__(256) void k_r0_coarse(const T *__restrict__ q0, const T *__restrict__ psiT,
                                                    const R0Seg *__restrict__ seg, double *__restrict__ part,
-                                                   R0Const<T> c, int nseg, int nrow, int64_t qs_run,
-                                                   int64_t qs_anchor) {
+                                                   R0Const<T> c, int nseg, int nrow, int pairs) {
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t r0 = (int64_t)blockIdx.x * 64 + lane;
@@ -649,7 +653,7 @@ __global__ __launch_bounds__(256) void k_r0_coarse(const T *__restrict__ q0, con
                 const int ra = __builtin_amdgcn_readlane(rec.a, n), rb = __builtin_amdgcn_readlane(rec.b, n);
                 const int k = __builtin_amdgcn_readlane(rec.pack, n) >> 20;
                 const int64_t srun = row + (int64_t)(base + n) * nrow;
-                q[u] = q0[srun * qs_run + rz * qs_anchor];
+                q[u] = pairs ? q0[2 * r0_pair_index(rz, srun, nseg)] : q0[srun * c.nxy + rz];
                 // the filament cell of this run at anchor r0: x = r0 + (a, b), periodic
                 const int64_t x = (int64_t)wrap1(iv + ra, c.nx) * c.ny + wrap1(jv + rb, c.ny);
                 pv[u] = psiT[(int64_t)k * c.nxy + x];
@@ -822,8 +826,7 @@ hipError_t launch_r0_coarse(const T *q0, bool pairs, const T *psi, T *psiT, cons
     // one anchor per lane (measured at the benchmark workload with the earlier form of the
     // kernel: 98.6 us per coarse pass in FP32 against 109 with 16-byte loads of the run totals)
     hipLaunchKernelGGL((k_r0_coarse<T>), dim3((unsigned)((c.nxy + 63) / 64), (unsigned)nsplit), dim3(256), 0, s,
-                       q0, psiT, seg, part, c, nseg, 4 * nsplit, pairs ? (int64_t)2 : c.nxy,
-                       pairs ? (int64_t)2 * nseg : (int64_t)1);
+                       q0, psiT, seg, part, c, nseg, 4 * nsplit, pairs ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double w = c.dA * dth;  // dx dy dth (q0 already carries ds)
