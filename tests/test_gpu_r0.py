@@ -134,6 +134,16 @@ def test_refusals():
     with pytest.raises(mmk.MMKError) as ei:
         ctx.tape_begin(2)
     assert ei.value.status == mmk.MMK_ERR_UNSUPPORTED
+    for bad in (-1, 2):   # the one-pass option takes 0 or 1
+        with pytest.raises(mmk.MMKError) as ei:
+            ctx.set_option("r0_onepass", bad)
+        assert ei.value.status == mmk.MMK_ERR_ARG
+    assert mmk.lib().mmk_set_option(ctx.h, len(mmk.OPTIONS), 0) == mmk.MMK_ERR_ARG   # no such option
+    ctx.profile(True)
+    for kid in (-1, len(mmk.KERNEL_IDS)):   # kernel ids 0 .. 9
+        with pytest.raises(mmk.MMKError) as ei:
+            ctx.profile_read(kid)
+        assert ei.value.status == mmk.MMK_ERR_ARG
     ctx.close()
     q = mmk.Context(ModelParams(nx=8, ny=8, ntheta=4, ns=8))
     q.set_state(torch.as_tensor(gen.make_psi0(8, 8, 4, seed=0)))
