@@ -81,10 +81,10 @@ hipError_t launch_r0_field(const T *Mb, T *M, const R0Seg *seg, const int32_t *s
 
 // ---- one anchor per block: depleted sub-cycling in one pass (Alg. 2's inner loop) ----------
 // With the clamp, every sub-step needs the coarse density of each anchor over all its tracked
-// cells.  In the anchor layout a block holds one anchor's tracked cells in registers (nthr
-// threads of C slots, whole runs per thread, the rest padding) and runs the n sub-steps there,
-// re-forming the clamp by a block-wide sum before each: M_b is read and written once per
-// micro-step.  The state is M[r0][C/4][nthr][4]: slot j of thread t (slot id j nthr + t) at
+// cells.  In the anchor layout a block holds the tracked cells of one anchor at a time in
+// registers (nthr threads of C slots, whole runs per thread, the rest padding) and runs the n
+// sub-steps there, re-forming the clamp by a block-wide sum before each: M_b is read and written
+// once per micro-step.  The state is M[r0][C/4][nthr][4]: slot j of thread t (slot id j nthr + t) at
 // ((j / 4) nthr + t) 4 + j % 4, so that a thread's slots come in 16-byte groups.
 struct R0Slots {
     bool ok = false;
@@ -121,8 +121,9 @@ template <typename T>
 hipError_t launch_r0_marg(const T *q01, int nrun, const R0Seg *seg, const int32_t *seg_start, T *m0, T *m1,
                           const R0Const<T> &c, hipStream_t s);
 // Between the anchor layout and the tiled one (vx > 0: M[tile][cell][64 vx]) or the caller's
-// (vx = 0: Mb[cell][x]); to_anchor = 1 writes the anchor layout (its padding slots untouched,
-// never read), else the other one (the tiled padding set to 0).
+// (vx = 0: Mb[cell][x]); to_anchor = 1 writes the anchor layout (its padding slots untouched: the
+// kernel loads them with their group and drops them), else the other one (the tiled padding set
+// to 0).
 template <typename T>
 hipError_t launch_r0_anchor_layout(const T *src, T *dst, const int32_t *cell_pos, const R0Const<T> &c, int vx,
                                    int64_t per_anchor, int nthr, bool to_anchor, hipStream_t s);
