@@ -4,6 +4,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -33,6 +34,19 @@ def test_psi_bytes_of_the_benchmark_launches():
     n_psi, nxy = 256 * 256 * 64, 256 * 256
     assert bench.psi_bytes(p, 4, False) == 4 * (3 * n_psi + 6 * nxy) == 51904512
     assert bench.psi_bytes(p, 4, True) == 4 * (4 * n_psi + 16 * nxy) == 71303168
+
+
+def test_anchor_resolved_bytes():
+    p = gen.ModelParams(nx=128, ny=128, ntheta=32, ns=32, rc=0.1)
+    nxy, ncell, nrun = 128 * 128, 13216, 3056
+    # one launch per micro-step with one anchor per block: read and write M_b, read psi, write the
+    # run-total pairs; the marginals read the pairs and write m0, m1
+    assert bench.r0_anchor_bytes(p, 4, ncell, nrun) == 4 * (2 * ncell * nxy + nxy * 32 + 2 * nrun * nxy) == 2134900736
+    assert bench.r0_marg_bytes(p, 4, nrun) == 4 * (2 * nrun * nxy + 2 * nxy * 32) == 404750336
+    # the plain anchor-resolved motor launch: M_b both ways, run totals, marginals, clamp and pool
+    assert bench.r0_motor_bytes(p, 4, ncell, nrun, True) == 1936850944
+    cells = np.array([[0, 0, 0, 0], [0, 0, 0, 1], [0, 0, 0, 3], [0, 0, 1, 4], [1, 0, 1, 5]])
+    assert bench.r0_runs(cells) == 4   # a gap in l, a new k, a new a
 
 
 def test_motor_flops_scale_with_cells_and_steps():
