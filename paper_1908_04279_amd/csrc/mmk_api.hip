@@ -98,7 +98,7 @@ Layout make_layout(const mmk_params &p, int ckpt_every, int max_tape_steps) {
     const R0Plan rp = r0 ? r0_plan_of(p) : R0Plan{};
     const size_t np = (size_t)n_psi(p), nxy = (size_t)p.nx * p.ny;
     // M, or the tiled anchor-resolved state (M[tile][cell][64 vx]) or its anchor layout
-    // (M[r0][C][nthr]), whichever is larger
+    // (M[r0][C/4][nthr][4]), whichever is larger
     const R0Slots rs = r0 ? r0_slots_of(p, rp) : R0Slots{};
     size_t nm = r0 ? (size_t)r0_tiled_elems(rp.ncell, (int64_t)nxy, r0_vx(e, rp.lmax)) : (size_t)n_m(p);
     if (rs.ok) nm = std::max(nm, (size_t)rs.per_anchor() * nxy);
