@@ -362,41 +362,50 @@ __device__ __forceinline__ int floor_div8(int a) { return a >= 0 ? a / 8 : -((-a
 __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 // force[c][x][y] = sum of window cell (x - o_t, y - o_t') of every tile (t, t') whose window
-// covers (x, y) modulo the grid, o the window origin 8 t - rx; in the fixed order (image of x,
-// t, image of y, t').  For an image X = x + m nx, the tiles whose window [8t - rx, 8t - rx +
-// wx) holds X are t in [ceil((X + rx - wx + 1) / 8), floor((X + rx) / 8)].
+// covers (x, y) modulo the grid, o the window origin 8 t - rx.  For an image X = x + m nx, the
+// tiles whose window [8t - rx, 8t - rx + wx) holds X are t in [ceil((X + rx - wx + 1) / 8),
+// floor((X + rx) / 8)].  A block: 64 grid cells (one per lane) and 4 waves; wave q takes the
+// tiles t with t = q mod 4, in the order (image of x, t, image of y, t'), and the 4 waves' sums
+// meet in LDS in a fixed order: the same bits on every run.
 template <typename T>
 __global__ __launch_bounds__(256) void k_force_merge(const double *__restrict__ part, T *__restrict__ force, int nx,
                                                      int ny, ForcePlan fp) {
+    __shared__ double red[2][4][64];
     const int64_t nxy = (int64_t)nx * ny;
     const int nwin = 2 * fp.wx * fp.wy;
-    for (int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cell < nxy;
-         cell += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(cell / ny), y = (int)(cell % ny);
-        double fx = 0.0, fy = 0.0;
-        // images X of x that some window can hold: -rx <= X <= 8 (tiles_i - 1) - rx + wx - 1
-        const int mx0 = -floor_div(x + fp.rx, nx), mx1 = floor_div(8 * (fp.tiles_i - 1) - fp.rx + fp.wx - 1 - x, nx);
-        const int my0 = -floor_div(y + fp.ry, ny), my1 = floor_div(8 * (fp.tiles_j - 1) - fp.ry + fp.wy - 1 - y, ny);
-        for (int mx = mx0; mx <= mx1; ++mx) {
-            const int X = x + mx * nx;
-            const int t0 = max(floor_div8(X + fp.rx - fp.wx + 8), 0), t1 = min(floor_div8(X + fp.rx), fp.tiles_i - 1);
-            for (int ti = t0; ti <= t1; ++ti) {
-                const int wxc = X - (8 * ti - fp.rx);
-                for (int my = my0; my <= my1; ++my) {
-                    const int Y = y + my * ny;
-                    const int u0 = max(floor_div8(Y + fp.ry - fp.wy + 8), 0);
-                    const int u1 = min(floor_div8(Y + fp.ry), fp.tiles_j - 1);
-                    for (int tj = u0; tj <= u1; ++tj) {
-                        const int wyc = Y - (8 * tj - fp.ry);
-                        const double *w = part + ((size_t)ti * fp.tiles_j + tj) * nwin + 2 * (wxc * fp.wy + wyc);
-                        fx += w[0];
-                        fy += w[1];
-                    }
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t cell = (int64_t)blockIdx.x * 64 + lane;
+    const bool ok = cell < nxy;
+    const int64_t cz = ok ? cell : 0;
+    const int x = (int)(cz / ny), y = (int)(cz % ny);
+    double fx = 0.0, fy = 0.0;
+    // images X of x that some window can hold: -rx <= X <= 8 (tiles_i - 1) - rx + wx - 1
+    const int mx0 = -floor_div(x + fp.rx, nx), mx1 = floor_div(8 * (fp.tiles_i - 1) - fp.rx + fp.wx - 1 - x, nx);
+    const int my0 = -floor_div(y + fp.ry, ny), my1 = floor_div(8 * (fp.tiles_j - 1) - fp.ry + fp.wy - 1 - y, ny);
+    for (int mx = mx0; mx <= mx1; ++mx) {
+        const int X = x + mx * nx;
+        const int t0 = max(floor_div8(X + fp.rx - fp.wx + 8), 0), t1 = min(floor_div8(X + fp.rx), fp.tiles_i - 1);
+        for (int ti = t0 + ((q - t0) % 4 + 4) % 4; ti <= t1; ti += 4) {
+            const int wxc = X - (8 * ti - fp.rx);
+            for (int my = my0; my <= my1; ++my) {
+                const int Y = y + my * ny;
+                const int u0 = max(floor_div8(Y + fp.ry - fp.wy + 8), 0);
+                const int u1 = min(floor_div8(Y + fp.ry), fp.tiles_j - 1);
+                for (int tj = u0; tj <= u1; ++tj) {
+                    const int wyc = Y - (8 * tj - fp.ry);
+                    const double *w = part + ((size_t)ti * fp.tiles_j + tj) * nwin + 2 * (wxc * fp.wy + wyc);
+                    fx += w[0];
+                    fy += w[1];
                 }
             }
         }
-        force[cell] = (T)fx;
-        force[nxy + cell] = (T)fy;
+    }
+    red[0][q][lane] = fx;
+    red[1][q][lane] = fy;
+    __syncthreads();
+    if (q == 0 && ok) {
+        force[cell] = (T)(((red[0][0][lane] + red[0][1][lane]) + red[0][2][lane]) + red[0][3][lane]);
+        force[nxy + cell] = (T)(((red[1][0][lane] + red[1][1][lane]) + red[1][2][lane]) + red[1][3][lane]);
     }
 }
 
@@ -444,9 +453,7 @@ hipError_t launch_motor_force(const T *M, const T *psi, const uint32_t *blk, con
     }
     if (e != hipSuccess) return e;
     const int64_t nxy = (int64_t)nx * ny;
-    int64_t blocks = (nxy + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_force_merge<T>, dim3((unsigned)blocks), dim3(256), 0, s, part, force, nx, ny, fp);
+    hipLaunchKernelGGL(k_force_merge<T>, dim3((unsigned)((nxy + 63) / 64)), dim3(256), 0, s, part, force, nx, ny, fp);
     return hipGetLastError();
 }
 template hipError_t launch_motor_force<float>(const float *, const float *, const uint32_t *, const int *,
