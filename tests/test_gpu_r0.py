@@ -391,6 +391,26 @@ def onepass_launches(ctx):
     return ctx.profile_read("r0_anchor_step")[1], ctx.profile_read("r0_motor_step")[1]
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kw", [
+    dict(nx=24, ny=24, ntheta=8, ns=8, rc=0.3),    # runs <= 4: 4 slots a thread, 64 threads
+    dict(nx=24, ny=24, ntheta=8, ns=8, rc=0.45),   # runs <= 8: 8 slots a thread, 128 threads
+])
+def test_onepass_few_slots_against_oracle(kw, precision):
+    """The one-pass kernel with 4 and 8 slots a thread (the forms that store each anchor after the
+    next one's loads in FP64 as well) and up to 3 anchors per block in turn, against the oracle:
+    FP64 1e-12, FP32 against the FP64 oracle 1e-5."""
+    p = ModelParams(**kw)
+    cells, psi0, Mb0, fl, dt = substep_r0_case(p, True, 3)
+    assert run_length_max(cells) <= 8
+    if precision:
+        psi0, Mb0 = psi0.astype(np.float32), Mb0.astype(np.float32)
+    g = run_r0_gpu(p, psi0, Mb0, fl, 3, 6, dt, precision=precision)
+    assert g["launches"]["r0_anchor_step"] == 6
+    o = run_r0_oracle(p, psi0.astype(np.float64), Mb0.astype(np.float64), fl, 3, 6, dt)
+    compare(g, o, 1e-5 if precision else 1e-12)
+
+
 @pytest.mark.parametrize("kw,precision", [
     (dict(nx=20, ny=18, ntheta=16, ns=16, rc=0.35), 0),           # 16 slots a thread
     (dict(nx=24, ny=22, ntheta=16, ns=24, rc=0.45, v0=1.7), 1),  # runs of 22 cells: 24 slots (FP32)
