@@ -1062,21 +1062,34 @@ mmk_status mmk_get_force(mmk_ctx *c, void *force) {
         return fail(c, MMK_ERR_UNSUPPORTED, "spreading window of %d x %d cells is too large", fp.wx, fp.wy);
     if (p.rc > 0 && r0_field_lds(p.ns, c->esz) > 160 * 1024)
         return fail(c, MMK_ERR_UNSUPPORTED, "ns too large for the anchor-marginal field kernel at this precision");
-    if (p.rc > 0) {  // the field kernel reads the tiled layout
-        const mmk_status st = c->esz == 4 ? r0_tiled<float>(c) : r0_tiled<double>(c);
-        if (st != MMK_OK) return st;
+    hipError_t e;
+    // The field kernel reads the tiled layout.  After one-pass steps the state is in the anchor
+    // layout: a tiled copy goes to the other M buffer (free between steps) and the state stays as
+    // it is, so that the next step needs no conversion.
+    size_t Mtiled = c->L.M[c->cur];
+    if (p.rc > 0 && c->r0_anch) {
+        const int vx = r0_vx(c->esz, c->r0.lmax), b = 1 - c->cur;
+        if (c->esz == 4)
+            e = launch_r0_anchor_layout<float>(c->at<float>(c->L.M[c->cur]), c->at<float>(c->L.M[b]),
+                                               c->at<int32_t>(c->L.r0cpos), r0_cst<float>(c, 0.0, 0), vx,
+                                               c->r0s.per_anchor(), c->r0s.nthr, false, c->stream);
+        else
+            e = launch_r0_anchor_layout<double>(c->at<double>(c->L.M[c->cur]), c->at<double>(c->L.M[b]),
+                                                c->at<int32_t>(c->L.r0cpos), r0_cst<double>(c, 0.0, 0), vx,
+                                                c->r0s.per_anchor(), c->r0s.nthr, false, c->stream);
+        HIPCHK(c, e, "anchor -> tiled layout of Mb");
+        Mtiled = c->L.M[b];
     }
     int slot;
     HIPCHK(c, prof_begin(c, 5, &slot), "hipEventRecord");
-    hipError_t e;
     // the anchor-resolved model spreads its anchor marginal (the r0 integral of Eq. (10))
     const size_t Msrc = p.rc > 0 ? c->L.Mmarg : c->L.M[c->cur];
     if (p.rc > 0) {
         if (c->esz == 4)
-            e = launch_r0_field<float>(c->at<float>(c->L.M[c->cur]), c->at<float>(c->L.Mmarg), c->at<R0Seg>(c->L.r0seg),
+            e = launch_r0_field<float>(c->at<float>(Mtiled), c->at<float>(c->L.Mmarg), c->at<R0Seg>(c->L.r0seg),
                                        c->at<int32_t>(c->L.r0start), r0_cst<float>(c, 0.0, 0), p.ns, c->stream);
         else
-            e = launch_r0_field<double>(c->at<double>(c->L.M[c->cur]), c->at<double>(c->L.Mmarg),
+            e = launch_r0_field<double>(c->at<double>(Mtiled), c->at<double>(c->L.Mmarg),
                                         c->at<R0Seg>(c->L.r0seg), c->at<int32_t>(c->L.r0start),
                                         r0_cst<double>(c, 0.0, 0), p.ns, c->stream);
         HIPCHK(c, e, "anchor-marginal field launch");

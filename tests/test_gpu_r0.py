@@ -497,8 +497,9 @@ def test_onepass_layout_round_trips():
 
 def test_onepass_graph_replays_are_bitwise():
     """mmk_step_graph on the one-pass path: the first graph includes the change to the anchor
-    layout, later ones start from it; a get_force in between (back to tiled) makes the next call
-    use the first graph again.  Every replay has the bits of mmk_step in a twin context."""
+    layout, later ones start from it; a get_force in between leaves the layout as it is, and a
+    get_state/set_state round trip (back to tiled) makes the next call use the first graph again.
+    Every replay has the bits of mmk_step in a twin context."""
     import torch
     from paper_1908_04279_amd import mmk
     p = ModelParams(nx=20, ny=18, ntheta=16, ns=16, rc=0.35)
@@ -510,7 +511,7 @@ def test_onepass_graph_replays_are_bitwise():
     for r in range(5):
         ctxs[0].step_graph(2, dt)
         ctxs[1].step(2, dt)
-        if r == 2:
+        if r in (1, 2):
             fa, fb = (c.get_force().double().cpu().numpy() for c in ctxs)
             assert np.array_equal(fa, fb)
         torch.cuda.synchronize()  # eager work and synchronisation between the replays
@@ -518,6 +519,9 @@ def test_onepass_graph_replays_are_bitwise():
         assert torch.equal(pa, pb) and torch.equal(Ma, Mbb), r
         assert torch.equal(ctxs[0].get_stress(), ctxs[1].get_stress()), r
         assert torch.equal(ctxs[0].get_motor_moments()[0], ctxs[1].get_motor_moments()[0]), r
+        if r == 2:  # set_state clears the step's outputs: after the checks
+            for c in ctxs:
+                c.set_state(*c.get_state())
     for c in ctxs:
         c.close()
 
