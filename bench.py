@@ -341,8 +341,9 @@ def r0_counters_traffic():
 def r0_substeps(args):
     """Fast motors (v0 = SUBSTEP_V0) on the anchor-resolved workload: one motor step per
     micro-step (dt at the motor limit) against motor sub-cycling (dt at the psi limit), as
-    simulated time per second; with depletion (every sub-step its own launch after its anchors'
-    clamp) and with linear attachment (the sub-steps in registers)."""
+    simulated time per second; with depletion (one pass per micro-step, or every sub-step its own
+    launch after its anchors' clamp) and with linear attachment (the sub-steps in registers); the
+    one-pass path also in FP64."""
     from paper_1908_04279_amd import mmk
     keep = ("micro_steps_per_s", "dt", "simulated_time_per_s", "motor_substeps", "motor_avg_us",
             "coarse_avg_us", "psi_avg_us", "onepass")
@@ -355,6 +356,9 @@ def r0_substeps(args):
                        ("subcycled_linear", dict(v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH, m_total=0.0))):
         r = run_r0(mmk.FP32, args.r0_steps, 20, 10, args.event_every, **over)
         d[name] = {k: r[k] for k in keep if k in r}
+    # the FP64 variant of the one-pass path (16 FP64 slots a thread)
+    r = run_r0(mmk.FP64, args.r0_steps, 20, 10, args.event_every, v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH)
+    d["subcycled_fp64"] = {k: r[k] for k in keep if k in r}
     d["speedup_simulated_time"] = (d["subcycled"]["simulated_time_per_s"]
                                    / d["one_motor_step"]["simulated_time_per_s"])
     d["speedup_simulated_time_launch_per_substep"] = (d["subcycled_launch_per_substep"]["simulated_time_per_s"]
