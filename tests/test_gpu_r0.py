@@ -452,15 +452,21 @@ def test_onepass_and_per_substep_paths_agree(kw, precision):
         assert err <= tol, (f, err)
 
 
-def test_onepass_layout_round_trips():
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_onepass_layout_round_trips(precision, tol):
     """One context through every change of the state's layout, against the oracle stepped alongside:
-    one-pass steps (anchor layout), get_state, get_anchors and get_force from it, steps of the other
-    path (tiled again), one-pass steps once more, a get_state/set_state round trip; FP64 1e-12."""
+    one-pass steps (anchor layout), get_state, get_anchors and get_force from it (the force leaves
+    the layout as it is: the next one-pass call starts from it), steps of the other path (tiled
+    again), one-pass steps once more, a get_state/set_state round trip; FP64 1e-12, FP32 (its
+    inputs rounded to FP32, the oracle in FP64) 1e-5."""
     import torch
     from paper_1908_04279_amd import mmk
     p = ModelParams(nx=20, ny=18, ntheta=16, ns=16, rc=0.35)
     cells, psi0, Mb0, fl, dt = substep_r0_case(p, True, 3)
-    ctx = mmk.Context(p)
+    if precision:
+        psi0, Mb0 = (a.astype(np.float32).astype(np.float64) for a in (psi0, Mb0))
+        fl = [tuple(a.astype(np.float32).astype(np.float64) for a in f) for f in fl]
+    ctx = mmk.Context(p, precision=precision)
     o = A.OracleR0(p)
     ctx.set_state(torch.as_tensor(psi0), torch.as_tensor(Mb0))
     o.set_state(psi0, Mb0)
@@ -477,7 +483,7 @@ def test_onepass_layout_round_trips():
             errs["force"] = rel_err(ctx.get_force().double().cpu().numpy(), A.r0_motor_force(p, cells, o.psi, o.Mb))
         print(tag, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
         for k, v in errs.items():
-            assert v <= 1e-12, (tag, k, v)
+            assert v <= tol, (tag, k, v)
 
     for e, (onepass, K) in enumerate([(1, 2), (1, 1), (0, 2), (1, 2)]):
         ctx.set_option("r0_onepass", onepass)
