@@ -210,7 +210,8 @@ mmk_status mmk_get_motor_moments(mmk_ctx *ctx, void *m0, void *m1);
  * order).  Needs state; MMK_ERR_UNSUPPORTED if the filament's reach makes the spreading window
  * ((8 + 2 r)^2 cells for a reach of r = L nx / (2 lx) cells, 8 bytes each, plus 18 KB of
  * staging) larger than the device's LDS per block; windows beyond 3072 cells cost one more
- * read of M per 3072 cells.  No host sync. */
+ * read of M per 3072 cells.  Leaves the state as it is (with rc > 0 it may use the second state
+ * buffer of the workspace as scratch).  No host sync. */
 mmk_status mmk_get_force(mmk_ctx *ctx, void *force);
 /* Anchor-resolved model only (rc > 0; else MMK_ERR_STATE): coarse [nx][ny] = the coarse density
  * of Eq. (5) at every anchor of the current state, and free_pool [nx][ny] = its free motors of
