@@ -679,7 +679,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=130)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["all", "fp32", "fp64", "fp32_1", "adjoint", "adjoint64", "depletion", "force",
-                                       "substeps", "r0", "r0_fp32", "r0_sub", "large", "c2", "launch_bound", "calib"],
+                                       "substeps", "r0", "r0_fp32", "r0_sub", "r0_sub64", "large", "c2", "launch_bound",
+                                       "calib"],
                     default="all",
                     help="restrict to one leg (used for profiler runs)")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -725,9 +726,10 @@ def main():
         print(json.dumps({"launch_bound_fp64_16x16x16x16": run_launch_bound(50)}), flush=True)
         return
 
-    if args.only == "r0_sub":  # the depleted sub-cycled anchor-resolved leg alone (profiler runs)
-        print(json.dumps({"anchor_resolved_subcycled_fp32": run_r0(
-            mmk.FP32, args.r0_steps, 20, 10, args.event_every, v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH)}), flush=True)
+    if args.only in ("r0_sub", "r0_sub64"):  # the depleted sub-cycled anchor-resolved leg alone (profiler runs)
+        prec, name = (mmk.FP64, "fp64") if args.only == "r0_sub64" else (mmk.FP32, "fp32")
+        print(json.dumps({f"anchor_resolved_subcycled_{name}": run_r0(
+            prec, args.r0_steps, 20, 10, args.event_every, v0=SUBSTEP_V0, motor_cfl=MOTOR_CFL_BENCH)}), flush=True)
         return
 
     if args.only in ("r0", "r0_fp32"):

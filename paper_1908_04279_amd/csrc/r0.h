@@ -93,7 +93,9 @@ struct R0Slots {
     // [C][nthr][2]: the slot's run and its first arclength cell, run | lo << 20 (-1 for padding),
     // and the run's offset and orientation, (a + 1024) | (b + 1024) << 11 | k << 22
     std::vector<int32_t> slot_tab;
-    std::vector<int32_t> cell_pos;     // [ncell][3]: slot (j nthr + t), a, b of every tracked cell
+    // [ncell][3]: slot (j nthr + t), a, b of every tracked cell; then [C nthr]: the cell at each
+    // position ((j / 4) nthr + t) 4 + j % 4 of an anchor's state, -1 for padding
+    std::vector<int32_t> cell_pos;
     int64_t per_anchor() const { return (int64_t)C * nthr; }
 };
 // Dynamic LDS of the one-pass kernel: its decoded slot table, 8 C nthr bytes (at most 160 KB).

@@ -138,7 +138,9 @@ R0Slots plan_r0_slots(const R0Plan &P, size_t esz) {
                 S.slot_tab[2 * q] = r | lo << 20;
                 S.slot_tab[2 * q + 1] = (g.a + 1024) | (g.b + 1024) << 11 | k << 22;
             }
-            S.cell_pos.assign((size_t)3 * P.ncell, 0);
+            // [ncell][3] (slot, a, b), then [C nthr]: the cell at each position of the anchor
+            // layout, -1 for padding
+            S.cell_pos.assign((size_t)3 * P.ncell + (size_t)C * T, -1);
             for (int t = 0; t < T; ++t)
                 for (int j = 0; j < C; ++j) {
                     const int r = S.slot_run[(size_t)j * T + t];
@@ -150,6 +152,7 @@ R0Slots plan_r0_slots(const R0Plan &P, size_t esz) {
                     S.cell_pos[3 * cell] = j * (int)T + t;
                     S.cell_pos[3 * cell + 1] = P.seg[r].a;
                     S.cell_pos[3 * cell + 2] = P.seg[r].b;
+                    S.cell_pos[3 * P.ncell + ((size_t)(j >> 2) * T + t) * 4 + (j & 3)] = (int32_t)cell;
                 }
             return S;
         }
@@ -599,36 +602,74 @@ __global__ __launch_bounds__(256) void k_r0_marg(const T *__restrict__ q01, int 
     }
 }
 
-// Anchor layout <-> tiled (tt = 64 vx > 0) or caller (tt = 0) layout, over the other layout's
-// elements in order (its side coalesced).
+// Anchor layout <-> tiled (tt = 64 vx > 0) or caller (tt = 0) layout, through LDS: a block takes
+// 64 consecutive anchors and 64 consecutive positions of the anchor layout.  The anchor side
+// moves as 64 rows of 64 consecutive values; on the other side, the cell at one position of 64
+// consecutive anchors sits at 64 consecutive filament cells x = r0 + (a, b) (within one row of
+// the grid), i.e. consecutive elements.  Padding positions (cell -1) are neither read nor written.
 template <typename T>
 __global__ __launch_bounds__(256) void k_r0_anchor_layout(const T *__restrict__ src, T *__restrict__ dst,
                                                           const int32_t *__restrict__ cell_pos, R0Const<T> c,
-                                                          int tt, int64_t per_anchor, int nthr, int64_t n,
-                                                          int to_anchor) {
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-        int64_t cell, x;
+                                                          int tt, int64_t per_anchor, int to_anchor) {
+    __shared__ T tile[64][65];
+    const int32_t *pos_cell = cell_pos + 3 * c.ncell;
+    const int64_t r_base = (int64_t)blockIdx.x * 64, p_base = (int64_t)blockIdx.y * 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // (cell, x) in the other layout
+    auto other = [&](int64_t cell, int64_t x) -> int64_t {
         if (tt > 0) {
-            const int64_t pt = c.ncell * tt, tl = e / pt, rem = e - tl * pt;
-            cell = rem / tt;
-            x = tl * tt + (rem - cell * tt);
-            if (x >= c.nxy) {
-                if (!to_anchor) dst[e] = T(0);
-                continue;
-            }
-        } else {
-            cell = e / c.nxy;
-            x = e - cell * c.nxy;
+            const int64_t tl = x / tt;
+            return (tl * c.ncell + cell) * tt + (x - tl * tt);
         }
-        const int i = (int)(x / c.ny), j = (int)(x - (int64_t)i * c.ny);
-        const int64_t r0 = (int64_t)wrap1(i - cell_pos[3 * cell + 1], c.nx) * c.ny + wrap1(j - cell_pos[3 * cell + 2], c.ny);
-        // slot j of thread t (slot id j nthr + t) sits at ((j / 4) nthr + t) 4 + j % 4
-        const int sl = cell_pos[3 * cell], sj = sl / nthr, st = sl - sj * nthr;
-        const int64_t q = r0 * per_anchor + ((int64_t)(sj >> 2) * nthr + st) * 4 + (sj & 3);
-        if (to_anchor)
-            dst[q] = src[e];
-        else
-            dst[e] = src[q];
+        return cell * c.nxy + x;
+    };
+    const int64_t ra = r_base + lane;  // this lane's anchor on the other side
+    const int ia = (int)(min(ra, c.nxy - 1) / c.ny), ja = (int)(min(ra, c.nxy - 1) - (int64_t)ia * c.ny);
+    // the cell and offset of position p_base + lane, read once and broadcast by lane
+    const int cell = pos_cell[p_base + lane];
+    const int oa = cell >= 0 ? cell_pos[3 * cell + 1] : 0, ob = cell >= 0 ? cell_pos[3 * cell + 2] : 0;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    if (!to_anchor) {
+        for (int ai = w; ai < 64; ai += 4) {
+            const int64_t r = r_base + ai;
+            if (r < c.nxy) tile[ai][lane] = src[r * per_anchor + p_base + lane];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int pi = wu + 4 * q;
+            const int cp = __builtin_amdgcn_readlane(cell, pi);
+            if (cp < 0 || ra >= c.nxy) continue;
+            const int64_t x = (int64_t)wrap1(ia + __builtin_amdgcn_readlane(oa, pi), c.nx) * c.ny +
+                              wrap1(ja + __builtin_amdgcn_readlane(ob, pi), c.ny);
+            dst[other(cp, x)] = tile[lane][pi];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int pi = wu + 4 * q;
+            const int cp = __builtin_amdgcn_readlane(cell, pi);
+            if (cp < 0 || ra >= c.nxy) continue;
+            const int64_t x = (int64_t)wrap1(ia + __builtin_amdgcn_readlane(oa, pi), c.nx) * c.ny +
+                              wrap1(ja + __builtin_amdgcn_readlane(ob, pi), c.ny);
+            tile[lane][pi] = src[other(cp, x)];
+        }
+        __syncthreads();
+        for (int ai = w; ai < 64; ai += 4) {
+            const int64_t r = r_base + ai;
+            if (r < c.nxy && cell >= 0) dst[r * per_anchor + p_base + lane] = tile[ai][lane];
+        }
+    }
+}
+
+// The tiled layout's padding (filament cells x >= nxy of the last tile) set to 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_r0_tiled_pad(T *__restrict__ dst, int64_t ncell, int64_t nxy, int tt) {
+    const int64_t last = nxy / tt, rem = nxy - last * tt, pad = tt - rem;
+    const int64_t n = ncell * pad;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int64_t cell = e / pad;
+        dst[(last * ncell + cell) * tt + rem + (e - cell * pad)] = T(0);
     }
 }
 
@@ -918,11 +959,17 @@ hipError_t launch_r0_marg(const T *q01, int nrun, const R0Seg *seg, const int32_
 template <typename T>
 hipError_t launch_r0_anchor_layout(const T *src, T *dst, const int32_t *cell_pos, const R0Const<T> &c, int vx,
                                    int64_t per_anchor, int nthr, bool to_anchor, hipStream_t s) {
-    const int64_t n = vx > 0 ? r0_tiled_elems(c.ncell, c.nxy, vx) : c.ncell * c.nxy;
-    if (n <= 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_r0_anchor_layout<T>, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, cell_pos, c,
-                       64 * vx, per_anchor, nthr, n, to_anchor ? 1 : 0);
+    (void)nthr;  // (the positions of the anchor layout carry their cells: cell_pos after its 3 ncell values)
+    if (c.ncell <= 0 || c.nxy <= 0) return hipSuccess;
+    if (per_anchor <= 0 || per_anchor % 64 != 0 || per_anchor / 64 > 65535) return hipErrorInvalidValue;
+    const int tt = 64 * vx;
+    if (!to_anchor && vx > 0 && c.nxy % tt != 0) {
+        const int64_t n = c.ncell * (tt - c.nxy % tt);
+        hipLaunchKernelGGL(k_r0_tiled_pad<T>, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0,
+                           s, dst, c.ncell, c.nxy, tt);
+    }
+    hipLaunchKernelGGL(k_r0_anchor_layout<T>, dim3((unsigned)((c.nxy + 63) / 64), (unsigned)(per_anchor / 64)),
+                       dim3(256), 0, s, src, dst, cell_pos, c, tt, per_anchor, to_anchor ? 1 : 0);
     return hipGetLastError();
 }
 
